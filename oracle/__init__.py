@@ -1,0 +1,137 @@
+"""Plain FP64 CPU oracle for Galerkin BEM entries (arXiv 1510.07244).
+
+TEST INFRASTRUCTURE ONLY: imported by ``tests/``, by the smoke check and by
+the CPU-baseline leg of the benchmark, never by the product package.  It
+shares no code with the HIP path; the only module both sides use is
+``bem_inputs`` (seeded meshes and index samples, no method arithmetic).
+
+The numerical work lives in ``oracle.c`` (see its header for the formulas
+and the paper passages they follow); this module marshals numpy arrays.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+from .build import LIB, build
+
+_lib = None
+
+LAPLACE, HELMHOLTZ = 0, 1
+SLP, DLP = 0, 1
+RULE_DUFFY, RULE_TRI7 = 0, 1
+DISJOINT, VERTEX, EDGE, IDENTICAL = 0, 1, 2, 3
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB):
+            build()
+        L = ctypes.CDLL(LIB)
+        dp = ctypes.POINTER(ctypes.c_double)
+        ip = ctypes.POINTER(ctypes.c_int32)
+        L.oracle_gauss01.argtypes = [ctypes.c_int, dp, dp]
+        L.oracle_tri7.argtypes = [dp, dp]
+        L.oracle_shared_vertices.argtypes = [ip, ctypes.c_int, ctypes.c_int]
+        L.oracle_ss_nregions.argtypes = [ctypes.c_int]
+        L.oracle_ss_rule.argtypes = [ctypes.c_int, ctypes.c_int, dp, dp]
+        L.oracle_ss_rule.restype = ctypes.c_long
+        L.oracle_entries.argtypes = [dp, ctypes.c_int, ip, ctypes.c_int,
+                                     ctypes.c_int, ctypes.c_int, ctypes.c_double,
+                                     ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                     ctypes.c_long, ip, ip, dp]
+        L.oracle_green_matrix.argtypes = [dp, ctypes.c_int, ip, ctypes.c_int,
+                                          ctypes.c_int, ctypes.c_double, ctypes.c_int,
+                                          ctypes.c_int, ctypes.c_int, ip,
+                                          ctypes.c_int, dp, dp, dp, ctypes.c_double, dp]
+        _lib = L
+    return _lib
+
+
+def _d(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def _i(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
+
+
+def gauss01(q):
+    """q-point Gauss-Legendre rule on [0,1] (nodes increasing)."""
+    x = np.zeros(q)
+    w = np.zeros(q)
+    if lib().oracle_gauss01(q, _d(x), _d(w)):
+        raise ValueError("bad order")
+    return x, w
+
+
+def tri7():
+    """Seven-point degree-5 triangle rule: barycentric (7,3), weights (7,)."""
+    b = np.zeros((7, 3))
+    w = np.zeros(7)
+    lib().oracle_tri7(_d(b), _d(w))
+    return b, w
+
+
+def shared_vertices(tri, i, j):
+    tri = np.ascontiguousarray(tri, dtype=np.int32)
+    return lib().oracle_shared_vertices(_i(tri), int(i), int(j))
+
+
+def ss_rule(case, q):
+    """Sauter-Schwab rule of the case (3 identical, 2 edge, 1 vertex) in
+    reference coordinates: pts (P,4) = (x^1, x^2, y^1, y^2), weights (P,)."""
+    nreg = lib().oracle_ss_nregions(case)
+    n = nreg * q ** 4
+    pts = np.zeros((n, 4))
+    w = np.zeros(n)
+    got = lib().oracle_ss_rule(case, q, _d(pts), _d(w))
+    if got != n:
+        raise ValueError("bad rule")
+    return pts, w
+
+
+def entries(v, tri, rows, cols, kernel=LAPLACE, layer=SLP, kappa=0.0,
+            rule=RULE_DUFFY, q_reg=4, q_sing=4):
+    """Galerkin entries G(rows[k], cols[k]) as complex128 (Laplace: Im = 0)."""
+    v = np.ascontiguousarray(v, dtype=np.float64)
+    tri = np.ascontiguousarray(tri, dtype=np.int32)
+    rows = np.ascontiguousarray(rows, dtype=np.int32).ravel()
+    cols = np.ascontiguousarray(cols, dtype=np.int32).ravel()
+    if rows.shape != cols.shape:
+        raise ValueError("rows/cols shape mismatch")
+    out = np.zeros(2 * rows.size)
+    rc = lib().oracle_entries(_d(v), v.shape[0], _i(tri), tri.shape[0], kernel, layer,
+                              float(kappa), rule, q_reg, q_sing, rows.size, _i(rows),
+                              _i(cols), _d(out))
+    if rc:
+        raise ValueError("oracle_entries: invalid arguments")
+    return out[0::2] + 1j * out[1::2]
+
+
+def block(v, tri, rows, cols, **op):
+    """Dense block G[rows x cols] (row-major numpy array)."""
+    rows = np.asarray(rows, dtype=np.int32)
+    cols = np.asarray(cols, dtype=np.int32)
+    R, C = np.meshgrid(rows, cols, indexing="ij")
+    return entries(v, tri, R.ravel(), C.ravel(), **op).reshape(rows.size, cols.size)
+
+
+def green_matrix(v, tri, rows, z, zn, zw, delta, kernel=LAPLACE, kappa=0.0, side=0, q=4):
+    """Green quadrature matrix (len(rows), 2m) complex128 of one cluster."""
+    v = np.ascontiguousarray(v, dtype=np.float64)
+    tri = np.ascontiguousarray(tri, dtype=np.int32)
+    rows = np.ascontiguousarray(rows, dtype=np.int32)
+    z = np.ascontiguousarray(z, dtype=np.float64)
+    zn = np.ascontiguousarray(zn, dtype=np.float64)
+    zw = np.ascontiguousarray(zw, dtype=np.float64)
+    m = zw.size
+    out = np.zeros(2 * rows.size * 2 * m)
+    rc = lib().oracle_green_matrix(_d(v), v.shape[0], _i(tri), tri.shape[0], kernel,
+                                   float(kappa), side, q, rows.size, _i(rows), m, _d(z),
+                                   _d(zn), _d(zw), float(delta), _d(out))
+    if rc:
+        raise ValueError("oracle_green_matrix: invalid arguments")
+    c = out[0::2] + 1j * out[1::2]
+    return c.reshape(2 * m, rows.size).T
