@@ -1,0 +1,191 @@
+"""Thin Python binding of the MI355X Galerkin BEM assembly library.
+
+Argument marshalling only: every step of the computation runs in the HIP
+kernels of ``libbem.so`` (C-ABI declared in ``include/bem.h``).  PyTorch
+provides device memory and streams.  There is no CPU fallback: importing the
+binding fails loudly when the library has not been built.
+"""
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libbem.so")
+
+BEM_OK, BEM_EINVAL, BEM_ENOMEM, BEM_EDEVICE, BEM_EUNSUPPORTED, BEM_ENONFINITE = 0, -1, -2, -3, -4, -5
+LAPLACE, HELMHOLTZ = 0, 1
+SLP, DLP = 0, 1
+PLAIN_FP64, MIXED = 0, 1
+RULE_DUFFY, RULE_TRI7 = 0, 1
+MAX_ORDER = 12
+
+_ERRNAMES = {BEM_EINVAL: "EINVAL", BEM_ENOMEM: "ENOMEM", BEM_EDEVICE: "EDEVICE",
+             BEM_EUNSUPPORTED: "EUNSUPPORTED", BEM_ENONFINITE: "ENONFINITE"}
+
+
+class BemError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{_ERRNAMES.get(code, code)}: {msg}")
+        self.code = code
+
+
+class bem_mesh(ctypes.Structure):
+    _fields_ = [("v", ctypes.c_void_p), ("nv", ctypes.c_int32),
+                ("tri", ctypes.c_void_p), ("nt", ctypes.c_int32)]
+
+
+class bem_op(ctypes.Structure):
+    _fields_ = [("kernel", ctypes.c_int32), ("layer", ctypes.c_int32),
+                ("precision", ctypes.c_int32), ("regular_rule", ctypes.c_int32),
+                ("q_regular", ctypes.c_int32), ("q_singular", ctypes.c_int32),
+                ("kappa", ctypes.c_double), ("near_singular_ratio", ctypes.c_double),
+                ("reserved", ctypes.c_int32 * 4)]
+
+
+class bem_blocks(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int32), ("row_ptr", ctypes.c_void_p), ("row_idx", ctypes.c_void_p),
+                ("row_len", ctypes.c_int64), ("col_ptr", ctypes.c_void_p),
+                ("col_idx", ctypes.c_void_p), ("col_len", ctypes.c_int64),
+                ("out_off", ctypes.c_void_p)]
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with paper_1510_07244_amd/build.py "
+                          "(or __graft_entry__.build()); there is no CPU fallback")
+    L = ctypes.CDLL(LIB_PATH)
+    P = ctypes.c_void_p
+    L.bem_create.argtypes = [ctypes.POINTER(P), ctypes.c_int]
+    L.bem_destroy.argtypes = [P]
+    L.bem_destroy.restype = None
+    L.bem_last_error.argtypes = [P]
+    L.bem_last_error.restype = ctypes.c_char_p
+    L.bem_check.argtypes = [P, P]
+    for name in ("bem_assemble_nearfield", "bem_assemble_coupling"):
+        getattr(L, name).argtypes = [P, ctypes.POINTER(bem_mesh), ctypes.POINTER(bem_op),
+                                     ctypes.POINTER(bem_blocks), P, ctypes.c_int64, P]
+    L.bem_eval_entries.argtypes = [P, ctypes.POINTER(bem_mesh), ctypes.POINTER(bem_op),
+                                   ctypes.c_int64, P, P, P, P]
+    return L
+
+
+_lib = _load()
+
+
+def lib():
+    return _lib
+
+
+def make_op(kernel=LAPLACE, layer=SLP, precision=PLAIN_FP64, regular_rule=RULE_DUFFY,
+            q_regular=4, q_singular=4, kappa=0.0, near_singular_ratio=0.0):
+    return bem_op(kernel, layer, precision, regular_rule, q_regular, q_singular, float(kappa),
+                  float(near_singular_ratio), (ctypes.c_int32 * 4)(0, 0, 0, 0))
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None and t.numel() > 0 else ctypes.c_void_p(0)
+
+
+def _stream(stream):
+    if stream is None:
+        import torch
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream))
+
+
+class Mesh:
+    """Device mesh: v (nv,3) float64 and tri (nt,3) int32 CUDA tensors."""
+
+    def __init__(self, v, tri):
+        import torch
+        self.v = v.to(device="cuda", dtype=torch.float64).contiguous()
+        self.tri = tri.to(device="cuda", dtype=torch.int32).contiguous()
+        self.c = bem_mesh(_ptr(self.v), self.v.shape[0], _ptr(self.tri), self.tri.shape[0])
+
+
+class Blocks:
+    """Device block list (CSR row/column triangle lists and output offsets)."""
+
+    def __init__(self, row_ptr, row_idx, col_ptr, col_idx, out_off):
+        import torch
+        dev = dict(device="cuda")
+        self.row_ptr = torch.as_tensor(row_ptr, dtype=torch.int32).to(**dev).contiguous()
+        self.row_idx = torch.as_tensor(row_idx, dtype=torch.int32).to(**dev).contiguous()
+        self.col_ptr = torch.as_tensor(col_ptr, dtype=torch.int32).to(**dev).contiguous()
+        self.col_idx = torch.as_tensor(col_idx, dtype=torch.int32).to(**dev).contiguous()
+        self.out_off = torch.as_tensor(out_off, dtype=torch.int64).to(**dev).contiguous()
+        self.n = self.out_off.numel()
+        self.c = bem_blocks(self.n, _ptr(self.row_ptr), _ptr(self.row_idx), self.row_idx.numel(),
+                            _ptr(self.col_ptr), _ptr(self.col_idx), self.col_idx.numel(),
+                            _ptr(self.out_off))
+
+    @classmethod
+    def from_lists(cls, rows, cols):
+        """Blocks from lists of row / column index arrays; outputs packed back
+        to back.  Returns (blocks, total number of entries)."""
+        import numpy as np
+        rp = np.zeros(len(rows) + 1, dtype=np.int64)
+        cp = np.zeros(len(cols) + 1, dtype=np.int64)
+        rp[1:] = np.cumsum([len(r) for r in rows])
+        cp[1:] = np.cumsum([len(c) for c in cols])
+        sizes = np.array([len(r) * len(c) for r, c in zip(rows, cols)], dtype=np.int64)
+        off = np.zeros(len(rows), dtype=np.int64)
+        off[1:] = np.cumsum(sizes)[:-1]
+        cat = lambda xs: np.concatenate([np.asarray(x, dtype=np.int32) for x in xs]) if xs else np.zeros(0, np.int32)
+        b = cls(rp.astype(np.int32), cat(rows), cp.astype(np.int32), cat(cols), off)
+        return b, int(sizes.sum())
+
+
+class Context:
+    """A library context on one device (``bem_create``)."""
+
+    def __init__(self, device=0):
+        h = ctypes.c_void_p()
+        rc = _lib.bem_create(ctypes.byref(h), int(device))
+        if rc:
+            raise BemError(rc, "bem_create failed")
+        self.h = h
+
+    def close(self):
+        if self.h:
+            _lib.bem_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def last_error(self):
+        return _lib.bem_last_error(self.h).decode()
+
+    def _rc(self, rc):
+        if rc:
+            raise BemError(rc, self.last_error())
+
+    def check(self, stream=None):
+        """bem_check: synchronise and raise on a device-side error flag."""
+        self._rc(_lib.bem_check(self.h, _stream(stream)))
+
+    def assemble_nearfield(self, mesh, op, blocks, out, stream=None):
+        self._rc(_lib.bem_assemble_nearfield(self.h, ctypes.byref(mesh.c), ctypes.byref(op),
+                                             ctypes.byref(blocks.c), _ptr(out), out.numel(),
+                                             _stream(stream)))
+
+    def assemble_coupling(self, mesh, op, pivots, out, stream=None):
+        self._rc(_lib.bem_assemble_coupling(self.h, ctypes.byref(mesh.c), ctypes.byref(op),
+                                            ctypes.byref(pivots.c), _ptr(out), out.numel(),
+                                            _stream(stream)))
+
+    def eval_entries(self, mesh, op, rows, cols, out, stream=None):
+        self._rc(_lib.bem_eval_entries(self.h, ctypes.byref(mesh.c), ctypes.byref(op),
+                                       rows.numel(), _ptr(rows), _ptr(cols), _ptr(out),
+                                       _stream(stream)))
+
+
+def out_dtype(op):
+    """torch dtype of one output entry for an operator."""
+    import torch
+    if op.precision == MIXED:
+        return torch.complex64 if op.kernel == HELMHOLTZ else torch.float32
+    return torch.complex128 if op.kernel == HELMHOLTZ else torch.float64

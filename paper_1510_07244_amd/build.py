@@ -1,0 +1,52 @@
+"""Build ``libbem.so`` (the C-ABI library) in-tree with hipcc for gfx950.
+
+Every HIP translation unit is compiled with packed FP32 instructions turned
+off (``-Xclang -target-feature -Xclang -packed-fp32-ops``); hipcc's host pass
+warns that it does not know that feature, which is harmless.
+"""
+import os
+import subprocess
+import sys
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+CSRC = os.path.join(HERE, "csrc")
+BUILD = os.path.join(HERE, "_build")
+LIB = os.path.join(HERE, "libbem.so")
+ARCH = os.environ.get("BEM_OFFLOAD_ARCH", "gfx950")
+
+SOURCES = ["bem_kernels.hip", "bem_quadrature.cpp", "bem_capi.cpp"]
+COMMON = ["-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-function",
+          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
+
+
+def _run(cmd, verbose):
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    p = subprocess.run(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT, text=True)
+    lines = [l for l in p.stdout.splitlines() if "packed-fp32-ops" not in l]
+    if lines and (verbose or p.returncode):
+        print("\n".join(lines), flush=True)
+    if p.returncode:
+        raise RuntimeError("command failed: " + " ".join(cmd))
+
+
+def build(verbose: bool = False) -> str:
+    os.makedirs(BUILD, exist_ok=True)
+    objs = []
+    for src in SOURCES:
+        obj = os.path.join(BUILD, src.rsplit(".", 1)[0] + ".o")
+        cmd = ["hipcc", *COMMON, "-c", os.path.join(CSRC, src), "-o", obj]
+        if src.endswith(".hip"):
+            cmd[1:1] = ["-x", "hip", f"--offload-arch={ARCH}"]
+        else:
+            cmd[1:1] = ["-ffp-contract=off"]
+        _run(cmd, verbose)
+        objs.append(obj)
+    _run(["hipcc", "-shared", "-fPIC", f"--offload-arch={ARCH}", "-o", LIB + ".tmp", *objs],
+         verbose)
+    os.replace(LIB + ".tmp", LIB)
+    return LIB
+
+
+if __name__ == "__main__":
+    print(build(verbose="-v" in sys.argv))

@@ -1,0 +1,288 @@
+// C-ABI entry points: argument validation, context state (flags, scratch,
+// quadrature tables) and kernel launches.  See include/bem.h.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstring>
+#include <new>
+
+#include "bem_internal.h"
+
+namespace {
+
+struct DeviceGuard {  // make the context's device current, restore on exit
+  int prev = -1;
+  explicit DeviceGuard(int dev) {
+    if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+    if (prev != dev) (void)hipSetDevice(dev);
+  }
+  ~DeviceGuard() {
+    int cur = -1;
+    if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
+  }
+};
+
+int fail(bem_ctx *ctx, int code, const std::string &msg) {
+  if (ctx) ctx->err = msg;
+  return code;
+}
+
+int hip_fail(bem_ctx *ctx, hipError_t e, const char *where) {
+  return fail(ctx, e == hipErrorOutOfMemory ? BEM_ENOMEM : BEM_EDEVICE,
+              std::string(where) + ": " + hipGetErrorString(e));
+}
+
+int check_op(bem_ctx *ctx, const bem_op *op) {
+  if (!op) return fail(ctx, BEM_EINVAL, "op is NULL");
+  if (op->kernel != BEM_LAPLACE && op->kernel != BEM_HELMHOLTZ)
+    return fail(ctx, BEM_EINVAL, "op.kernel must be BEM_LAPLACE or BEM_HELMHOLTZ");
+  if (op->layer != BEM_SLP && op->layer != BEM_DLP)
+    return fail(ctx, BEM_EINVAL, "op.layer must be BEM_SLP or BEM_DLP");
+  if (op->precision != BEM_PLAIN_FP64 && op->precision != BEM_MIXED)
+    return fail(ctx, BEM_EINVAL, "op.precision must be BEM_PLAIN_FP64 or BEM_MIXED");
+  if (op->regular_rule != BEM_RULE_DUFFY && op->regular_rule != BEM_RULE_TRI7)
+    return fail(ctx, BEM_EINVAL, "op.regular_rule must be BEM_RULE_DUFFY or BEM_RULE_TRI7");
+  if (op->q_regular < 1 || op->q_regular > BEM_MAX_ORDER || op->q_singular < 1 ||
+      op->q_singular > BEM_MAX_ORDER)
+    return fail(ctx, BEM_EINVAL, "quadrature orders must be in [1, BEM_MAX_ORDER]");
+  if (!std::isfinite(op->kappa) || !std::isfinite(op->near_singular_ratio) ||
+      op->near_singular_ratio < 0)
+    return fail(ctx, BEM_EINVAL, "op.kappa / op.near_singular_ratio must be finite (ratio >= 0)");
+  for (int k = 0; k < 4; ++k)
+    if (op->reserved[k]) return fail(ctx, BEM_EINVAL, "op.reserved must be zero");
+  if (op->precision == BEM_MIXED)
+    return fail(ctx, BEM_EUNSUPPORTED, "mixed precision is not available in this build");
+  return BEM_OK;
+}
+
+int check_mesh(bem_ctx *ctx, const bem_mesh *m) {
+  if (!m) return fail(ctx, BEM_EINVAL, "mesh is NULL");
+  if (m->nv < 0 || m->nt < 0) return fail(ctx, BEM_EINVAL, "mesh sizes must be >= 0");
+  if (m->nt > 0 && (!m->v || !m->tri || m->nv == 0))
+    return fail(ctx, BEM_EINVAL, "mesh arrays are NULL");
+  return BEM_OK;
+}
+
+int check_blocks(bem_ctx *ctx, const bem_blocks *b, const void *out, int64_t out_len) {
+  if (!b) return fail(ctx, BEM_EINVAL, "blocks is NULL");
+  if (b->n < 0 || b->row_len < 0 || b->col_len < 0 || out_len < 0)
+    return fail(ctx, BEM_EINVAL, "negative size");
+  if (b->n > 0 && (!b->row_ptr || !b->col_ptr || !b->out_off))
+    return fail(ctx, BEM_EINVAL, "block arrays are NULL");
+  if ((b->row_len > 0 && !b->row_idx) || (b->col_len > 0 && !b->col_idx))
+    return fail(ctx, BEM_EINVAL, "row_idx / col_idx is NULL");
+  if (out_len > 0 && !out) return fail(ctx, BEM_EINVAL, "out is NULL");
+  return BEM_OK;
+}
+
+// Geometry scratch of at least nt triangles; grows (after a device sync).
+int ensure_geo(bem_ctx *ctx, int32_t nt, int64_t *ldg) {
+  const int64_t ld = ((int64_t)nt + 63) / 64 * 64;
+  const size_t need = (size_t)bem::GEO_NF * (size_t)(ld > 0 ? ld : 64);
+  if (need > ctx->geo_cap) {
+    hipError_t e = hipDeviceSynchronize();
+    if (e != hipSuccess) return hip_fail(ctx, e, "hipDeviceSynchronize");
+    if (ctx->geo) (void)hipFree(ctx->geo);
+    ctx->geo = nullptr;
+    ctx->geo_cap = 0;
+    e = hipMalloc(&ctx->geo, need * sizeof(double));
+    if (e != hipSuccess) return hip_fail(ctx, e, "hipMalloc(geometry)");
+    ctx->geo_cap = need;
+  }
+  *ldg = ld > 0 ? ld : 64;
+  return BEM_OK;
+}
+
+// Device quadrature tables for (rule, q_regular, q_singular), built once.
+int get_rules(bem_ctx *ctx, const bem_op *op, const bem::DevRules **out) {
+  const int qr = op->regular_rule == BEM_RULE_TRI7 ? 0 : op->q_regular;
+  const auto key = std::make_tuple(op->regular_rule, qr, op->q_singular);
+  auto it = ctx->rules.find(key);
+  if (it != ctx->rules.end()) {
+    *out = &it->second;
+    return BEM_OK;
+  }
+  bem::DevRules d;
+  try {
+    const bem::TriRule tr = bem::triangle_rule(op->regular_rule, op->q_regular);
+    d.nq = (int)tr.s.size();
+    std::vector<double> h;
+    h.insert(h.end(), tr.s.begin(), tr.s.end());
+    h.insert(h.end(), tr.t.begin(), tr.t.end());
+    h.insert(h.end(), tr.w.begin(), tr.w.end());
+    hipError_t e = hipMalloc(&d.tri, h.size() * sizeof(double));
+    if (e != hipSuccess) return hip_fail(ctx, e, "hipMalloc(rule)");
+    e = hipMemcpy(d.tri, h.data(), h.size() * sizeof(double), hipMemcpyHostToDevice);
+    if (e != hipSuccess) return hip_fail(ctx, e, "hipMemcpy(rule)");
+    for (int cls = 1; cls <= 3; ++cls) {
+      const bem::SSRule r = bem::ss_rule(cls, op->q_singular);
+      d.np[cls] = (int)r.w.size();
+      std::vector<double> hs;
+      for (const auto *vec : {&r.xs, &r.xt, &r.ys, &r.yt, &r.w}) hs.insert(hs.end(), vec->begin(), vec->end());
+      e = hipMalloc(&d.ss[cls], hs.size() * sizeof(double));
+      if (e != hipSuccess) return hip_fail(ctx, e, "hipMalloc(ss rule)");
+      e = hipMemcpy(d.ss[cls], hs.data(), hs.size() * sizeof(double), hipMemcpyHostToDevice);
+      if (e != hipSuccess) return hip_fail(ctx, e, "hipMemcpy(ss rule)");
+    }
+  } catch (const std::bad_alloc &) {
+    return fail(ctx, BEM_ENOMEM, "host allocation failed");
+  } catch (const std::exception &ex) {
+    return fail(ctx, BEM_EINVAL, ex.what());
+  }
+  auto ins = ctx->rules.emplace(key, d);
+  *out = &ins.first->second;
+  return BEM_OK;
+}
+
+int assemble_blocks(bem_ctx *ctx, const bem_mesh *mesh, const bem_op *op,
+                    const bem_blocks *blocks, void *out, int64_t out_len, void *stream,
+                    bool coupling) {
+  if (!ctx) return BEM_EINVAL;
+  int rc;
+  if ((rc = check_mesh(ctx, mesh)) || (rc = check_op(ctx, op)) ||
+      (rc = check_blocks(ctx, blocks, out, out_len)))
+    return rc;
+  if (blocks->n == 0) return BEM_OK;
+  if (mesh->nt == 0) return fail(ctx, BEM_EINVAL, "blocks given for an empty mesh");
+  DeviceGuard g(ctx->device);
+  int64_t ldg;
+  const bem::DevRules *rules;
+  if ((rc = ensure_geo(ctx, mesh->nt, &ldg)) || (rc = get_rules(ctx, op, &rules))) return rc;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  hipError_t e = bem::launch_geometry(*mesh, ctx->geo, ldg, ctx->flags, s);
+  if (e != hipSuccess) return hip_fail(ctx, e, "geometry kernel launch");
+  bem::BlockArgs a{};
+  a.v = mesh->v;
+  a.tri = mesh->tri;
+  a.nv = mesh->nv;
+  a.nt = mesh->nt;
+  a.geo = ctx->geo;
+  a.ldg = ldg;
+  a.nblocks = blocks->n;
+  a.row_ptr = blocks->row_ptr;
+  a.row_idx = blocks->row_idx;
+  a.col_ptr = blocks->col_ptr;
+  a.col_idx = blocks->col_idx;
+  a.row_len = blocks->row_len;
+  a.col_len = blocks->col_len;
+  a.out_off = blocks->out_off;
+  a.out = out;
+  a.out_len = out_len;
+  a.rule = rules->tri;
+  a.nq = rules->nq;
+  const int xc = bem::rule_chunk(rules->nq);
+  a.nq_pad = (rules->nq + xc - 1) / xc * xc;
+  size_t lds;
+  bem::block_tile_shape(a.nq_pad, op->layer, &a.tr, &a.tc, &lds);
+  for (int c = 0; c < 4; ++c) a.ss[c] = rules->ss[c], a.ss_np[c] = rules->np[c];
+  a.kappa = op->kernel == BEM_HELMHOLTZ ? op->kappa : 0.0;
+  a.flags = ctx->flags;
+  e = bem::launch_blocks(op->kernel, op->layer, coupling, a, s);
+  if (e != hipSuccess) return hip_fail(ctx, e, "block kernel launch");
+  return BEM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int bem_create(bem_ctx **out, int device) {
+  if (!out) return BEM_EINVAL;
+  *out = nullptr;
+  int n = 0;
+  if (hipGetDeviceCount(&n) != hipSuccess || n <= 0) return BEM_EDEVICE;
+  if (device < 0 || device >= n) return BEM_EINVAL;
+  bem_ctx *ctx = new (std::nothrow) bem_ctx;
+  if (!ctx) return BEM_ENOMEM;
+  ctx->device = device;
+  DeviceGuard g(device);
+  hipError_t e = hipMalloc(&ctx->flags, 256);
+  if (e == hipSuccess) e = hipMemset(ctx->flags, 0, 256);
+  if (e != hipSuccess) {
+    delete ctx;
+    return e == hipErrorOutOfMemory ? BEM_ENOMEM : BEM_EDEVICE;
+  }
+  *out = ctx;
+  return BEM_OK;
+}
+
+void bem_destroy(bem_ctx *ctx) {
+  if (!ctx) return;
+  {
+    DeviceGuard g(ctx->device);
+    (void)hipDeviceSynchronize();
+    for (auto &kv : ctx->rules) {
+      (void)hipFree(kv.second.tri);
+      for (int c = 0; c < 4; ++c)
+        if (kv.second.ss[c]) (void)hipFree(kv.second.ss[c]);
+    }
+    if (ctx->geo) (void)hipFree(ctx->geo);
+    if (ctx->flags) (void)hipFree(ctx->flags);
+  }
+  delete ctx;
+}
+
+const char *bem_last_error(const bem_ctx *ctx) { return ctx ? ctx->err.c_str() : "no context"; }
+
+int bem_check(bem_ctx *ctx, void *stream) {
+  if (!ctx) return BEM_EINVAL;
+  DeviceGuard g(ctx->device);
+  hipError_t e = hipStreamSynchronize(static_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return hip_fail(ctx, e, "hipStreamSynchronize");
+  unsigned f = 0;
+  e = hipMemcpy(&f, ctx->flags, sizeof f, hipMemcpyDeviceToHost);
+  if (e == hipSuccess) e = hipMemset(ctx->flags, 0, sizeof f);
+  if (e != hipSuccess) return hip_fail(ctx, e, "reading device flags");
+  if (f & bem::FLAG_EINVAL) return fail(ctx, BEM_EINVAL, "invalid index or degenerate triangle seen on the device");
+  if (f & bem::FLAG_NONFINITE) return fail(ctx, BEM_ENONFINITE, "non-finite entry computed");
+  return BEM_OK;
+}
+
+int bem_assemble_nearfield(bem_ctx *ctx, const bem_mesh *mesh, const bem_op *op,
+                           const bem_blocks *blocks, void *out, int64_t out_len, void *stream) {
+  return assemble_blocks(ctx, mesh, op, blocks, out, out_len, stream, false);
+}
+
+int bem_assemble_coupling(bem_ctx *ctx, const bem_mesh *mesh, const bem_op *op,
+                          const bem_blocks *pivots, void *out, int64_t out_len, void *stream) {
+  return assemble_blocks(ctx, mesh, op, pivots, out, out_len, stream, true);
+}
+
+int bem_eval_entries(bem_ctx *ctx, const bem_mesh *mesh, const bem_op *op, int64_t n,
+                     const int32_t *rows, const int32_t *cols, void *out, void *stream) {
+  if (!ctx) return BEM_EINVAL;
+  int rc;
+  if ((rc = check_mesh(ctx, mesh)) || (rc = check_op(ctx, op))) return rc;
+  if (n < 0) return fail(ctx, BEM_EINVAL, "n < 0");
+  if (n == 0) return BEM_OK;
+  if (!rows || !cols || !out) return fail(ctx, BEM_EINVAL, "rows / cols / out is NULL");
+  if (mesh->nt == 0) return fail(ctx, BEM_EINVAL, "entries requested on an empty mesh");
+  DeviceGuard g(ctx->device);
+  int64_t ldg;
+  const bem::DevRules *rules;
+  if ((rc = ensure_geo(ctx, mesh->nt, &ldg)) || (rc = get_rules(ctx, op, &rules))) return rc;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  hipError_t e = bem::launch_geometry(*mesh, ctx->geo, ldg, ctx->flags, s);
+  if (e != hipSuccess) return hip_fail(ctx, e, "geometry kernel launch");
+  bem::EntryArgs a{};
+  a.v = mesh->v;
+  a.tri = mesh->tri;
+  a.nv = mesh->nv;
+  a.nt = mesh->nt;
+  a.geo = ctx->geo;
+  a.ldg = ldg;
+  a.n = n;
+  a.rows = rows;
+  a.cols = cols;
+  a.out = out;
+  a.rule = rules->tri;
+  a.nq = rules->nq;
+  for (int c = 0; c < 4; ++c) a.ss[c] = rules->ss[c], a.ss_np[c] = rules->np[c];
+  a.kappa = op->kernel == BEM_HELMHOLTZ ? op->kappa : 0.0;
+  a.flags = ctx->flags;
+  e = bem::launch_entries(op->kernel, op->layer, a, s);
+  if (e != hipSuccess) return hip_fail(ctx, e, "entry kernel launch");
+  return BEM_OK;
+}
+
+}  // extern "C"
