@@ -159,6 +159,40 @@ int bem_assemble_coupling(bem_ctx *ctx, const bem_mesh *mesh, const bem_op *op,
 int bem_eval_entries(bem_ctx *ctx, const bem_mesh *mesh, const bem_op *op, int64_t n,
                      const int32_t *rows, const int32_t *cols, void *out, void *stream);
 
+/* ---------------------------------------------------------------------
+ * Host-side H^2 structure (Sec. 2.3, the first and third construction steps;
+ * adaptive, so plain host code).  All pointers are HOST memory, owned by the
+ * caller; the calls are synchronous and touch no device.
+ * --------------------------------------------------------------------- */
+
+/* Cluster tree by geometric bisection (Sec. 2.3, cluster trees).  A cluster
+ * with more than `leaf` triangles is split at the midpoint of the longest
+ * side of the bounding box of its triangle centroids ((v0 + v1 + v2) / 3);
+ * centroids on the midpoint go to the first son, ties between equally long
+ * sides to the lowest axis, and the order inside each son is the order in
+ * the father.  Clusters are numbered depth-first, the root is 0.
+ * Outputs: perm[nt] (cluster c holds perm[cl_begin[c] .. cl_end[c])),
+ * *ncl, cl_begin / cl_end / cl_level [ncl], cl_son [2*ncl] (-1 for leaves),
+ * cl_box [6*ncl] = (lo x, y, z, hi x, y, z) of the union of the triangles'
+ * vertex boxes (the bounding box B_t).  Array capacities are max_clusters
+ * (2 nt - 1 always suffices).  BEM_EINVAL for bad ids, sizes or capacity. */
+int bem_cluster_tree(const double *v, int32_t nv, const int32_t *tri, int32_t nt, int32_t leaf,
+                     int32_t max_clusters, int32_t *perm, int32_t *ncl, int32_t *cl_begin,
+                     int32_t *cl_end, int32_t *cl_son, int32_t *cl_level, double *cl_box);
+
+/* Block tree (Sec. 2.3, block trees and admissibility).  From (root, root),
+ * a block (t, s) is an admissible (far-field) leaf when
+ *     max(diam B_t, diam B_s) <= eta * dist(B_t, B_s)
+ * (Euclidean box diagonal and box-to-box distance), an inadmissible
+ * (near-field) leaf when t or s has no sons, and otherwise has the sons
+ * sons(t) x sons(s) in the order (t1,s1), (t1,s2), (t2,s1), (t2,s2).  Leaves
+ * are listed depth-first as pairs (t, s) in near_ts / far_ts [2*max_blocks].
+ * *nnear / *nfar receive the counts even when they exceed max_blocks (then
+ * BEM_EINVAL is returned and the lists are truncated). */
+int bem_block_tree(int32_t ncl, const int32_t *cl_son, const double *cl_box, double eta,
+                   int32_t max_blocks, int32_t *near_ts, int32_t *nnear, int32_t *far_ts,
+                   int32_t *nfar);
+
 #ifdef __cplusplus
 }
 #endif

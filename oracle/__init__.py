@@ -135,3 +135,8 @@ def green_matrix(v, tri, rows, z, zn, zw, delta, kernel=LAPLACE, kappa=0.0, side
         raise ValueError("oracle_green_matrix: invalid arguments")
     c = out[0::2] + 1j * out[1::2]
     return c.reshape(2 * m, rows.size).T
+
+
+def num_threads():
+    """OpenMP threads the oracle's loops use."""
+    return int(lib().oracle_num_threads())

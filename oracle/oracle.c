@@ -578,3 +578,16 @@ int oracle_green_matrix(const double *v, int nv, const int32_t *tri, int nt,
     }
     return 0;
 }
+
+/* Number of OpenMP threads the oracle's parallel loops use. */
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+int oracle_num_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}

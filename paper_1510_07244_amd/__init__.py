@@ -65,6 +65,10 @@ def _load():
                                      ctypes.POINTER(bem_blocks), P, ctypes.c_int64, P]
     L.bem_eval_entries.argtypes = [P, ctypes.POINTER(bem_mesh), ctypes.POINTER(bem_op),
                                    ctypes.c_int64, P, P, P, P]
+    L.bem_cluster_tree.argtypes = [P, ctypes.c_int32, P, ctypes.c_int32, ctypes.c_int32,
+                                   ctypes.c_int32, P, P, P, P, P, P, P]
+    L.bem_block_tree.argtypes = [ctypes.c_int32, P, P, ctypes.c_double, ctypes.c_int32,
+                                 P, P, P, P]
     return L
 
 
@@ -181,6 +185,65 @@ class Context:
         self._rc(_lib.bem_eval_entries(self.h, ctypes.byref(mesh.c), ctypes.byref(op),
                                        rows.numel(), _ptr(rows), _ptr(cols), _ptr(out),
                                        _stream(stream)))
+
+
+def _np_ptr(a):
+    return ctypes.c_void_p(a.ctypes.data)
+
+
+class ClusterTree:
+    """Host cluster tree (``bem_cluster_tree``): perm, begin/end, sons, level,
+    box (lo, hi); ``idx(c)`` gives the triangle ids of cluster c."""
+
+    def __init__(self, v, tri, leaf=64):
+        import numpy as np
+        v = np.ascontiguousarray(v, dtype=np.float64)
+        tri = np.ascontiguousarray(tri, dtype=np.int32)
+        nt = tri.shape[0]
+        cap = max(2 * nt - 1, 1)
+        self.perm = np.zeros(nt, dtype=np.int32)
+        ncl = ctypes.c_int32()
+        self.begin = np.zeros(cap, dtype=np.int32)
+        self.end = np.zeros(cap, dtype=np.int32)
+        self.sons = np.zeros(2 * cap, dtype=np.int32)
+        self.level = np.zeros(cap, dtype=np.int32)
+        self.box = np.zeros(6 * cap, dtype=np.float64)
+        rc = _lib.bem_cluster_tree(_np_ptr(v), v.shape[0], _np_ptr(tri), nt, int(leaf), cap,
+                                   _np_ptr(self.perm), ctypes.byref(ncl), _np_ptr(self.begin),
+                                   _np_ptr(self.end), _np_ptr(self.sons), _np_ptr(self.level),
+                                   _np_ptr(self.box))
+        if rc:
+            raise BemError(rc, "bem_cluster_tree failed")
+        n = ncl.value
+        self.n = n
+        self.begin, self.end, self.level = self.begin[:n], self.end[:n], self.level[:n]
+        self.sons = self.sons[:2 * n].reshape(n, 2)
+        self.box = self.box[:6 * n].reshape(n, 6)
+
+    def idx(self, c):
+        return self.perm[self.begin[c]:self.end[c]]
+
+    def is_leaf(self, c):
+        return self.sons[c, 0] < 0
+
+
+def block_tree(ct, eta=2.0):
+    """(near, far) lists of (t, s) cluster pairs (``bem_block_tree``)."""
+    import numpy as np
+    cap = 1024
+    while True:
+        near = np.zeros(2 * cap, dtype=np.int32)
+        far = np.zeros(2 * cap, dtype=np.int32)
+        nn, nf = ctypes.c_int32(), ctypes.c_int32()
+        sons = np.ascontiguousarray(ct.sons.ravel())
+        box = np.ascontiguousarray(ct.box.ravel())
+        rc = _lib.bem_block_tree(ct.n, _np_ptr(sons), _np_ptr(box), float(eta), cap,
+                                 _np_ptr(near), ctypes.byref(nn), _np_ptr(far), ctypes.byref(nf))
+        if rc == 0:
+            return near[:2 * nn.value].reshape(-1, 2), far[:2 * nf.value].reshape(-1, 2)
+        if max(nn.value, nf.value) <= cap:
+            raise BemError(rc, "bem_block_tree failed")
+        cap = max(nn.value, nf.value)
 
 
 def out_dtype(op):

@@ -14,7 +14,7 @@ BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libbem.so")
 ARCH = os.environ.get("BEM_OFFLOAD_ARCH", "gfx950")
 
-SOURCES = ["bem_kernels.hip", "bem_quadrature.cpp", "bem_capi.cpp"]
+SOURCES = ["bem_kernels.hip", "bem_quadrature.cpp", "bem_capi.cpp", "bem_h2_tree.cpp"]
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-function",
           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
 
