@@ -14,7 +14,8 @@ BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libbem.so")
 ARCH = os.environ.get("BEM_OFFLOAD_ARCH", "gfx950")
 
-SOURCES = ["bem_kernels.hip", "bem_quadrature.cpp", "bem_capi.cpp", "bem_h2_tree.cpp"]
+SOURCES = ["bem_blocks.hip", "bem_kernels.hip", "bem_quadrature.cpp", "bem_capi.cpp",
+           "bem_h2_tree.cpp"]
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-function",
           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
 
@@ -31,8 +32,9 @@ def _run(cmd, verbose):
 
 
 def build(verbose: bool = False) -> str:
+    from concurrent.futures import ThreadPoolExecutor
     os.makedirs(BUILD, exist_ok=True)
-    objs = []
+    objs, cmds = [], []
     for src in SOURCES:
         obj = os.path.join(BUILD, src.rsplit(".", 1)[0] + ".o")
         cmd = ["hipcc", *COMMON, "-c", os.path.join(CSRC, src), "-o", obj]
@@ -40,8 +42,10 @@ def build(verbose: bool = False) -> str:
             cmd[1:1] = ["-x", "hip", f"--offload-arch={ARCH}"]
         else:
             cmd[1:1] = ["-ffp-contract=off"]
-        _run(cmd, verbose)
+        cmds.append(cmd)
         objs.append(obj)
+    with ThreadPoolExecutor(max_workers=min(8, len(cmds))) as pool:
+        list(pool.map(lambda c: _run(c, verbose), cmds))
     _run(["hipcc", "-shared", "-fPIC", f"--offload-arch={ARCH}", "-o", LIB + ".tmp", *objs],
          verbose)
     os.replace(LIB + ".tmp", LIB)

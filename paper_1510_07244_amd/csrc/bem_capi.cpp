@@ -2,6 +2,7 @@
 // quadrature tables) and kernel launches.  See include/bem.h.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <new>
@@ -114,6 +115,27 @@ int get_rules(bem_ctx *ctx, const bem_op *op, const bem::DevRules **out) {
     if (e != hipSuccess) return hip_fail(ctx, e, "hipMalloc(rule)");
     e = hipMemcpy(d.tri, h.data(), h.size() * sizeof(double), hipMemcpyHostToDevice);
     if (e != hipSuccess) return hip_fail(ctx, e, "hipMemcpy(rule)");
+    {
+      const bem::XiRule xr = bem::xi_rule(op->q_singular);
+      const int q = op->q_singular;
+      // [xi_a | w_a xi_a^2 | w_a xi_a | M1 = sum w xi, M2 = sum w xi^2]
+      std::vector<double> hx(3 * q + 2, 0.0);
+      double m1 = 0, m2 = 0;
+      for (int k = 0; k < q; ++k) {
+        hx[k] = xr.x[k];
+        hx[q + k] = xr.w3[k] / xr.x[k];
+        hx[2 * q + k] = xr.w3[k] / (xr.x[k] * xr.x[k]);
+        m1 += hx[2 * q + k];
+        m2 += hx[q + k];
+      }
+      hx[3 * q] = m1;
+      hx[3 * q + 1] = m2;
+      d.nxi = q;
+      e = hipMalloc(&d.xi, hx.size() * sizeof(double));
+      if (e != hipSuccess) return hip_fail(ctx, e, "hipMalloc(xi rule)");
+      e = hipMemcpy(d.xi, hx.data(), hx.size() * sizeof(double), hipMemcpyHostToDevice);
+      if (e != hipSuccess) return hip_fail(ctx, e, "hipMemcpy(xi rule)");
+    }
     for (int cls = 1; cls <= 3; ++cls) {
       const bem::SSRule r = bem::ss_rule(cls, op->q_singular);
       d.np[cls] = (int)r.w.size();
@@ -170,14 +192,17 @@ int assemble_blocks(bem_ctx *ctx, const bem_mesh *mesh, const bem_op *op,
   a.out_len = out_len;
   a.rule = rules->tri;
   a.nq = rules->nq;
-  const int xc = bem::rule_chunk(rules->nq);
+  const int xc = bem::rule_chunk(rules->nq, op->kernel);
   a.nq_pad = (rules->nq + xc - 1) / xc * xc;
   size_t lds;
-  bem::block_tile_shape(a.nq_pad, op->layer, &a.tr, &a.tc, &lds);
-  for (int c = 0; c < 4; ++c) a.ss[c] = rules->ss[c], a.ss_np[c] = rules->np[c];
+  if (!bem::block_tile_shape(a.nq_pad, ctx->lds_budget, &a.tr, &a.tc, &lds))
+    return fail(ctx, BEM_EUNSUPPORTED, "quadrature order too high for the LDS budget");
+  for (int c = 0; c < 4; ++c) a.ss.eta[c] = rules->ss[c], a.ss.np[c] = rules->np[c];
+  a.ss.xi = rules->xi;
+  a.ss.q = rules->nxi;
   a.kappa = op->kernel == BEM_HELMHOLTZ ? op->kappa : 0.0;
   a.flags = ctx->flags;
-  e = bem::launch_blocks(op->kernel, op->layer, coupling, a, s);
+  e = bem::launch_blocks(op->kernel, op->layer, coupling, a, lds, s);
   if (e != hipSuccess) return hip_fail(ctx, e, "block kernel launch");
   return BEM_OK;
 }
@@ -196,6 +221,11 @@ int bem_create(bem_ctx **out, int device) {
   if (!ctx) return BEM_ENOMEM;
   ctx->device = device;
   DeviceGuard g(device);
+  int lds_max = 0;
+  if (hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, device) ==
+          hipSuccess &&
+      lds_max >= 64 * 1024)
+    ctx->lds_budget = std::min<size_t>((size_t)lds_max, 80 * 1024);  // keep 2 workgroups per CU
   hipError_t e = hipMalloc(&ctx->flags, 256);
   if (e == hipSuccess) e = hipMemset(ctx->flags, 0, 256);
   if (e != hipSuccess) {
@@ -213,6 +243,7 @@ void bem_destroy(bem_ctx *ctx) {
     (void)hipDeviceSynchronize();
     for (auto &kv : ctx->rules) {
       (void)hipFree(kv.second.tri);
+      if (kv.second.xi) (void)hipFree(kv.second.xi);
       for (int c = 0; c < 4; ++c)
         if (kv.second.ss[c]) (void)hipFree(kv.second.ss[c]);
     }
@@ -277,7 +308,9 @@ int bem_eval_entries(bem_ctx *ctx, const bem_mesh *mesh, const bem_op *op, int64
   a.out = out;
   a.rule = rules->tri;
   a.nq = rules->nq;
-  for (int c = 0; c < 4; ++c) a.ss[c] = rules->ss[c], a.ss_np[c] = rules->np[c];
+  for (int c = 0; c < 4; ++c) a.ss.eta[c] = rules->ss[c], a.ss.np[c] = rules->np[c];
+  a.ss.xi = rules->xi;
+  a.ss.q = rules->nxi;
   a.kappa = op->kernel == BEM_HELMHOLTZ ? op->kappa : 0.0;
   a.flags = ctx->flags;
   e = bem::launch_entries(op->kernel, op->layer, a, s);

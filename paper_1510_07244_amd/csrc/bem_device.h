@@ -1,0 +1,279 @@
+// Device helpers shared by the kernels (gfx950, wave64): reciprocal square
+// root, sine/cosine, accumulators, pair classification, the Sauter-Schwab
+// relabelling and the wave-cooperative singular-pair quadrature.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "bem_internal.h"
+
+namespace bem {
+namespace dev {
+
+constexpr double kInv4Pi = 0.0795774715459476678844418816863;  // 1 / (4 pi)
+constexpr int kThreads = 256;
+constexpr int kWave = 64;
+
+// 1/sqrt(a) for a > 0: hardware estimate (relative error below 6e-8) and one
+// Newton step y (3 - a y^2) / 2, which leaves a relative error near 1e-15.
+__device__ __forceinline__ double rsqrt_newton(double a) {
+  const double y = __builtin_amdgcn_rsq(a);
+  const double t = a * y;
+  const double e = fma(-t, y, 1.0);
+  return fma(0.5 * y, e, y);
+}
+
+// sin and cos of x: Cody-Waite reduction x = k pi/2 + r, |r| <= pi/4, with
+// pi/2 split into three parts (the first two with 33 significant bits so that
+// k * part is exact for |k| < 2^20), then the Taylor polynomials of sin and
+// cos on [-pi/4, pi/4] truncated after x^17 / x^18 (remainders below 1e-19),
+// and the quadrant of k.
+constexpr double kTwoOverPi = 0.63661977236758134308;
+constexpr double kPio2a = 1.5707963267341256;     // 0x1.921fb544p+0
+constexpr double kPio2b = 6.077100506303966e-11;  // 0x1.0b4611a6p-34
+constexpr double kPio2c = 2.0222662487959506e-21; // 0x1.3198a2e037073p-69
+
+__device__ __forceinline__ void sincos_cw(double x, double *s, double *c) {
+  const double k = __builtin_rint(x * kTwoOverPi);
+  double r = fma(-k, kPio2a, x);
+  r = fma(-k, kPio2b, r);
+  r = fma(-k, kPio2c, r);
+  const double r2 = r * r;
+  double ps = 1.0 / 355687428096000.0;       //  1/17!
+  ps = fma(ps, r2, -1.0 / 1307674368000.0);  // -1/15!
+  ps = fma(ps, r2, 1.0 / 6227020800.0);      //  1/13!
+  ps = fma(ps, r2, -1.0 / 39916800.0);       // -1/11!
+  ps = fma(ps, r2, 1.0 / 362880.0);          //  1/9!
+  ps = fma(ps, r2, -1.0 / 5040.0);           // -1/7!
+  ps = fma(ps, r2, 1.0 / 120.0);             //  1/5!
+  ps = fma(ps, r2, -1.0 / 6.0);              // -1/3!
+  const double sr = fma(r * r2, ps, r);
+  double pc = -1.0 / 6402373705728000.0;     // -1/18!
+  pc = fma(pc, r2, 1.0 / 20922789888000.0);  //  1/16!
+  pc = fma(pc, r2, -1.0 / 87178291200.0);    // -1/14!
+  pc = fma(pc, r2, 1.0 / 479001600.0);       //  1/12!
+  pc = fma(pc, r2, -1.0 / 3628800.0);        // -1/10!
+  pc = fma(pc, r2, 1.0 / 40320.0);           //  1/8!
+  pc = fma(pc, r2, -1.0 / 720.0);            // -1/6!
+  pc = fma(pc, r2, 1.0 / 24.0);              //  1/4!
+  pc = fma(pc, r2, -0.5);                    // -1/2!
+  const double cr = fma(r2, pc, 1.0);
+  const int q = static_cast<int>(k) & 3;
+  const double a = (q & 1) ? cr : sr;
+  const double b = (q & 1) ? sr : cr;
+  *s = (q & 2) ? -a : a;
+  *c = ((q + 1) & 2) ? -b : b;
+}
+
+template <int KERNEL>
+struct Acc;
+template <>
+struct Acc<BEM_LAPLACE> {
+  double re = 0.0;
+};
+template <>
+struct Acc<BEM_HELMHOLTZ> {
+  double re = 0.0, im = 0.0;
+};
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int o = kWave / 2; o >= 1; o >>= 1) v += __shfl_xor(v, o, kWave);
+  return v;
+}
+
+template <int KERNEL>
+__device__ __forceinline__ void store(void *out, int64_t k, const Acc<KERNEL> &v,
+                                      unsigned *flags) {
+  if constexpr (KERNEL == BEM_LAPLACE) {
+    if (!isfinite(v.re)) atomicOr(flags, FLAG_NONFINITE);
+    static_cast<double *>(out)[k] = v.re;
+  } else {
+    if (!isfinite(v.re) || !isfinite(v.im)) atomicOr(flags, FLAG_NONFINITE);
+    static_cast<double2 *>(out)[k] = make_double2(v.re, v.im);
+  }
+}
+
+__device__ __forceinline__ int shared_vertex_count(int a0, int a1, int a2, int b0, int b1, int b2) {
+  return (a0 == b0) + (a0 == b1) + (a0 == b2) + (a1 == b0) + (a1 == b1) + (a1 == b2) +
+         (a2 == b0) + (a2 == b1) + (a2 == b2);
+}
+
+// rotate (t0, t1, t2) left by k in {0, 1, 2}, without indexing an array
+__device__ __forceinline__ void rotate3(int t0, int t1, int t2, int k, int *o0, int *o1, int *o2) {
+  *o0 = k == 0 ? t0 : (k == 1 ? t1 : t2);
+  *o1 = k == 0 ? t1 : (k == 1 ? t2 : t0);
+  *o2 = k == 0 ? t2 : (k == 1 ? t0 : t1);
+}
+
+// Relabelling of a singular pair (common vertices first):
+//   identical: mesh order; edge: the common vertices (lo, hi) by global id,
+//   then the third vertex; vertex: the common vertex, then the other two in
+//   the mesh's cyclic order.
+__device__ __forceinline__ void relabel(int i0, int i1, int i2, int j0, int j1, int j2, int cls,
+                                        int li[3], int lj[3]) {
+  if (cls == CLS_IDENTICAL) {
+    li[0] = i0, li[1] = i1, li[2] = i2;
+    lj[0] = j0, lj[1] = j1, lj[2] = j2;
+    return;
+  }
+  const bool s0 = i0 == j0 || i0 == j1 || i0 == j2;
+  const bool s1 = i1 == j0 || i1 == j1 || i1 == j2;
+  const bool s2 = i2 == j0 || i2 == j1 || i2 == j2;
+  if (cls == CLS_EDGE) {
+    const int ca = s0 ? i0 : i1;            // first common vertex in i's order
+    const int cb = s2 ? i2 : (s1 && s0 ? i1 : i2);
+    const int lo = min(ca, cb), hi = max(ca, cb);
+    const int ci = !s0 ? i0 : (!s1 ? i1 : i2);
+    const bool r0 = j0 == lo || j0 == hi, r1 = j1 == lo || j1 == hi;
+    const int cj = !r0 ? j0 : (!r1 ? j1 : j2);
+    li[0] = lo, li[1] = hi, li[2] = ci;
+    lj[0] = lo, lj[1] = hi, lj[2] = cj;
+    return;
+  }
+  const int ka = s0 ? 0 : (s1 ? 1 : 2);
+  const int a = ka == 0 ? i0 : (ka == 1 ? i1 : i2);
+  const int kb = j0 == a ? 0 : (j1 == a ? 1 : 2);
+  rotate3(i0, i1, i2, ka, &li[0], &li[1], &li[2]);
+  rotate3(j0, j1, j2, kb, &lj[0], &lj[1], &lj[2]);
+}
+
+// ---------------------------------------------------------- Sauter-Schwab
+// After relabelling, both affine maps start at a common vertex, so for a rule
+// point (x^, y^) = xi g(eta) the difference is x - y = xi d(eta) with
+//   d = g1 E1_i + g2 E2_i - g3 E1_j - g4 E2_j,   r = xi |d|.
+// With the Jacobian's factor xi^3 the xi sum of the Laplace kernels is a
+// moment of the xi rule:  SLP  sum_a w_a xi_a^2 / |d|,
+//                         DLP  sum_a w_a xi_a <d, n_j> / |d|^3;
+// the Helmholtz kernels keep the xi sum (e^{i kappa xi |d|}).
+struct PairGeo {
+  double E1i[3], E2i[3], E1j[3], E2j[3], n[3];
+  double scale;  // sqrt(g_i) sqrt(g_j) / (4 pi)
+};
+
+typedef const double __attribute__((address_space(4))) *uniform_ptr;
+
+// Loads and relabels pair (i, j) of class cls; false (and the flag) if a
+// vertex id is out of range.
+__device__ __forceinline__ bool pair_geometry(const double *v, const int32_t *tri, int nv,
+                                              const double *geo, int64_t ldg, int i, int j,
+                                              int cls, unsigned *flags, PairGeo *g) {
+  const int i0 = tri[3 * (int64_t)i], i1 = tri[3 * (int64_t)i + 1], i2 = tri[3 * (int64_t)i + 2];
+  const int j0 = tri[3 * (int64_t)j], j1 = tri[3 * (int64_t)j + 1], j2 = tri[3 * (int64_t)j + 2];
+  const bool ok = i0 >= 0 && i0 < nv && i1 >= 0 && i1 < nv && i2 >= 0 && i2 < nv && j0 >= 0 &&
+                  j0 < nv && j1 >= 0 && j1 < nv && j2 >= 0 && j2 < nv;
+  if (!ok) {
+    atomicOr(flags, FLAG_EINVAL);
+    return false;
+  }
+  int li[3], lj[3];
+  relabel(i0, i1, i2, j0, j1, j2, cls, li, lj);
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    const double pi0 = v[3 * (int64_t)li[0] + c], pi1 = v[3 * (int64_t)li[1] + c],
+                 pi2 = v[3 * (int64_t)li[2] + c];
+    const double pj0 = v[3 * (int64_t)lj[0] + c], pj1 = v[3 * (int64_t)lj[1] + c],
+                 pj2 = v[3 * (int64_t)lj[2] + c];
+    g->E1i[c] = pi1 - pi0;
+    g->E2i[c] = pi2 - pi1;
+    g->E1j[c] = pj1 - pj0;
+    g->E2j[c] = pj2 - pj1;
+  }
+  g->n[0] = geo[G_NX * ldg + j];
+  g->n[1] = geo[G_NY * ldg + j];
+  g->n[2] = geo[G_NZ * ldg + j];
+  g->scale = geo[G_SG * ldg + i] * geo[G_SG * ldg + j] * kInv4Pi;
+  return true;
+}
+
+// Adds the contribution of one eta point (map g at xi = 1, eta weight w).
+// Laplace sums are completed by the xi moment in ss_finish.
+template <int KERNEL, int LAYER>
+__device__ __forceinline__ void eta_point(const PairGeo &g, double g1, double g2, double g3,
+                                          double g4, double w, const SSArgs &ss, double kappa,
+                                          double *are, double *aim) {
+  double d[3];
+#pragma unroll
+  for (int c = 0; c < 3; ++c)
+    d[c] = fma(g1, g.E1i[c], fma(g2, g.E2i[c], fma(-g3, g.E1j[c], -g4 * g.E2j[c])));
+  const double rho2 = fma(d[0], d[0], fma(d[1], d[1], d[2] * d[2]));
+  const double z = rsqrt_newton(rho2);  // 1 / |d|
+  if constexpr (KERNEL == BEM_LAPLACE) {
+    if constexpr (LAYER == BEM_SLP) {
+      *are = fma(w, z, *are);
+    } else {
+      const double dn = fma(d[0], g.n[0], fma(d[1], g.n[1], d[2] * g.n[2]));
+      *are = fma(w * dn, z * z * z, *are);
+    }
+  } else {
+    const double rho = rho2 * z;
+    const uniform_ptr X = (uniform_ptr)(ss.xi);
+    const int q = ss.q;
+    double base = w * z;  // SLP: w_a xi_a^2 e^{i k xi rho} / rho
+    if constexpr (LAYER == BEM_DLP)
+      base = w * fma(d[0], g.n[0], fma(d[1], g.n[1], d[2] * g.n[2])) * z * z * z;
+    for (int a = 0; a < q; ++a) {
+      const double xa = X[a];
+      const double kr = kappa * xa * rho;
+      double sn, cs;
+      sincos_cw(kr, &sn, &cs);
+      if constexpr (LAYER == BEM_SLP) {
+        const double c = base * X[q + a];  // w_a xi_a^2
+        *are = fma(c, cs, *are);
+        *aim = fma(c, sn, *aim);
+      } else {  // w_a xi_a e^{i kr} (1 - i kr) <d, n> / |d|^3
+        const double c = base * X[2 * q + a];
+        *are = fma(c, fma(kr, sn, cs), *are);
+        *aim = fma(c, fma(-kr, cs, sn), *aim);
+      }
+    }
+  }
+}
+
+template <int KERNEL, int LAYER>
+__device__ __forceinline__ Acc<KERNEL> ss_finish(const PairGeo &g, const SSArgs &ss, double are,
+                                                 double aim) {
+  Acc<KERNEL> r;
+  if constexpr (KERNEL == BEM_LAPLACE) {
+    const uniform_ptr X = (uniform_ptr)(ss.xi);
+    const double moment = LAYER == BEM_SLP ? X[3 * ss.q + 1] : X[3 * ss.q];
+    r.re = are * moment * g.scale;
+  } else {
+    r.re = are * g.scale;
+    r.im = aim * g.scale;
+  }
+  return r;
+}
+
+// One singular pair per lane; all lanes of the wave share the class, so the
+// eta table is read with wave-uniform (scalar) loads.
+template <int KERNEL, int LAYER>
+__device__ __forceinline__ Acc<KERNEL> ss_pair_lane(const PairGeo &g, const SSArgs &ss, int cls,
+                                                    double kappa) {
+  const uniform_ptr T = (uniform_ptr)(ss.eta[cls]);
+  const int n = ss.np[cls];
+  double are = 0.0, aim = 0.0;
+  for (int p = 0; p < n; ++p)
+    eta_point<KERNEL, LAYER>(g, T[p], T[n + p], T[2 * n + p], T[3 * n + p], T[4 * n + p], ss,
+                             kappa, &are, &aim);
+  return ss_finish<KERNEL, LAYER>(g, ss, are, aim);
+}
+
+// One singular pair per wave: lanes stride over the eta points, then a
+// butterfly sum.  Every lane returns the entry.
+template <int KERNEL, int LAYER>
+__device__ Acc<KERNEL> ss_pair_wave(const PairGeo &g, const SSArgs &ss, int cls, double kappa) {
+  const int lane = threadIdx.x & (kWave - 1);
+  const double *T = ss.eta[cls];
+  const int n = ss.np[cls];
+  double are = 0.0, aim = 0.0;
+  for (int p = lane; p < n; p += kWave)
+    eta_point<KERNEL, LAYER>(g, T[p], T[n + p], T[2 * n + p], T[3 * n + p], T[4 * n + p], ss,
+                             kappa, &are, &aim);
+  are = wave_sum(are);
+  if constexpr (KERNEL == BEM_HELMHOLTZ) aim = wave_sum(aim);
+  return ss_finish<KERNEL, LAYER>(g, ss, are, aim);
+}
+
+}  // namespace dev
+}  // namespace bem

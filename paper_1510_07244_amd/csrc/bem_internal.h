@@ -25,13 +25,19 @@ struct TriRule {
 };
 TriRule triangle_rule(int rule, int q);
 
-// Sauter-Schwab rule of one singular class in reference coordinates
-// (x^1, x^2, y^1, y^2) with weights (Gauss weight times Jacobian).
+// Sauter-Schwab rule of one singular class, factored as (x^, y^) = xi g(eta):
+// per region and (eta1, eta2, eta3) Gauss triple the map g at xi = 1
+// (xs, xt, ys, yt) and the weight w_b w_c w_d J(eta) / xi^3; the xi nodes and
+// weights w_a xi_a^3 are in XiRule.
 struct SSRule {
   std::vector<double> xs, xt, ys, yt, w;
 };
+struct XiRule {
+  std::vector<double> x, w3;
+};
 enum { CLS_DISJOINT = 0, CLS_VERTEX = 1, CLS_EDGE = 2, CLS_IDENTICAL = 3 };
 SSRule ss_rule(int cls, int q);
+XiRule xi_rule(int q);
 
 // --------------------------------------------------------------- geometry
 // Per-triangle geometry, structure of arrays: geo[f * ldg + i].
@@ -53,8 +59,18 @@ enum : unsigned { FLAG_EINVAL = 1u, FLAG_NONFINITE = 2u };
 struct DevRules {
   int nq = 0;         // points per triangle (regular rule)
   double *tri = nullptr;  // [3][nq]: s, t, w
-  int np[4] = {0, 0, 0, 0};  // Sauter-Schwab points per class (index = class)
+  int np[4] = {0, 0, 0, 0};  // Sauter-Schwab eta points per class (index = class)
   double *ss[4] = {nullptr, nullptr, nullptr, nullptr};  // [5][np]: xs, xt, ys, yt, w
+  int nxi = 0;               // Sauter-Schwab order q
+  double *xi = nullptr;      // [3q + 2]: xi, w xi^2, w xi, then M1 = sum w xi, M2 = sum w xi^2
+};
+
+// Device Sauter-Schwab tables as seen by the kernels.
+struct SSArgs {
+  const double *eta[4];  // per class [5][np]
+  int32_t np[4];
+  const double *xi;      // [4][q]
+  int32_t q;
 };
 
 // Arguments of the block kernels (passed by value).
@@ -73,8 +89,7 @@ struct BlockArgs {
   const double *rule;  // [3][nq]
   int32_t nq, nq_pad;
   int32_t tr, tc;      // sub-tile rows / columns
-  const double *ss[4];
-  int32_t ss_np[4];
+  SSArgs ss;
   double kappa;
   unsigned *flags;
 };
@@ -90,8 +105,7 @@ struct EntryArgs {
   void *out;
   const double *rule;
   int32_t nq;
-  const double *ss[4];
-  int32_t ss_np[4];
+  SSArgs ss;
   double kappa;
   unsigned *flags;
 };
@@ -100,16 +114,19 @@ struct EntryArgs {
 hipError_t launch_geometry(const bem_mesh &m, double *geo, int64_t ldg, unsigned *flags,
                            hipStream_t s);
 hipError_t launch_blocks(int kernel, int layer, bool coupling, const BlockArgs &a,
-                         hipStream_t s);
+                         size_t lds_bytes, hipStream_t s);
 hipError_t launch_entries(int kernel, int layer, const EntryArgs &a, hipStream_t s);
-// choose the sub-tile shape and LDS bytes for a padded rule size
-void block_tile_shape(int nq_pad, int layer, int *tr, int *tc, size_t *lds_bytes);
-int rule_chunk(int nq);  // x-points per register chunk for a rule of nq points
+// sub-tile shape (rows, columns) and LDS bytes of the block kernel for a
+// padded rule size within an LDS budget; false if nothing fits
+bool block_tile_shape(int nq_pad, size_t lds_budget, int *tr, int *tc, size_t *lds_bytes);
+size_t block_lds_bytes(int nq_pad, int tr, int tc);
+int rule_chunk(int nq, int kernel);  // x-points per register chunk
 
 }  // namespace bem
 
 struct bem_ctx {
   int device = 0;
+  size_t lds_budget = 64 * 1024;  // LDS bytes one workgroup may use
   std::string err;
   unsigned *flags = nullptr;      // device, 1 word
   double *geo = nullptr;          // device scratch

@@ -159,6 +159,11 @@ static void ss_point(int cls, int reg, double xi, double h1, double h2, double h
   }
 }
 
+// Every region map above is linear in xi and every Jacobian carries the
+// factor xi^3, so a rule point factors into its xi part and its eta part:
+//   (x^, y^) = xi * g(eta),   weight = (w_a xi_a^3) * (w_b w_c w_d J(eta) / xi^3).
+// The table stores g (the map at xi = 1) and the eta weight for every region
+// and (eta1, eta2, eta3) Gauss triple; the xi nodes and weights are separate.
 SSRule ss_rule(int cls, int q) {
   if (q < 1 || q > BEM_MAX_ORDER) throw std::invalid_argument("order");
   const int nreg = cls == CLS_IDENTICAL ? 6 : cls == CLS_EDGE ? 5 : cls == CLS_VERTEX ? 2 : 0;
@@ -167,18 +172,29 @@ SSRule ss_rule(int cls, int q) {
   gauss_legendre01(q, gx.data(), gw.data());
   SSRule r;
   for (int reg = 0; reg < nreg; ++reg)
-    for (int a = 0; a < q; ++a)
-      for (int b = 0; b < q; ++b)
-        for (int c = 0; c < q; ++c)
-          for (int d = 0; d < q; ++d) {
-            double p[4], jac;
-            ss_point(cls, reg, gx[a], gx[b], gx[c], gx[d], p, &jac);
-            r.xs.push_back(p[0]);
-            r.xt.push_back(p[1]);
-            r.ys.push_back(p[2]);
-            r.yt.push_back(p[3]);
-            r.w.push_back(gw[a] * gw[b] * gw[c] * gw[d] * jac);
-          }
+    for (int b = 0; b < q; ++b)
+      for (int c = 0; c < q; ++c)
+        for (int d = 0; d < q; ++d) {
+          double p[4], jac;
+          ss_point(cls, reg, 1.0, gx[b], gx[c], gx[d], p, &jac);  // xi = 1: J = eta part
+          r.xs.push_back(p[0]);
+          r.xt.push_back(p[1]);
+          r.ys.push_back(p[2]);
+          r.yt.push_back(p[3]);
+          r.w.push_back(gw[b] * gw[c] * gw[d] * jac);
+        }
+  return r;
+}
+
+XiRule xi_rule(int q) {
+  if (q < 1 || q > BEM_MAX_ORDER) throw std::invalid_argument("order");
+  std::vector<double> gx(q), gw(q);
+  gauss_legendre01(q, gx.data(), gw.data());
+  XiRule r;
+  for (int a = 0; a < q; ++a) {
+    r.x.push_back(gx[a]);
+    r.w3.push_back(gw[a] * gx[a] * gx[a] * gx[a]);
+  }
   return r;
 }
 
