@@ -1,14 +1,24 @@
-"""Benchmark: Galerkin near-field assembly of the Laplace single- and
-double-layer operators on the 8192-triangle octahedron sphere (cluster tree
-by bounding-box bisection with leaf size 64, admissibility
-max(diam) <= 2 dist, Sauter-Schwab order 4, Duffy/Gauss order 4, plain FP64).
+"""Benchmark: H^2-matrix setup of the Laplace single- and double-layer
+operators on the 8192-triangle octahedron sphere (cluster tree by bounding-box
+bisection, leaf size 64; admissibility max(diam) <= 2 dist; Sauter-Schwab and
+Duffy/Gauss order 4; Green quadrature order 4 on each face of the Green box;
+cross-approximation tolerance 5e-8, which keeps sampled admissible blocks
+within 1e-6 relative error of the dense FP64 oracle -- checked by the GPU
+tests; plain FP64).
 
-One step = bem_assemble_nearfield for the SLP and for the DLP over all
-inadmissible blocks of the block tree, inputs resident in HBM.  Prints one
-JSON line (value = entries/s over the whole step) with a roofline object for
-the dominant kernel (the DLP block kernel, VALU-bound FP64) measured live
-with HIP events on the launch stream, and the FP64 CPU oracle's throughput
-on a bounded sample of the same blocks as cpu_baseline.
+Setup (timed once per repeat, wall clock, host pivot search included):
+cluster/block trees, nested row basis (Green matrices side 0) and the
+double layer's column basis (side 1), each level: Green matrices on the GPU,
+cross approximation on the host, basis contraction on the matrix cores; then
+near-field and coupling blocks of both operators.
+
+One step (the data-parallel hot path, inputs resident in HBM, pivots as
+chosen by the setup): Green matrices and basis contractions of both bases,
+near-field blocks of SLP and DLP, coupling blocks of SLP and DLP.  value =
+Galerkin entries (near field + coupling) per second.  The roofline object is
+for the dominant kernel, the DLP near-field block kernel (VALU-bound FP64),
+measured with HIP events on its launch stream; cpu_baseline is the FP64 CPU
+oracle on a bounded sample of the same blocks.
 
     python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu-baseline]
 """
@@ -25,18 +35,21 @@ sys.path.insert(0, ROOT)
 
 METRIC = "Galerkin entries/s + H2 setup time at 1e-6 rel err, learned/mixed vs plain FP64"
 FP64_VALU_PEAK = 78.6e12  # 256 CU x 4 SIMD x 16 lanes x 2 flop (FMA) x 2.4 GHz
-# algorithmic flops per quadrature point (FMA = 2, rsqrt = 1), and the extra
-# flops of a Sauter-Schwab point (region map and difference vector)
+# Algorithmic flops (FMA = 2, rsqrt = sincos = 1) per regular point pair,
+# by (kernel, layer); a Sauter-Schwab point of the factored rule adds the
+# difference vector d(eta) = 4 scaled edge vectors (24 flops).
 FLOPS_PER_POINT = {(0, 0): 11.0, (0, 1): 19.0, (1, 0): 18.0, (1, 1): 30.0}
-SS_EXTRA = 35.0
+SS_EXTRA = 24.0
 SS_REGIONS = {3: 6, 2: 5, 1: 2}
+Q = 4
 
 
 def parse():
     p = argparse.ArgumentParser()
     p.add_argument("--gpus", type=int, default=1)
-    p.add_argument("--steps", type=int, default=50)
+    p.add_argument("--steps", type=int, default=30)
     p.add_argument("--warmup", type=int, default=3)
+    p.add_argument("--setup-repeats", type=int, default=3)
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--cpu-seconds", type=float, default=12.0)
     return p.parse_args()
@@ -55,89 +68,143 @@ def class_counts(tri, rows, cols):
     return counts
 
 
-def launch_flops(counts, kernel, layer, q_reg, q_sing):
+def near_flops(counts, kernel, layer, q_reg, q_sing):
+    """Laplace: the singular xi sums are moments, q^3 eta points per region."""
     f = FLOPS_PER_POINT[(kernel, layer)]
     flops = counts[0] * (q_reg ** 2) ** 2 * f
     for cls, nreg in SS_REGIONS.items():
-        flops += counts[cls] * nreg * q_sing ** 4 * (f + SS_EXTRA)
+        pts = nreg * q_sing ** 3 * (1 if kernel == 0 else q_sing)
+        flops += counts[cls] * pts * (f + SS_EXTRA)
     return float(flops)
 
 
-def cpu_baseline(m, rows, cols, q, seconds):
+class H2Bench:
+    def __init__(self, pk, ctx, m):
+        import torch
+        from paper_1510_07244_amd.h2 import H2Setup
+        self.pk, self.ctx, self.m = pk, ctx, m
+        sync = torch.cuda.synchronize
+        t0 = time.perf_counter()
+        self.h = h = H2Setup(ctx, m.v, m.tri, kernel=pk.LAPLACE, q_regular=Q, q_singular=Q)
+        t1 = time.perf_counter()
+        self.V = h.basis(0)
+        self.W = h.basis(1)
+        sync()
+        t2 = time.perf_counter()
+        self.near, self.n_near = h.near_blocks()
+        self.cs, self.n_cs = h.coupling_blocks(self.V, self.V)
+        self.cd, self.n_cd = h.coupling_blocks(self.V, self.W)
+        self.ops = [h.op(pk.SLP), h.op(pk.DLP)]
+        f64 = dict(dtype=torch.float64, device="cuda")
+        self.out = {k: torch.empty(n, **f64) for k, n in
+                    (("ns", self.n_near), ("nd", self.n_near), ("cs", self.n_cs), ("cd", self.n_cd))}
+        self.assemble()
+        ctx.check()
+        t3 = time.perf_counter()
+        self.t_tree, self.t_bases, self.t_assembly = t1 - t0, t2 - t1, t3 - t2
+        self.t_setup = t3 - t0
+
+    def assemble(self, stream=None, ev=None):
+        ctx, h, o = self.ctx, self.h, self.out
+        seq = [("ns", lambda: ctx.assemble_nearfield(h.mesh, self.ops[0], self.near, o["ns"], stream)),
+               ("nd", lambda: ctx.assemble_nearfield(h.mesh, self.ops[1], self.near, o["nd"], stream)),
+               ("cs", lambda: ctx.assemble_coupling(h.mesh, self.ops[0], self.cs, o["cs"], stream)),
+               ("cd", lambda: ctx.assemble_coupling(h.mesh, self.ops[1], self.cd, o["cd"], stream))]
+        for name, call in seq:
+            if ev:
+                ev[name][0].record(stream)
+            call()
+            if ev:
+                ev[name][1].record(stream)
+
+    def step(self, stream, ev=None):
+        if ev:
+            ev["bases"][0].record(stream)
+        self.h.basis_replay(self.V, stream)
+        self.h.basis_replay(self.W, stream)
+        if ev:
+            ev["bases"][1].record(stream)
+        self.assemble(stream, ev)
+
+    def entries(self):
+        return 2 * self.n_near + self.n_cs + self.n_cd
+
+
+def cpu_baseline(m, hb, seconds):
     import oracle
-    from bem_inputs import sample_subset
-    order = sample_subset(np.arange(len(rows)), len(rows), seed=1)
+    h = hb.h
     rng = np.random.Generator(np.random.PCG64(1))
-    order = order[rng.permutation(order.size)]
+    work = [("near", k) for k in range(len(h.near))] + [("far", k) for k in range(len(h.far))]
+    order = rng.permutation(len(work))
     n = 0
-    t0 = time.perf_counter()
     used = 0
-    for k in order:
-        for layer in (0, 1):
-            g = oracle.block(m.v, m.tri, rows[k], cols[k], layer=layer, q_reg=q, q_sing=q)
-            n += g.size
+    t0 = time.perf_counter()
+    for idx in order:
+        kind, k = work[idx]
+        if kind == "near":
+            t, s = h.near[k]
+            pairs = [(h.ct.idx(t), h.ct.idx(s), 0), (h.ct.idx(t), h.ct.idx(s), 1)]
+        else:
+            t, s = h.far[k]
+            pairs = [(hb.V.piv[t], hb.V.piv[s], 0), (hb.V.piv[t], hb.W.piv[s], 1)]
+        for r, c, layer in pairs:
+            n += oracle.block(m.v, m.tri, r, c, layer=layer, q_reg=Q, q_sing=Q).size
         used += 1
         if time.perf_counter() - t0 > seconds:
             break
     dt = time.perf_counter() - t0
     return {"value": n / dt, "unit": "entries/s", "cores": oracle.num_threads(), "kind": "oracle",
-            "sample": f"{used} of {len(rows)} near blocks (seeded order), SLP and DLP, "
-                      f"{n} entries in {dt:.1f} s"}
+            "sample": f"{used} of {len(work)} blocks (near field and coupling, seeded order), SLP "
+                      f"and DLP each: {n} entries in {dt:.1f} s"}
 
 
 def main():
     args = parse()
     if args.gpus != 1:
-        print(f"bench.py measures one GPU only (got --gpus {args.gpus}): the assembly shards "
-              "by blocks with no communication, see the sharding notes; run with --gpus 1",
-              file=sys.stderr)
+        print(f"bench.py measures one GPU only (got --gpus {args.gpus}): block assembly shards "
+              "over GPUs without communication; run with --gpus 1", file=sys.stderr)
         sys.exit(2)
     import torch
     import paper_1510_07244_amd as pk
     from bem_inputs import octahedron_sphere
 
-    q = 4
     m = octahedron_sphere(32)
-    ct = pk.ClusterTree(m.v, m.tri, leaf=64)
-    near, far = pk.block_tree(ct, eta=2.0)
-    rows = [ct.idx(t) for t, s in near]
-    cols = [ct.idx(s) for t, s in near]
-    counts = class_counts(m.tri, rows, cols)
     ctx = pk.Context(0)
-    mesh = pk.Mesh(torch.from_numpy(m.v), torch.from_numpy(m.tri))
-    blocks, total = pk.Blocks.from_lists(rows, cols)
-    ops = [pk.make_op(pk.LAPLACE, layer, q_regular=q, q_singular=q) for layer in (pk.SLP, pk.DLP)]
-    outs = [torch.empty(total, dtype=torch.float64, device="cuda") for _ in ops]
+    setups = []
+    hb = None
+    for _ in range(max(1, args.setup_repeats)):
+        hb = H2Bench(pk, ctx, m)
+        setups.append((hb.t_setup, hb.t_tree, hb.t_bases, hb.t_assembly))
     stream = torch.cuda.current_stream()
-    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(args.steps)]
-
-    def step(events=None):
-        for k, (op, out) in enumerate(zip(ops, outs)):
-            if events:
-                events[2 * k].record(stream)
-            ctx.assemble_nearfield(mesh, op, blocks, out, stream=stream)
-            if events:
-                events[2 * k + 1].record(stream)
-
+    names = ["bases", "ns", "nd", "cs", "cd"]
+    evs = [{k: (torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+            for k in names} for _ in range(args.steps)]
     for _ in range(args.warmup):
-        step()
+        hb.step(stream)
     ctx.check(stream)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for k in range(args.steps):
-        step(ev[k])
+        hb.step(stream, evs[k])
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     ctx.check(stream)
     ms_step = (t1 - t0) * 1e3 / args.steps
-    ms_slp = float(np.mean([e[0].elapsed_time(e[1]) for e in ev]))
-    ms_dlp = float(np.mean([e[2].elapsed_time(e[3]) for e in ev]))
-    entries = 2 * total
-    f_slp = launch_flops(counts, 0, 0, q, q)
-    f_dlp = launch_flops(counts, 0, 1, q, q)
+    phase = {k: float(np.mean([e[k][0].elapsed_time(e[k][1]) for e in evs])) for k in names}
+
+    h = hb.h
+    rows = [h.ct.idx(t) for t, s in h.near]
+    cols = [h.ct.idx(s) for t, s in h.near]
+    counts = class_counts(m.tri, rows, cols)
+    f_dlp = near_flops(counts, 0, 1, Q, Q)
+    f_slp = near_flops(counts, 0, 0, Q, Q)
+    st = np.array(setups)
+    best = int(np.argmin(st[:, 0]))
+    ranks_v = hb.V.rank[hb.V.rank > 0]
+    ranks_w = hb.W.rank[hb.W.rank > 0]
     result = {
         "metric": METRIC,
-        "value": entries / (ms_step * 1e-3),
+        "value": hb.entries() / (ms_step * 1e-3),
         "unit": "entries/s",
         "n_gpus": 1,
         "steps": args.steps,
@@ -149,29 +216,37 @@ def main():
         "dtype": "f64",
         "data": "synthetic",
         "config": {
-            "workload": "Laplace SLP+DLP near field, octahedron sphere 8192 triangles, leaf 64, "
-                        "eta 2, Sauter-Schwab q=4, Duffy/Gauss q=4, plain FP64",
-            "triangles": int(m.nt), "near_blocks": int(len(near)), "far_blocks": int(len(far)),
-            "entries_per_step": int(entries),
+            "workload": "Laplace SLP+DLP H2 matrix, octahedron sphere 8192 triangles, leaf 64, "
+                        "eta 2, Sauter-Schwab q=4, Duffy/Gauss q=4, Green order 4, ACA 5e-8, "
+                        "plain FP64",
+            "triangles": int(m.nt), "near_blocks": int(len(h.near)), "far_blocks": int(len(h.far)),
+            "entries_per_step": int(hb.entries()),
+            "near_entries_per_operator": int(hb.n_near),
+            "coupling_entries": {"slp": int(hb.n_cs), "dlp": int(hb.n_cd)},
+            "rank_mean": {"row_basis": float(ranks_v.mean()), "dlp_column_basis": float(ranks_w.mean())},
             "pairs_by_class": {"disjoint": int(counts[0]), "vertex": int(counts[1]),
                                "edge": int(counts[2]), "identical": int(counts[3])},
         },
+        "h2_setup_s": {"best": float(st[best, 0]), "median": float(np.median(st[:, 0])),
+                       "tree": float(st[best, 1]), "bases": float(st[best, 2]),
+                       "assembly": float(st[best, 3]), "repeats": int(st.shape[0])},
+        "phase_ms": phase,
         "roofline": {
-            "kernel": "k_blocks<Laplace, DLP> (+ geometry kernel in the same call)",
-            "bound": "alu", "achieved": f_dlp / (ms_dlp * 1e-3) / 1e12,
+            "kernel": "k_blocks<Laplace, DLP> near field (+ geometry kernel in the same call)",
+            "bound": "alu", "achieved": f_dlp / (phase["nd"] * 1e-3) / 1e12,
             "peak": FP64_VALU_PEAK / 1e12, "unit": "TFLOP/s",
-            "frac": f_dlp / (ms_dlp * 1e-3) / FP64_VALU_PEAK, "traffic": None,
-            "ms_per_launch": ms_dlp, "flops_per_launch": f_dlp,
+            "frac": f_dlp / (phase["nd"] * 1e-3) / FP64_VALU_PEAK, "traffic": None,
+            "ms_per_launch": phase["nd"], "flops_per_launch": f_dlp,
         },
         "roofline_slp": {
-            "kernel": "k_blocks<Laplace, SLP>", "bound": "alu",
-            "achieved": f_slp / (ms_slp * 1e-3) / 1e12, "peak": FP64_VALU_PEAK / 1e12,
-            "unit": "TFLOP/s", "frac": f_slp / (ms_slp * 1e-3) / FP64_VALU_PEAK,
-            "ms_per_launch": ms_slp, "flops_per_launch": f_slp,
+            "kernel": "k_blocks<Laplace, SLP> near field", "bound": "alu",
+            "achieved": f_slp / (phase["ns"] * 1e-3) / 1e12, "peak": FP64_VALU_PEAK / 1e12,
+            "unit": "TFLOP/s", "frac": f_slp / (phase["ns"] * 1e-3) / FP64_VALU_PEAK,
+            "ms_per_launch": phase["ns"], "flops_per_launch": f_slp,
         },
     }
     if not args.no_cpu_baseline:
-        result["cpu_baseline"] = cpu_baseline(m, rows, cols, q, args.cpu_seconds)
+        result["cpu_baseline"] = cpu_baseline(m, hb, args.cpu_seconds)
     ctx.close()
     print(json.dumps(result), flush=True)
 

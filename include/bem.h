@@ -160,6 +160,52 @@ int bem_eval_entries(bem_ctx *ctx, const bem_mesh *mesh, const bem_op *op, int64
                      const int32_t *rows, const int32_t *cols, void *out, void *stream);
 
 /* ---------------------------------------------------------------------
+ * Cluster bases of the Green cross approximation (Sec. 2.3-2.4).
+ * --------------------------------------------------------------------- */
+
+/* Green quadrature matrices (Sec. 2.3, eq. green_matrix), one per cluster c.
+ * Rows: the triangles row_idx[row_ptr[c] .. row_ptr[c+1]) (the cluster t for
+ * a leaf, t^ = union of the sons' pivots for a father); columns: the m Green
+ * quadrature points of the cluster, z[c][nu][3] with outward unit normals
+ * zn[c][nu][3] and weights zw[c][nu], and delta[c] = diam(B_t).  Entry
+ * (r, nu) and (r, m + nu) of the output (column-major, leading dimension
+ * n_c, at out + out_off[c]) are
+ *     side 0:  sqrt(w) int_tau g(x, z) dx,  sqrt(w) delta int_tau d/dn(z) g(x, z) dx
+ *     side 1:  sqrt(w) int_tau d/dn(x) g(x, z) dx,
+ *              sqrt(w) delta int_tau d/dn(x) d/dn(z) g(x, z) dx
+ * (side 0: the row basis of both operators and the column basis of the
+ * single layer; side 1: the column basis of the double layer, whose kernel is
+ * d/dn(y) g(x, y)).  Triangle integrals use the Duffy/Gauss rule of order
+ * op->q_regular; op->kernel and op->kappa select the kernel.  All arrays are
+ * device memory; entry type double (Laplace) or double[2] (Helmholtz);
+ * out_off[c] + 2 m n_c <= out_len.  Index errors raise the device flag.
+ * max_rows (>= 0) is a hint, the largest n_c, that only sets how many
+ * workgroups share one cluster; any value gives the same result. */
+int bem_green_matrix(bem_ctx *ctx, const bem_mesh *mesh, const bem_op *op, int32_t side,
+                     int32_t ncl, const int32_t *row_ptr, const int32_t *row_idx, int64_t row_len,
+                     int32_t m, const double *z, const double *zn, const double *zw,
+                     const double *delta, const int64_t *out_off, void *out, int64_t out_len,
+                     int32_t max_rows, void *stream);
+
+/* Basis contraction on the FP64 matrix cores (Sec. 2.3, algebraic
+ * interpolation): for each matrix c,
+ *     V_c = A_c[:, tau_c] * P_c,   P_c = A_c[t~_c, tau_c]^{-1}
+ * with A_c the n_c x acols Green matrix at A + a_off[c] (column-major,
+ * leading dimension n_c), tau_c = piv_cols[c * max_rank .. + rank[c]) its
+ * pivot columns and P_c the rank[c] x rank[c] inverse of its pivot block at
+ * pinv + c * max_rank^2 (column-major, leading dimension rank[c]; complex
+ * interleaved when is_complex).  V_c (n_c x rank[c], column-major) goes to
+ * V + v_off[c].  nrows, rank, piv_cols, pinv, a_off, v_off, A and V are
+ * device memory; lengths a_len / v_len count entries.  For a father cluster
+ * the result is the transfer matrix V^_t of the nested basis.  max_rows is
+ * a launch-shape hint (the largest n_c) like in bem_green_matrix. */
+int bem_basis_contract(bem_ctx *ctx, int32_t is_complex, int32_t nmat, const int32_t *nrows,
+                       const int32_t *rank, int32_t max_rank, const int32_t *piv_cols,
+                       const double *pinv, const void *A, const int64_t *a_off, int32_t acols,
+                       int64_t a_len, void *V, const int64_t *v_off, int64_t v_len,
+                       int32_t max_rows, void *stream);
+
+/* ---------------------------------------------------------------------
  * Host-side H^2 structure (Sec. 2.3, the first and third construction steps;
  * adaptive, so plain host code).  All pointers are HOST memory, owned by the
  * caller; the calls are synchronous and touch no device.
@@ -192,6 +238,32 @@ int bem_cluster_tree(const double *v, int32_t nv, const int32_t *tri, int32_t nt
 int bem_block_tree(int32_t ncl, const int32_t *cl_son, const double *cl_box, double eta,
                    int32_t max_blocks, int32_t *near_ts, int32_t *nnear, int32_t *far_ts,
                    int32_t *nfar);
+
+/* Green boxes and quadrature points (Sec. 2.3).  For cluster c with bounding
+ * box cl_box[6c .. 6c+6) = (lo, hi): delta[c] = diam(B_t) (box diagonal) and
+ * omega_t = B_t grown by delta/2 on every side, so that
+ * dist(B_t, boundary of omega_t) = delta/2.  Its six faces, in the order
+ * (-x, +x, -y, +y, -z, +z), each carry qg x qg tensor Gauss points (first
+ * tangential axis = the lower axis index, varying slowest); m = 6 qg^2 points
+ * per cluster: z[c][nu][3], outward unit normals zn[c][nu][3], weights
+ * zw[c][nu] (Gauss weights times the face area).  Host memory. */
+int bem_green_points(int32_t ncl, const double *cl_box, int32_t qg, double *z, double *zn,
+                     double *zw, double *delta);
+
+/* Adaptive cross approximation with full pivoting (Sec. 2.3, eq. aca) of
+ * nmat matrices, the adaptive part of the method (host, OpenMP over
+ * matrices).  Matrix t has nrows[t] rows and ncols columns at A + a_off[t]
+ * (entries; column-major, leading dimension nrows[t]; complex interleaved
+ * when is_complex).  Each step takes the residual entry of largest modulus
+ * (ties: smallest row, then smallest column) as pivot and subtracts its
+ * cross; it stops when that modulus is at most eps times the first pivot's
+ * or after max_rank steps.  Outputs: rank[t]; the pivot rows (t~, local row
+ * numbers) and columns (tau) in piv_rows / piv_cols [t * max_rank ..]; and
+ * the inverse of the pivot block A[t~, tau] in pinv + t * max_rank^2 (leading
+ * dimension rank[t]).  BEM_ENONFINITE if a pivot block is singular. */
+int bem_aca(int32_t nmat, const int64_t *a_off, const int32_t *nrows, int32_t ncols,
+            int32_t is_complex, const double *A, double eps, int32_t max_rank, int32_t *rank,
+            int32_t *piv_rows, int32_t *piv_cols, double *pinv);
 
 #ifdef __cplusplus
 }

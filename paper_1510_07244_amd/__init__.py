@@ -252,3 +252,79 @@ def out_dtype(op):
     if op.precision == MIXED:
         return torch.complex64 if op.kernel == HELMHOLTZ else torch.float32
     return torch.complex128 if op.kernel == HELMHOLTZ else torch.float64
+
+
+def _setup_bases_api():
+    P = ctypes.c_void_p
+    _lib.bem_green_points.argtypes = [ctypes.c_int32, P, ctypes.c_int32, P, P, P, P]
+    _lib.bem_aca.argtypes = [ctypes.c_int32, P, P, ctypes.c_int32, ctypes.c_int32, P,
+                             ctypes.c_double, ctypes.c_int32, P, P, P, P]
+    _lib.bem_green_matrix.argtypes = [P, ctypes.POINTER(bem_mesh), ctypes.POINTER(bem_op),
+                                      ctypes.c_int32, ctypes.c_int32, P, P, ctypes.c_int64,
+                                      ctypes.c_int32, P, P, P, P, P, P, ctypes.c_int64,
+                                      ctypes.c_int32, P]
+    _lib.bem_basis_contract.argtypes = [P, ctypes.c_int32, ctypes.c_int32, P, P, ctypes.c_int32,
+                                        P, P, P, P, ctypes.c_int32, ctypes.c_int64, P, P,
+                                        ctypes.c_int64, ctypes.c_int32, P]
+
+
+_setup_bases_api()
+
+
+def green_points(boxes, qg):
+    """``bem_green_points``: boxes (ncl, 6) -> z (ncl, m, 3), zn, zw (ncl, m), delta."""
+    import numpy as np
+    boxes = np.ascontiguousarray(boxes, dtype=np.float64).reshape(-1, 6)
+    ncl = boxes.shape[0]
+    m = 6 * qg * qg
+    z = np.zeros((ncl, m, 3))
+    zn = np.zeros((ncl, m, 3))
+    zw = np.zeros((ncl, m))
+    delta = np.zeros(ncl)
+    rc = _lib.bem_green_points(ncl, _np_ptr(boxes), int(qg), _np_ptr(z), _np_ptr(zn),
+                               _np_ptr(zw), _np_ptr(delta))
+    if rc:
+        raise BemError(rc, "bem_green_points failed")
+    return z, zn, zw, delta
+
+
+def aca(A, a_off, nrows, ncols, eps, max_rank, is_complex=False):
+    """``bem_aca`` on packed host matrices (float64 array; complex as
+    interleaved pairs).  Returns rank, piv_rows, piv_cols, pinv."""
+    import numpy as np
+    A = np.ascontiguousarray(A)
+    a_off = np.ascontiguousarray(a_off, dtype=np.int64)
+    nrows = np.ascontiguousarray(nrows, dtype=np.int32)
+    nmat = nrows.size
+    rank = np.zeros(nmat, dtype=np.int32)
+    piv_rows = np.zeros((nmat, max_rank), dtype=np.int32)
+    piv_cols = np.zeros((nmat, max_rank), dtype=np.int32)
+    pinv = np.zeros((nmat, max_rank * max_rank * (2 if is_complex else 1)), dtype=np.float64)
+    rc = _lib.bem_aca(nmat, _np_ptr(a_off), _np_ptr(nrows), int(ncols), int(bool(is_complex)),
+                      _np_ptr(A), float(eps), int(max_rank), _np_ptr(rank), _np_ptr(piv_rows),
+                      _np_ptr(piv_cols), _np_ptr(pinv))
+    if rc:
+        raise BemError(rc, "bem_aca failed")
+    return rank, piv_rows, piv_cols, pinv
+
+
+def _context_green_matrix(self, mesh, op, side, row_ptr, row_idx, z, zn, zw, delta, out_off,
+                          out, max_rows=64, stream=None):
+    m = zw.shape[-1] if zw.dim() > 1 else zw.numel()
+    self._rc(_lib.bem_green_matrix(self.h, ctypes.byref(mesh.c), ctypes.byref(op), int(side),
+                                   out_off.numel(), _ptr(row_ptr), _ptr(row_idx), row_idx.numel(),
+                                   int(m), _ptr(z), _ptr(zn), _ptr(zw), _ptr(delta),
+                                   _ptr(out_off), _ptr(out), out.numel(), int(max_rows),
+                                   _stream(stream)))
+
+
+def _context_basis_contract(self, is_complex, nrows, rank, max_rank, piv_cols, pinv, A, a_off,
+                            acols, V, v_off, max_rows=64, stream=None):
+    self._rc(_lib.bem_basis_contract(self.h, int(bool(is_complex)), nrows.numel(), _ptr(nrows),
+                                     _ptr(rank), int(max_rank), _ptr(piv_cols), _ptr(pinv),
+                                     _ptr(A), _ptr(a_off), int(acols), A.numel(), _ptr(V),
+                                     _ptr(v_off), V.numel(), int(max_rows), _stream(stream)))
+
+
+Context.green_matrix = _context_green_matrix
+Context.basis_contract = _context_basis_contract

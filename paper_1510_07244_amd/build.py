@@ -14,8 +14,10 @@ BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libbem.so")
 ARCH = os.environ.get("BEM_OFFLOAD_ARCH", "gfx950")
 
-SOURCES = ["bem_blocks.hip", "bem_kernels.hip", "bem_quadrature.cpp", "bem_capi.cpp",
-           "bem_h2_tree.cpp"]
+SOURCES = ["bem_blocks.hip", "bem_kernels.hip", "bem_bases.hip", "bem_quadrature.cpp",
+           "bem_capi.cpp", "bem_h2_tree.cpp", "bem_h2_host.cpp"]
+OPENMP = {"bem_h2_host.cpp"}
+OMP_LIB = "/opt/rocm/llvm/lib"
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-function",
           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
 
@@ -41,13 +43,13 @@ def build(verbose: bool = False) -> str:
         if src.endswith(".hip"):
             cmd[1:1] = ["-x", "hip", f"--offload-arch={ARCH}"]
         else:
-            cmd[1:1] = ["-ffp-contract=off"]
+            cmd[1:1] = ["-ffp-contract=off"] + (["-fopenmp"] if src in OPENMP else [])
         cmds.append(cmd)
         objs.append(obj)
     with ThreadPoolExecutor(max_workers=min(8, len(cmds))) as pool:
         list(pool.map(lambda c: _run(c, verbose), cmds))
-    _run(["hipcc", "-shared", "-fPIC", f"--offload-arch={ARCH}", "-o", LIB + ".tmp", *objs],
-         verbose)
+    _run(["hipcc", "-shared", "-fPIC", f"--offload-arch={ARCH}", "-fopenmp",
+          f"-Wl,-rpath,{OMP_LIB}", "-o", LIB + ".tmp", *objs], verbose)
     os.replace(LIB + ".tmp", LIB)
     return LIB
 

@@ -1,0 +1,210 @@
+// Cluster-basis kernels of the Green cross approximation (Sec. 2.3-2.4) for
+// gfx950: the Green quadrature matrices A_t (kernel evaluations against the
+// quadrature points of the Green box) and the basis contraction
+// V_t = (A_t)[:, tau] (A_t)[t~, tau]^{-1} on the FP64 matrix cores.
+#include <hip/hip_runtime.h>
+
+#include <type_traits>
+
+#include "bem_device.h"
+
+namespace bem {
+namespace {
+
+using namespace dev;
+
+// ------------------------------------------------------------ Green matrix
+// Entry (row triangle tau_i, Green point z_nu with normal n_nu, weight w_nu)
+// of the two columns nu and m + nu (Sec. 2.3, eq. green_matrix):
+//   side 0:  sqrt(w) int g(x, z) dx,        sqrt(w) delta int d/dn(z) g(x, z) dx
+//   side 1:  sqrt(w) int d/dn(x) g(x, z) dx, sqrt(w) delta int d/dn(x) d/dn(z) g(x, z) dx
+// (side 1 is the column basis of the double layer).  Triangle integrals use
+// the Duffy rule: int_tau f = sqrt(g) sum_k w_k f(Phi(s_k, t_k)).
+template <int KERNEL, int SIDE>
+__global__ __launch_bounds__(kThreads) void k_green(const GreenArgs a) {
+  const int c = blockIdx.x;
+  const int64_t rp0 = a.row_ptr[c], rp1 = a.row_ptr[c + 1];
+  const int64_t off = a.out_off[c];
+  const int64_t n = rp1 - rp0;
+  const int m = a.m;
+  const bool ok = rp0 >= 0 && rp0 <= rp1 && rp1 <= a.row_len && off >= 0 && off <= a.out_len &&
+                  (n == 0 || 2 * (int64_t)m <= (a.out_len - off) / n);
+  if (!ok) {
+    if (threadIdx.x == 0) atomicOr(a.flags, FLAG_EINVAL);
+    return;
+  }
+  const double delta = a.delta[c];
+  const int64_t L = a.ldg;
+  // the entries of one cluster are spread over gridDim.y workgroups
+  for (int64_t e = (int64_t)blockIdx.y * kThreads + threadIdx.x; e < n * m;
+       e += (int64_t)gridDim.y * kThreads) {
+    const int64_t r = e % n;
+    const int nu = (int)(e / n);
+    const int id = a.row_idx[rp0 + r];
+    if (id < 0 || id >= a.nt) {
+      atomicOr(a.flags, FLAG_EINVAL);
+      continue;
+    }
+    const double *zp = a.z + 3 * ((int64_t)c * m + nu);
+    const double *np = a.zn + 3 * ((int64_t)c * m + nu);
+    const double zx = zp[0], zy = zp[1], zz = zp[2];
+    const double mx = np[0], my = np[1], mz = np[2];
+    const double wz = a.zw[(int64_t)c * m + nu];
+    // x - z at the rule points: (v0 - z) + s e1 + t e2
+    const double dx0 = a.geo[G_V0X * L + id] - zx, dy0 = a.geo[G_V0Y * L + id] - zy,
+                 dz0 = a.geo[G_V0Z * L + id] - zz;
+    const double e1x = a.geo[G_E1X * L + id], e1y = a.geo[G_E1Y * L + id], e1z = a.geo[G_E1Z * L + id];
+    const double e2x = a.geo[G_E2X * L + id], e2y = a.geo[G_E2Y * L + id], e2z = a.geo[G_E2Z * L + id];
+    const double nx = a.geo[G_NX * L + id], ny = a.geo[G_NY * L + id], nz = a.geo[G_NZ * L + id];
+    double pr = 0, pi = 0, qr = 0, qi = 0;  // + and - columns
+    for (int k = 0; k < a.nq; ++k) {
+      const double s = a.rule[k], t = a.rule[a.nq + k], w = a.rule[2 * a.nq + k];
+      const double dx = fma(s, e1x, fma(t, e2x, dx0));
+      const double dy = fma(s, e1y, fma(t, e2y, dy0));
+      const double dz = fma(s, e1z, fma(t, e2z, dz0));
+      const double r2 = fma(dx, dx, fma(dy, dy, dz * dz));
+      const double iz = rsqrt_newton(r2);  // 1 / r
+      const double i3 = iz * iz * iz;
+      const double dnz = fma(dx, mx, fma(dy, my, dz * mz));  // <x - z, n_z>
+      const double dnx = fma(dx, nx, fma(dy, ny, dz * nz));  // <x - z, n_x>
+      if constexpr (KERNEL == BEM_LAPLACE) {
+        if constexpr (SIDE == 0) {
+          pr = fma(w, iz, pr);
+          qr = fma(w, dnz * i3, qr);
+        } else {
+          const double nn = fma(nx, mx, fma(ny, my, nz * mz));
+          pr = fma(w, -dnx * i3, pr);
+          qr = fma(w, fma(-3.0 * dnx * dnz, iz * iz, nn) * i3, qr);
+        }
+      } else {
+        const double r = r2 * iz, kr = a.kappa * r;
+        double sn, cs;
+        sincos_cw(kr, &sn, &cs);
+        // e^{ikr} (1 - i kr) = (cs + kr sn) + i (sn - kr cs)
+        const double ar = fma(kr, sn, cs), ai = fma(-kr, cs, sn);
+        if constexpr (SIDE == 0) {
+          pr = fma(w * iz, cs, pr);
+          pi = fma(w * iz, sn, pi);
+          qr = fma(w * dnz * i3, ar, qr);
+          qi = fma(w * dnz * i3, ai, qi);
+        } else {
+          const double nn = fma(nx, mx, fma(ny, my, nz * mz));
+          pr = fma(-w * dnx * i3, ar, pr);
+          pi = fma(-w * dnx * i3, ai, pi);
+          // e^{ikr} [ (1 - i kr) nn / r^3 + (k^2 r^2 - 3 + 3 i kr) dnx dnz / r^5 ]
+          const double u = dnx * dnz * iz * iz;
+          const double br = fma(kr, kr, -3.0), bi = 3.0 * kr;
+          const double tr = fma(nn, 1.0, u * br), ti = fma(-nn, kr, u * bi);  // (1 - i kr) nn + u (br + i bi)
+          qr = fma(w * i3, cs * tr - sn * ti, qr);
+          qi = fma(w * i3, sn * tr + cs * ti, qi);
+        }
+      }
+    }
+    const double sg = a.geo[G_SG * L + id];
+    const double sp = sqrt(wz) * sg * kInv4Pi, sm = sp * delta;
+    const int64_t ip = off + r + n * nu, im = off + r + n * (m + nu);
+    if constexpr (KERNEL == BEM_LAPLACE) {
+      static_cast<double *>(a.out)[ip] = pr * sp;
+      static_cast<double *>(a.out)[im] = qr * sm;
+    } else {
+      static_cast<double2 *>(a.out)[ip] = make_double2(pr * sp, pi * sp);
+      static_cast<double2 *>(a.out)[im] = make_double2(qr * sm, qi * sm);
+    }
+  }
+}
+
+// ------------------------------------------------------- basis contraction
+// V_c (n_c x k_c) = A_c[:, tau_c] (n_c x k_c) * P_c (k_c x k_c), all
+// column-major, one workgroup per matrix, one wave per 16 x 16 output tile.
+// v_mfma_f64_16x16x4_f64: lane l supplies A(l % 16, l / 16) and
+// B(l / 16, l % 16) of a 16 x 4 by 4 x 16 product and holds
+// D(l / 16 + 4 r, l % 16) in its four result registers r.
+typedef double d4 __attribute__((ext_vector_type(4)));
+
+template <bool CPLX>
+__global__ __launch_bounds__(kThreads) void k_contract(const ContractArgs a) {
+  const int c = blockIdx.x;
+  const int n = a.nrows[c], k = a.rank[c], lda_cols = a.acols;
+  const int64_t aoff = a.a_off[c], voff = a.v_off[c];
+  if (n < 0 || k < 0 || k > a.max_rank || aoff < 0 || voff < 0 ||
+      aoff + (int64_t)n * lda_cols > a.a_len || voff + (int64_t)n * k > a.v_len) {
+    if (threadIdx.x == 0) atomicOr(a.flags, FLAG_EINVAL);
+    return;
+  }
+  const int wave = threadIdx.x / kWave, lane = threadIdx.x & (kWave - 1);
+  const int32_t *tau = a.piv_cols + (int64_t)c * a.max_rank;
+  const int64_t poff = (int64_t)c * a.max_rank * a.max_rank;
+  const int ti = (n + 15) / 16, tj = (k + 15) / 16;
+  const int li = lane & 15, lk = lane >> 4;
+  constexpr int U = 4;  // k-steps whose operands are loaded before the MFMAs
+  // the tiles of one matrix are spread over gridDim.y workgroups
+  for (int tile = blockIdx.y * (kThreads / kWave) + wave; tile < ti * tj;
+       tile += gridDim.y * (kThreads / kWave)) {
+    const int i0 = (tile % ti) * 16, j0 = (tile / ti) * 16;
+    const int row = i0 + li, col = j0 + li;
+    d4 re = {0, 0, 0, 0}, im = {0, 0, 0, 0};
+    for (int k0 = 0; k0 < k; k0 += 4 * U) {
+      using T = typename std::conditional<CPLX, double2, double>::type;
+      T av[U], bv[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int kk = k0 + 4 * u + lk;
+        int tc = kk < k ? tau[kk] : 0;
+        if (tc < 0 || tc >= lda_cols) {  // never read outside A_c
+          atomicOr(a.flags, FLAG_EINVAL);
+          tc = 0;
+        }
+        const bool va = row < n && kk < k, vb = kk < k && col < k;
+        const T *A = static_cast<const T *>(a.A);
+        const T *P = reinterpret_cast<const T *>(a.pinv);
+        av[u] = va ? A[aoff + row + (int64_t)n * tc] : T{};
+        bv[u] = vb ? P[poff + kk + (int64_t)k * col] : T{};
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        if constexpr (!CPLX) {
+          re = __builtin_amdgcn_mfma_f64_16x16x4f64(av[u], bv[u], re, 0, 0, 0);
+        } else {
+          re = __builtin_amdgcn_mfma_f64_16x16x4f64(av[u].x, bv[u].x, re, 0, 0, 0);
+          re = __builtin_amdgcn_mfma_f64_16x16x4f64(-av[u].y, bv[u].y, re, 0, 0, 0);
+          im = __builtin_amdgcn_mfma_f64_16x16x4f64(av[u].x, bv[u].y, im, 0, 0, 0);
+          im = __builtin_amdgcn_mfma_f64_16x16x4f64(av[u].y, bv[u].x, im, 0, 0, 0);
+        }
+      }
+    }
+    for (int r = 0; r < 4; ++r) {
+      const int row = i0 + lk + 4 * r, col = j0 + li;
+      if (row < n && col < k) {
+        if constexpr (!CPLX)
+          static_cast<double *>(a.V)[voff + row + (int64_t)n * col] = re[r];
+        else
+          static_cast<double2 *>(a.V)[voff + row + (int64_t)n * col] = make_double2(re[r], im[r]);
+      }
+    }
+  }
+}
+
+}  // namespace
+
+hipError_t launch_green(int kernel, int side, const GreenArgs &a, int grid_y, hipStream_t s) {
+  if (a.ncl == 0) return hipSuccess;
+  const dim3 grid(a.ncl, grid_y < 1 ? 1 : grid_y), block(kThreads);
+  if (kernel == BEM_LAPLACE) {
+    if (side == 0) hipLaunchKernelGGL((k_green<BEM_LAPLACE, 0>), grid, block, 0, s, a);
+    else hipLaunchKernelGGL((k_green<BEM_LAPLACE, 1>), grid, block, 0, s, a);
+  } else {
+    if (side == 0) hipLaunchKernelGGL((k_green<BEM_HELMHOLTZ, 0>), grid, block, 0, s, a);
+    else hipLaunchKernelGGL((k_green<BEM_HELMHOLTZ, 1>), grid, block, 0, s, a);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_contract(bool cplx, const ContractArgs &a, int grid_y, hipStream_t s) {
+  if (a.nmat == 0) return hipSuccess;
+  const dim3 grid(a.nmat, grid_y < 1 ? 1 : grid_y), block(kThreads);
+  if (cplx) hipLaunchKernelGGL((k_contract<true>), grid, block, 0, s, a);
+  else hipLaunchKernelGGL((k_contract<false>), grid, block, 0, s, a);
+  return hipGetLastError();
+}
+
+}  // namespace bem

@@ -279,6 +279,93 @@ int bem_assemble_coupling(bem_ctx *ctx, const bem_mesh *mesh, const bem_op *op,
   return assemble_blocks(ctx, mesh, op, pivots, out, out_len, stream, true);
 }
 
+int bem_green_matrix(bem_ctx *ctx, const bem_mesh *mesh, const bem_op *op, int32_t side,
+                     int32_t ncl, const int32_t *row_ptr, const int32_t *row_idx, int64_t row_len,
+                     int32_t m, const double *z, const double *zn, const double *zw,
+                     const double *delta, const int64_t *out_off, void *out, int64_t out_len,
+                     int32_t max_rows, void *stream) {
+  if (!ctx) return BEM_EINVAL;
+  int rc;
+  if ((rc = check_mesh(ctx, mesh)) || (rc = check_op(ctx, op))) return rc;
+  if (side != 0 && side != 1) return fail(ctx, BEM_EINVAL, "side must be 0 or 1");
+  if (ncl < 0 || m < 0 || row_len < 0 || out_len < 0) return fail(ctx, BEM_EINVAL, "negative size");
+  if (ncl == 0) return BEM_OK;
+  if (!row_ptr || (row_len > 0 && !row_idx) || (m > 0 && (!z || !zn || !zw)) || !delta ||
+      !out_off || (out_len > 0 && !out))
+    return fail(ctx, BEM_EINVAL, "NULL array");
+  if (mesh->nt == 0) return fail(ctx, BEM_EINVAL, "empty mesh");
+  DeviceGuard g(ctx->device);
+  bem_op duffy = *op;  // Green matrices always use the Duffy rule of order q_regular
+  duffy.regular_rule = BEM_RULE_DUFFY;
+  int64_t ldg;
+  const bem::DevRules *rules;
+  if ((rc = ensure_geo(ctx, mesh->nt, &ldg)) || (rc = get_rules(ctx, &duffy, &rules))) return rc;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  hipError_t e = bem::launch_geometry(*mesh, ctx->geo, ldg, ctx->flags, s);
+  if (e != hipSuccess) return hip_fail(ctx, e, "geometry kernel launch");
+  bem::GreenArgs a{};
+  a.geo = ctx->geo;
+  a.ldg = ldg;
+  a.nt = mesh->nt;
+  a.ncl = ncl;
+  a.row_ptr = row_ptr;
+  a.row_idx = row_idx;
+  a.row_len = row_len;
+  a.m = m;
+  a.z = z;
+  a.zn = zn;
+  a.zw = zw;
+  a.delta = delta;
+  a.out_off = out_off;
+  a.out = out;
+  a.out_len = out_len;
+  a.rule = rules->tri;
+  a.nq = rules->nq;
+  a.kappa = op->kernel == BEM_HELMHOLTZ ? op->kappa : 0.0;
+  a.flags = ctx->flags;
+  // workgroups per cluster from the row-count hint (any hint is correct)
+  const int64_t per = ((int64_t)std::max(max_rows, 1) * m + 255) / 256;
+  e = bem::launch_green(op->kernel, side, a, (int)std::min<int64_t>(per, 64), s);
+  if (e != hipSuccess) return hip_fail(ctx, e, "green kernel launch");
+  return BEM_OK;
+}
+
+int bem_basis_contract(bem_ctx *ctx, int32_t is_complex, int32_t nmat, const int32_t *nrows,
+                       const int32_t *rank, int32_t max_rank, const int32_t *piv_cols,
+                       const double *pinv, const void *A, const int64_t *a_off, int32_t acols,
+                       int64_t a_len, void *V, const int64_t *v_off, int64_t v_len,
+                       int32_t max_rows, void *stream) {
+  if (!ctx) return BEM_EINVAL;
+  if (nmat < 0 || max_rank < 1 || acols < 0 || a_len < 0 || v_len < 0)
+    return fail(ctx, BEM_EINVAL, "invalid size");
+  if (nmat == 0) return BEM_OK;
+  if (!nrows || !rank || !piv_cols || !pinv || !a_off || !v_off || (a_len > 0 && !A) ||
+      (v_len > 0 && !V))
+    return fail(ctx, BEM_EINVAL, "NULL array");
+  DeviceGuard g(ctx->device);
+  bem::ContractArgs a{};
+  a.nmat = nmat;
+  a.nrows = nrows;
+  a.rank = rank;
+  a.piv_cols = piv_cols;
+  a.max_rank = max_rank;
+  a.pinv = pinv;
+  a.A = A;
+  a.a_off = a_off;
+  a.acols = acols;
+  a.a_len = a_len;
+  a.V = V;
+  a.v_off = v_off;
+  a.v_len = v_len;
+  a.flags = ctx->flags;
+  // workgroups per matrix (four 16 x 16 tiles each) from the row-count hint
+  const int64_t tiles = (int64_t)((std::max(max_rows, 1) + 15) / 16) * ((max_rank + 15) / 16);
+  hipError_t e = bem::launch_contract(is_complex != 0, a, (int)std::min<int64_t>((tiles + 3) / 4, 64),
+                                      static_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return hip_fail(ctx, e, "contraction kernel launch");
+  return BEM_OK;
+}
+
 int bem_eval_entries(bem_ctx *ctx, const bem_mesh *mesh, const bem_op *op, int64_t n,
                      const int32_t *rows, const int32_t *cols, void *out, void *stream) {
   if (!ctx) return BEM_EINVAL;

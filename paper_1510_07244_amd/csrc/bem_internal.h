@@ -110,6 +110,42 @@ struct EntryArgs {
   unsigned *flags;
 };
 
+struct GreenArgs {
+  const double *geo;
+  int64_t ldg;
+  int32_t nt;
+  int32_t ncl;
+  const int32_t *row_ptr, *row_idx;
+  int64_t row_len;
+  int32_t m;
+  const double *z, *zn, *zw, *delta;
+  const int64_t *out_off;
+  void *out;
+  int64_t out_len;
+  const double *rule;
+  int32_t nq;
+  double kappa;
+  unsigned *flags;
+};
+
+struct ContractArgs {
+  int32_t nmat;
+  const int32_t *nrows, *rank, *piv_cols;
+  int32_t max_rank;
+  const double *pinv;
+  const void *A;
+  const int64_t *a_off;
+  int32_t acols;
+  int64_t a_len;
+  void *V;
+  const int64_t *v_off;
+  int64_t v_len;
+  unsigned *flags;
+};
+
+hipError_t launch_green(int kernel, int side, const GreenArgs &a, int grid_y, hipStream_t s);
+hipError_t launch_contract(bool cplx, const ContractArgs &a, int grid_y, hipStream_t s);
+
 // launchers (bem_kernels.hip); return a hipError_t
 hipError_t launch_geometry(const bem_mesh &m, double *geo, int64_t ldg, unsigned *flags,
                            hipStream_t s);

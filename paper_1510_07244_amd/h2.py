@@ -1,0 +1,180 @@
+"""H^2-matrix setup by Green cross approximation (Sec. 2.3-2.4), driving the
+C-ABI: cluster and block trees (host), Green boxes and points (host), Green
+matrices (GPU), adaptive cross approximation (host), basis contraction (GPU
+matrix cores), coupling and near-field blocks (GPU).  This module only
+orders the calls and moves arrays; every numerical step is a library call.
+
+The H^2 approximation of an admissible block is
+    G|_{t x s} ~ V_t G|_{t~ x s~} W_s^T
+with V_t the nested row basis (side-0 Green matrices) and W_s the column
+basis: W = V for the single layer, side-1 Green matrices for the double layer.
+Nested bases store for each cluster the matrix V^_c whose rows belong to the
+triangles ``rows[c]`` (the cluster for a leaf, t^ = union of the sons' pivots
+for a father); the full basis is V_t = diag(V_t1, V_t2) V^_t.
+"""
+import time
+
+import numpy as np
+
+from . import (HELMHOLTZ, LAPLACE, SLP, DLP, Blocks, ClusterTree, Mesh, block_tree, green_points,
+               aca, make_op)
+
+
+def _dev(a, dtype):
+    import torch
+    return torch.as_tensor(np.ascontiguousarray(a)).to(device="cuda", dtype=dtype)
+
+
+class LevelPlan:
+    """Device inputs of one tree level of a basis construction (cached so that
+    the GPU part can be replayed without the host pivot search)."""
+
+
+class ClusterBasis:
+    def __init__(self, side, ncl):
+        self.side = side
+        self.rows = [None] * ncl   # triangle ids of the rows of V^_c
+        self.piv = [None] * ncl    # pivot triangles t~_c
+        self.rank = np.zeros(ncl, dtype=np.int32)
+        self.levels = []           # LevelPlan per height
+        self.where = [None] * ncl  # (level index, position in level)
+
+    def vhat(self, c):
+        """V^_c as a host numpy array (n_c x k_c)."""
+        li, p = self.where[c]
+        lv = self.levels[li]
+        n, k = lv.nrows_h[p], self.rank[c]
+        o = lv.v_off_h[p]
+        flat = lv.V.cpu().numpy()
+        return flat[o:o + n * k].reshape(k, n).T
+
+
+class H2Setup:
+    # Cross-approximation tolerance 5e-8 with Green order 4 keeps every
+    # sampled admissible block of the 8192-triangle sphere below 1e-6 relative
+    # error for the single and the double layer (3e-7 does not for the latter).
+    def __init__(self, ctx, v, tri, kernel=LAPLACE, kappa=0.0, q_regular=4, q_singular=4,
+                 leaf=64, eta=2.0, qg=4, eps=5e-8):
+        import torch
+        self.ctx = ctx
+        self.v = np.ascontiguousarray(v, dtype=np.float64)
+        self.tri = np.ascontiguousarray(tri, dtype=np.int32)
+        self.kernel, self.kappa = kernel, float(kappa)
+        self.q_regular, self.q_singular = q_regular, q_singular
+        self.qg, self.eps = qg, eps
+        self.cplx = kernel == HELMHOLTZ
+        self.adtype = torch.complex128 if self.cplx else torch.float64
+        self.mesh = Mesh(torch.from_numpy(self.v), torch.from_numpy(self.tri))
+        t0 = time.perf_counter()
+        self.ct = ClusterTree(self.v, self.tri, leaf=leaf)
+        self.near, self.far = block_tree(self.ct, eta=eta)
+        self.t_tree = time.perf_counter() - t0
+        # heights: leaves 0, fathers 1 + max(sons)
+        n = self.ct.n
+        self.height = np.zeros(n, dtype=np.int32)
+        for c in range(n - 1, -1, -1):  # sons have larger numbers (pre-order)
+            s = self.ct.sons[c]
+            if s[0] >= 0:
+                self.height[c] = 1 + max(self.height[s[0]], self.height[s[1]])
+        self.z, self.zn, self.zw, self.delta = green_points(self.ct.box, qg)
+        self.m = self.zw.shape[1]
+
+    def op(self, layer):
+        return make_op(self.kernel, layer, q_regular=self.q_regular, q_singular=self.q_singular,
+                       kappa=self.kappa)
+
+    # ----------------------------------------------------------- bases
+    def basis(self, side):
+        """Construct the nested cluster basis of one side, level by level."""
+        import torch
+        ct, m = self.ct, self.m
+        B = ClusterBasis(side, ct.n)
+        op = self.op(SLP)
+        for h in range(int(self.height.max()) + 1):
+            cls = np.nonzero(self.height == h)[0]
+            lv = LevelPlan()
+            lv.cls = cls
+            rows = []
+            for c in cls:
+                s = ct.sons[c]
+                r = ct.idx(c) if s[0] < 0 else np.concatenate([B.piv[s[0]], B.piv[s[1]]])
+                B.rows[c] = r.astype(np.int32)
+                rows.append(B.rows[c])
+            nrows = np.array([r.size for r in rows], dtype=np.int32)
+            rp = np.zeros(cls.size + 1, dtype=np.int32)
+            rp[1:] = np.cumsum(nrows)
+            a_off = np.zeros(cls.size, dtype=np.int64)
+            a_off[1:] = np.cumsum(nrows.astype(np.int64) * 2 * m)[:-1]
+            lv.row_ptr = _dev(rp, torch.int32)
+            lv.row_idx = _dev(np.concatenate(rows), torch.int32)
+            lv.z = _dev(self.z[cls], torch.float64)
+            lv.zn = _dev(self.zn[cls], torch.float64)
+            lv.zw = _dev(self.zw[cls], torch.float64)
+            lv.delta = _dev(self.delta[cls], torch.float64)
+            lv.a_off = _dev(a_off, torch.int64)
+            lv.A = torch.empty(int(nrows.astype(np.int64).sum() * 2 * m), dtype=self.adtype,
+                               device="cuda")
+            lv.max_rows = int(nrows.max())
+            self.ctx.green_matrix(self.mesh, op, side, lv.row_ptr, lv.row_idx, lv.z, lv.zn, lv.zw,
+                                  lv.delta, lv.a_off, lv.A, max_rows=lv.max_rows)
+            self.ctx.check()
+            A_h = lv.A.cpu().numpy()
+            Af = A_h.view(np.float64) if self.cplx else A_h
+            max_rank = int(min(nrows.max(), 2 * m))
+            rank, prow, pcol, pinv = aca(Af, a_off, nrows, 2 * m, self.eps, max_rank,
+                                         is_complex=self.cplx)
+            for p, c in enumerate(cls):
+                k = rank[p]
+                B.rank[c] = k
+                B.piv[c] = B.rows[c][prow[p, :k]]
+                B.where[c] = (len(B.levels), p)
+            v_off = np.zeros(cls.size, dtype=np.int64)
+            v_off[1:] = np.cumsum(nrows.astype(np.int64) * rank)[:-1]
+            lv.nrows_h, lv.v_off_h = nrows, v_off
+            lv.nrows = _dev(nrows, torch.int32)
+            lv.rank = _dev(rank, torch.int32)
+            lv.piv_cols = _dev(pcol, torch.int32)
+            lv.pinv = _dev(pinv, torch.float64)
+            lv.max_rank = max_rank
+            lv.v_off = _dev(v_off, torch.int64)
+            lv.V = torch.empty(int((nrows.astype(np.int64) * rank).sum()), dtype=self.adtype,
+                               device="cuda")
+            self.ctx.basis_contract(self.cplx, lv.nrows, lv.rank, max_rank, lv.piv_cols, lv.pinv,
+                                    lv.A, lv.a_off, 2 * m, lv.V, lv.v_off, max_rows=lv.max_rows)
+            B.levels.append(lv)
+        self.ctx.check()
+        return B
+
+    def basis_replay(self, B, stream=None):
+        """Enqueue the GPU part of a basis construction again (Green matrices
+        and contractions) with the pivots and inverses already chosen."""
+        op = self.op(SLP)
+        for lv in B.levels:
+            self.ctx.green_matrix(self.mesh, op, B.side, lv.row_ptr, lv.row_idx, lv.z, lv.zn,
+                                  lv.zw, lv.delta, lv.a_off, lv.A, max_rows=lv.max_rows,
+                                  stream=stream)
+            self.ctx.basis_contract(self.cplx, lv.nrows, lv.rank, lv.max_rank, lv.piv_cols,
+                                    lv.pinv, lv.A, lv.a_off, 2 * self.m, lv.V, lv.v_off,
+                                    max_rows=lv.max_rows, stream=stream)
+
+    def full_basis(self, B, c):
+        """V_t (rows ordered like the cluster's triangles) as a host array."""
+        s = self.ct.sons[c]
+        if s[0] < 0:
+            return B.vhat(c)
+        V1, V2 = self.full_basis(B, s[0]), self.full_basis(B, s[1])
+        D = np.zeros((V1.shape[0] + V2.shape[0], V1.shape[1] + V2.shape[1]), dtype=V1.dtype)
+        D[:V1.shape[0], :V1.shape[1]] = V1
+        D[V1.shape[0]:, V1.shape[1]:] = V2
+        return D @ B.vhat(c)
+
+    # ----------------------------------------------------------- blocks
+    def near_blocks(self):
+        rows = [self.ct.idx(t) for t, s in self.near]
+        cols = [self.ct.idx(s) for t, s in self.near]
+        return Blocks.from_lists(rows, cols)
+
+    def coupling_blocks(self, row_basis, col_basis):
+        rows = [row_basis.piv[t] for t, s in self.far]
+        cols = [col_basis.piv[s] for t, s in self.far]
+        return Blocks.from_lists(rows, cols)

@@ -1,0 +1,69 @@
+"""Host parts of the Green cross approximation (no GPU): Green boxes and
+points against the oracle's, and the adaptive cross approximation against
+what linear algebra fixes (exact rank recovery, interpolation property,
+inverse of the pivot block, tie-breaking)."""
+import numpy as np
+import pytest
+
+from bem_inputs import octahedron_sphere
+from oracle import htree
+
+
+def test_green_points_match_oracle():
+    import paper_1510_07244_amd as pk
+    m = octahedron_sphere(8)
+    ct = pk.ClusterTree(m.v, m.tri)
+    for qg in (1, 3, 4):
+        z, zn, zw, delta = pk.green_points(ct.box, qg)
+        for c in range(ct.n):
+            lo, hi, dref = htree.green_box(htree.Cluster(idx=None, lo=ct.box[c, :3], hi=ct.box[c, 3:]))
+            zr, znr, zwr = htree.green_points(lo, hi, qg)
+            assert abs(delta[c] - dref) <= 1e-15 * dref
+            assert np.allclose(z[c], zr, rtol=0, atol=4e-16)
+            assert np.array_equal(zn[c], znr)
+            assert np.allclose(zw[c], zwr, rtol=1e-14, atol=0)
+
+
+@pytest.mark.parametrize("cplx", [False, True])
+def test_aca_recovers_low_rank_and_interpolates(cplx):
+    import paper_1510_07244_amd as pk
+    rng = np.random.default_rng(4)
+    mats, nrows = [], []
+    for n, r in ((40, 5), (64, 12), (17, 17), (30, 1)):
+        U = rng.standard_normal((n, r))
+        W = rng.standard_normal((r, 24))
+        if cplx:
+            U = U + 1j * rng.standard_normal((n, r))
+            W = W + 1j * rng.standard_normal((r, 24))
+        mats.append((U @ W, r))
+        nrows.append(n)
+    off = np.zeros(len(mats), dtype=np.int64)
+    off[1:] = np.cumsum([a.size for a, _ in mats])[:-1]
+    packed = np.concatenate([a.T.ravel() for a, _ in mats])  # column-major
+    flat = packed.view(np.float64) if cplx else packed
+    rank, prow, pcol, pinv = pk.aca(flat, off, nrows, 24, 1e-12, 24, is_complex=cplx)
+    for t, (A, r) in enumerate(mats):
+        k = rank[t]
+        assert k == r
+        rows, cols = prow[t, :k], pcol[t, :k]
+        assert len(set(rows)) == k and len(set(cols)) == k
+        P = pinv[t].view(np.complex128) if cplx else pinv[t]
+        P = P[:k * k].reshape(k, k).T  # column-major, leading dimension k
+        assert np.allclose(P @ A[np.ix_(rows, cols)], np.eye(k), atol=1e-9)
+        V = A[:, cols] @ P
+        assert np.allclose(V[rows], np.eye(k), atol=1e-9)          # R_t V_t = I
+        assert np.linalg.norm(V @ A[rows] - A) <= 1e-9 * np.linalg.norm(A)
+
+
+def test_aca_first_pivot_and_ties():
+    import paper_1510_07244_amd as pk
+    A = np.array([[1.0, 3.0], [-3.0, 2.0], [0.5, 0.0]])  # |3| twice: row 0 col 1 wins (smallest row)
+    flat = A.T.ravel()
+    rank, prow, pcol, _ = pk.aca(flat, [0], [3], 2, 0.0, 2)
+    assert prow[0, 0] == 0 and pcol[0, 0] == 1
+
+
+def test_aca_rejects_bad_arguments():
+    import paper_1510_07244_amd as pk
+    with pytest.raises(pk.BemError):
+        pk.aca(np.zeros(4), [0], [2], 2, -1.0, 2)
