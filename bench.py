@@ -42,6 +42,8 @@ FLOPS_PER_POINT = {(0, 0): 11.0, (0, 1): 19.0, (1, 0): 18.0, (1, 1): 30.0}
 SS_EXTRA = 24.0
 SS_REGIONS = {3: 6, 2: 5, 1: 2}
 Q = 4
+FP32_VALU_PEAK = 157.3e12  # published, with packed FP32 (this build does not use packed FP32)
+MIXED_RATIO = 0.5  # mixed form: pairs with box gap < 0.5 max diameter stay FP64
 
 
 def parse():
@@ -52,6 +54,7 @@ def parse():
     p.add_argument("--setup-repeats", type=int, default=3)
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--cpu-seconds", type=float, default=12.0)
+    p.add_argument("--batched-meshes", type=int, default=64)
     return p.parse_args()
 
 
@@ -79,10 +82,11 @@ def near_flops(counts, kernel, layer, q_reg, q_sing):
 
 
 class H2Bench:
-    def __init__(self, pk, ctx, m):
+    def __init__(self, pk, ctx, m, mixed=False):
         import torch
         from paper_1510_07244_amd.h2 import H2Setup
         self.pk, self.ctx, self.m = pk, ctx, m
+        self.mixed = mixed
         sync = torch.cuda.synchronize
         t0 = time.perf_counter()
         self.h = h = H2Setup(ctx, m.v, m.tri, kernel=pk.LAPLACE, q_regular=Q, q_singular=Q)
@@ -95,8 +99,12 @@ class H2Bench:
         self.cs, self.n_cs = h.coupling_blocks(self.V, self.V)
         self.cd, self.n_cd = h.coupling_blocks(self.V, self.W)
         self.ops = [h.op(pk.SLP), h.op(pk.DLP)]
-        f64 = dict(dtype=torch.float64, device="cuda")
-        self.out = {k: torch.empty(n, **f64) for k, n in
+        if mixed:  # regular pairs in FP32, singular and near-singular in FP64
+            for op in self.ops:
+                op.precision = pk.MIXED
+                op.near_singular_ratio = MIXED_RATIO
+        dt = dict(dtype=torch.float32 if mixed else torch.float64, device="cuda")
+        self.out = {k: torch.empty(n, **dt) for k, n in
                     (("ns", self.n_near), ("nd", self.n_near), ("cs", self.n_cs), ("cd", self.n_cd))}
         self.assemble()
         ctx.check()
@@ -128,6 +136,98 @@ class H2Bench:
 
     def entries(self):
         return 2 * self.n_near + self.n_cs + self.n_cd
+
+
+class BatchedBench:
+    """Batched form: near-field and coupling blocks of the Laplace single
+    layer on `count` seeded perturbed spheres (512..8192 triangles,
+    log-uniform), each with its own H^2 setup, assembled by one persistent
+    graph-captured launch (autotuned) against the per-call loop."""
+
+    def __init__(self, pk, ctx, count):
+        import torch
+        from bem_inputs import perturbed_sphere_batch
+        from paper_1510_07244_amd.h2 import H2Setup
+        self.pk, self.ctx = pk, ctx
+        self.meshes = perturbed_sphere_batch(count)
+        t0 = time.perf_counter()
+        self.items = []
+        for m in self.meshes:
+            h = H2Setup(ctx, m.v, m.tri, kernel=pk.LAPLACE, q_regular=Q, q_singular=Q)
+            V = h.basis(0)
+            near, n_near = h.near_blocks()
+            cs, n_cs = h.coupling_blocks(V, V)
+            self.items.append((h, near, n_near, cs, n_cs))
+        torch.cuda.synchronize()
+        self.t_bases = time.perf_counter() - t0
+        self.op = pk.make_op(pk.LAPLACE, pk.SLP, q_regular=Q, q_singular=Q)
+        dt = dict(dtype=torch.float64, device="cuda")
+        self.out = [(torch.empty(n_near, **dt), torch.empty(n_cs, **dt))
+                    for h, near, n_near, cs, n_cs in self.items]
+        entries = []
+        for (h, near, n_near, cs, n_cs), (on, oc) in zip(self.items, self.out):
+            entries += [(h.mesh, near, on, 0), (h.mesh, cs, oc, 1)]
+        t1 = time.perf_counter()
+        self.plan = pk.Plan(ctx, self.op, entries, autotune=True)
+        torch.cuda.synchronize()
+        self.t_plan = time.perf_counter() - t1
+        self.n_entries = sum(n_near + n_cs for h, near, n_near, cs, n_cs in self.items)
+        self.triangles = sum(m.nt for m in self.meshes)
+
+    def per_call(self, stream):
+        for (h, near, n_near, cs, n_cs), (on, oc) in zip(self.items, self.out):
+            self.ctx.assemble_nearfield(h.mesh, self.op, near, on, stream)
+            self.ctx.assemble_coupling(h.mesh, self.op, cs, oc, stream)
+
+    def batched(self, stream):
+        self.plan.run(stream)
+
+    def time(self, torch, fn, stream, steps, warmup):
+        for _ in range(warmup):
+            fn(stream)
+        self.ctx.check(stream)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            fn(stream)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) * 1e3 / steps
+        self.ctx.check(stream)
+        return dt
+
+    def result(self, torch, stream, steps, warmup):
+        ms_b = self.time(torch, self.batched, stream, steps, warmup)
+        ms_p = self.time(torch, self.per_call, stream, steps, warmup)
+        sizes = [int(m.nt) for m in self.meshes]
+        return {
+            "value": self.n_entries / (ms_b * 1e-3), "unit": "entries/s", "ms_per_step": ms_b,
+            "per_call_ms_per_step": ms_p, "per_call_value": self.n_entries / (ms_p * 1e-3),
+            "speedup_vs_per_call": ms_p / ms_b, "entries_per_step": int(self.n_entries),
+            "workload": f"Laplace SLP near field + coupling blocks of {len(sizes)} perturbed "
+                        f"spheres ({min(sizes)}..{max(sizes)} triangles, {self.triangles} total), "
+                        "each with its own H2 setup (leaf 64, eta 2, ACA 5e-8), plain FP64",
+            "tiles": self.plan.tiles, "tune": self.plan.config,
+            "plan_s": self.t_plan, "bases_s": self.t_bases,
+        }
+
+
+def run_leg(torch, ctx, hb, stream, steps, warmup):
+    """Time `steps` steps after `warmup`; per-phase HIP-event means."""
+    names = ["bases", "ns", "nd", "cs", "cd"]
+    evs = [{k: (torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+            for k in names} for _ in range(steps)]
+    for _ in range(warmup):
+        hb.step(stream)
+    ctx.check(stream)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(steps):
+        hb.step(stream, evs[k])
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ctx.check(stream)
+    phase = {k: float(np.mean([e[k][0].elapsed_time(e[k][1]) for e in evs])) for k in names}
+    return (t1 - t0) * 1e3 / steps, phase
 
 
 def cpu_baseline(m, hb, seconds):
@@ -176,21 +276,13 @@ def main():
         hb = H2Bench(pk, ctx, m)
         setups.append((hb.t_setup, hb.t_tree, hb.t_bases, hb.t_assembly))
     stream = torch.cuda.current_stream()
-    names = ["bases", "ns", "nd", "cs", "cd"]
-    evs = [{k: (torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
-            for k in names} for _ in range(args.steps)]
-    for _ in range(args.warmup):
-        hb.step(stream)
-    ctx.check(stream)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for k in range(args.steps):
-        hb.step(stream, evs[k])
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    ctx.check(stream)
-    ms_step = (t1 - t0) * 1e3 / args.steps
-    phase = {k: float(np.mean([e[k][0].elapsed_time(e[k][1]) for e in evs])) for k in names}
+    ms_step, phase = run_leg(torch, ctx, hb, stream, args.steps, args.warmup)
+    hm = H2Bench(pk, ctx, m, mixed=True)
+    ms_step_m, phase_m = run_leg(torch, ctx, hm, stream, args.steps, args.warmup)
+    batched = None
+    if args.batched_meshes > 0:
+        bb = BatchedBench(pk, ctx, args.batched_meshes)
+        batched = bb.result(torch, stream, args.steps, args.warmup)
 
     h = hb.h
     rows = [h.ct.idx(t) for t, s in h.near]
@@ -244,7 +336,26 @@ def main():
             "unit": "TFLOP/s", "frac": f_slp / (phase["ns"] * 1e-3) / FP64_VALU_PEAK,
             "ms_per_launch": phase["ns"], "flops_per_launch": f_slp,
         },
+        "forms": {
+            "plain_fp64": {"value": hb.entries() / (ms_step * 1e-3), "ms_per_step": ms_step},
+            "mixed": {
+                "value": hm.entries() / (ms_step_m * 1e-3), "ms_per_step": ms_step_m,
+                "speedup_vs_plain": ms_step / ms_step_m, "phase_ms": phase_m,
+                "near_singular_ratio": MIXED_RATIO,
+                "dtype": "f32 regular pairs, f64 singular/near-singular, f32 out",
+                "h2_setup_s": float(hm.t_setup),
+                "roofline": {
+                    "kernel": "k_blocks<Laplace, DLP, mixed> near field", "bound": "alu",
+                    "achieved": f_dlp / (phase_m["nd"] * 1e-3) / 1e12,
+                    "peak": FP32_VALU_PEAK / 1e12, "unit": "TFLOP/s",
+                    "frac": f_dlp / (phase_m["nd"] * 1e-3) / FP32_VALU_PEAK,
+                    "ms_per_launch": phase_m["nd"], "flops_per_launch": f_dlp,
+                },
+            },
+        },
     }
+    if batched:
+        result["forms"]["batched"] = batched
     if not args.no_cpu_baseline:
         result["cpu_baseline"] = cpu_baseline(m, hb, args.cpu_seconds)
     ctx.close()

@@ -160,6 +160,77 @@ int bem_eval_entries(bem_ctx *ctx, const bem_mesh *mesh, const bem_op *op, int64
                      const int32_t *rows, const int32_t *cols, void *out, void *stream);
 
 /* ---------------------------------------------------------------------
+ * Batched assembly in one persistent launch.
+ *
+ * Sec. 3 assembles a matrix by splitting its blocks into work lists of a
+ * bounded size that worker threads dequeue and run on the GPU (Algorithms
+ * add_block / assemble_gpu and schedule_tasks).  Here the lists of many
+ * block lists, possibly of many meshes, become one device queue of
+ * sub-tiles (at most 64 x 64 entries of one block), sorted by decreasing
+ * estimated cost; a fixed grid of workgroups pops sub-tiles from it until
+ * it is empty.  The queue, per-mesh geometry and launch are built once by
+ * bem_plan_batched and captured in a HIP graph (a counter-reset kernel,
+ * the geometry kernels and the persistent kernel); bem_run_batched replays
+ * it.  Entries are bitwise equal to those of bem_assemble_nearfield /
+ * bem_assemble_coupling when the x-point chunk equals theirs (the default).
+ * --------------------------------------------------------------------- */
+
+typedef struct bem_plan bem_plan;
+
+/* One batch entry: a block list of one mesh and its output. */
+typedef struct {
+  const bem_mesh *mesh;     /* host struct; its arrays are device memory */
+  const bem_blocks *blocks; /* host struct; its arrays are device memory */
+  int32_t coupling;         /* 0: near-field blocks, 1: coupling blocks (no
+                               common vertices allowed, as bem_assemble_coupling) */
+  int32_t reserved;         /* must be 0 */
+  void *out;                /* device, out_len entries of the output type */
+  int64_t out_len;
+} bem_batch;
+
+/* Launch configuration of the persistent kernel.  In: a field left 0 is
+ * chosen by the library (by timing candidates when autotune = 1, else its
+ * default); out: the configuration used. */
+typedef struct {
+  int32_t grid;      /* workgroups (default 2 per compute unit) */
+  int32_t tile_rows; /* sub-tile rows, 1..64 (default: the per-block kernel's) */
+  int32_t tile_cols; /* sub-tile columns, 1..64 */
+  int32_t x_chunk;   /* regular-rule points per register chunk: 4, 5, 7, 8 or 9
+                        (default: the per-block kernel's) */
+  int32_t autotune;  /* 1: time the candidates of every field left 0 */
+  int32_t reserved[3];
+  double tuned_ms;   /* out: time of one launch of the chosen configuration
+                        (0 when nothing was timed) */
+} bem_tune;
+
+/* Plan the batched assembly of `nbatch` entries with one operator.
+ * The plan keeps the device pointers of every mesh, block list and output
+ * and reads their CONTENTS at every run, except the block lists' row_ptr,
+ * col_ptr, out_off, row_idx and col_idx and the meshes' tri, which are read
+ * once here (synchronously) to build the queue: changing those after
+ * planning requires a new plan.  Meshes given by identical descriptors share
+ * one geometry buffer.  The plan owns its device memory (geometry, queue,
+ * counter) and a HIP graph; autotuning launches the kernel (writing the
+ * outputs) on `stream`.  `cache_path` (may be NULL) names a text file of
+ * tuned configurations, one JSON object per line, keyed by device and
+ * workload; a hit skips the timing and a new result is appended.
+ * Host-visible errors (ranges, offsets, ids) fail with BEM_EINVAL here. */
+int bem_plan_batched(bem_ctx *ctx, const bem_op *op, int32_t nbatch, const bem_batch *batches,
+                     bem_tune *tune, const char *cache_path, void *stream, bem_plan **plan);
+
+/* Enqueue one replay of the plan's graph on `stream`.  Runs of one plan
+ * share its queue counter and geometry: they must not overlap in time
+ * (successive runs on one stream are fine).  Device flags are raised on the
+ * plan's context as for the per-call entry points (see bem_check). */
+int bem_run_batched(bem_plan *plan, void *stream);
+
+/* Sub-tiles in the plan's queue (0 for a NULL plan). */
+int64_t bem_plan_tiles(const bem_plan *plan);
+
+/* Release a plan (waits for its device work).  NULL is a no-op. */
+void bem_plan_destroy(bem_plan *plan);
+
+/* ---------------------------------------------------------------------
  * Cluster bases of the Green cross approximation (Sec. 2.3-2.4).
  * --------------------------------------------------------------------- */
 

@@ -328,3 +328,82 @@ def _context_basis_contract(self, is_complex, nrows, rank, max_rank, piv_cols, p
 
 Context.green_matrix = _context_green_matrix
 Context.basis_contract = _context_basis_contract
+
+
+# ------------------------------------------------------------ batched plans
+class bem_batch(ctypes.Structure):
+    _fields_ = [("mesh", ctypes.POINTER(bem_mesh)), ("blocks", ctypes.POINTER(bem_blocks)),
+                ("coupling", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("out", ctypes.c_void_p), ("out_len", ctypes.c_int64)]
+
+
+class bem_tune(ctypes.Structure):
+    _fields_ = [("grid", ctypes.c_int32), ("tile_rows", ctypes.c_int32),
+                ("tile_cols", ctypes.c_int32), ("x_chunk", ctypes.c_int32),
+                ("autotune", ctypes.c_int32), ("reserved", ctypes.c_int32 * 3),
+                ("tuned_ms", ctypes.c_double)]
+
+
+def _setup_plan_api():
+    P = ctypes.c_void_p
+    _lib.bem_plan_batched.argtypes = [P, ctypes.POINTER(bem_op), ctypes.c_int32,
+                                      ctypes.POINTER(bem_batch), ctypes.POINTER(bem_tune),
+                                      ctypes.c_char_p, P, ctypes.POINTER(P)]
+    _lib.bem_run_batched.argtypes = [P, P]
+    _lib.bem_plan_tiles.argtypes = [P]
+    _lib.bem_plan_tiles.restype = ctypes.c_int64
+    _lib.bem_plan_destroy.argtypes = [P]
+    _lib.bem_plan_destroy.restype = None
+
+
+_setup_plan_api()
+
+
+class Plan:
+    """``bem_plan_batched``: one persistent, graph-captured assembly of many
+    block lists.  ``entries`` is a list of (mesh, blocks, out, coupling);
+    the plan keeps references to them (the device pointers are captured).
+    ``tune`` fixes fields of the launch configuration (grid, tile_rows,
+    tile_cols, x_chunk); ``autotune`` times candidates for the others;
+    ``cache`` names the tuning cache file."""
+
+    def __init__(self, ctx, op, entries, tune=None, autotune=False, cache=None, stream=None):
+        self.ctx, self.op, self.entries = ctx, op, list(entries)
+        n = len(self.entries)
+        self._c = (bem_batch * max(n, 1))()
+        for k, (mesh, blocks, out, coupling) in enumerate(self.entries):
+            self._c[k] = bem_batch(ctypes.pointer(mesh.c), ctypes.pointer(blocks.c),
+                                   int(bool(coupling)), 0, _ptr(out), out.numel())
+        t = dict(tune or {})
+        self.tune = bem_tune(int(t.get("grid", 0)), int(t.get("tile_rows", 0)),
+                             int(t.get("tile_cols", 0)), int(t.get("x_chunk", 0)),
+                             int(bool(autotune)), (ctypes.c_int32 * 3)(0, 0, 0), 0.0)
+        h = ctypes.c_void_p()
+        path = os.fsencode(cache) if cache else None
+        ctx._rc(_lib.bem_plan_batched(ctx.h, ctypes.byref(op), n, self._c, ctypes.byref(self.tune),
+                                      path, _stream(stream), ctypes.byref(h)))
+        self.h = h
+
+    @property
+    def config(self):
+        t = self.tune
+        return dict(grid=t.grid, tile_rows=t.tile_rows, tile_cols=t.tile_cols,
+                    x_chunk=t.x_chunk, tuned_ms=t.tuned_ms)
+
+    @property
+    def tiles(self):
+        return int(_lib.bem_plan_tiles(self.h))
+
+    def run(self, stream=None):
+        self.ctx._rc(_lib.bem_run_batched(self.h, _stream(stream)))
+
+    def close(self):
+        if getattr(self, "h", None):
+            _lib.bem_plan_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

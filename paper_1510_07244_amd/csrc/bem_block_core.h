@@ -1,0 +1,242 @@
+// Building blocks of the block assembly kernels (gfx950, wave64): LDS layout
+// of a sub-tile and the per-entry regular sums in FP64 and in FP32.  Shared by
+// the per-block kernel and the persistent batched kernel (bem_blocks.hip).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "bem_device.h"
+
+namespace bem {
+namespace blk {
+
+using namespace dev;
+
+constexpr double kPad = 1.0e4;       // coordinate of column padding points (weight 0)
+constexpr uint16_t kNoPair = 0xffff; // empty slot of the sorted singular list
+constexpr int kNearSingular = 0;     // list class of near-singular regular pairs (mixed)
+
+// LDS layout of one sub-tile (up to TR rows x TC columns; triangle rule of nq
+// points padded to nqp with zero weights):
+//   ys[nqp][TC]    column points.  Plain: 6 doubles (-2Y0, -2Y1, -2Y2, |Y|^2,
+//                  w sqrt(g_j), <Y, n_j>) with Y = 2 (y - c) in block-local
+//                  coordinates.  Mixed: 8 floats (Y0, Y1, Y2, w sqrt(g_j),
+//                  <Y, n_j>, pad) with Y = 2 (y - v0_j) local to the column
+//                  triangle.  Read as 16-byte words (broadcast in a wave).
+//   rg[10][TR]     row geometry 2 (v0 - c), 2 e1, 2 e2, sqrt(g_i)
+//   rule[3][nqp]   s, t, w of the triangle rule
+//   cn[3][TC]      column normals
+//   mixed only:    cg[3][TC] = 2 (v0_j - c); rb[6][TR], cb[6][TC] boxes
+//   ints           rid[TR], rv[3][TR], cid[TC], cv[3][TC], count, bad,
+//                  per-class counts[4] and cursors[4]
+//   list[TR*TC]    uint16 codes (row | col << 6 | class << 12) of the pairs
+//                  left to the FP64 pass (singular; near-singular if mixed)
+//   sorted[TR*TC + 256]  the same codes grouped by class, each class padded
+//                  to a multiple of 64 with kNoPair
+struct Lds {
+  double *ys, *rg, *rule, *cn, *cg, *rb, *cb;
+  int *rid, *rv, *cid, *cv, *count, *bad, *ccount, *cursor;
+  uint16_t *list, *sorted;
+};
+
+__host__ __device__ __forceinline__ int ypoint_doubles(bool mixed) { return mixed ? 4 : 6; }
+
+template <bool MIXED>
+__device__ __forceinline__ Lds carve(double *base, int nqp, int TR, int TC) {
+  Lds l;
+  l.ys = base;
+  l.rg = l.ys + ypoint_doubles(MIXED) * nqp * TC;
+  l.rule = l.rg + 10 * TR;
+  l.cn = l.rule + 3 * nqp;
+  l.cg = l.cn + 3 * TC;
+  l.rb = l.cg + (MIXED ? 3 * TC : 0);
+  l.cb = l.rb + (MIXED ? 6 * TR : 0);
+  int *ib = reinterpret_cast<int *>(l.cb + (MIXED ? 6 * TC : 0));
+  l.rid = ib;
+  l.rv = l.rid + TR;
+  l.cid = l.rv + 3 * TR;
+  l.cv = l.cid + TC;
+  l.count = l.cv + 3 * TC;
+  l.bad = l.count + 1;
+  l.ccount = l.bad + 1;
+  l.cursor = l.ccount + 4;
+  l.list = reinterpret_cast<uint16_t *>(l.cursor + 4);
+  l.sorted = l.list + TR * TC;
+  return l;
+}
+
+// FP64 sum over the point pairs of one regular entry (sub-tile row rl,
+// column cl): sum_b wy_b sum_a wx_a k'(x_a, y_b), where k' omits the factor
+// 1/(4 pi) and, for the double layer, the factor 1/2 of the scaled normal
+// distance.  4 |x - y|^2 = |X|^2 + |Y|^2 + X . (-2Y) in block-local
+// coordinates; 1/r from v_rsq_f64 and one Newton step.
+template <int KERNEL, int LAYER, int XC>
+__device__ __forceinline__ Acc<KERNEL> regular_entry(const Lds &l, int TR, int TC, int nqp, int rl,
+                                                     int cl, double kq) {
+  const double D0 = l.rg[0 * TR + rl], D1 = l.rg[1 * TR + rl], D2 = l.rg[2 * TR + rl];
+  const double A0 = l.rg[3 * TR + rl], A1 = l.rg[4 * TR + rl], A2 = l.rg[5 * TR + rl];
+  const double B0 = l.rg[6 * TR + rl], B1 = l.rg[7 * TR + rl], B2 = l.rg[8 * TR + rl];
+  const double SG = l.rg[9 * TR + rl];
+  double n0 = 0, n1 = 0, n2 = 0;
+  if constexpr (LAYER == BEM_DLP) {
+    n0 = l.cn[cl];
+    n1 = l.cn[TC + cl];
+    n2 = l.cn[2 * TC + cl];
+  }
+  const double2 *ycol = reinterpret_cast<const double2 *>(l.ys) + 3 * cl;
+  const int ystride = 3 * TC;  // double2 per point index
+  Acc<KERNEL> acc;
+  for (int ch = 0; ch < nqp; ch += XC) {
+    double X0[XC], X1[XC], X2[XC], XX[XC], WX[XC], XN[XC];
+#pragma unroll
+    for (int a = 0; a < XC; ++a) {
+      const double s = l.rule[ch + a], t = l.rule[nqp + ch + a], w = l.rule[2 * nqp + ch + a];
+      X0[a] = fma(s, A0, fma(t, B0, D0));
+      X1[a] = fma(s, A1, fma(t, B1, D1));
+      X2[a] = fma(s, A2, fma(t, B2, D2));
+      XX[a] = fma(X0[a], X0[a], fma(X1[a], X1[a], X2[a] * X2[a]));
+      WX[a] = w * SG;
+      if constexpr (LAYER == BEM_DLP) XN[a] = fma(X0[a], n0, fma(X1[a], n1, X2[a] * n2));
+    }
+    double2 c0 = ycol[0], c1 = ycol[1], c2 = ycol[2];
+    for (int kb = 0; kb < nqp; ++kb) {
+      // prefetch the next column point while this one is used
+      const double2 *yn = ycol + (kb + 1 < nqp ? kb + 1 : kb) * ystride;
+      const double2 p0 = yn[0], p1 = yn[1], p2 = yn[2];
+      const double M0 = c0.x, M1 = c0.y, M2 = c1.x, YY = c1.y, WY = c2.x, YN = c2.y;
+      double ire = 0.0, iim = 0.0;
+#pragma unroll
+      for (int a = 0; a < XC; ++a) {
+        double s = XX[a] + YY;
+        s = fma(X0[a], M0, s);
+        s = fma(X1[a], M1, s);
+        s = fma(X2[a], M2, s);  // s = 4 r^2
+        // h ~ 1/(2r); one Newton step gives z = h (3 - s h^2) ~ 1/r
+        const double h = __builtin_amdgcn_rsq(s);
+        const double t = s * h;
+        const double e = fma(-t, h, 3.0);
+        const double z = h * e;
+        if constexpr (KERNEL == BEM_LAPLACE) {
+          if constexpr (LAYER == BEM_SLP) {
+            ire = fma(WX[a], z, ire);
+          } else {
+            const double dn = XN[a] - YN;  // 2 <x - y, n_j>
+            ire = fma(WX[a] * dn, z * z * z, ire);
+          }
+        } else {
+          const double kr = kq * s * z;  // kappa r  (kq = kappa / 4)
+          double sn, cs;
+          sincos_cw(kr, &sn, &cs);
+          if constexpr (LAYER == BEM_SLP) {
+            const double wz = WX[a] * z;
+            ire = fma(wz, cs, ire);
+            iim = fma(wz, sn, iim);
+          } else {
+            const double u = WX[a] * (XN[a] - YN) * z * z * z;
+            ire = fma(u, fma(kr, sn, cs), ire);
+            iim = fma(u, fma(-kr, cs, sn), iim);
+          }
+        }
+      }
+      acc.re = fma(WY, ire, acc.re);
+      if constexpr (KERNEL == BEM_HELMHOLTZ) acc.im = fma(WY, iim, acc.im);
+      c0 = p0;
+      c1 = p1;
+      c2 = p2;
+    }
+  }
+  return acc;
+}
+
+// FP32 sum of one regular entry of the mixed form, in coordinates local to
+// the row triangle's first vertex v0_i (per entry, so that the FP32 rounding
+// of coordinates is relative to the pair's own size):
+//   X_a = 2 (x_a - v0_i),  Y'_b = D + Y_b,  D = 2 (v0_j - v0_i) rounded once,
+//   4 r^2 = |X|^2 + |Y'|^2 - 2 X . Y',  h = v_rsq_f32(4 r^2) = 1/(2r).
+// Returns the same sum as regular_entry (with k' as there).
+template <int KERNEL, int LAYER, int XC>
+__device__ __forceinline__ Acc<KERNEL> regular_entry_f32(const Lds &l, int TR, int TC, int nqp,
+                                                         int rl, int cl, double kappa) {
+  const double A0 = l.rg[3 * TR + rl], A1 = l.rg[4 * TR + rl], A2 = l.rg[5 * TR + rl];
+  const double B0 = l.rg[6 * TR + rl], B1 = l.rg[7 * TR + rl], B2 = l.rg[8 * TR + rl];
+  const double SG = l.rg[9 * TR + rl];
+  const float d0 = (float)(l.cg[cl] - l.rg[0 * TR + rl]);
+  const float d1 = (float)(l.cg[TC + cl] - l.rg[1 * TR + rl]);
+  const float d2 = (float)(l.cg[2 * TC + cl] - l.rg[2 * TR + rl]);
+  float n0 = 0, n1 = 0, n2 = 0, dn = 0;
+  if constexpr (LAYER == BEM_DLP) {
+    n0 = (float)l.cn[cl];
+    n1 = (float)l.cn[TC + cl];
+    n2 = (float)l.cn[2 * TC + cl];
+    dn = fmaf(d0, n0, fmaf(d1, n1, d2 * n2));
+  }
+  const float hk = 0.5f * (float)kappa;  // kappa r = (kappa / 2) (4 r^2) h
+  const float4 *ycol = reinterpret_cast<const float4 *>(l.ys) + 2 * cl;
+  const int ystride = 2 * TC;  // float4 per point index
+  float are = 0.0f, aim = 0.0f;
+  for (int ch = 0; ch < nqp; ch += XC) {
+    float X0[XC], X1[XC], X2[XC], XX[XC], WX[XC], XN[XC];
+#pragma unroll
+    for (int a = 0; a < XC; ++a) {
+      const double s = l.rule[ch + a], t = l.rule[nqp + ch + a], w = l.rule[2 * nqp + ch + a];
+      const float x0 = (float)fma(s, A0, t * B0), x1 = (float)fma(s, A1, t * B1),
+                  x2 = (float)fma(s, A2, t * B2);
+      XX[a] = fmaf(x0, x0, fmaf(x1, x1, x2 * x2));
+      X0[a] = -2.0f * x0;
+      X1[a] = -2.0f * x1;
+      X2[a] = -2.0f * x2;
+      // h = 1/(2r): the SLP's k' = 1/r = 2h, the DLP's k' = 2 <x - y, n> / r^3
+      // = 8 h^3 <X - Y', n> (same k' as the FP64 path)
+      WX[a] = (float)(w * SG) * (LAYER == BEM_SLP ? 2.0f : 8.0f);
+      if constexpr (LAYER == BEM_DLP) XN[a] = fmaf(x0, n0, fmaf(x1, n1, x2 * n2));
+    }
+    float4 c0 = ycol[0], c1 = ycol[1];
+    for (int kb = 0; kb < nqp; ++kb) {
+      const float4 *yn = ycol + (kb + 1 < nqp ? kb + 1 : kb) * ystride;
+      const float4 p0 = yn[0], p1 = yn[1];
+      const float y0 = d0 + c0.x, y1 = d1 + c0.y, y2 = d2 + c0.z, WY = c0.w;
+      const float YY = fmaf(y0, y0, fmaf(y1, y1, y2 * y2));
+      const float YN = dn + c1.x;  // <Y', n_j>
+      float ire = 0.0f, iim = 0.0f;
+#pragma unroll
+      for (int a = 0; a < XC; ++a) {
+        float s = XX[a] + YY;
+        s = fmaf(X0[a], y0, s);
+        s = fmaf(X1[a], y1, s);
+        s = fmaf(X2[a], y2, s);  // 4 r^2
+        const float h = __builtin_amdgcn_rsqf(s);
+        if constexpr (KERNEL == BEM_LAPLACE) {
+          if constexpr (LAYER == BEM_SLP) {
+            ire = fmaf(WX[a], h, ire);
+          } else {
+            ire = fmaf(WX[a] * (XN[a] - YN), h * h * h, ire);
+          }
+        } else {
+          const float kr = hk * s * h;
+          float sn, cs;
+          sincos_cw_f32(kr, &sn, &cs);
+          if constexpr (LAYER == BEM_SLP) {
+            const float wz = WX[a] * h;
+            ire = fmaf(wz, cs, ire);
+            iim = fmaf(wz, sn, iim);
+          } else {
+            const float u = WX[a] * (XN[a] - YN) * h * h * h;
+            ire = fmaf(u, fmaf(kr, sn, cs), ire);
+            iim = fmaf(u, fmaf(-kr, cs, sn), iim);
+          }
+        }
+      }
+      are = fmaf(WY, ire, are);
+      if constexpr (KERNEL == BEM_HELMHOLTZ) aim = fmaf(WY, iim, aim);
+      c0 = p0;
+      c1 = p1;
+    }
+  }
+  Acc<KERNEL> acc;
+  acc.re = are;
+  if constexpr (KERNEL == BEM_HELMHOLTZ) acc.im = aim;
+  return acc;
+}
+
+}  // namespace blk
+}  // namespace bem

@@ -9,19 +9,7 @@
 
 #include "bem_internal.h"
 
-namespace {
-
-struct DeviceGuard {  // make the context's device current, restore on exit
-  int prev = -1;
-  explicit DeviceGuard(int dev) {
-    if (hipGetDevice(&prev) != hipSuccess) prev = -1;
-    if (prev != dev) (void)hipSetDevice(dev);
-  }
-  ~DeviceGuard() {
-    int cur = -1;
-    if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
-  }
-};
+namespace bem {
 
 int fail(bem_ctx *ctx, int code, const std::string &msg) {
   if (ctx) ctx->err = msg;
@@ -51,8 +39,6 @@ int check_op(bem_ctx *ctx, const bem_op *op) {
     return fail(ctx, BEM_EINVAL, "op.kappa / op.near_singular_ratio must be finite (ratio >= 0)");
   for (int k = 0; k < 4; ++k)
     if (op->reserved[k]) return fail(ctx, BEM_EINVAL, "op.reserved must be zero");
-  if (op->precision == BEM_MIXED)
-    return fail(ctx, BEM_EUNSUPPORTED, "mixed precision is not available in this build");
   return BEM_OK;
 }
 
@@ -195,19 +181,23 @@ int assemble_blocks(bem_ctx *ctx, const bem_mesh *mesh, const bem_op *op,
   const int xc = bem::rule_chunk(rules->nq, op->kernel);
   a.nq_pad = (rules->nq + xc - 1) / xc * xc;
   size_t lds;
-  if (!bem::block_tile_shape(a.nq_pad, ctx->lds_budget, &a.tr, &a.tc, &lds))
+  const bool mixed = op->precision == BEM_MIXED;
+  if (!bem::block_tile_shape(a.nq_pad, mixed, ctx->lds_budget, &a.tr, &a.tc, &lds))
     return fail(ctx, BEM_EUNSUPPORTED, "quadrature order too high for the LDS budget");
+  a.near_ratio = op->near_singular_ratio;
   for (int c = 0; c < 4; ++c) a.ss.eta[c] = rules->ss[c], a.ss.np[c] = rules->np[c];
   a.ss.xi = rules->xi;
   a.ss.q = rules->nxi;
   a.kappa = op->kernel == BEM_HELMHOLTZ ? op->kappa : 0.0;
   a.flags = ctx->flags;
-  e = bem::launch_blocks(op->kernel, op->layer, coupling, a, lds, s);
+  e = bem::launch_blocks(op->kernel, op->layer, coupling, mixed, a, lds, s);
   if (e != hipSuccess) return hip_fail(ctx, e, "block kernel launch");
   return BEM_OK;
 }
 
-}  // namespace
+}  // namespace bem
+
+using namespace bem;
 
 extern "C" {
 
@@ -400,7 +390,7 @@ int bem_eval_entries(bem_ctx *ctx, const bem_mesh *mesh, const bem_op *op, int64
   a.ss.q = rules->nxi;
   a.kappa = op->kernel == BEM_HELMHOLTZ ? op->kappa : 0.0;
   a.flags = ctx->flags;
-  e = bem::launch_entries(op->kernel, op->layer, a, s);
+  e = bem::launch_entries(op->kernel, op->layer, op->precision == BEM_MIXED, a, s);
   if (e != hipSuccess) return hip_fail(ctx, e, "entry kernel launch");
   return BEM_OK;
 }

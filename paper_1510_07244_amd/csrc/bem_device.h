@@ -65,6 +65,34 @@ __device__ __forceinline__ void sincos_cw(double x, double *s, double *c) {
   *c = ((q + 1) & 2) ? -b : b;
 }
 
+// FP32 sine and cosine for the mixed-precision path: the same Cody-Waite
+// reduction with pi/2 truncated to 12 + 12 + 24 significant bits (k * part
+// exact for |k| < 2^12), Taylor polynomials to x^9 / x^10 (remainders below
+// 2e-9 on [-pi/4, pi/4]).
+__device__ __forceinline__ void sincos_cw_f32(float x, float *s, float *c) {
+  const float k = __builtin_rintf(x * 0.63661977f);
+  float r = fmaf(-k, 1.5703125f, x);              // 0x1.92p+0
+  r = fmaf(-k, 4.837512969970703125e-4f, r);      // 0x1.fb4p-12
+  r = fmaf(-k, 7.549789415861596e-8f, r);         // 0x1.4442dp-24
+  const float r2 = r * r;
+  float ps = 1.0f / 362880.0f;
+  ps = fmaf(ps, r2, -1.0f / 5040.0f);
+  ps = fmaf(ps, r2, 1.0f / 120.0f);
+  ps = fmaf(ps, r2, -1.0f / 6.0f);
+  const float sr = fmaf(r * r2, ps, r);
+  float pc = -1.0f / 3628800.0f;
+  pc = fmaf(pc, r2, 1.0f / 40320.0f);
+  pc = fmaf(pc, r2, -1.0f / 720.0f);
+  pc = fmaf(pc, r2, 1.0f / 24.0f);
+  pc = fmaf(pc, r2, -0.5f);
+  const float cr = fmaf(r2, pc, 1.0f);
+  const int q = static_cast<int>(k) & 3;
+  const float a = (q & 1) ? cr : sr;
+  const float b = (q & 1) ? sr : cr;
+  *s = (q & 2) ? -a : a;
+  *c = ((q + 1) & 2) ? -b : b;
+}
+
 template <int KERNEL>
 struct Acc;
 template <>
@@ -92,6 +120,76 @@ __device__ __forceinline__ void store(void *out, int64_t k, const Acc<KERNEL> &v
     if (!isfinite(v.re) || !isfinite(v.im)) atomicOr(flags, FLAG_NONFINITE);
     static_cast<double2 *>(out)[k] = make_double2(v.re, v.im);
   }
+}
+
+// Store for the plain (double / double2) or mixed (float / float2) output.
+template <int KERNEL, bool MIXED>
+__device__ __forceinline__ void store_as(void *out, int64_t k, const Acc<KERNEL> &v,
+                                         unsigned *flags) {
+  if constexpr (!MIXED) {
+    store<KERNEL>(out, k, v, flags);
+  } else if constexpr (KERNEL == BEM_LAPLACE) {
+    const float r = static_cast<float>(v.re);
+    if (!isfinite(r)) atomicOr(flags, FLAG_NONFINITE);
+    static_cast<float *>(out)[k] = r;
+  } else {
+    const float r = static_cast<float>(v.re), i = static_cast<float>(v.im);
+    if (!isfinite(r) || !isfinite(i)) atomicOr(flags, FLAG_NONFINITE);
+    static_cast<float2 *>(out)[k] = make_float2(r, i);
+  }
+}
+
+// One regular (disjoint) pair in FP64 with its rule points computed on the
+// fly from the geometry arrays: sqrt(g_i g_j) sum_a w_a sum_b w_b k(x_a, y_b).
+template <int KERNEL, int LAYER>
+__device__ __forceinline__ Acc<KERNEL> regular_pair_fp64(const double *g, int64_t L,
+                                                         const double *R, int nq, double kappa,
+                                                         int i, int j) {
+  double D[3], E1i[3], E2i[3], E1j[3], E2j[3];
+  for (int c = 0; c < 3; ++c) {
+    D[c] = g[(G_V0X + c) * L + i] - g[(G_V0X + c) * L + j];
+    E1i[c] = g[(G_E1X + c) * L + i];
+    E2i[c] = g[(G_E2X + c) * L + i];
+    E1j[c] = g[(G_E1X + c) * L + j];
+    E2j[c] = g[(G_E2X + c) * L + j];
+  }
+  const double nx = g[G_NX * L + j], ny = g[G_NY * L + j], nz = g[G_NZ * L + j];
+  double are = 0.0, aim = 0.0;
+  for (int qa = 0; qa < nq; ++qa) {
+    double x[3];
+    for (int c = 0; c < 3; ++c) x[c] = fma(R[qa], E1i[c], fma(R[nq + qa], E2i[c], D[c]));
+    double ire = 0.0, iim = 0.0;
+    for (int qb = 0; qb < nq; ++qb) {
+      double d[3];
+      for (int c = 0; c < 3; ++c) d[c] = fma(-R[qb], E1j[c], fma(-R[nq + qb], E2j[c], x[c]));
+      const double r2 = fma(d[0], d[0], fma(d[1], d[1], d[2] * d[2]));
+      const double z = rsqrt_newton(r2);
+      double k = z;
+      if constexpr (LAYER == BEM_DLP) k = fma(d[0], nx, fma(d[1], ny, d[2] * nz)) * z * z * z;
+      const double w = R[2 * nq + qb];
+      if constexpr (KERNEL == BEM_LAPLACE) {
+        ire = fma(w, k, ire);
+      } else {
+        const double kr = kappa * r2 * z;
+        double sn, cs;
+        sincos_cw(kr, &sn, &cs);
+        if constexpr (LAYER == BEM_SLP) {
+          ire = fma(w * k, cs, ire);
+          iim = fma(w * k, sn, iim);
+        } else {
+          ire = fma(w * k, fma(kr, sn, cs), ire);
+          iim = fma(w * k, fma(-kr, cs, sn), iim);
+        }
+      }
+    }
+    are = fma(R[2 * nq + qa], ire, are);
+    aim = fma(R[2 * nq + qa], iim, aim);
+  }
+  const double scale = g[G_SG * L + i] * g[G_SG * L + j] * kInv4Pi;
+  Acc<KERNEL> v;
+  v.re = are * scale;
+  if constexpr (KERNEL == BEM_HELMHOLTZ) v.im = aim * scale;
+  return v;
 }
 
 __device__ __forceinline__ int shared_vertex_count(int a0, int a1, int a2, int b0, int b1, int b2) {

@@ -91,6 +91,7 @@ struct BlockArgs {
   int32_t tr, tc;      // sub-tile rows / columns
   SSArgs ss;
   double kappa;
+  double near_ratio;   // mixed form: near-singular box-distance ratio
   unsigned *flags;
 };
 
@@ -143,20 +144,65 @@ struct ContractArgs {
   unsigned *flags;
 };
 
+// Arguments of the persistent batched block kernel: one BlockArgs per batch
+// entry (all with the same rule and sub-tile shape) and a queue of sub-tiles.
+struct PersistentArgs {
+  const BlockArgs *batches;  // device [nbatch]
+  const int32_t *coupling;   // device [nbatch]: 1 = coupling block list
+  const int4 *tiles;         // device [ntiles]: batch, block, first row, first column
+  int32_t ntiles, nbatch;
+  int32_t *counter;          // device queue head, 0 at launch
+  int32_t grid;              // workgroups
+};
+
+// xc: x-points per register chunk (4, 5, 7, 8 or 9; nq_pad of every batch
+// entry is nq rounded up to a multiple of it)
+hipError_t launch_persistent(int kernel, int layer, bool mixed, int xc, const PersistentArgs &p,
+                             size_t lds_bytes, hipStream_t s);
+hipError_t launch_reset_counter(int32_t *counter, hipStream_t s);
+
 hipError_t launch_green(int kernel, int side, const GreenArgs &a, int grid_y, hipStream_t s);
 hipError_t launch_contract(bool cplx, const ContractArgs &a, int grid_y, hipStream_t s);
 
 // launchers (bem_kernels.hip); return a hipError_t
 hipError_t launch_geometry(const bem_mesh &m, double *geo, int64_t ldg, unsigned *flags,
                            hipStream_t s);
-hipError_t launch_blocks(int kernel, int layer, bool coupling, const BlockArgs &a,
+hipError_t launch_blocks(int kernel, int layer, bool coupling, bool mixed, const BlockArgs &a,
                          size_t lds_bytes, hipStream_t s);
-hipError_t launch_entries(int kernel, int layer, const EntryArgs &a, hipStream_t s);
+hipError_t launch_entries(int kernel, int layer, bool mixed, const EntryArgs &a, hipStream_t s);
 // sub-tile shape (rows, columns) and LDS bytes of the block kernel for a
 // padded rule size within an LDS budget; false if nothing fits
-bool block_tile_shape(int nq_pad, size_t lds_budget, int *tr, int *tc, size_t *lds_bytes);
-size_t block_lds_bytes(int nq_pad, int tr, int tc);
+bool block_tile_shape(int nq_pad, bool mixed, size_t lds_budget, int *tr, int *tc,
+                      size_t *lds_bytes);
+size_t block_lds_bytes(int nq_pad, int tr, int tc, bool mixed);
 int rule_chunk(int nq, int kernel);  // x-points per register chunk
+
+}  // namespace bem
+
+struct bem_ctx;
+
+namespace bem {
+
+struct DeviceGuard {  // make the context's device current, restore on exit
+  int prev = -1;
+  explicit DeviceGuard(int dev) {
+    if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+    if (prev != dev) (void)hipSetDevice(dev);
+  }
+  ~DeviceGuard() {
+    int cur = -1;
+    if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
+  }
+};
+
+// shared argument checks and context helpers (bem_capi.cpp); they set the
+// context's error text and return a BEM_ code
+int fail(bem_ctx *ctx, int code, const std::string &msg);
+int hip_fail(bem_ctx *ctx, hipError_t e, const char *where);
+int check_op(bem_ctx *ctx, const bem_op *op);
+int check_mesh(bem_ctx *ctx, const bem_mesh *m);
+int check_blocks(bem_ctx *ctx, const bem_blocks *b, const void *out, int64_t out_len);
+int get_rules(bem_ctx *ctx, const bem_op *op, const DevRules **out);
 
 }  // namespace bem
 

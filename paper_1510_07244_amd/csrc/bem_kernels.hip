@@ -49,9 +49,10 @@ __global__ void k_geometry(const double *v, int32_t nv, const int32_t *tri, int3
 }
 
 // ---------------------------------------------------------------- entries
-// Arbitrary (i, j) list: one lane per regular entry with its points computed
-// on the fly; singular entries are listed and done by whole waves.
-template <int KERNEL, int LAYER>
+// Arbitrary (i, j) list: one lane per regular entry (FP64, points computed on
+// the fly); singular entries are listed and done by whole waves.  The mixed
+// form stores the FP64 values rounded to FP32.
+template <int KERNEL, int LAYER, bool MIXED>
 __global__ __launch_bounds__(kThreads) void k_entries(const EntryArgs a) {
   __shared__ int list[kThreads];
   __shared__ int count;
@@ -70,56 +71,9 @@ __global__ __launch_bounds__(kThreads) void k_entries(const EntryArgs a) {
       if (cls) {
         list[atomicAdd(&count, 1)] = tid;
       } else {
-        const double *g = a.geo;
-        const int64_t L = a.ldg;
-        double D[3], E1i[3], E2i[3], E1j[3], E2j[3];
-        for (int c = 0; c < 3; ++c) {
-          D[c] = g[(G_V0X + c) * L + i] - g[(G_V0X + c) * L + j];
-          E1i[c] = g[(G_E1X + c) * L + i];
-          E2i[c] = g[(G_E2X + c) * L + i];
-          E1j[c] = g[(G_E1X + c) * L + j];
-          E2j[c] = g[(G_E2X + c) * L + j];
-        }
-        const double nx = g[G_NX * L + j], ny = g[G_NY * L + j], nz = g[G_NZ * L + j];
-        const int nq = a.nq;
-        const double *R = a.rule;
-        double are = 0.0, aim = 0.0;
-        for (int qa = 0; qa < nq; ++qa) {
-          double x[3];
-          for (int c = 0; c < 3; ++c) x[c] = fma(R[qa], E1i[c], fma(R[nq + qa], E2i[c], D[c]));
-          double ire = 0.0, iim = 0.0;
-          for (int qb = 0; qb < nq; ++qb) {
-            double d[3];
-            for (int c = 0; c < 3; ++c)
-              d[c] = fma(-R[qb], E1j[c], fma(-R[nq + qb], E2j[c], x[c]));
-            const double r2 = fma(d[0], d[0], fma(d[1], d[1], d[2] * d[2]));
-            const double z = rsqrt_newton(r2);
-            double k = z;
-            if constexpr (LAYER == BEM_DLP) k = fma(d[0], nx, fma(d[1], ny, d[2] * nz)) * z * z * z;
-            const double w = R[2 * nq + qb];
-            if constexpr (KERNEL == BEM_LAPLACE) {
-              ire = fma(w, k, ire);
-            } else {
-              const double kr = a.kappa * r2 * z;
-              double sn, cs;
-              sincos_cw(kr, &sn, &cs);
-              if constexpr (LAYER == BEM_SLP) {
-                ire = fma(w * k, cs, ire);
-                iim = fma(w * k, sn, iim);
-              } else {
-                ire = fma(w * k, fma(kr, sn, cs), ire);
-                iim = fma(w * k, fma(-kr, cs, sn), iim);
-              }
-            }
-          }
-          are = fma(R[2 * nq + qa], ire, are);
-          aim = fma(R[2 * nq + qa], iim, aim);
-        }
-        const double scale = g[G_SG * L + i] * g[G_SG * L + j] * kInv4Pi;
-        Acc<KERNEL> v;
-        v.re = are * scale;
-        if constexpr (KERNEL == BEM_HELMHOLTZ) v.im = aim * scale;
-        store<KERNEL>(a.out, e, v, a.flags);
+        const Acc<KERNEL> v =
+            regular_pair_fp64<KERNEL, LAYER>(a.geo, a.ldg, a.rule, a.nq, a.kappa, i, j);
+        store_as<KERNEL, MIXED>(a.out, e, v, a.flags);
       }
     }
   }
@@ -134,9 +88,15 @@ __global__ __launch_bounds__(kThreads) void k_entries(const EntryArgs a) {
     PairGeo g;
     if (pair_geometry(a.v, a.tri, a.nv, a.geo, a.ldg, i, j, cls, a.flags, &g)) {
       const Acc<KERNEL> v = ss_pair_wave<KERNEL, LAYER>(g, a.ss, cls, a.kappa);
-      if (lane == 0) store<KERNEL>(a.out, ee, v, a.flags);
+      if (lane == 0) store_as<KERNEL, MIXED>(a.out, ee, v, a.flags);
     }
   }
+}
+
+template <int KERNEL, int LAYER>
+void launch_entries_kl(bool mixed, const EntryArgs &a, dim3 grid, dim3 block, hipStream_t s) {
+  if (mixed) hipLaunchKernelGGL((k_entries<KERNEL, LAYER, true>), grid, block, 0, s, a);
+  else hipLaunchKernelGGL((k_entries<KERNEL, LAYER, false>), grid, block, 0, s, a);
 }
 
 }  // namespace
@@ -149,15 +109,15 @@ hipError_t launch_geometry(const bem_mesh &m, double *geo, int64_t ldg, unsigned
   return hipGetLastError();
 }
 
-hipError_t launch_entries(int kernel, int layer, const EntryArgs &a, hipStream_t s) {
+hipError_t launch_entries(int kernel, int layer, bool mixed, const EntryArgs &a, hipStream_t s) {
   if (a.n == 0) return hipSuccess;
   const dim3 grid((unsigned)((a.n + kThreads - 1) / kThreads)), block(kThreads);
   if (kernel == BEM_LAPLACE) {
-    if (layer == BEM_SLP) hipLaunchKernelGGL((k_entries<BEM_LAPLACE, BEM_SLP>), grid, block, 0, s, a);
-    else hipLaunchKernelGGL((k_entries<BEM_LAPLACE, BEM_DLP>), grid, block, 0, s, a);
+    if (layer == BEM_SLP) launch_entries_kl<BEM_LAPLACE, BEM_SLP>(mixed, a, grid, block, s);
+    else launch_entries_kl<BEM_LAPLACE, BEM_DLP>(mixed, a, grid, block, s);
   } else {
-    if (layer == BEM_SLP) hipLaunchKernelGGL((k_entries<BEM_HELMHOLTZ, BEM_SLP>), grid, block, 0, s, a);
-    else hipLaunchKernelGGL((k_entries<BEM_HELMHOLTZ, BEM_DLP>), grid, block, 0, s, a);
+    if (layer == BEM_SLP) launch_entries_kl<BEM_HELMHOLTZ, BEM_SLP>(mixed, a, grid, block, s);
+    else launch_entries_kl<BEM_HELMHOLTZ, BEM_DLP>(mixed, a, grid, block, s);
   }
   return hipGetLastError();
 }

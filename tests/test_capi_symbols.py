@@ -33,11 +33,30 @@ def test_library_exports_every_declared_symbol():
     assert not missing, missing
 
 
-def test_struct_layouts_match_header():
+def test_struct_layouts_match_header(tmp_path):
+    """Sizes and field offsets of the binding's ctypes structs equal those
+    the C compiler gives the header's structs."""
+    import subprocess
     import paper_1510_07244_amd as pk
-    assert ctypes.sizeof(pk.bem_mesh) == 32
-    assert ctypes.sizeof(pk.bem_op) == 6 * 4 + 2 * 8 + 4 * 4
-    assert ctypes.sizeof(pk.bem_blocks) == 64
+    structs = [pk.bem_mesh, pk.bem_op, pk.bem_blocks, pk.bem_batch, pk.bem_tune]
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "bem.h"', "int main(void) {"]
+    for st in structs:
+        n = st.__name__
+        lines.append(f'  printf("{n} %zu\\n", sizeof({n}));')
+        for f in st._fields_:
+            lines.append(f'  printf("{n}.{f[0]} %zu\\n", offsetof({n}, {f[0]}));')
+    lines.append("  return 0; }")
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    got = dict(l.split() for l in subprocess.run([str(exe)], capture_output=True, text=True,
+                                                   check=True).stdout.splitlines())
+    for st in structs:
+        n = st.__name__
+        assert int(got[n]) == ctypes.sizeof(st), n
+        for f in st._fields_:
+            assert int(got[f"{n}.{f[0]}"]) == getattr(st, f[0]).offset, (n, f[0])
 
 
 def test_calls_reject_null_context_without_gpu():
@@ -47,7 +66,11 @@ def test_calls_reject_null_context_without_gpu():
     assert lib.bem_assemble_nearfield(None, None, None, None, None, 0, None) == pk.BEM_EINVAL
     assert lib.bem_eval_entries(None, None, None, 0, None, None, None, None) == pk.BEM_EINVAL
     assert lib.bem_last_error(None) == b"no context"
+    assert lib.bem_plan_batched(None, None, 0, None, None, None, None, None) == pk.BEM_EINVAL
+    assert lib.bem_run_batched(None, None) == pk.BEM_EINVAL
+    assert lib.bem_plan_tiles(None) == 0
     lib.bem_destroy(None)
+    lib.bem_plan_destroy(None)
 
 
 def test_oracle_is_not_reachable_from_the_product_package():

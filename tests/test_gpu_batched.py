@@ -1,0 +1,213 @@
+"""GPU tests of the batched persistent form (bem_plan_batched / bem_run_batched).
+
+* Entries of every batch entry equal, bit for bit, those of the per-call
+  entry points at the same x-point chunk (the default), for near-field and
+  coupling lists of meshes of uneven size, plain and mixed precision,
+  Laplace and Helmholtz.
+* Graph replays: outputs are overwritten with NaN by eager work between
+  replays; every replay reproduces the eager result exactly.
+* Against the oracle: sampled blocks at 1e-12 relative (plain FP64).
+* The autotuner: a valid configuration, results within rounding of the
+  default plan's, and a second plan served from the cache file.
+* Host-visible errors (an out-of-range triangle id) are rejected at plan time.
+"""
+import json
+
+import numpy as np
+import pytest
+
+import oracle
+from bem_inputs import perturbed_sphere, sample_subset
+from oracle import htree
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def pk():
+    import paper_1510_07244_amd as pk
+    return pk
+
+
+@pytest.fixture(scope="module")
+def ctx(pk):
+    c = pk.Context(0)
+    yield c
+    c.close()
+
+
+def _lists(m, seed, n_near, n_coup):
+    cl = htree.cluster_tree(m.v, m.tri, 64)
+    near, far = htree.block_tree(cl, 2.0)
+    pick = [near[k] for k in sample_subset(np.arange(len(near)), n_near, seed=seed)]
+    pick += [b for b in near if b[0] == b[1]][:2]
+    nrows = [cl[t].idx for t, s in pick]
+    ncols = [cl[s].idx for t, s in pick]
+    fk = sample_subset(np.arange(len(far)), n_coup, seed=seed + 1)
+    crows = [sample_subset(cl[far[k][0]].idx, 17 + 7 * (k % 5), seed=k) for k in fk]
+    ccols = [sample_subset(cl[far[k][1]].idx, 9 + 11 * (k % 4), seed=k + 3) for k in fk]
+    return (nrows, ncols), (crows, ccols)
+
+
+@pytest.fixture(scope="module")
+def batch(pk):
+    """Four perturbed spheres of uneven size, one near-field and one coupling
+    list each (eight batch entries)."""
+    import torch
+    meshes, entries = [], []
+    for seed in (3, 11, 20, 41):
+        m = perturbed_sphere(seed, n_min=8, n_max=20)
+        mesh = pk.Mesh(torch.from_numpy(m.v), torch.from_numpy(m.tri))
+        (nr, nc), (cr, cc) = _lists(m, seed, 6, 5)
+        for coupling, (rows, cols) in ((0, (nr, nc)), (1, (cr, cc))):
+            blocks, total = pk.Blocks.from_lists(rows, cols)
+            entries.append(dict(m=m, mesh=mesh, blocks=blocks, total=total, coupling=coupling,
+                                rows=rows, cols=cols))
+        meshes.append(m)
+    return entries
+
+
+def _per_call(pk, ctx, op, e):
+    import torch
+    out = torch.full((e["total"],), float("nan"), dtype=pk.out_dtype(op), device="cuda")
+    f = ctx.assemble_coupling if e["coupling"] else ctx.assemble_nearfield
+    f(e["mesh"], op, e["blocks"], out)
+    ctx.check()
+    return out
+
+
+def _plan(pk, ctx, op, batch, **kw):
+    import torch
+    outs = [torch.full((e["total"],), float("nan"), dtype=pk.out_dtype(op), device="cuda")
+            for e in batch]
+    plan = pk.Plan(ctx, op, [(e["mesh"], e["blocks"], o, e["coupling"]) for e, o in zip(batch, outs)],
+                   **kw)
+    return plan, outs
+
+
+def _bits(t):
+    import torch
+    x = t.cpu()
+    if x.is_complex():
+        x = torch.view_as_real(x)
+    return x.numpy().view(np.uint8)
+
+
+def _kw(op):
+    return dict(kernel=op.kernel, layer=op.layer, kappa=op.kappa, rule=op.regular_rule,
+                q_reg=op.q_regular, q_sing=op.q_singular)
+
+
+@pytest.mark.parametrize("kernel,layer,precision,kappa", [
+    (0, 0, 0, 0.0), (0, 1, 0, 0.0), (0, 0, 1, 0.0), (0, 1, 1, 0.0), (1, 0, 0, 4.0), (1, 1, 1, 4.0)])
+def test_batched_equals_per_call_bitwise(pk, ctx, batch, kernel, layer, precision, kappa):
+    op = pk.make_op(kernel, layer, precision=precision, q_regular=4, q_singular=4, kappa=kappa,
+                    near_singular_ratio=0.5 if precision else 0.0)
+    ref = [_per_call(pk, ctx, op, e) for e in batch]
+    plan, outs = _plan(pk, ctx, op, batch)
+    assert plan.tiles > 0
+    plan.run()
+    ctx.check()
+    for e, r, o in zip(batch, ref, outs):
+        assert np.array_equal(_bits(o), _bits(r)), (e["m"].name, e["coupling"])
+    plan.close()
+
+
+def test_graph_replays_match_eager(pk, ctx, batch):
+    import torch
+    op = pk.make_op(pk.LAPLACE, pk.SLP, q_regular=4, q_singular=4)
+    ref = [_per_call(pk, ctx, op, e) for e in batch]
+    plan, outs = _plan(pk, ctx, op, batch)
+    for rep in range(4):
+        for o in outs:
+            o.fill_(float("nan"))  # eager work between replays
+        torch.cuda.synchronize()
+        plan.run()
+        ctx.check()
+        for r, o in zip(ref, outs):
+            assert np.array_equal(_bits(o), _bits(r)), rep
+    plan.close()
+
+
+def test_batched_against_oracle(pk, ctx, batch):
+    op = pk.make_op(pk.LAPLACE, pk.DLP, q_regular=4, q_singular=4)
+    plan, outs = _plan(pk, ctx, op, batch)
+    plan.run()
+    ctx.check()
+    for e, o in zip(batch[:4], outs[:4]):
+        res = o.cpu().numpy()
+        off = 0
+        for k, (r, c) in enumerate(zip(e["rows"], e["cols"])):
+            g = res[off:off + len(r) * len(c)].reshape(len(c), len(r)).T
+            off += len(r) * len(c)
+            if k % 3:
+                continue
+            ref = oracle.block(e["m"].v, e["m"].tri, r, c, **_kw(op)).real
+            assert np.abs(g - ref).max() <= 1e-12 * np.abs(ref).max()
+    plan.close()
+
+
+def test_autotune_and_cache(pk, ctx, batch, tmp_path):
+    import torch
+    op = pk.make_op(pk.LAPLACE, pk.SLP, q_regular=4, q_singular=4)
+    base, base_outs = _plan(pk, ctx, op, batch)
+    base.run()
+    ctx.check()
+    cache = str(tmp_path / "tune.jsonl")
+    plan, outs = _plan(pk, ctx, op, batch, autotune=True, cache=cache)
+    cfg = plan.config
+    assert cfg["tuned_ms"] > 0
+    assert 1 <= cfg["tile_rows"] <= 64 and 1 <= cfg["tile_cols"] <= 64
+    assert cfg["x_chunk"] in (4, 5, 7, 8, 9) and cfg["grid"] > 0
+    for o in outs:
+        o.fill_(float("nan"))
+    plan.run()
+    ctx.check()
+    for a, b in zip(base_outs, outs):
+        a, b = a.cpu().numpy(), b.cpu().numpy()
+        assert np.all(np.isfinite(b))
+        assert np.abs(a - b).max() <= 1e-13 * np.abs(a).max()
+    lines = [json.loads(l) for l in open(cache)]
+    assert len(lines) == 1 and lines[0]["x_chunk"] == cfg["x_chunk"]
+    again, outs2 = _plan(pk, ctx, op, batch, autotune=True, cache=cache)
+    c2 = again.config
+    assert c2["tuned_ms"] == 0.0  # served from the cache, nothing timed
+    assert [c2[k] for k in ("grid", "tile_rows", "tile_cols", "x_chunk")] == \
+        [cfg[k] for k in ("grid", "tile_rows", "tile_cols", "x_chunk")]
+    assert len(open(cache).readlines()) == 1
+    for p in (base, plan, again):
+        p.close()
+    torch.cuda.synchronize()
+
+
+def test_fixed_configuration_and_small_tiles(pk, ctx, batch):
+    # a ragged sub-tile shape and a small grid still give the per-call bits
+    op = pk.make_op(pk.LAPLACE, pk.SLP, q_regular=4, q_singular=4)
+    ref = [_per_call(pk, ctx, op, e) for e in batch]
+    plan, outs = _plan(pk, ctx, op, batch, tune=dict(grid=7, tile_rows=24, tile_cols=40))
+    assert plan.config["tile_rows"] == 24 and plan.config["grid"] == 7
+    plan.run()
+    ctx.check()
+    for r, o in zip(ref, outs):
+        assert np.array_equal(_bits(o), _bits(r))
+    plan.close()
+
+
+def test_plan_rejects_bad_ids_before_launch(pk, ctx):
+    import torch
+    m = perturbed_sphere(5, n_min=8, n_max=8)
+    mesh = pk.Mesh(torch.from_numpy(m.v), torch.from_numpy(m.tri))
+    rows = [np.arange(10, dtype=np.int32)]
+    cols = [np.array([0, 1, m.nt], dtype=np.int32)]  # m.nt is out of range
+    blocks, total = pk.Blocks.from_lists(rows, cols)
+    out = torch.zeros(total, dtype=torch.float64, device="cuda")
+    op = pk.make_op(pk.LAPLACE, pk.SLP)
+    with pytest.raises(pk.BemError) as ei:
+        pk.Plan(ctx, op, [(mesh, blocks, out, 0)])
+    assert ei.value.code == pk.BEM_EINVAL
+    # an empty batch is a valid plan that does nothing
+    empty = pk.Plan(ctx, op, [])
+    assert empty.tiles == 0
+    empty.run()
+    ctx.check()
+    empty.close()

@@ -1,0 +1,137 @@
+"""GPU tests of the mixed-precision form: regular pairs in FP32 with FP32
+accumulation, singular and near-singular pairs in FP64, FP32 / complex64
+output.  Bar: at most 1e-6 relative Frobenius error per block against the
+FP64 oracle at the plain orders.  Entries that the form must take in FP64
+(singular pairs; pairs closer than the near-singular ratio) must match the
+oracle to FP32 rounding (2^-23 relative plus a few ulps of summation)."""
+import numpy as np
+import pytest
+
+import oracle
+from bem_inputs import cube_surface, octahedron_sphere, sample_subset
+from oracle import htree
+
+pytestmark = pytest.mark.gpu
+BLOCK_TOL = 1e-6
+
+
+@pytest.fixture(scope="module")
+def pk():
+    import paper_1510_07244_amd as pk
+    return pk
+
+
+@pytest.fixture(scope="module")
+def ctx(pk):
+    c = pk.Context(0)
+    yield c
+    c.close()
+
+
+def _assemble(pk, ctx, m, op, rows, cols, coupling=False):
+    import torch
+    mesh = pk.Mesh(torch.from_numpy(m.v), torch.from_numpy(m.tri))
+    blocks, total = pk.Blocks.from_lists(rows, cols)
+    out = torch.full((total,), float("nan"), dtype=pk.out_dtype(op), device="cuda")
+    (ctx.assemble_coupling if coupling else ctx.assemble_nearfield)(mesh, op, blocks, out)
+    ctx.check()
+    res = out.cpu().numpy()
+    outs, o = [], 0
+    for r, c in zip(rows, cols):
+        outs.append(res[o:o + len(r) * len(c)].reshape(len(c), len(r)).T)
+        o += len(r) * len(c)
+    return outs
+
+
+def _kw(op):
+    return dict(kernel=op.kernel, layer=op.layer, kappa=op.kappa, rule=op.regular_rule,
+                q_reg=op.q_regular, q_sing=op.q_singular)
+
+
+def _boxes(m):
+    p = m.v[m.tri]
+    return p.min(axis=1), p.max(axis=1)
+
+
+def _near_singular(m, rows, cols, ratio):
+    lo, hi = _boxes(m)
+    gap = np.maximum(0, np.maximum(lo[cols][None] - hi[rows][:, None], lo[rows][:, None] - hi[cols][None]))
+    d2 = (gap ** 2).sum(-1)
+    di = ((hi - lo) ** 2).sum(-1)
+    return d2 < ratio ** 2 * np.maximum(di[rows][:, None], di[cols][None])
+
+
+@pytest.mark.parametrize("layer", [0, 1])
+def test_mixed_laplace_sphere8192_blocks(pk, ctx, layer):
+    m = octahedron_sphere(32)
+    op = pk.make_op(pk.LAPLACE, layer, precision=pk.MIXED, q_regular=4, q_singular=4,
+                    near_singular_ratio=0.5)
+    cl = htree.cluster_tree(m.v, m.tri, 64)
+    near, far = htree.block_tree(cl, 2.0)
+    pick = [near[k] for k in sample_subset(np.arange(len(near)), 16, seed=4)]
+    pick += [b for b in near if b[0] == b[1]][:3]
+    rows = [cl[t].idx for t, s in pick]
+    cols = [cl[s].idx for t, s in pick]
+    got = _assemble(pk, ctx, m, op, rows, cols)
+    for g, r, c in zip(got, rows, cols):
+        assert g.dtype == np.float32
+        ref = oracle.block(m.v, m.tri, r, c, **_kw(op)).real
+        err = np.linalg.norm(g - ref) / np.linalg.norm(ref)
+        assert err <= BLOCK_TOL, err
+        # singular and near-singular entries come from the FP64 path
+        sing = np.array([[oracle.shared_vertices(m.tri, i, j) > 0 for j in c] for i in r])
+        fp64 = sing | _near_singular(m, r, c, 0.5)
+        if fp64.any():
+            rel = np.abs(g[fp64] - ref[fp64]) / np.abs(ref[fp64])
+            assert rel.max() <= 2e-7, rel.max()
+
+
+def test_mixed_coupling_and_entries(pk, ctx):
+    import torch
+    m = octahedron_sphere(32)
+    op = pk.make_op(pk.LAPLACE, pk.DLP, precision=pk.MIXED, q_regular=4, q_singular=4)
+    cl = htree.cluster_tree(m.v, m.tri, 64)
+    _, far = htree.block_tree(cl, 2.0)
+    pick = sample_subset(np.arange(len(far)), 20, seed=8)
+    rows = [sample_subset(cl[far[k][0]].idx, 40, seed=k) for k in pick]
+    cols = [sample_subset(cl[far[k][1]].idx, 33, seed=k + 1) for k in pick]
+    got = _assemble(pk, ctx, m, op, rows, cols, coupling=True)
+    for g, r, c in zip(got, rows, cols):
+        ref = oracle.block(m.v, m.tri, r, c, **_kw(op)).real
+        assert np.linalg.norm(g - ref) <= BLOCK_TOL * np.linalg.norm(ref)
+    # entry lists in the mixed form: FP64 values stored as FP32
+    r = np.array([0, 5, 9, 100, 7000], dtype=np.int32)
+    c = np.array([0, 6, 2000, 101, 7001], dtype=np.int32)
+    mesh = pk.Mesh(torch.from_numpy(m.v), torch.from_numpy(m.tri))
+    out = torch.zeros(r.size, dtype=torch.float32, device="cuda")
+    ctx.eval_entries(mesh, op, torch.from_numpy(r).cuda(), torch.from_numpy(c).cuda(), out)
+    ctx.check()
+    ref = oracle.entries(m.v, m.tri, r, c, **_kw(op)).real
+    assert np.all(np.abs(out.cpu().numpy() - ref) <= 2e-7 * np.abs(ref) + 1e-30)
+
+
+@pytest.mark.parametrize("layer,kappa", [(0, 8.0), (1, 8.0), (1, 2.0)])
+def test_mixed_helmholtz_blocks(pk, ctx, layer, kappa):
+    m = octahedron_sphere(16)
+    op = pk.make_op(pk.HELMHOLTZ, layer, precision=pk.MIXED, q_regular=5, q_singular=5,
+                    kappa=kappa, near_singular_ratio=0.5)
+    cl = htree.cluster_tree(m.v, m.tri, 64)
+    near, _ = htree.block_tree(cl, 2.0)
+    pick = [near[k] for k in sample_subset(np.arange(len(near)), 8, seed=2)] + [near[0]]
+    rows = [cl[t].idx for t, s in pick]
+    cols = [cl[s].idx for t, s in pick]
+    got = _assemble(pk, ctx, m, op, rows, cols)
+    for g, r, c in zip(got, rows, cols):
+        assert g.dtype == np.complex64
+        ref = oracle.block(m.v, m.tri, r, c, **_kw(op))
+        assert np.linalg.norm(g - ref) <= BLOCK_TOL * np.linalg.norm(ref)
+
+
+def test_mixed_cube_dlp_without_near_singular_path(pk, ctx):
+    # ratio 0: every disjoint pair in FP32, still within the block bar
+    m = cube_surface(4)
+    op = pk.make_op(pk.LAPLACE, pk.DLP, precision=pk.MIXED, q_regular=4, q_singular=4)
+    idx = np.arange(m.nt, dtype=np.int32)
+    got = _assemble(pk, ctx, m, op, [idx[:200]], [idx[150:384]])[0]
+    ref = oracle.block(m.v, m.tri, idx[:200], idx[150:384], **_kw(op)).real
+    assert np.linalg.norm(got - ref) <= BLOCK_TOL * np.linalg.norm(ref)
