@@ -231,6 +231,85 @@ int64_t bem_plan_tiles(const bem_plan *plan);
 void bem_plan_destroy(bem_plan *plan);
 
 /* ---------------------------------------------------------------------
+ * Learned order selection.
+ *
+ * The regular near-field pairs of Sec. 2.2 all take the same Duffy/Gauss
+ * order, sized for the closest pairs; farther pairs reach the same accuracy
+ * with fewer points (the paper's Sec. 4 varies the order by hand).  A small
+ * network -- 8 inputs, three hidden layers of 64 ReLU units, n_out outputs
+ * -- trained on pairs this library generates predicts, per pair, the log10
+ * error of the rule at orders 1 .. 6 against order 8, and the assembly then
+ * takes per entry the smallest order predicted to stay within a tolerance;
+ * the plain order is the fallback.
+ *
+ * Parameter vector (FP32, bem_mlp_params floats): [mu(8), sigma(8),
+ * W1(64 x 8), b1(64), W2(64 x 64), b2, W3(64 x 64), b3, W4(n_out x 64),
+ * b4(n_out)], every W row-major; the first layer sees (x - mu) / sigma.
+ * Inputs of a vertex-disjoint pair (tau_i, tau_j), with centroids c, areas
+ * |tau|, longest edges d, unit normals n and D = max(d_i, d_j),
+ * r = |c_i - c_j|:
+ *   x0 = ln(r / D), x1 = sqrt(3)/4 d_i^2/|tau_i|, x2 = the same for tau_j,
+ *   x3 = min(|tau_i|, |tau_j|) / max(..), x4 = kappa D, x5 = <n_i, n_j>,
+ *   x6 = 0 (single layer) or 1 (double layer), x7 = |<c_i - c_j, n_j>| / r.
+ * Targets for q = 1 .. 6: e_q = log10(max(|G_q - G_8| / max(|G_8|,
+ * 1e-3 s), 1e-16)) with s = |tau_i| |tau_j| / (4 pi r) and G_q the entry by
+ * the Duffy/Gauss rule of order q.
+ * --------------------------------------------------------------------- */
+
+/* Floats in the parameter vector for n_out outputs (1 .. 16); BEM_EINVAL
+ * otherwise. */
+int bem_mlp_params(int32_t n_out);
+
+/* y[n][n_out] = network(x[n][8]).  fp16 = 0: FP32 on the vector units;
+ * fp16 = 1: weights, standardised inputs and activations rounded to FP16,
+ * products on the matrix cores with FP32 accumulation.  All device. */
+int bem_mlp_forward(bem_ctx *ctx, int32_t n_out, int32_t fp16, const float *params, int64_t n,
+                    const float *x, float *y, void *stream);
+
+/* Gradient (FP32) of the mean squared error L = mean over the n samples and
+ * n_out outputs of (y - t)^2 with respect to the parameters (zero for mu and
+ * sigma), by reverse-mode differentiation, summed over samples in a fixed
+ * order (deterministic).  x[n][8], t[n][n_out], grad[bem_mlp_params], loss
+ * (one float, may be NULL): device.  Uses context scratch (grown as
+ * needed). */
+int bem_mlp_grad(bem_ctx *ctx, int32_t n_out, const float *params, int64_t n, const float *x,
+                 const float *t, float *grad, float *loss, void *stream);
+
+/* One Adam step (Kingma and Ba): m = b1 m + (1 - b1) g, v = b2 v +
+ * (1 - b2) g^2, p -= lr (m / (1 - b1^step)) / (sqrt(v / (1 - b2^step)) + eps).
+ * params, grad, m, v: device float[np]; step counts from 1. */
+int bem_mlp_adam(bem_ctx *ctx, int64_t np, float *params, const float *grad, float *m, float *v,
+                 int32_t step, float lr, float beta1, float beta2, float eps, void *stream);
+
+/* Training samples: inputs x[n][8] and targets t[n][6] of the pairs
+ * (rows[k], cols[k]) for the operator's kernel and layer (plain FP64
+ * rules; q_singular and the regular rule of op are not used).  Pairs with a
+ * common vertex are invalid: flag raised (BEM_EINVAL at bem_check), their
+ * row set to NaN. */
+int bem_selector_samples(bem_ctx *ctx, const bem_mesh *mesh, const bem_op *op, int64_t n,
+                         const int32_t *rows, const int32_t *cols, float *x, float *t,
+                         void *stream);
+
+/* Orders of the entries of near-field blocks (layout of the blocks' output,
+ * one int8 per entry): 0 for pairs with a common vertex, else the smallest
+ * q in [q_min, q_regular - 1] such that the FP16 network (n_out = 6,
+ * params) predicts e_q' + margin <= log10(tol) at every q' in
+ * [q, q_regular - 1]; q_regular when q_regular - 1 fails.  The comparison is
+ * made in FP32.  op: Duffy rule, q_regular in [2, 6]. */
+int bem_select_orders(bem_ctx *ctx, const bem_mesh *mesh, const bem_op *op,
+                      const bem_blocks *blocks, const float *params, double tol, double margin,
+                      int32_t q_min, int8_t *orders, int64_t orders_len, void *stream);
+
+/* Near-field blocks like bem_assemble_nearfield (plain FP64, Duffy rule,
+ * q_regular in [2, 6]), each regular entry with the order orders[entry]
+ * (device int8, the output's layout) in [2, q_regular]; an order outside
+ * raises the flag and leaves the entry unwritten.  With q_regular
+ * everywhere the result equals bem_assemble_nearfield's bit for bit. */
+int bem_assemble_nearfield_learned(bem_ctx *ctx, const bem_mesh *mesh, const bem_op *op,
+                                   const bem_blocks *blocks, const int8_t *orders, void *out,
+                                   int64_t out_len, void *stream);
+
+/* ---------------------------------------------------------------------
  * Cluster bases of the Green cross approximation (Sec. 2.3-2.4).
  * --------------------------------------------------------------------- */
 

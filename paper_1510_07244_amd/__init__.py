@@ -407,3 +407,73 @@ class Plan:
             self.close()
         except Exception:
             pass
+
+
+# ------------------------------------------------------------ learned form
+def _setup_learned_api():
+    P, i32, i64, f32, f64 = (ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_float,
+                             ctypes.c_double)
+    M, O, B = ctypes.POINTER(bem_mesh), ctypes.POINTER(bem_op), ctypes.POINTER(bem_blocks)
+    _lib.bem_mlp_params.argtypes = [i32]
+    _lib.bem_mlp_forward.argtypes = [P, i32, i32, P, i64, P, P, P]
+    _lib.bem_mlp_grad.argtypes = [P, i32, P, i64, P, P, P, P, P]
+    _lib.bem_mlp_adam.argtypes = [P, i64, P, P, P, P, i32, f32, f32, f32, f32, P]
+    _lib.bem_selector_samples.argtypes = [P, M, O, i64, P, P, P, P, P]
+    _lib.bem_select_orders.argtypes = [P, M, O, B, P, f64, f64, i32, P, i64, P]
+    _lib.bem_assemble_nearfield_learned.argtypes = [P, M, O, B, P, P, i64, P]
+
+
+_setup_learned_api()
+SEL_OUT = 6  # selector outputs: predicted log10 error at orders 1 .. 6
+
+
+def mlp_params(n_out):
+    n = _lib.bem_mlp_params(int(n_out))
+    if n < 0:
+        raise BemError(n, "n_out must be in [1, 16]")
+    return n
+
+
+def _context_mlp_forward(self, n_out, params, x, y, fp16=False, stream=None):
+    self._rc(_lib.bem_mlp_forward(self.h, int(n_out), int(bool(fp16)), _ptr(params),
+                                  x.shape[0], _ptr(x), _ptr(y), _stream(stream)))
+
+
+def _context_mlp_grad(self, n_out, params, x, t, grad, loss=None, stream=None):
+    self._rc(_lib.bem_mlp_grad(self.h, int(n_out), _ptr(params), x.shape[0], _ptr(x), _ptr(t),
+                               _ptr(grad), _ptr(loss), _stream(stream)))
+
+
+def _context_mlp_adam(self, params, grad, m, v, step, lr, beta1=0.9, beta2=0.999, eps=1e-8,
+                      stream=None):
+    self._rc(_lib.bem_mlp_adam(self.h, params.numel(), _ptr(params), _ptr(grad), _ptr(m), _ptr(v),
+                               int(step), float(lr), float(beta1), float(beta2), float(eps),
+                               _stream(stream)))
+
+
+def _context_selector_samples(self, mesh, op, rows, cols, x, t, stream=None):
+    self._rc(_lib.bem_selector_samples(self.h, ctypes.byref(mesh.c), ctypes.byref(op),
+                                       rows.numel(), _ptr(rows), _ptr(cols), _ptr(x), _ptr(t),
+                                       _stream(stream)))
+
+
+def _context_select_orders(self, mesh, op, blocks, params, orders, tol, margin, q_min=2,
+                           stream=None):
+    self._rc(_lib.bem_select_orders(self.h, ctypes.byref(mesh.c), ctypes.byref(op),
+                                    ctypes.byref(blocks.c), _ptr(params), float(tol),
+                                    float(margin), int(q_min), _ptr(orders), orders.numel(),
+                                    _stream(stream)))
+
+
+def _context_assemble_nearfield_learned(self, mesh, op, blocks, orders, out, stream=None):
+    self._rc(_lib.bem_assemble_nearfield_learned(self.h, ctypes.byref(mesh.c), ctypes.byref(op),
+                                                 ctypes.byref(blocks.c), _ptr(orders), _ptr(out),
+                                                 out.numel(), _stream(stream)))
+
+
+Context.mlp_forward = _context_mlp_forward
+Context.mlp_grad = _context_mlp_grad
+Context.mlp_adam = _context_mlp_adam
+Context.selector_samples = _context_selector_samples
+Context.select_orders = _context_select_orders
+Context.assemble_nearfield_learned = _context_assemble_nearfield_learned

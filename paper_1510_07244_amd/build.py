@@ -14,8 +14,9 @@ BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libbem.so")
 ARCH = os.environ.get("BEM_OFFLOAD_ARCH", "gfx950")
 
-SOURCES = ["bem_blocks.hip", "bem_kernels.hip", "bem_bases.hip", "bem_quadrature.cpp",
-           "bem_capi.cpp", "bem_plan.cpp", "bem_h2_tree.cpp", "bem_h2_host.cpp"]
+SOURCES = ["bem_blocks.hip", "bem_kernels.hip", "bem_bases.hip", "bem_mlp.hip",
+           "bem_quadrature.cpp", "bem_capi.cpp", "bem_plan.cpp", "bem_learned.cpp",
+           "bem_h2_tree.cpp", "bem_h2_host.cpp"]
 OPENMP = {"bem_h2_host.cpp"}
 OMP_LIB = "/opt/rocm/llvm/lib"
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-function",

@@ -15,6 +15,7 @@ using namespace dev;
 constexpr double kPad = 1.0e4;       // coordinate of column padding points (weight 0)
 constexpr uint16_t kNoPair = 0xffff; // empty slot of the sorted singular list
 constexpr int kNearSingular = 0;     // list class of near-singular regular pairs (mixed)
+constexpr int kSortPad = 384;        // room for the padding of up to 6 groups
 
 // LDS layout of one sub-tile (up to TR rows x TC columns; triangle rule of nq
 // points padded to nqp with zero weights):
@@ -28,14 +29,17 @@ constexpr int kNearSingular = 0;     // list class of near-singular regular pair
 //   cn[3][TC]      column normals
 //   mixed only:    cg[3][TC] = 2 (v0_j - c); rb[6][TR], cb[6][TC] boxes
 //   ints           rid[TR], rv[3][TR], cid[TC], cv[3][TC], count, bad,
-//                  per-class counts[4] and cursors[4]
-//   list[TR*TC]    uint16 codes (row | col << 6 | class << 12) of the pairs
-//                  left to the FP64 pass (singular; near-singular if mixed)
-//   sorted[TR*TC + 256]  the same codes grouped by class, each class padded
-//                  to a multiple of 64 with kNoPair
+//                  rcount, pad, per-group counts[16] and cursors[16]
+//                  (classes at 0 .. 3, orders q at 8 + q)
+//   list[TR*TC]    uint16 codes (row | col << 6 | group << 12) of the pairs
+//                  left to the FP64 pass (singular; near-singular if mixed),
+//                  from the front; with per-entry orders, the regular pairs
+//                  (group = order) from the back
+//   sorted[TR*TC + kSortPad]  codes grouped (by class or by order), each
+//                  group padded to a multiple of 64 with kNoPair
 struct Lds {
   double *ys, *rg, *rule, *cn, *cg, *rb, *cb;
-  int *rid, *rv, *cid, *cv, *count, *bad, *ccount, *cursor;
+  int *rid, *rv, *cid, *cv, *count, *bad, *rcount, *ccount, *cursor;
   uint16_t *list, *sorted;
 };
 
@@ -58,9 +62,10 @@ __device__ __forceinline__ Lds carve(double *base, int nqp, int TR, int TC) {
   l.cv = l.cid + TC;
   l.count = l.cv + 3 * TC;
   l.bad = l.count + 1;
-  l.ccount = l.bad + 1;
-  l.cursor = l.ccount + 4;
-  l.list = reinterpret_cast<uint16_t *>(l.cursor + 4);
+  l.rcount = l.bad + 1;
+  l.ccount = l.rcount + 2;
+  l.cursor = l.ccount + 16;
+  l.list = reinterpret_cast<uint16_t *>(l.cursor + 16);
   l.sorted = l.list + TR * TC;
   return l;
 }

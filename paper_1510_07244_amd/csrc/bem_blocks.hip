@@ -63,26 +63,21 @@ __device__ __forceinline__ void load_rule(const BlockArgs &a, const Lds &l) {
   }
 }
 
-// One sub-tile: rows r0 .. r0 + TR, columns c0 .. c0 + TC of the block.
-// Starts and ends with a workgroup barrier; returns early (uniformly) if a
-// triangle id is invalid.
-template <int KERNEL, int LAYER, int XC, bool MIXED>
-__device__ void subtile(const BlockArgs &a, const Lds &l, const BlockHdr &h, int64_t r0,
-                        int64_t c0, int coupling) {
-  const int tid = threadIdx.x;
-  const int nqp = a.nq_pad, nq = a.nq, TR = a.tr, TC = a.tc;
-  const int64_t nr = h.nr, off = h.off, L = a.ldg;
+// Phase A of a sub-tile (rows r0 .. r0 + tr, columns c0 .. c0 + tc): reset
+// the counters, then triangle ids (validated), vertex ids, row geometry in
+// block-local coordinates and column normals (and boxes in the mixed form).
+// Starts with a barrier (the previous sub-tile is done with the LDS) and ends
+// with one; false (uniformly, flag raised) if a triangle id is invalid.
+template <bool MIXED>
+__device__ bool stage_tile(const BlockArgs &a, const Lds &l, const BlockHdr &h, int64_t r0,
+                           int64_t c0, int tr, int tc) {
+  const int tid = threadIdx.x, TR = a.tr, TC = a.tc;
+  const int64_t L = a.ldg;
   const double cx = h.cx, cy = h.cy, cz = h.cz;
-  const double kq = 0.25 * a.kappa;
-  const double scale = (LAYER == BEM_DLP ? 0.5 : 1.0) * kInv4Pi;
-  const int wave = tid / kWave, lane = tid & (kWave - 1);
-  const double ratio = a.near_ratio;
-  const int tr = (int)min((int64_t)TR, h.nr - r0), tc = (int)min((int64_t)TC, h.nc - c0);
-  __syncthreads();  // the previous sub-tile is done with the LDS
-  if (tid < 4) l.ccount[tid] = 0, l.cursor[tid] = 0;
-  if (tid == 0) *l.count = 0, *l.bad = 0;
   __syncthreads();
-  // phase A: triangle ids (validated), vertex ids, row geometry, normals
+  if (tid < 16) l.ccount[tid] = 0, l.cursor[tid] = 0;
+  if (tid == 0) *l.count = 0, *l.bad = 0, *l.rcount = 0;
+  __syncthreads();
   for (int k = tid; k < tr + tc; k += kThreads) {
     const bool isrow = k < tr;
     const int id = isrow ? a.row_idx[h.rp0 + r0 + k] : a.col_idx[h.cp0 + c0 + (k - tr)];
@@ -118,10 +113,20 @@ __device__ void subtile(const BlockArgs &a, const Lds &l, const BlockHdr &h, int
   __syncthreads();
   if (*l.bad) {
     if (tid == 0) atomicOr(a.flags, FLAG_EINVAL);
-    return;
+    return false;
   }
-  // phase B: column quadrature points
-  for (int k = tid; k < tc * nqp; k += kThreads) {
+  return true;
+}
+
+// Phase B: the column quadrature points of the rule in l.rule (nq points
+// padded to nqp with zero weights), then a barrier.
+template <bool MIXED>
+__device__ void stage_columns(const BlockArgs &a, const Lds &l, const BlockHdr &h, int tc, int nq,
+                              int nqp) {
+  const int TC = a.tc;
+  const int64_t L = a.ldg;
+  const double cx = h.cx, cy = h.cy, cz = h.cz;
+  for (int k = threadIdx.x; k < tc * nqp; k += kThreads) {
     const int cl = k % tc, q = k / tc;
     const int id = l.cid[cl];
     const bool real = q < nq;
@@ -159,6 +164,75 @@ __device__ void subtile(const BlockArgs &a, const Lds &l, const BlockHdr &h, int
     }
   }
   __syncthreads();
+}
+
+// Phases D and E: the listed pairs (front of l.list, *l.count of them),
+// grouped by class (identical, edge, vertex, near-singular), each group
+// padded to a multiple of 64 so that every wave-sized chunk holds one class,
+// then one pair per lane in FP64.  Expects a barrier after the listing.
+template <int KERNEL, int LAYER, bool MIXED>
+__device__ void singular_pass(const BlockArgs &a, const Lds &l, const BlockHdr &h, int64_t r0,
+                              int64_t c0) {
+  const int tid = threadIdx.x, wave = tid / kWave, lane = tid & (kWave - 1);
+  const int ns = *l.count;
+  if (ns == 0) return;
+  const int n3 = (l.ccount[3] + 63) & ~63, n2 = (l.ccount[2] + 63) & ~63,
+            n1 = (l.ccount[1] + 63) & ~63, n0 = (l.ccount[0] + 63) & ~63;
+  const int seg[4] = {n3 + n2 + n1, n3 + n2, n3, 0};  // start of the group of class c
+  const int total = n3 + n2 + n1 + n0;
+  for (int k = tid; k < total; k += kThreads) l.sorted[k] = kNoPair;
+  __syncthreads();
+  for (int k = tid; k < ns; k += kThreads) {
+    const uint16_t code = l.list[k];
+    const int cls = code >> 12;
+    l.sorted[seg[cls] + atomicAdd(&l.cursor[cls], 1)] = code;
+  }
+  __syncthreads();
+  for (int chunk = wave; chunk * kWave < total; chunk += kThreads / kWave) {
+    const int pos = chunk * kWave;
+    const int cls = pos < seg[2] ? CLS_IDENTICAL
+                    : pos < seg[1] ? CLS_EDGE
+                    : pos < seg[0] ? CLS_VERTEX : kNearSingular;
+    const uint16_t code = l.sorted[pos + lane];
+    const bool active = code != kNoPair;
+    const int rl = code & 63, cl = (code >> 6) & 63;
+    const int64_t dst = h.off + (r0 + rl) + h.nr * (c0 + cl);
+    if (cls == kNearSingular) {
+      if (active) {
+        const Acc<KERNEL> v = regular_pair_fp64<KERNEL, LAYER>(a.geo, a.ldg, a.rule, a.nq,
+                                                               a.kappa, l.rid[rl], l.cid[cl]);
+        store_as<KERNEL, MIXED>(a.out, dst, v, a.flags);
+      }
+      continue;
+    }
+    PairGeo g;
+    bool have = false;
+    if (active) have = pair_geometry(a.v, a.tri, a.nv, a.geo, a.ldg, l.rid[rl], l.cid[cl], cls,
+                                     a.flags, &g);
+    if (!have) {  // idle lane: harmless finite geometry, result discarded
+      for (int c = 0; c < 3; ++c)
+        g.E1i[c] = c == 0, g.E2i[c] = c == 1, g.E1j[c] = -(c == 2), g.E2j[c] = 0, g.n[c] = 0;
+      g.scale = 0.0;
+    }
+    const Acc<KERNEL> v = ss_pair_lane<KERNEL, LAYER>(g, a.ss, cls, a.kappa);
+    if (have) store_as<KERNEL, MIXED>(a.out, dst, v, a.flags);
+  }
+}
+
+// One sub-tile: rows r0 .. r0 + TR, columns c0 .. c0 + TC of the block.
+// Returns early (uniformly) if a triangle id is invalid.
+template <int KERNEL, int LAYER, int XC, bool MIXED>
+__device__ void subtile(const BlockArgs &a, const Lds &l, const BlockHdr &h, int64_t r0,
+                        int64_t c0, int coupling) {
+  const int tid = threadIdx.x;
+  const int nqp = a.nq_pad, TR = a.tr, TC = a.tc;
+  const int64_t nr = h.nr, off = h.off;
+  const double kq = 0.25 * a.kappa;
+  const double scale = (LAYER == BEM_DLP ? 0.5 : 1.0) * kInv4Pi;
+  const double ratio = a.near_ratio;
+  const int tr = (int)min((int64_t)TR, h.nr - r0), tc = (int)min((int64_t)TC, h.nc - c0);
+  if (!stage_tile<MIXED>(a, l, h, r0, c0, tr, tc)) return;
+  stage_columns<MIXED>(a, l, h, tc, a.nq, nqp);
   // phase C: regular entries, one per lane; the rest is listed
   for (int e = tid; e < tr * tc; e += kThreads) {
     const int rl = e % tr, cl = e / tr;
@@ -199,53 +273,117 @@ __device__ void subtile(const BlockArgs &a, const Lds &l, const BlockHdr &h, int
     store_as<KERNEL, MIXED>(a.out, off + (r0 + rl) + nr * (c0 + cl), v, a.flags);
   }
   __syncthreads();
-  const int ns = *l.count;
-  if (ns == 0) return;
-  // phase D: group the listed pairs by class (identical, edge, vertex,
-  // near-singular), each group padded to a multiple of 64 so that every
-  // wave-sized chunk holds one class
-  const int n3 = (l.ccount[3] + 63) & ~63, n2 = (l.ccount[2] + 63) & ~63,
-            n1 = (l.ccount[1] + 63) & ~63, n0 = (l.ccount[0] + 63) & ~63;
-  const int seg[4] = {n3 + n2 + n1, n3 + n2, n3, 0};  // start of the group of class c
-  const int total = n3 + n2 + n1 + n0;
-  for (int k = tid; k < total; k += kThreads) l.sorted[k] = kNoPair;
-  __syncthreads();
-  for (int k = tid; k < ns; k += kThreads) {
-    const uint16_t code = l.list[k];
-    const int cls = code >> 12;
-    l.sorted[seg[cls] + atomicAdd(&l.cursor[cls], 1)] = code;
+  singular_pass<KERNEL, LAYER, MIXED>(a, l, h, r0, c0);
+}
+
+// x-points per register chunk of the learned kernel for order q (q = 2 .. 6);
+// equal to rule_chunk(q * q), so that an order map holding the plain order
+// everywhere reproduces the plain kernel bit for bit.
+__host__ __device__ constexpr int learned_xc(int kernel, int q) {
+  return q == 2 ? 4 : q == 3 ? 9 : q == 4 ? (kernel == BEM_LAPLACE ? 8 : 4)
+         : q == 5 ? 5 : (kernel == BEM_LAPLACE ? 9 : 4);
+}
+
+template <int KERNEL, int LAYER>
+__device__ __forceinline__ Acc<KERNEL> regular_entry_q(int q, const Lds &l, int TR, int TC,
+                                                       int nqp, int rl, int cl, double kq) {
+  switch (q) {
+    case 2: return regular_entry<KERNEL, LAYER, learned_xc(KERNEL, 2)>(l, TR, TC, nqp, rl, cl, kq);
+    case 3: return regular_entry<KERNEL, LAYER, learned_xc(KERNEL, 3)>(l, TR, TC, nqp, rl, cl, kq);
+    case 4: return regular_entry<KERNEL, LAYER, learned_xc(KERNEL, 4)>(l, TR, TC, nqp, rl, cl, kq);
+    case 5: return regular_entry<KERNEL, LAYER, learned_xc(KERNEL, 5)>(l, TR, TC, nqp, rl, cl, kq);
+    default: return regular_entry<KERNEL, LAYER, learned_xc(KERNEL, 6)>(l, TR, TC, nqp, rl, cl, kq);
   }
-  __syncthreads();
-  // phase E: one pair per lane in FP64, one class per wave-sized chunk
-  for (int chunk = wave; chunk * kWave < total; chunk += kThreads / kWave) {
-    const int pos = chunk * kWave;
-    const int cls = pos < seg[2] ? CLS_IDENTICAL
-                    : pos < seg[1] ? CLS_EDGE
-                    : pos < seg[0] ? CLS_VERTEX : kNearSingular;
-    const uint16_t code = l.sorted[pos + lane];
-    const bool active = code != kNoPair;
-    const int rl = code & 63, cl = (code >> 6) & 63;
-    const int64_t dst = off + (r0 + rl) + nr * (c0 + cl);
-    if (cls == kNearSingular) {
-      if (active) {
-        const Acc<KERNEL> v = regular_pair_fp64<KERNEL, LAYER>(a.geo, a.ldg, a.rule, nq, a.kappa,
-                                                               l.rid[rl], l.cid[cl]);
-        store_as<KERNEL, MIXED>(a.out, dst, v, a.flags);
-      }
+}
+
+// Sub-tile of the learned form (plain FP64): every regular entry takes the
+// Duffy/Gauss order of the order map (2 .. q_max); the entries are grouped by
+// order (each group padded to a multiple of 64, one order per wave-sized
+// chunk) and each order's column points are staged in turn.  Singular pairs
+// as in the plain kernel.
+template <int KERNEL, int LAYER>
+__device__ void subtile_learned(const BlockArgs &a, const OrderRules &o, const Lds &l,
+                                const BlockHdr &h, int64_t r0, int64_t c0) {
+  const int tid = threadIdx.x, wave = tid / kWave, lane = tid & (kWave - 1);
+  const int TR = a.tr, TC = a.tc;
+  const int64_t nr = h.nr, off = h.off;
+  const double kq = 0.25 * a.kappa;
+  const double scale = (LAYER == BEM_DLP ? 0.5 : 1.0) * kInv4Pi;
+  const int tr = (int)min((int64_t)TR, h.nr - r0), tc = (int)min((int64_t)TC, h.nc - c0);
+  const int cap = TR * TC;
+  if (!stage_tile<false>(a, l, h, r0, c0, tr, tc)) return;
+  // classify: singular pairs to the front of the list, regular ones (with
+  // their order) to the back
+  for (int e = tid; e < tr * tc; e += kThreads) {
+    const int rl = e % tr, cl = e / tr;
+    const int cls = shared_vertex_count(l.rv[rl], l.rv[TR + rl], l.rv[2 * TR + rl], l.cv[cl],
+                                        l.cv[TC + cl], l.cv[2 * TC + cl]);
+    if (cls) {
+      l.list[atomicAdd(l.count, 1)] = (uint16_t)(rl | (cl << 6) | (cls << 12));
+      atomicAdd(&l.ccount[cls], 1);
       continue;
     }
-    PairGeo g;
-    bool have = false;
-    if (active) have = pair_geometry(a.v, a.tri, a.nv, a.geo, a.ldg, l.rid[rl], l.cid[cl], cls,
-                                     a.flags, &g);
-    if (!have) {  // idle lane: harmless finite geometry, result discarded
-      for (int c = 0; c < 3; ++c)
-        g.E1i[c] = c == 0, g.E2i[c] = c == 1, g.E1j[c] = -(c == 2), g.E2j[c] = 0, g.n[c] = 0;
-      g.scale = 0.0;
+    const int q = o.orders[off + (r0 + rl) + nr * (c0 + cl)];
+    if (q < 2 || q > o.q_max) {
+      atomicOr(a.flags, FLAG_EINVAL);
+      continue;
     }
-    const Acc<KERNEL> v = ss_pair_lane<KERNEL, LAYER>(g, a.ss, cls, a.kappa);
-    if (have) store_as<KERNEL, MIXED>(a.out, dst, v, a.flags);
+    l.list[cap - 1 - atomicAdd(l.rcount, 1)] = (uint16_t)(rl | (cl << 6) | (q << 12));
+    atomicAdd(&l.ccount[8 + q], 1);
   }
+  __syncthreads();
+  const int nreg = *l.rcount;
+  int seg[7];
+  int total = 0;
+  for (int q = o.q_max; q >= 2; --q) {
+    seg[q] = total;
+    total += (l.ccount[8 + q] + 63) & ~63;
+  }
+  for (int k = tid; k < total; k += kThreads) l.sorted[k] = kNoPair;
+  __syncthreads();
+  for (int k = tid; k < nreg; k += kThreads) {
+    const uint16_t code = l.list[cap - 1 - k];
+    const int q = code >> 12;
+    l.sorted[seg[q] + atomicAdd(&l.cursor[8 + q], 1)] = code;
+  }
+  __syncthreads();
+  for (int q = o.q_max; q >= 2; --q) {
+    const int n = l.ccount[8 + q];
+    if (n == 0) continue;
+    const int xc = learned_xc(KERNEL, q);
+    const int nq = o.nq[q], nqp = (nq + xc - 1) / xc * xc;
+    for (int k = tid; k < nqp; k += kThreads) {
+      const bool real = k < nq;
+      l.rule[k] = real ? o.rule[q][k] : 0.0;
+      l.rule[nqp + k] = real ? o.rule[q][nq + k] : 0.0;
+      l.rule[2 * nqp + k] = real ? o.rule[q][2 * nq + k] : 0.0;
+    }
+    __syncthreads();
+    stage_columns<false>(a, l, h, tc, nq, nqp);
+    const int span = (n + 63) & ~63;
+    for (int chunk = wave; chunk * kWave < span; chunk += kThreads / kWave) {
+      const uint16_t code = l.sorted[seg[q] + chunk * kWave + lane];
+      if (code == kNoPair) continue;
+      const int rl = code & 63, cl = (code >> 6) & 63;
+      Acc<KERNEL> v = regular_entry_q<KERNEL, LAYER>(q, l, TR, TC, nqp, rl, cl, kq);
+      v.re *= scale;
+      if constexpr (KERNEL == BEM_HELMHOLTZ) v.im *= scale;
+      store_as<KERNEL, false>(a.out, off + (r0 + rl) + nr * (c0 + cl), v, a.flags);
+    }
+    __syncthreads();  // before the next order's points replace these
+  }
+  singular_pass<KERNEL, LAYER, false>(a, l, h, r0, c0);
+}
+
+template <int KERNEL, int LAYER>
+__global__ __launch_bounds__(kThreads, 2) void k_blocks_learned(const BlockArgs a,
+                                                                const OrderRules o) {
+  extern __shared__ double lds_raw[];
+  BlockHdr h;
+  if (!block_header(a, blockIdx.x, &h) || h.nr == 0 || h.nc == 0) return;
+  const Lds l = carve<false>(lds_raw, a.nq_pad, a.tr, a.tc);
+  for (int64_t r0 = 0; r0 < h.nr; r0 += a.tr)
+    for (int64_t c0 = 0; c0 < h.nc; c0 += a.tc) subtile_learned<KERNEL, LAYER>(a, o, l, h, r0, c0);
 }
 
 template <int KERNEL, int LAYER, int XC, bool MIXED>
@@ -351,8 +489,8 @@ size_t block_lds_bytes(int nq_pad, int tr, int tc, bool mixed) {
   size_t dbl = (size_t)blk::ypoint_doubles(mixed) * nq_pad * tc + 10 * (size_t)tr +
                3 * (size_t)nq_pad + 3 * (size_t)tc;
   if (mixed) dbl += 3 * (size_t)tc + 6 * (size_t)tr + 6 * (size_t)tc;
-  const size_t ints = (size_t)4 * tr + 4 * (size_t)tc + 10;
-  return dbl * 8 + ints * 4 + (size_t)2 * (2 * (size_t)tr * tc + 256);
+  const size_t ints = (size_t)4 * tr + 4 * (size_t)tc + 36;
+  return dbl * 8 + ints * 4 + (size_t)2 * (2 * (size_t)tr * tc + blk::kSortPad);
 }
 
 bool block_tile_shape(int nq_pad, bool mixed, size_t lds_budget, int *tr, int *tc,
@@ -378,6 +516,22 @@ hipError_t launch_blocks(int kernel, int layer, bool coupling, bool mixed, const
                             : launch_kl<BEM_LAPLACE, BEM_DLP>(coupling, mixed, a, lds, s);
   return layer == BEM_SLP ? launch_kl<BEM_HELMHOLTZ, BEM_SLP>(coupling, mixed, a, lds, s)
                           : launch_kl<BEM_HELMHOLTZ, BEM_DLP>(coupling, mixed, a, lds, s);
+}
+
+int learned_chunk(int q, int kernel) { return learned_xc(kernel, q); }
+
+hipError_t launch_blocks_learned(int kernel, int layer, const BlockArgs &a, const OrderRules &o,
+                                 size_t lds, hipStream_t s) {
+  if (a.nblocks == 0) return hipSuccess;
+  const dim3 grid(a.nblocks), block(kThreads);
+  if (kernel == BEM_LAPLACE) {
+    if (layer == BEM_SLP) hipLaunchKernelGGL((k_blocks_learned<BEM_LAPLACE, BEM_SLP>), grid, block, lds, s, a, o);
+    else hipLaunchKernelGGL((k_blocks_learned<BEM_LAPLACE, BEM_DLP>), grid, block, lds, s, a, o);
+  } else {
+    if (layer == BEM_SLP) hipLaunchKernelGGL((k_blocks_learned<BEM_HELMHOLTZ, BEM_SLP>), grid, block, lds, s, a, o);
+    else hipLaunchKernelGGL((k_blocks_learned<BEM_HELMHOLTZ, BEM_DLP>), grid, block, lds, s, a, o);
+  }
+  return hipGetLastError();
 }
 
 hipError_t launch_reset_counter(int32_t *counter, hipStream_t s) {

@@ -238,6 +238,7 @@ void bem_destroy(bem_ctx *ctx) {
         if (kv.second.ss[c]) (void)hipFree(kv.second.ss[c]);
     }
     if (ctx->geo) (void)hipFree(ctx->geo);
+    if (ctx->mlp_scratch) (void)hipFree(ctx->mlp_scratch);
     if (ctx->flags) (void)hipFree(ctx->flags);
   }
   delete ctx;

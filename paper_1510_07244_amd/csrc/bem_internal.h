@@ -155,6 +155,67 @@ struct PersistentArgs {
   int32_t grid;              // workgroups
 };
 
+// ----------------------------------------------------------- learned form
+constexpr int kSelQ = 6;  // selector outputs: predicted log10 error at orders 1 .. 6
+
+// Training samples of the order selector (inputs and targets of pairs).
+struct SampleArgs {
+  const int32_t *tri;
+  int32_t nt;
+  const double *geo;
+  int64_t ldg;
+  int64_t n;
+  const int32_t *rows, *cols;
+  float *x, *t;                   // [n][8], [n][kSelQ]
+  const double *rule[kSelQ + 1];  // Duffy rules of orders 1 .. kSelQ, then the reference order
+  int32_t nq[kSelQ + 1];
+  double kappa;
+  unsigned *flags;
+};
+
+// Order selection over the entries of near-field blocks.
+struct SelectArgs {
+  const int32_t *tri;
+  int32_t nt;
+  const double *geo;
+  int64_t ldg;
+  int32_t nblocks;
+  const int32_t *row_ptr, *row_idx, *col_ptr, *col_idx;
+  int64_t row_len, col_len;
+  const int64_t *out_off;
+  int8_t *orders;
+  int64_t out_len;
+  const float *params;
+  int32_t layer, q_plain, q_min;
+  float margin, log_tol;
+  double kappa;
+  unsigned *flags;
+};
+
+// Per-entry orders of the learned near-field kernel: Duffy rules of orders
+// 2 .. q_max (index = order) and the order map (one byte per output entry).
+struct OrderRules {
+  const double *rule[BEM_MAX_ORDER + 1];
+  int32_t nq[BEM_MAX_ORDER + 1];
+  const int8_t *orders;
+  int32_t q_max;
+};
+
+int mlp_params(int n_out);
+size_t mlp_grad_scratch_floats(int n_out, int64_t n);
+hipError_t launch_mlp_grad(int n_out, const float *P, int64_t n, const float *x, const float *t,
+                           float *part, float *lpart, float *grad, float *loss, hipStream_t s);
+hipError_t launch_mlp_adam(int64_t np, float *p, const float *g, float *m, float *v, float lr,
+                           float b1, float b2, float eps, float c1, float c2, hipStream_t s);
+hipError_t launch_mlp_forward(bool f16, int n_out, const float *P, int64_t n, const float *x,
+                              float *y, hipStream_t s);
+hipError_t launch_selector_samples(int kernel, int layer, const SampleArgs &a, hipStream_t s);
+hipError_t launch_select_orders(const SelectArgs &a, hipStream_t s);
+// x-points per register chunk of the learned kernel for order q
+int learned_chunk(int q, int kernel);
+hipError_t launch_blocks_learned(int kernel, int layer, const BlockArgs &a, const OrderRules &o,
+                                 size_t lds_bytes, hipStream_t s);
+
 // xc: x-points per register chunk (4, 5, 7, 8 or 9; nq_pad of every batch
 // entry is nq rounded up to a multiple of it)
 hipError_t launch_persistent(int kernel, int layer, bool mixed, int xc, const PersistentArgs &p,
@@ -203,6 +264,8 @@ int check_op(bem_ctx *ctx, const bem_op *op);
 int check_mesh(bem_ctx *ctx, const bem_mesh *m);
 int check_blocks(bem_ctx *ctx, const bem_blocks *b, const void *out, int64_t out_len);
 int get_rules(bem_ctx *ctx, const bem_op *op, const DevRules **out);
+// geometry scratch of the context for nt triangles; leading dimension out
+int ensure_geo(bem_ctx *ctx, int32_t nt, int64_t *ldg);
 
 }  // namespace bem
 
@@ -213,5 +276,7 @@ struct bem_ctx {
   unsigned *flags = nullptr;      // device, 1 word
   double *geo = nullptr;          // device scratch
   size_t geo_cap = 0;             // doubles
+  float *mlp_scratch = nullptr;   // device: per-workgroup gradient partial sums
+  size_t mlp_cap = 0;             // floats
   std::map<std::tuple<int, int, int>, bem::DevRules> rules;
 };

@@ -1,0 +1,259 @@
+// C-ABI of the learned form: the order selector's network (FP32 training,
+// FP16 inference), its training samples, order selection over near-field
+// blocks and the near-field assembly with per-entry orders.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+
+#include "bem_internal.h"
+
+using namespace bem;
+
+namespace {
+
+int grow_mlp_scratch(bem_ctx *ctx, size_t floats) {
+  if (floats <= ctx->mlp_cap) return BEM_OK;
+  hipError_t e = hipDeviceSynchronize();
+  if (e != hipSuccess) return hip_fail(ctx, e, "hipDeviceSynchronize");
+  if (ctx->mlp_scratch) (void)hipFree(ctx->mlp_scratch);
+  ctx->mlp_scratch = nullptr;
+  ctx->mlp_cap = 0;
+  e = hipMalloc(&ctx->mlp_scratch, floats * sizeof(float));
+  if (e != hipSuccess) return hip_fail(ctx, e, "hipMalloc(network scratch)");
+  ctx->mlp_cap = floats;
+  return BEM_OK;
+}
+
+// Duffy rules of orders 1 .. max (index = order) for an operator.
+int order_rules(bem_ctx *ctx, const bem_op *op, int qmax, const DevRules **r) {
+  for (int q = 1; q <= qmax; ++q) {
+    bem_op o = *op;
+    o.regular_rule = BEM_RULE_DUFFY;
+    o.q_regular = q;
+    int rc = get_rules(ctx, &o, &r[q]);
+    if (rc) return rc;
+  }
+  return BEM_OK;
+}
+
+int block_list_args(bem_ctx *ctx, const bem_mesh *mesh, const bem_op *op, const bem_blocks *b,
+                    const void *out, int64_t out_len) {
+  int rc;
+  if ((rc = check_mesh(ctx, mesh)) || (rc = check_op(ctx, op)) ||
+      (rc = check_blocks(ctx, b, out, out_len)))
+    return rc;
+  if (b->n > 0 && mesh->nt == 0) return fail(ctx, BEM_EINVAL, "blocks given for an empty mesh");
+  return BEM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int bem_mlp_params(int32_t n_out) {
+  if (n_out < 1 || n_out > 16) return BEM_EINVAL;
+  return mlp_params(n_out);
+}
+
+int bem_mlp_forward(bem_ctx *ctx, int32_t n_out, int32_t fp16, const float *params, int64_t n,
+                    const float *x, float *y, void *stream) {
+  if (!ctx) return BEM_EINVAL;
+  if (n_out < 1 || n_out > 16 || (fp16 != 0 && fp16 != 1) || n < 0)
+    return fail(ctx, BEM_EINVAL, "n_out in [1, 16], fp16 0/1, n >= 0");
+  if (n == 0) return BEM_OK;
+  if (!params || !x || !y) return fail(ctx, BEM_EINVAL, "NULL array");
+  DeviceGuard g(ctx->device);
+  hipError_t e = launch_mlp_forward(fp16 == 1, n_out, params, n, x, y, static_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return hip_fail(ctx, e, "network forward launch");
+  return BEM_OK;
+}
+
+int bem_mlp_grad(bem_ctx *ctx, int32_t n_out, const float *params, int64_t n, const float *x,
+                 const float *t, float *grad, float *loss, void *stream) {
+  if (!ctx) return BEM_EINVAL;
+  if (n_out < 1 || n_out > 16 || n < 1) return fail(ctx, BEM_EINVAL, "n_out in [1, 16], n >= 1");
+  if (!params || !x || !t || !grad) return fail(ctx, BEM_EINVAL, "NULL array");
+  if (n > ((int64_t)1 << 31) * 16) return fail(ctx, BEM_EINVAL, "n too large");
+  DeviceGuard g(ctx->device);
+  const size_t need = mlp_grad_scratch_floats(n_out, n);
+  int rc = grow_mlp_scratch(ctx, need);
+  if (rc) return rc;
+  const int64_t nwg = (n + 15) / 16;
+  float *part = ctx->mlp_scratch, *lpart = ctx->mlp_scratch + (size_t)nwg * mlp_params(n_out);
+  hipError_t e = launch_mlp_grad(n_out, params, n, x, t, part, lpart, grad, loss,
+                                 static_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return hip_fail(ctx, e, "network gradient launch");
+  return BEM_OK;
+}
+
+int bem_mlp_adam(bem_ctx *ctx, int64_t np, float *params, const float *grad, float *m, float *v,
+                 int32_t step, float lr, float beta1, float beta2, float eps, void *stream) {
+  if (!ctx) return BEM_EINVAL;
+  if (np < 0 || step < 1 || !(lr >= 0) || !(beta1 >= 0 && beta1 < 1) || !(beta2 >= 0 && beta2 < 1) ||
+      !(eps > 0))
+    return fail(ctx, BEM_EINVAL, "Adam: np >= 0, step >= 1, lr >= 0, betas in [0, 1), eps > 0");
+  if (np == 0) return BEM_OK;
+  if (!params || !grad || !m || !v) return fail(ctx, BEM_EINVAL, "NULL array");
+  DeviceGuard g(ctx->device);
+  const float c1 = (float)(1.0 / (1.0 - std::pow((double)beta1, step)));
+  const float c2 = (float)(1.0 / (1.0 - std::pow((double)beta2, step)));
+  hipError_t e = launch_mlp_adam(np, params, grad, m, v, lr, beta1, beta2, eps, c1, c2,
+                                 static_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return hip_fail(ctx, e, "Adam launch");
+  return BEM_OK;
+}
+
+int bem_selector_samples(bem_ctx *ctx, const bem_mesh *mesh, const bem_op *op, int64_t n,
+                         const int32_t *rows, const int32_t *cols, float *x, float *t,
+                         void *stream) {
+  if (!ctx) return BEM_EINVAL;
+  int rc;
+  if ((rc = check_mesh(ctx, mesh)) || (rc = check_op(ctx, op))) return rc;
+  if (op->precision != BEM_PLAIN_FP64)
+    return fail(ctx, BEM_EUNSUPPORTED, "selector samples use the plain FP64 rules");
+  if (n < 0) return fail(ctx, BEM_EINVAL, "n < 0");
+  if (n == 0) return BEM_OK;
+  if (!rows || !cols || !x || !t) return fail(ctx, BEM_EINVAL, "NULL array");
+  if (mesh->nt == 0) return fail(ctx, BEM_EINVAL, "empty mesh");
+  DeviceGuard g(ctx->device);
+  const DevRules *r[kSelQ + 1];
+  const DevRules *ref;
+  bem_op o8 = *op;
+  o8.regular_rule = BEM_RULE_DUFFY;
+  o8.q_regular = 8;
+  int64_t ldg;
+  if ((rc = order_rules(ctx, op, kSelQ, r)) || (rc = get_rules(ctx, &o8, &ref)) ||
+      (rc = ensure_geo(ctx, mesh->nt, &ldg)))
+    return rc;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  hipError_t e = launch_geometry(*mesh, ctx->geo, ldg, ctx->flags, s);
+  if (e != hipSuccess) return hip_fail(ctx, e, "geometry kernel launch");
+  SampleArgs a{};
+  a.tri = mesh->tri;
+  a.nt = mesh->nt;
+  a.geo = ctx->geo;
+  a.ldg = ldg;
+  a.n = n;
+  a.rows = rows;
+  a.cols = cols;
+  a.x = x;
+  a.t = t;
+  for (int q = 1; q <= kSelQ; ++q) a.rule[q - 1] = r[q]->tri, a.nq[q - 1] = r[q]->nq;
+  a.rule[kSelQ] = ref->tri;
+  a.nq[kSelQ] = ref->nq;
+  a.kappa = op->kernel == BEM_HELMHOLTZ ? op->kappa : 0.0;
+  a.flags = ctx->flags;
+  e = launch_selector_samples(op->kernel, op->layer, a, s);
+  if (e != hipSuccess) return hip_fail(ctx, e, "selector samples launch");
+  return BEM_OK;
+}
+
+int bem_select_orders(bem_ctx *ctx, const bem_mesh *mesh, const bem_op *op,
+                      const bem_blocks *blocks, const float *params, double tol, double margin,
+                      int32_t q_min, int8_t *orders, int64_t orders_len, void *stream) {
+  if (!ctx) return BEM_EINVAL;
+  int rc;
+  if ((rc = block_list_args(ctx, mesh, op, blocks, orders, orders_len))) return rc;
+  if (op->regular_rule != BEM_RULE_DUFFY || op->q_regular < 2 || op->q_regular > kSelQ)
+    return fail(ctx, BEM_EUNSUPPORTED, "order selection needs the Duffy rule with q_regular in [2, 6]");
+  if (!(tol > 0) || !std::isfinite(tol) || !std::isfinite(margin) || q_min < 2 ||
+      q_min > op->q_regular)
+    return fail(ctx, BEM_EINVAL, "tol > 0, finite margin, q_min in [2, q_regular]");
+  if (!params) return fail(ctx, BEM_EINVAL, "params is NULL");
+  if (blocks->n == 0) return BEM_OK;
+  DeviceGuard g(ctx->device);
+  int64_t ldg;
+  if ((rc = ensure_geo(ctx, mesh->nt, &ldg))) return rc;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  hipError_t e = launch_geometry(*mesh, ctx->geo, ldg, ctx->flags, s);
+  if (e != hipSuccess) return hip_fail(ctx, e, "geometry kernel launch");
+  SelectArgs a{};
+  a.tri = mesh->tri;
+  a.nt = mesh->nt;
+  a.geo = ctx->geo;
+  a.ldg = ldg;
+  a.nblocks = blocks->n;
+  a.row_ptr = blocks->row_ptr;
+  a.row_idx = blocks->row_idx;
+  a.col_ptr = blocks->col_ptr;
+  a.col_idx = blocks->col_idx;
+  a.row_len = blocks->row_len;
+  a.col_len = blocks->col_len;
+  a.out_off = blocks->out_off;
+  a.orders = orders;
+  a.out_len = orders_len;
+  a.params = params;
+  a.layer = op->layer;
+  a.q_plain = op->q_regular;
+  a.q_min = q_min;
+  a.margin = (float)margin;
+  a.log_tol = (float)std::log10(tol);
+  a.kappa = op->kernel == BEM_HELMHOLTZ ? op->kappa : 0.0;
+  a.flags = ctx->flags;
+  e = launch_select_orders(a, s);
+  if (e != hipSuccess) return hip_fail(ctx, e, "order selection launch");
+  return BEM_OK;
+}
+
+int bem_assemble_nearfield_learned(bem_ctx *ctx, const bem_mesh *mesh, const bem_op *op,
+                                   const bem_blocks *blocks, const int8_t *orders, void *out,
+                                   int64_t out_len, void *stream) {
+  if (!ctx) return BEM_EINVAL;
+  int rc;
+  if ((rc = block_list_args(ctx, mesh, op, blocks, out, out_len))) return rc;
+  if (op->precision != BEM_PLAIN_FP64 || op->regular_rule != BEM_RULE_DUFFY ||
+      op->q_regular < 2 || op->q_regular > kSelQ)
+    return fail(ctx, BEM_EUNSUPPORTED,
+                "per-entry orders need plain FP64, the Duffy rule and q_regular in [2, 6]");
+  if (out_len > 0 && !orders) return fail(ctx, BEM_EINVAL, "orders is NULL");
+  if (blocks->n == 0) return BEM_OK;
+  DeviceGuard g(ctx->device);
+  const DevRules *r[BEM_MAX_ORDER + 1] = {};
+  int64_t ldg;
+  if ((rc = order_rules(ctx, op, op->q_regular, r)) || (rc = ensure_geo(ctx, mesh->nt, &ldg)))
+    return rc;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  hipError_t e = launch_geometry(*mesh, ctx->geo, ldg, ctx->flags, s);
+  if (e != hipSuccess) return hip_fail(ctx, e, "geometry kernel launch");
+  OrderRules o{};
+  for (int q = 2; q <= op->q_regular; ++q) o.rule[q] = r[q]->tri, o.nq[q] = r[q]->nq;
+  o.orders = orders;
+  o.q_max = op->q_regular;
+  const DevRules *plain = r[op->q_regular];
+  BlockArgs a{};
+  a.v = mesh->v;
+  a.tri = mesh->tri;
+  a.nv = mesh->nv;
+  a.nt = mesh->nt;
+  a.geo = ctx->geo;
+  a.ldg = ldg;
+  a.nblocks = blocks->n;
+  a.row_ptr = blocks->row_ptr;
+  a.row_idx = blocks->row_idx;
+  a.col_ptr = blocks->col_ptr;
+  a.col_idx = blocks->col_idx;
+  a.row_len = blocks->row_len;
+  a.col_len = blocks->col_len;
+  a.out_off = blocks->out_off;
+  a.out = out;
+  a.out_len = out_len;
+  a.rule = plain->tri;
+  a.nq = plain->nq;
+  // LDS sized for the largest order (q^2 points are a multiple of its chunk)
+  const int xc = learned_chunk(op->q_regular, op->kernel);
+  a.nq_pad = (plain->nq + xc - 1) / xc * xc;
+  size_t lds;
+  if (!block_tile_shape(a.nq_pad, false, ctx->lds_budget, &a.tr, &a.tc, &lds))
+    return fail(ctx, BEM_EUNSUPPORTED, "quadrature order too high for the LDS budget");
+  for (int c = 0; c < 4; ++c) a.ss.eta[c] = plain->ss[c], a.ss.np[c] = plain->np[c];
+  a.ss.xi = plain->xi;
+  a.ss.q = plain->nxi;
+  a.kappa = op->kernel == BEM_HELMHOLTZ ? op->kappa : 0.0;
+  a.flags = ctx->flags;
+  e = launch_blocks_learned(op->kernel, op->layer, a, o, lds, s);
+  if (e != hipSuccess) return hip_fail(ctx, e, "learned block kernel launch");
+  return BEM_OK;
+}
+
+}  // extern "C"
