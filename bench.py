@@ -55,6 +55,8 @@ def parse():
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--cpu-seconds", type=float, default=12.0)
     p.add_argument("--batched-meshes", type=int, default=64)
+    p.add_argument("--learned-n", type=int, default=128,
+                   help="octahedron subdivision of the learned-form sphere (nt = 8 n^2)")
     return p.parse_args()
 
 
@@ -211,6 +213,121 @@ class BatchedBench:
         }
 
 
+class LearnedBench:
+    """Learned form: the order selector trained on the GPU on 1e6 pairs drawn
+    from the near fields of the config-1..3 meshes (Laplace SLP/DLP on the
+    512- and 8192-triangle spheres, Helmholtz kappa 2/4/8 SLP/DLP on the
+    32768-triangle sphere and the 24576-triangle cube), then applied to the
+    near field of a large sphere: selection (FP16 inference) + per-entry
+    order assembly against the plain fixed-order assembly."""
+
+    TOL, MARGIN = 1e-7, 0.5
+
+    def __init__(self, pk, ctx, n):
+        import torch
+        from bem_inputs import cube_surface, octahedron_sphere
+        from paper_1510_07244_amd.selector import Selector, samples
+        self.pk, self.ctx = pk, ctx
+        L, H = pk.LAPLACE, pk.HELMHOLTZ
+        jobs = []
+        s1, s2, s3, cube = (octahedron_sphere(8), octahedron_sphere(32), octahedron_sphere(64),
+                            cube_surface(32))
+        for layer in (0, 1):
+            jobs.append((s1.v, s1.tri, pk.make_op(L, layer), 50000, 10 + layer))
+            jobs.append((s2.v, s2.tri, pk.make_op(L, layer), 200000, 20 + layer))
+            for k in (2.0, 4.0, 8.0):
+                jobs.append((s3.v, s3.tri, pk.make_op(H, layer, kappa=k), 50000, 30 + layer + int(k)))
+                jobs.append((cube.v, cube.tri, pk.make_op(H, layer, kappa=k), 33334, 40 + layer + int(k)))
+        t0 = time.perf_counter()
+        X, T = samples(ctx, jobs)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        self.sel = Selector(ctx, seed=0)
+        self.sel.set_standardisation(X)
+        self.losses = self.sel.fit(X, T, epochs=12, batch=4096, lr=2e-3, seed=1)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        self.n_train, self.t_samples, self.t_train = int(X.shape[0]), t1 - t0, t2 - t1
+        del X, T
+        self.m = m = octahedron_sphere(n)
+        self.mesh = pk.Mesh(torch.from_numpy(m.v), torch.from_numpy(m.tri))
+        ct = pk.ClusterTree(m.v, m.tri, leaf=64)
+        near, _ = pk.block_tree(ct, eta=2.0)
+        self.nblocks = len(near)
+        self.blocks, self.total = pk.Blocks.from_lists([ct.idx(t) for t, s in near],
+                                                       [ct.idx(s) for t, s in near])
+        # blocks for the error check (seeded sample), as offsets into the output
+        sizes = np.array([ct.idx(t).size * ct.idx(s).size for t, s in near], dtype=np.int64)
+        offs = np.concatenate([[0], np.cumsum(sizes)[:-1]])
+        rng = np.random.Generator(np.random.PCG64(5))
+        self.check = [(int(offs[k]), int(sizes[k])) for k in rng.choice(len(near), 256, replace=False)]
+
+    def leg(self, torch, op, stream, steps, warmup):
+        ctx, pk = self.ctx, self.pk
+        dt = pk.out_dtype(op)
+        plain = torch.empty(self.total, dtype=dt, device="cuda")
+        learned = torch.empty(self.total, dtype=dt, device="cuda")
+        orders = torch.empty(self.total, dtype=torch.int8, device="cuda")
+        sel = lambda: ctx.select_orders(self.mesh, op, self.blocks, self.sel.params, orders,
+                                        self.TOL, self.MARGIN, 2, stream)
+        runs = {
+            "plain": lambda: ctx.assemble_nearfield(self.mesh, op, self.blocks, plain, stream),
+            "select": sel,
+            "learned": lambda: ctx.assemble_nearfield_learned(self.mesh, op, self.blocks, orders,
+                                                              learned, stream),
+        }
+        ms = {}
+        for name in ("plain", "select", "learned"):
+            for _ in range(warmup):
+                runs[name]()
+            ctx.check(stream)
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            for _ in range(steps):
+                runs[name]()
+            e1.record(stream)
+            e1.synchronize()
+            ctx.check(stream)
+            ms[name] = e0.elapsed_time(e1) / steps
+        q = orders.to(torch.int64)
+        reg = q > 0
+        qp = op.q_regular
+        counts = {int(k): int((q == k).sum()) for k in range(2, qp + 1)}
+        pts_plain = float(reg.sum()) * qp ** 4
+        pts_learned = float((q[reg] ** 4).sum())
+        errs = []
+        for o, n in self.check:
+            a, b = learned[o:o + n], plain[o:o + n]
+            errs.append(float(torch.linalg.vector_norm(a - b) / torch.linalg.vector_norm(b)))
+        tot = float(torch.linalg.vector_norm(learned - plain) / torch.linalg.vector_norm(plain))
+        del plain, learned, orders
+        return {"plain_ms": ms["plain"], "select_ms": ms["select"], "learned_ms": ms["learned"],
+                "speedup_vs_plain": ms["plain"] / (ms["select"] + ms["learned"]),
+                "assembly_speedup_excl_select": ms["plain"] / ms["learned"],
+                "points_fraction": pts_learned / pts_plain, "orders": counts,
+                "max_block_rel_err_vs_plain": max(errs), "near_field_rel_err_vs_plain": tot,
+                "entries": int(self.total)}
+
+    def result(self, torch, stream, steps, warmup):
+        pk = self.pk
+        legs = {}
+        for name, op in (("laplace_slp", pk.make_op(pk.LAPLACE, pk.SLP, q_regular=4, q_singular=4)),
+                         ("laplace_dlp", pk.make_op(pk.LAPLACE, pk.DLP, q_regular=4, q_singular=4)),
+                         ("helmholtz8_slp", pk.make_op(pk.HELMHOLTZ, pk.SLP, q_regular=5,
+                                                       q_singular=5, kappa=8.0))):
+            legs[name] = self.leg(torch, op, stream, steps, warmup)
+        return {
+            "workload": f"near field of the octahedron sphere with {self.m.nt} triangles "
+                        f"({self.nblocks} blocks, leaf 64, eta 2): plain fixed order (q=4 Laplace, "
+                        "q=5 Helmholtz kappa 8) vs learned per-entry orders "
+                        f"(tol {self.TOL}, margin {self.MARGIN}); FP64",
+            "training": {"pairs": self.n_train, "samples_s": self.t_samples,
+                         "train_s": self.t_train, "loss_first_epoch": float(self.losses[0]),
+                         "loss_last_epoch": float(self.losses[-1])},
+            "legs": legs,
+        }
+
+
 def run_leg(torch, ctx, hb, stream, steps, warmup):
     """Time `steps` steps after `warmup`; per-phase HIP-event means."""
     names = ["bases", "ns", "nd", "cs", "cd"]
@@ -283,6 +400,12 @@ def main():
     if args.batched_meshes > 0:
         bb = BatchedBench(pk, ctx, args.batched_meshes)
         batched = bb.result(torch, stream, args.steps, args.warmup)
+        del bb
+    learned = None
+    if args.learned_n > 0:
+        lb = LearnedBench(pk, ctx, args.learned_n)
+        learned = lb.result(torch, stream, min(args.steps, 10), 1)
+        del lb
 
     h = hb.h
     rows = [h.ct.idx(t) for t, s in h.near]
@@ -356,6 +479,8 @@ def main():
     }
     if batched:
         result["forms"]["batched"] = batched
+    if learned:
+        result["forms"]["learned"] = learned
     if not args.no_cpu_baseline:
         result["cpu_baseline"] = cpu_baseline(m, hb, args.cpu_seconds)
     ctx.close()

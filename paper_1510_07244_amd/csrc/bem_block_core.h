@@ -92,7 +92,8 @@ __device__ __forceinline__ Acc<KERNEL> regular_entry(const Lds &l, int TR, int T
   const int ystride = 3 * TC;  // double2 per point index
   Acc<KERNEL> acc;
   for (int ch = 0; ch < nqp; ch += XC) {
-    double X0[XC], X1[XC], X2[XC], XX[XC], WX[XC], XN[XC];
+    // WN = wx <X, n_j>, so that wx <X - Y, n_j> = fma(-wx, <Y, n_j>, WN)
+    double X0[XC], X1[XC], X2[XC], XX[XC], WX[XC], WN[XC];
 #pragma unroll
     for (int a = 0; a < XC; ++a) {
       const double s = l.rule[ch + a], t = l.rule[nqp + ch + a], w = l.rule[2 * nqp + ch + a];
@@ -101,35 +102,34 @@ __device__ __forceinline__ Acc<KERNEL> regular_entry(const Lds &l, int TR, int T
       X2[a] = fma(s, A2, fma(t, B2, D2));
       XX[a] = fma(X0[a], X0[a], fma(X1[a], X1[a], X2[a] * X2[a]));
       WX[a] = w * SG;
-      if constexpr (LAYER == BEM_DLP) XN[a] = fma(X0[a], n0, fma(X1[a], n1, X2[a] * n2));
+      if constexpr (LAYER == BEM_DLP) WN[a] = WX[a] * fma(X0[a], n0, fma(X1[a], n1, X2[a] * n2));
     }
-    double2 c0 = ycol[0], c1 = ycol[1], c2 = ycol[2];
-    for (int kb = 0; kb < nqp; ++kb) {
-      // prefetch the next column point while this one is used
-      const double2 *yn = ycol + (kb + 1 < nqp ? kb + 1 : kb) * ystride;
-      const double2 p0 = yn[0], p1 = yn[1], p2 = yn[2];
+    const double2 *yp = ycol;
+#pragma unroll 2
+    for (int kb = 0; kb < nqp; ++kb, yp += ystride) {
+      const double2 c0 = yp[0], c1 = yp[1], c2 = yp[2];
       const double M0 = c0.x, M1 = c0.y, M2 = c1.x, YY = c1.y, WY = c2.x, YN = c2.y;
+      // the XC chains are written stage by stage so that they interleave
+      double sq[XC], h[XC];
+#pragma unroll
+      for (int a = 0; a < XC; ++a)
+        sq[a] = fma(X2[a], M2, fma(X1[a], M1, fma(X0[a], M0, XX[a] + YY)));  // 4 r^2
+#pragma unroll
+      for (int a = 0; a < XC; ++a) h[a] = __builtin_amdgcn_rsq(sq[a]);     // ~ 1/(2r)
       double ire = 0.0, iim = 0.0;
 #pragma unroll
       for (int a = 0; a < XC; ++a) {
-        double s = XX[a] + YY;
-        s = fma(X0[a], M0, s);
-        s = fma(X1[a], M1, s);
-        s = fma(X2[a], M2, s);  // s = 4 r^2
-        // h ~ 1/(2r); one Newton step gives z = h (3 - s h^2) ~ 1/r
-        const double h = __builtin_amdgcn_rsq(s);
-        const double t = s * h;
-        const double e = fma(-t, h, 3.0);
-        const double z = h * e;
+        // one Newton step: z = h (3 - s h^2) ~ 1/r
+        const double z = h[a] * fma(-(sq[a] * h[a]), h[a], 3.0);
         if constexpr (KERNEL == BEM_LAPLACE) {
           if constexpr (LAYER == BEM_SLP) {
             ire = fma(WX[a], z, ire);
           } else {
-            const double dn = XN[a] - YN;  // 2 <x - y, n_j>
-            ire = fma(WX[a] * dn, z * z * z, ire);
+            const double u = fma(-WX[a], YN, WN[a]);  // wx 2 <x - y, n_j>
+            ire = fma(u, z * z * z, ire);
           }
         } else {
-          const double kr = kq * s * z;  // kappa r  (kq = kappa / 4)
+          const double kr = kq * sq[a] * z;  // kappa r  (kq = kappa / 4)
           double sn, cs;
           sincos_cw(kr, &sn, &cs);
           if constexpr (LAYER == BEM_SLP) {
@@ -137,7 +137,7 @@ __device__ __forceinline__ Acc<KERNEL> regular_entry(const Lds &l, int TR, int T
             ire = fma(wz, cs, ire);
             iim = fma(wz, sn, iim);
           } else {
-            const double u = WX[a] * (XN[a] - YN) * z * z * z;
+            const double u = fma(-WX[a], YN, WN[a]) * z * z * z;
             ire = fma(u, fma(kr, sn, cs), ire);
             iim = fma(u, fma(-kr, cs, sn), iim);
           }
@@ -145,9 +145,6 @@ __device__ __forceinline__ Acc<KERNEL> regular_entry(const Lds &l, int TR, int T
       }
       acc.re = fma(WY, ire, acc.re);
       if constexpr (KERNEL == BEM_HELMHOLTZ) acc.im = fma(WY, iim, acc.im);
-      c0 = p0;
-      c1 = p1;
-      c2 = p2;
     }
   }
   return acc;
@@ -180,7 +177,8 @@ __device__ __forceinline__ Acc<KERNEL> regular_entry_f32(const Lds &l, int TR, i
   const int ystride = 2 * TC;  // float4 per point index
   float are = 0.0f, aim = 0.0f;
   for (int ch = 0; ch < nqp; ch += XC) {
-    float X0[XC], X1[XC], X2[XC], XX[XC], WX[XC], XN[XC];
+    // WN = wx <X, n_j>, so that wx <X - Y', n_j> = fma(-wx, <Y', n_j>, WN)
+    float X0[XC], X1[XC], X2[XC], XX[XC], WX[XC], WN[XC];
 #pragma unroll
     for (int a = 0; a < XC; ++a) {
       const double s = l.rule[ch + a], t = l.rule[nqp + ch + a], w = l.rule[2 * nqp + ch + a];
@@ -193,39 +191,41 @@ __device__ __forceinline__ Acc<KERNEL> regular_entry_f32(const Lds &l, int TR, i
       // h = 1/(2r): the SLP's k' = 1/r = 2h, the DLP's k' = 2 <x - y, n> / r^3
       // = 8 h^3 <X - Y', n> (same k' as the FP64 path)
       WX[a] = (float)(w * SG) * (LAYER == BEM_SLP ? 2.0f : 8.0f);
-      if constexpr (LAYER == BEM_DLP) XN[a] = fmaf(x0, n0, fmaf(x1, n1, x2 * n2));
+      if constexpr (LAYER == BEM_DLP) WN[a] = WX[a] * fmaf(x0, n0, fmaf(x1, n1, x2 * n2));
     }
-    float4 c0 = ycol[0], c1 = ycol[1];
-    for (int kb = 0; kb < nqp; ++kb) {
-      const float4 *yn = ycol + (kb + 1 < nqp ? kb + 1 : kb) * ystride;
-      const float4 p0 = yn[0], p1 = yn[1];
+    const float4 *yp = ycol;
+#pragma unroll 2
+    for (int kb = 0; kb < nqp; ++kb, yp += ystride) {
+      const float4 c0 = yp[0], c1 = yp[1];
       const float y0 = d0 + c0.x, y1 = d1 + c0.y, y2 = d2 + c0.z, WY = c0.w;
       const float YY = fmaf(y0, y0, fmaf(y1, y1, y2 * y2));
       const float YN = dn + c1.x;  // <Y', n_j>
+      // the XC chains are written stage by stage so that they interleave
+      float sq[XC], h[XC];
+#pragma unroll
+      for (int a = 0; a < XC; ++a)
+        sq[a] = fmaf(X2[a], y2, fmaf(X1[a], y1, fmaf(X0[a], y0, XX[a] + YY)));  // 4 r^2
+#pragma unroll
+      for (int a = 0; a < XC; ++a) h[a] = __builtin_amdgcn_rsqf(sq[a]);
       float ire = 0.0f, iim = 0.0f;
 #pragma unroll
       for (int a = 0; a < XC; ++a) {
-        float s = XX[a] + YY;
-        s = fmaf(X0[a], y0, s);
-        s = fmaf(X1[a], y1, s);
-        s = fmaf(X2[a], y2, s);  // 4 r^2
-        const float h = __builtin_amdgcn_rsqf(s);
         if constexpr (KERNEL == BEM_LAPLACE) {
           if constexpr (LAYER == BEM_SLP) {
-            ire = fmaf(WX[a], h, ire);
+            ire = fmaf(WX[a], h[a], ire);
           } else {
-            ire = fmaf(WX[a] * (XN[a] - YN), h * h * h, ire);
+            ire = fmaf(fmaf(-WX[a], YN, WN[a]), h[a] * h[a] * h[a], ire);
           }
         } else {
-          const float kr = hk * s * h;
+          const float kr = hk * sq[a] * h[a];
           float sn, cs;
           sincos_cw_f32(kr, &sn, &cs);
           if constexpr (LAYER == BEM_SLP) {
-            const float wz = WX[a] * h;
+            const float wz = WX[a] * h[a];
             ire = fmaf(wz, cs, ire);
             iim = fmaf(wz, sn, iim);
           } else {
-            const float u = WX[a] * (XN[a] - YN) * h * h * h;
+            const float u = fmaf(-WX[a], YN, WN[a]) * h[a] * h[a] * h[a];
             ire = fmaf(u, fmaf(kr, sn, cs), ire);
             iim = fmaf(u, fmaf(-kr, cs, sn), iim);
           }
@@ -233,8 +233,6 @@ __device__ __forceinline__ Acc<KERNEL> regular_entry_f32(const Lds &l, int TR, i
       }
       are = fmaf(WY, ire, are);
       if constexpr (KERNEL == BEM_HELMHOLTZ) aim = fmaf(WY, iim, aim);
-      c0 = p0;
-      c1 = p1;
     }
   }
   Acc<KERNEL> acc;
