@@ -215,9 +215,9 @@ class BatchedBench:
 
 class LearnedBench:
     """Learned form: the order selector trained on the GPU on 1e6 pairs drawn
-    from the near fields of the config-1..3 meshes (Laplace SLP/DLP on the
-    512- and 8192-triangle spheres, Helmholtz kappa 2/4/8 SLP/DLP on the
-    32768-triangle sphere and the 24576-triangle cube), then applied to the
+    from the near fields of the config-1..3 meshes (the 512-, 8192- and
+    32768-triangle spheres and the 24576-triangle cube; Laplace SLP/DLP on
+    all, Helmholtz kappa 2/4/8 SLP/DLP on the last two), then applied to the
     near field of a large sphere: selection (FP16 inference) + per-entry
     order assembly against the plain fixed-order assembly."""
 
@@ -233,18 +233,20 @@ class LearnedBench:
         s1, s2, s3, cube = (octahedron_sphere(8), octahedron_sphere(32), octahedron_sphere(64),
                             cube_surface(32))
         for layer in (0, 1):
-            jobs.append((s1.v, s1.tri, pk.make_op(L, layer), 50000, 10 + layer))
-            jobs.append((s2.v, s2.tri, pk.make_op(L, layer), 200000, 20 + layer))
+            jobs.append((s1.v, s1.tri, pk.make_op(L, layer), 40000, 10 + layer))
+            jobs.append((s2.v, s2.tri, pk.make_op(L, layer), 120000, 20 + layer))
+            jobs.append((s3.v, s3.tri, pk.make_op(L, layer), 100000, 30 + layer))
+            jobs.append((cube.v, cube.tri, pk.make_op(L, layer), 40000, 40 + layer))
             for k in (2.0, 4.0, 8.0):
-                jobs.append((s3.v, s3.tri, pk.make_op(H, layer, kappa=k), 50000, 30 + layer + int(k)))
-                jobs.append((cube.v, cube.tri, pk.make_op(H, layer, kappa=k), 33334, 40 + layer + int(k)))
+                jobs.append((s3.v, s3.tri, pk.make_op(H, layer, kappa=k), 40000, 50 + layer + int(k)))
+                jobs.append((cube.v, cube.tri, pk.make_op(H, layer, kappa=k), 26667, 60 + layer + int(k)))
         t0 = time.perf_counter()
         X, T = samples(ctx, jobs)
         torch.cuda.synchronize()
         t1 = time.perf_counter()
         self.sel = Selector(ctx, seed=0)
         self.sel.set_standardisation(X)
-        self.losses = self.sel.fit(X, T, epochs=12, batch=4096, lr=2e-3, seed=1)
+        self.losses = self.sel.fit(X, T, epochs=20, batch=4096, lr=2e-3, seed=1)
         torch.cuda.synchronize()
         t2 = time.perf_counter()
         self.n_train, self.t_samples, self.t_train = int(X.shape[0]), t1 - t0, t2 - t1

@@ -249,8 +249,10 @@ void bem_plan_destroy(bem_plan *plan);
  * |tau|, longest edges d, unit normals n and D = max(d_i, d_j),
  * r = |c_i - c_j|:
  *   x0 = ln(r / D), x1 = sqrt(3)/4 d_i^2/|tau_i|, x2 = the same for tau_j,
- *   x3 = min(|tau_i|, |tau_j|) / max(..), x4 = kappa D, x5 = <n_i, n_j>,
- *   x6 = 0 (single layer) or 1 (double layer), x7 = |<c_i - c_j, n_j>| / r.
+ *   x3 = min(|tau_i|, |tau_j|) / max(..), x4 = kappa D,
+ *   x5 = ln max(|n_i - n_j|^2, 1e-12), x6 = 0 (single layer) or 1 (double
+ *   layer), x7 = ln max(|<c_i - c_j, n_j>| / r, 1e-8)
+ * (differences in FP64, the rest in FP32).
  * Targets for q = 1 .. 6: e_q = log10(max(|G_q - G_8| / max(|G_8|,
  * 1e-3 s), 1e-16)) with s = |tau_i| |tau_j| / (4 pi r) and G_q the entry by
  * the Duffy/Gauss rule of order q.

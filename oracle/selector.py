@@ -12,9 +12,13 @@ areas |tau|, longest edges d and unit normals n (from the mesh order):
     x2  = sqrt(3)/4 d_j^2 / |tau_j|
     x3  = min(|tau_i|, |tau_j|) / max(|tau_i|, |tau_j|)
     x4  = kappa D                            (0 for Laplace)
-    x5  = <n_i, n_j>
+    x5  = ln max(|n_i - n_j|^2, 1e-12)       (= ln 2(1 - cos angle))
     x6  = 0 single layer, 1 double layer
-    x7  = |<(c_i - c_j) / r, n_j>|
+    x7  = ln max(|<c_i - c_j, n_j>| / r, 1e-8)
+
+(the logarithms resolve nearly parallel normals and nearly in-plane
+separations, where the double layer's entries are small and its rules'
+relative errors large).
 
 Targets, for q = 1 .. 6 (the Duffy/Gauss rule of Sec. 2.2 with q Gauss
 points per coordinate; q^4 points per pair) against the same rule at
@@ -65,9 +69,9 @@ def features(v, tri, rows, cols, layer=SLP, kappa=0.0):
     f[:, 2] = np.sqrt(3.0) / 4.0 * d[cols] ** 2 / area[cols]
     f[:, 3] = np.minimum(area[rows], area[cols]) / np.maximum(area[rows], area[cols])
     f[:, 4] = kappa * D
-    f[:, 5] = (n[rows] * n[cols]).sum(-1)
+    f[:, 5] = np.log(np.maximum(((n[rows] - n[cols]) ** 2).sum(-1), 1e-12))
     f[:, 6] = float(layer)
-    f[:, 7] = np.abs((sep / r[:, None] * n[cols]).sum(-1))
+    f[:, 7] = np.log(np.maximum(np.abs((sep * n[cols]).sum(-1)) / r, 1e-8))
     return f
 
 

@@ -201,94 +201,102 @@ __global__ __launch_bounds__(kThreads) void k_mlp_fwd32(int n_out, const float *
 }
 
 // ------------------------------------------------------------ inference (FP16)
-typedef _Float16 h4 __attribute__((ext_vector_type(4)));
+typedef _Float16 h8 __attribute__((ext_vector_type(8)));
 typedef float f4 __attribute__((ext_vector_type(4)));
 
-// Row of the 16 x 16 result held by lane group g (= lane / 16) in result
-// register r of v_mfma_f32_16x16x16_f16; the column is lane % 16.
+// v_mfma_f32_16x16x32_f16 (read on the device with an in-bounds probe): the
+// A operand of lane l holds row l % 16 at the eight k-slots (g, j) of its
+// lane group g = l / 16, the B operand column l % 16 at the same slots, and
+// result register r holds row 4 g + r, column l % 16.
 __device__ __forceinline__ constexpr int drow(int g, int r) { return 4 * g + r; }
 
-// The network's weights as matrix-core operands of one wave.  Layers are
-// computed transposed, H^T = W Z^T: the weights are the A operand (lane
-// holds row lane % 16, k-slots of its lane group) and the activations of 16
-// samples the B operand (lane holds sample lane % 16), so that a layer's
-// result registers are directly the next layer's B operand when slot (g, j)
-// of the A operand carries k index drow(g, j).
+// Layers are computed transposed, H^T = W Z^T: the weights are the A operand
+// and the activations of 16 samples the B operand.  For a 64-wide layer the
+// B operand of k-step ks (32 neurons) is the result registers of tiles 2 ks
+// and 2 ks + 1, so A's slot (g, j) carries neuron kidx(ks, g, j).
+__device__ __forceinline__ constexpr int kidx(int ks, int g, int j) {
+  return ks * 32 + (j < 4 ? drow(g, j) : 16 + drow(g, j - 4));
+}
+
 struct Net16 {
-  h4 a1[4], a2[4][4], a3[4][4], a4[4];
-  f4 c1[4], c2[4], c3[4], c4;  // biases in result layout
-  float mu[4], isg[4];         // this lane's input standardisation (lane group 0, 1)
+  h8 a1[4], a2[4][2], a3[4][2], a4[2];
 };
 
-__device__ __forceinline__ void load_net(const float *__restrict__ P, int n_out, Net16 *N) {
+// Biases in LDS: b1, b2, b3 (64 each), b4 (16, zero padded); input
+// standardisation mu and 1 / sigma (8 each).
+constexpr int kBiasFloats = 3 * kHid + kOutMax + 2 * kIn;
+
+__device__ __forceinline__ void load_net(const float *__restrict__ P, int n_out, Net16 *N,
+                                         float *bias) {
   const Off of = offsets(n_out);
   const int l = threadIdx.x & 63, g = l >> 4, c = l & 15;
   for (int mt = 0; mt < 4; ++mt) {
     const int row = mt * 16 + c;
-    for (int j = 0; j < 4; ++j) {
-      const int f = 4 * g + j;  // input feature of slot (g, j)
-      N->a1[mt][j] = (_Float16)(g < 2 ? P[of.w1 + row * kIn + f] : 0.0f);
-    }
-    for (int kt = 0; kt < 4; ++kt)
-      for (int j = 0; j < 4; ++j) {
-        const int k = kt * 16 + drow(g, j);
-        N->a2[mt][kt][j] = (_Float16)P[of.w2 + row * kHid + k];
-        N->a3[mt][kt][j] = (_Float16)P[of.w3 + row * kHid + k];
+    for (int j = 0; j < 8; ++j)
+      N->a1[mt][j] = (_Float16)(g == 0 ? P[of.w1 + row * kIn + j] : 0.0f);
+    for (int ks = 0; ks < 2; ++ks)
+      for (int j = 0; j < 8; ++j) {
+        N->a2[mt][ks][j] = (_Float16)P[of.w2 + row * kHid + kidx(ks, g, j)];
+        N->a3[mt][ks][j] = (_Float16)P[of.w3 + row * kHid + kidx(ks, g, j)];
       }
-    for (int r = 0; r < 4; ++r) {
-      const int o = mt * 16 + drow(g, r);
-      N->c1[mt][r] = P[of.b1 + o];
-      N->c2[mt][r] = P[of.b2 + o];
-      N->c3[mt][r] = P[of.b3 + o];
-    }
   }
-  for (int kt = 0; kt < 4; ++kt)
-    for (int j = 0; j < 4; ++j)
-      N->a4[kt][j] = (_Float16)(c < n_out ? P[of.w4 + c * kHid + kt * 16 + drow(g, j)] : 0.0f);
-  for (int r = 0; r < 4; ++r) {
-    const int o = drow(g, r);
-    N->c4[r] = o < n_out ? P[of.b4 + o] : 0.0f;
-  }
-  for (int j = 0; j < 4; ++j) {
-    const int f = (4 * g + j) & 7;
-    N->mu[j] = P[of.mu + f];
-    N->isg[j] = 1.0f / P[of.sigma + f];
+  for (int ks = 0; ks < 2; ++ks)
+    for (int j = 0; j < 8; ++j)
+      N->a4[ks][j] = (_Float16)(c < n_out ? P[of.w4 + c * kHid + kidx(ks, g, j)] : 0.0f);
+  for (int k = threadIdx.x; k < kBiasFloats; k += blockDim.x) {
+    float v;
+    if (k < 3 * kHid) v = P[(k < kHid ? of.b1 : k < 2 * kHid ? of.b2 - kHid : of.b3 - 2 * kHid) + k];
+    else if (k < 3 * kHid + kOutMax) v = k - 3 * kHid < n_out ? P[of.b4 + k - 3 * kHid] : 0.0f;
+    else if (k < 3 * kHid + kOutMax + kIn) v = P[of.mu + k - 3 * kHid - kOutMax];
+    else v = 1.0f / P[of.sigma + k - 3 * kHid - kOutMax - kIn];
+    bias[k] = v;
   }
 }
 
-__device__ __forceinline__ h4 relu_h4(f4 v) {
-  h4 r;
-  for (int j = 0; j < 4; ++j) r[j] = (_Float16)fmaxf(v[j], 0.0f);
+__device__ __forceinline__ f4 bias4(const float *bias, int base, int g) {
+  return *reinterpret_cast<const f4 *>(bias + base + drow(g, 0));
+}
+
+__device__ __forceinline__ h8 relu_pair(f4 lo, f4 hi) {
+  h8 r;
+  for (int j = 0; j < 4; ++j) {
+    r[j] = (_Float16)fmaxf(lo[j], 0.0f);
+    r[j + 4] = (_Float16)fmaxf(hi[j], 0.0f);
+  }
   return r;
 }
 
-// Network outputs for the 16 samples of a wave-group.  `feat` holds this
-// lane's four raw inputs (features 4g .. 4g+3 of sample lane % 16; unused
-// for lane groups 2, 3).  Returns the result registers: output drow(g, r)
-// of sample lane % 16.
-__device__ __forceinline__ f4 net16(const Net16 &N, const float feat[4]) {
+// Standardised FP16 inputs of one sample (the same arithmetic everywhere).
+__device__ __forceinline__ h8 standardise(const float x[8], const float *bias) {
+  const float *mu = bias + 3 * kHid + kOutMax, *isg = mu + kIn;
+  h8 b;
+  for (int j = 0; j < 8; ++j) b[j] = (_Float16)((x[j] - mu[j]) * isg[j]);
+  return b;
+}
+
+// Outputs for 16 samples: lanes 0..15 hold the standardised inputs of sample
+// lane (zeros elsewhere).  Result register r of lane l: output drow(l/16, r)
+// of sample l % 16.
+__device__ __forceinline__ f4 net16(const Net16 &N, const float *bias, h8 b) {
   const int g = (threadIdx.x & 63) >> 4;
-  h4 b;
-  for (int j = 0; j < 4; ++j)
-    b[j] = (_Float16)(g < 2 ? (feat[j] - N.mu[j]) * N.isg[j] : 0.0f);
-  h4 hb1[4], hb2[4], hb3[4];
+  f4 t1[4], t2[4], t3[4];
   for (int mt = 0; mt < 4; ++mt)
-    hb1[mt] = relu_h4(__builtin_amdgcn_mfma_f32_16x16x16f16(N.a1[mt], b, N.c1[mt], 0, 0, 0));
+    t1[mt] = __builtin_amdgcn_mfma_f32_16x16x32_f16(N.a1[mt], b, bias4(bias, mt * 16, g), 0, 0, 0);
+  const h8 h1[2] = {relu_pair(t1[0], t1[1]), relu_pair(t1[2], t1[3])};
   for (int mt = 0; mt < 4; ++mt) {
-    f4 acc = N.c2[mt];
-    for (int kt = 0; kt < 4; ++kt)
-      acc = __builtin_amdgcn_mfma_f32_16x16x16f16(N.a2[mt][kt], hb1[kt], acc, 0, 0, 0);
-    hb2[mt] = relu_h4(acc);
+    f4 acc = bias4(bias, kHid + mt * 16, g);
+    for (int ks = 0; ks < 2; ++ks) acc = __builtin_amdgcn_mfma_f32_16x16x32_f16(N.a2[mt][ks], h1[ks], acc, 0, 0, 0);
+    t2[mt] = acc;
   }
+  const h8 h2[2] = {relu_pair(t2[0], t2[1]), relu_pair(t2[2], t2[3])};
   for (int mt = 0; mt < 4; ++mt) {
-    f4 acc = N.c3[mt];
-    for (int kt = 0; kt < 4; ++kt)
-      acc = __builtin_amdgcn_mfma_f32_16x16x16f16(N.a3[mt][kt], hb2[kt], acc, 0, 0, 0);
-    hb3[mt] = relu_h4(acc);
+    f4 acc = bias4(bias, 2 * kHid + mt * 16, g);
+    for (int ks = 0; ks < 2; ++ks) acc = __builtin_amdgcn_mfma_f32_16x16x32_f16(N.a3[mt][ks], h2[ks], acc, 0, 0, 0);
+    t3[mt] = acc;
   }
-  f4 acc = N.c4;
-  for (int kt = 0; kt < 4; ++kt)
-    acc = __builtin_amdgcn_mfma_f32_16x16x16f16(N.a4[kt], hb3[kt], acc, 0, 0, 0);
+  const h8 h3[2] = {relu_pair(t3[0], t3[1]), relu_pair(t3[2], t3[3])};
+  f4 acc = bias4(bias, 3 * kHid, g);
+  for (int ks = 0; ks < 2; ++ks) acc = __builtin_amdgcn_mfma_f32_16x16x32_f16(N.a4[ks], h3[ks], acc, 0, 0, 0);
   return acc;
 }
 
@@ -296,17 +304,22 @@ __device__ __forceinline__ f4 net16(const Net16 &N, const float feat[4]) {
 __global__ __launch_bounds__(kThreads) void k_mlp_infer16(int n_out, const float *__restrict__ P,
                                                           int64_t n, const float *__restrict__ x,
                                                           float *__restrict__ y) {
+  __shared__ __attribute__((aligned(16))) float bias[kBiasFloats];
   Net16 N;
-  load_net(P, n_out, &N);
+  load_net(P, n_out, &N, bias);
+  __syncthreads();
   const int l = threadIdx.x & 63, g = l >> 4;
   const int64_t nwaves = (int64_t)gridDim.x * (kThreads / kWave);
   const int64_t w0 = (int64_t)blockIdx.x * (kThreads / kWave) + threadIdx.x / kWave;
   for (int64_t s0 = w0 * 16; s0 < n; s0 += nwaves * 16) {
     const int64_t s = s0 + (l & 15);
-    float f[4] = {0.0f, 0.0f, 0.0f, 0.0f};
-    if (g < 2 && s < n)
-      for (int j = 0; j < 4; ++j) f[j] = x[s * kIn + 4 * g + j];
-    const f4 out = net16(N, f);
+    h8 b = {0, 0, 0, 0, 0, 0, 0, 0};
+    if (g == 0 && s < n) {
+      float f[8];
+      for (int j = 0; j < 8; ++j) f[j] = x[s * kIn + j];
+      b = standardise(f, bias);
+    }
+    const f4 out = net16(N, bias, b);
     for (int r = 0; r < 4; ++r) {
       const int o = drow(g, r);
       if (s < n && o < n_out) y[s * n_out + o] = out[r];
@@ -315,44 +328,53 @@ __global__ __launch_bounds__(kThreads) void k_mlp_infer16(int n_out, const float
 }
 
 // ------------------------------------------------------------ pair inputs
-// Inputs of a regular pair (i, j) from the triangle geometry (FP64, then
-// rounded to FP32): see the selector's definition in the header.
-__device__ __forceinline__ void pair_features(const double *g, int64_t L, int i, int j,
-                                              int layer, double kappa, float f[8]) {
-  double ci[3], cj[3], ni[3], nj[3];
-  double di = 0.0, dj = 0.0;
-  {
-    double a2 = 0, b2 = 0, s2 = 0, c2 = 0, d2 = 0, t2 = 0;
-    for (int c = 0; c < 3; ++c) {
-      const double e1i = g[(G_E1X + c) * L + i], e2i = g[(G_E2X + c) * L + i];
-      const double e1j = g[(G_E1X + c) * L + j], e2j = g[(G_E2X + c) * L + j];
-      ci[c] = g[(G_V0X + c) * L + i] + (2.0 * e1i + e2i) / 3.0;
-      cj[c] = g[(G_V0X + c) * L + j] + (2.0 * e1j + e2j) / 3.0;
-      ni[c] = g[(G_NX + c) * L + i];
-      nj[c] = g[(G_NX + c) * L + j];
-      a2 = fma(e1i, e1i, a2);
-      b2 = fma(e2i, e2i, b2);
-      s2 = fma(e1i + e2i, e1i + e2i, s2);
-      c2 = fma(e1j, e1j, c2);
-      d2 = fma(e2j, e2j, d2);
-      t2 = fma(e1j + e2j, e1j + e2j, t2);
-    }
-    di = sqrt(fmax(a2, fmax(b2, s2)));
-    dj = sqrt(fmax(c2, fmax(d2, t2)));
+// Per-triangle part of the inputs: centroid c = v0 + (2 e1 + e2) / 3 and
+// unit normal (FP64), longest edge d, area and aspect sqrt(3)/4 d^2 / area
+// (FP32).
+struct TriIn {
+  double c[3], n[3];
+  float d, area, aspect;
+};
+
+__device__ __forceinline__ TriIn tri_inputs(const double *g, int64_t L, int i) {
+  TriIn t;
+  double a2 = 0, b2 = 0, s2 = 0;
+  for (int k = 0; k < 3; ++k) {
+    const double e1 = g[(G_E1X + k) * L + i], e2 = g[(G_E2X + k) * L + i];
+    t.c[k] = g[(G_V0X + k) * L + i] + (2.0 * e1 + e2) / 3.0;
+    t.n[k] = g[(G_NX + k) * L + i];
+    a2 = fma(e1, e1, a2);
+    b2 = fma(e2, e2, b2);
+    s2 = fma(e1 + e2, e1 + e2, s2);
   }
-  const double ai = 0.5 * g[G_SG * L + i], aj = 0.5 * g[G_SG * L + j];
-  const double D = fmax(di, dj);
-  const double s0 = ci[0] - cj[0], s1 = ci[1] - cj[1], s2 = ci[2] - cj[2];
-  const double r = sqrt(fma(s0, s0, fma(s1, s1, s2 * s2)));
-  const double q = 0.4330127018922193;  // sqrt(3) / 4
-  f[0] = (float)log(r / D);
-  f[1] = (float)(q * di * di / ai);
-  f[2] = (float)(q * dj * dj / aj);
-  f[3] = (float)(fmin(ai, aj) / fmax(ai, aj));
-  f[4] = (float)(kappa * D);
-  f[5] = (float)fma(ni[0], nj[0], fma(ni[1], nj[1], ni[2] * nj[2]));
+  const double d = sqrt(fmax(a2, fmax(b2, s2)));
+  const double area = 0.5 * g[G_SG * L + i];
+  t.d = (float)d;
+  t.area = (float)area;
+  t.aspect = (float)(0.4330127018922193 * d * d / area);  // sqrt(3)/4 d^2 / area
+  return t;
+}
+
+// Inputs of the pair (i, j): x0 = ln(r / D), x1, x2 aspects, x3 area ratio,
+// x4 = kappa D, x5 = ln max(|n_i - n_j|^2, 1e-12), x6 = layer,
+// x7 = ln max(|<c_i - c_j, n_j>| / r, 1e-8).  Differences in FP64, the rest
+// in FP32.
+__device__ __forceinline__ void pair_inputs(const TriIn &ti, const TriIn &tj, int layer,
+                                            float kappa, float f[8]) {
+  const double s0 = ti.c[0] - tj.c[0], s1 = ti.c[1] - tj.c[1], s2 = ti.c[2] - tj.c[2];
+  const double m0 = ti.n[0] - tj.n[0], m1 = ti.n[1] - tj.n[1], m2 = ti.n[2] - tj.n[2];
+  const float r = sqrtf((float)fma(s0, s0, fma(s1, s1, s2 * s2)));
+  const float dn = (float)fabs(fma(s0, tj.n[0], fma(s1, tj.n[1], s2 * tj.n[2])));
+  const float nn = (float)fma(m0, m0, fma(m1, m1, m2 * m2));
+  const float D = fmaxf(ti.d, tj.d);
+  f[0] = __logf(r / D);
+  f[1] = ti.aspect;
+  f[2] = tj.aspect;
+  f[3] = fminf(ti.area, tj.area) / fmaxf(ti.area, tj.area);
+  f[4] = kappa * D;
+  f[5] = __logf(fmaxf(nn, 1e-12f));
   f[6] = (float)layer;
-  f[7] = (float)fabs(fma(s0, nj[0], fma(s1, nj[1], s2 * nj[2])) / r);
+  f[7] = __logf(fmaxf(dn / r, 1e-8f));
 }
 
 template <int KERNEL, int LAYER>
@@ -384,20 +406,15 @@ __global__ __launch_bounds__(kThreads) void k_selector_samples(const SampleArgs 
     for (int q = 0; q < kSelQ; ++q) a.t[k * kSelQ + q] = __builtin_nanf("");
     return;
   }
+  const TriIn ti = tri_inputs(a.geo, a.ldg, i), tj = tri_inputs(a.geo, a.ldg, j);
   float f[8];
-  pair_features(a.geo, a.ldg, i, j, LAYER, a.kappa, f);
+  pair_inputs(ti, tj, LAYER, (float)a.kappa, f);
   for (int c = 0; c < kIn; ++c) a.x[k * kIn + c] = f[c];
   const Acc<KERNEL> ref = regular_pair_fp64<KERNEL, LAYER>(a.geo, a.ldg, a.rule[kSelQ], a.nq[kSelQ],
                                                           a.kappa, i, j);
   // size of a single-layer entry of the pair: |tau_i| |tau_j| / (4 pi r)
   double r2 = 0.0;
-  for (int c = 0; c < 3; ++c) {
-    const double d = (a.geo[(G_V0X + c) * a.ldg + i] +
-                      (2.0 * a.geo[(G_E1X + c) * a.ldg + i] + a.geo[(G_E2X + c) * a.ldg + i]) / 3.0) -
-                     (a.geo[(G_V0X + c) * a.ldg + j] +
-                      (2.0 * a.geo[(G_E1X + c) * a.ldg + j] + a.geo[(G_E2X + c) * a.ldg + j]) / 3.0);
-    r2 = fma(d, d, r2);
-  }
+  for (int c = 0; c < 3; ++c) r2 = fma(ti.c[c] - tj.c[c], ti.c[c] - tj.c[c], r2);
   const double s = 0.25 * a.geo[G_SG * a.ldg + i] * a.geo[G_SG * a.ldg + j] * kInv4Pi / sqrt(r2);
   const double den = fmax(entry_abs<KERNEL>(ref), 1e-3 * s);
   for (int q = 0; q < kSelQ; ++q) {
@@ -407,17 +424,22 @@ __global__ __launch_bounds__(kThreads) void k_selector_samples(const SampleArgs 
   }
 }
 
-// Lane group and result register holding output o (inverse of drow).
-__device__ __forceinline__ constexpr int dgroup(int o) { return o / 4; }
-__device__ __forceinline__ constexpr int dreg(int o) { return o % 4; }
-
 // Orders of the entries of near-field blocks: 0 for pairs with a common
 // vertex, else the smallest order in [q_min, q_plain - 1] whose predicted
 // error plus the margin is at most log10(tol) at it and at every order above
-// it below q_plain; q_plain when q_plain - 1 fails.  One workgroup per block;
-// each wave takes 16 entries at a time.
+// it below q_plain; q_plain when q_plain - 1 fails.  One workgroup per block,
+// 64 x 64 sub-tiles; the sub-tile's triangles' inputs are staged in LDS, each
+// lane forms the inputs of one entry, and each wave runs the network on its
+// 64 entries in four groups of 16 (inputs moved to lanes 0..15 by lane
+// shuffles).
+constexpr int kSelTile = 64;
+
 __global__ __launch_bounds__(kThreads) void k_select_orders(const SelectArgs a) {
-  const int b = blockIdx.x;
+  __shared__ __attribute__((aligned(16))) float bias[kBiasFloats];
+  __shared__ double sc[2][3][kSelTile], sn[2][3][kSelTile];
+  __shared__ float sd[2][3][kSelTile];  // d, area, aspect
+  __shared__ int sv[2][3][kSelTile], sbad;
+  const int b = blockIdx.x, tid = threadIdx.x;
   const int64_t rp0 = a.row_ptr[b], rp1 = a.row_ptr[b + 1];
   const int64_t cp0 = a.col_ptr[b], cp1 = a.col_ptr[b + 1];
   const int64_t off = a.out_off[b];
@@ -426,51 +448,96 @@ __global__ __launch_bounds__(kThreads) void k_select_orders(const SelectArgs a) 
   const int64_t nr = rp1 - rp0, nc = cp1 - cp0;
   ok = ok && (nr == 0 || nc <= (a.out_len - off) / nr);
   if (!ok) {
-    if (threadIdx.x == 0) atomicOr(a.flags, FLAG_EINVAL);
+    if (tid == 0) atomicOr(a.flags, FLAG_EINVAL);
     return;
   }
   Net16 N;
-  load_net(a.params, kSelQ, &N);
-  const int l = threadIdx.x & 63, g = l >> 4, wave = threadIdx.x / kWave;
-  const int64_t ne = nr * nc;
-  for (int64_t e0 = (int64_t)wave * 16; e0 < ne; e0 += 16 * (kThreads / kWave)) {
-    const int64_t e = e0 + (l & 15);
-    const bool live = e < ne;
-    int i = -1, j = -1, cls = 1;
-    if (live) {
-      i = a.row_idx[rp0 + e % nr];
-      j = a.col_idx[cp0 + e / nr];
-      if (i < 0 || i >= a.nt || j < 0 || j >= a.nt) {
-        atomicOr(a.flags, FLAG_EINVAL);
-        i = -1;
-      } else {
-        const int *ti = a.tri + 3 * (int64_t)i, *tj = a.tri + 3 * (int64_t)j;
-        cls = shared_vertex_count(ti[0], ti[1], ti[2], tj[0], tj[1], tj[2]);
-      }
-    }
-    float f[4] = {0.0f, 0.0f, 0.0f, 0.0f};
-    if (i >= 0 && cls == 0 && g < 2) {
-      float all[8];
-      pair_features(a.geo, a.ldg, i, j, a.layer, a.kappa, all);
-      for (int c = 0; c < 4; ++c) f[c] = all[4 * g + c];
-    }
-    const f4 out = net16(N, f);
-    // gather the kSelQ outputs of sample l % 16 into lane group 0
-    float pred[kSelQ];
-    for (int o = 0; o < kSelQ; ++o) pred[o] = __shfl(out[dreg(o)], dgroup(o) * 16 + (l & 15), kWave);
-    if (g == 0 && i >= 0) {
-      int q = 0;
-      if (cls == 0) {
-        q = a.q_plain;
-        bool run = true;
-        for (int qq = a.q_plain - 1; qq >= a.q_min; --qq) {
-          run = run && pred[qq - 1] + a.margin <= a.log_tol;
-          if (run) q = qq;
+  load_net(a.params, kSelQ, &N, bias);
+  const int l = tid & 63, g = l >> 4, wave = tid / kWave;
+  const float kappa = (float)a.kappa;
+  for (int64_t r0 = 0; r0 < nr; r0 += kSelTile)
+    for (int64_t c0 = 0; c0 < nc; c0 += kSelTile) {
+      const int tr = (int)min((int64_t)kSelTile, nr - r0), tc = (int)min((int64_t)kSelTile, nc - c0);
+      __syncthreads();  // LDS of the previous sub-tile no longer read
+      if (tid == 0) sbad = 0;
+      __syncthreads();
+      for (int k = tid; k < tr + tc; k += kThreads) {
+        const int side = k < tr ? 0 : 1, p = side ? k - tr : k;
+        const int id = side ? a.col_idx[cp0 + c0 + p] : a.row_idx[rp0 + r0 + p];
+        if (id < 0 || id >= a.nt) {
+          sbad = 1;
+          continue;
         }
+        const TriIn t = tri_inputs(a.geo, a.ldg, id);
+        for (int m = 0; m < 3; ++m) {
+          sc[side][m][p] = t.c[m];
+          sn[side][m][p] = t.n[m];
+          sv[side][m][p] = a.tri[3 * (int64_t)id + m];
+        }
+        sd[side][0][p] = t.d;
+        sd[side][1][p] = t.area;
+        sd[side][2][p] = t.aspect;
       }
-      a.orders[off + e] = (int8_t)q;
+      __syncthreads();
+      if (sbad) {
+        if (tid == 0) atomicOr(a.flags, FLAG_EINVAL);
+        continue;  // uniform
+      }
+      const int ne = tr * tc;
+      for (int e0 = wave * 64; e0 < ne; e0 += kThreads) {  // no barrier inside: trip counts differ
+        const int e = e0 + l;
+        const bool live = e < ne;
+        const int rl = live ? e % tr : 0, cl = live ? e / tr : 0;
+        const int cls = shared_vertex_count(sv[0][0][rl], sv[0][1][rl], sv[0][2][rl], sv[1][0][cl],
+                                            sv[1][1][cl], sv[1][2][cl]);
+        // standardised inputs of this lane's entry, packed as four half2 words
+        uint32_t w[4] = {0, 0, 0, 0};
+        if (live && cls == 0) {
+          TriIn ti, tj;
+          for (int m = 0; m < 3; ++m) {
+            ti.c[m] = sc[0][m][rl], ti.n[m] = sn[0][m][rl];
+            tj.c[m] = sc[1][m][cl], tj.n[m] = sn[1][m][cl];
+          }
+          ti.d = sd[0][0][rl], ti.area = sd[0][1][rl], ti.aspect = sd[0][2][rl];
+          tj.d = sd[1][0][cl], tj.area = sd[1][1][cl], tj.aspect = sd[1][2][cl];
+          float f[8];
+          pair_inputs(ti, tj, a.layer, kappa, f);
+          const h8 hb = standardise(f, bias);
+          for (int k = 0; k < 4; ++k) {
+            const _Float16 lo = hb[2 * k], hi = hb[2 * k + 1];
+            w[k] = (uint32_t)__builtin_bit_cast(uint16_t, lo) |
+                   ((uint32_t)__builtin_bit_cast(uint16_t, hi) << 16);
+          }
+        }
+        int q = 0;
+        for (int grp = 0; grp < 4; ++grp) {
+          // lanes 0..15 take the inputs of entry grp * 16 + lane
+          h8 bop = {0, 0, 0, 0, 0, 0, 0, 0};
+          uint32_t v[4];
+          for (int k = 0; k < 4; ++k) v[k] = (uint32_t)__shfl((int)w[k], grp * 16 + (l & 15), kWave);
+          if (g == 0)
+            for (int k = 0; k < 4; ++k) {
+              bop[2 * k] = __builtin_bit_cast(_Float16, (uint16_t)(v[k] & 0xffff));
+              bop[2 * k + 1] = __builtin_bit_cast(_Float16, (uint16_t)(v[k] >> 16));
+            }
+          const f4 out = net16(N, bias, bop);
+          // outputs 0..5 of entry grp * 16 + (l & 15) into lane group 0
+          float pred[kSelQ];
+          for (int o = 0; o < kSelQ; ++o)
+            pred[o] = __shfl(out[o & 3], (o >> 2) * 16 + (l & 15), kWave);
+          int qq = a.q_plain;
+          bool run = true;
+          for (int t = a.q_plain - 1; t >= a.q_min; --t) {
+            run = run && pred[t - 1] + a.margin <= a.log_tol;
+            if (run) qq = t;
+          }
+          // back to the lane that owns the entry
+          const int got = __shfl(qq, l & 15, kWave);
+          if ((l >> 4) == grp) q = got;
+        }
+        if (live) a.orders[off + (r0 + rl) + nr * (c0 + cl)] = (int8_t)(cls ? 0 : q);
+      }
     }
-  }
 }
 
 }  // namespace

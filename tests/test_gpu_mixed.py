@@ -82,7 +82,11 @@ def test_mixed_laplace_sphere8192_blocks(pk, ctx, layer):
         sing = np.array([[oracle.shared_vertices(m.tri, i, j) > 0 for j in c] for i in r])
         fp64 = sing | _near_singular(m, r, c, 0.5)
         if fp64.any():
-            rel = np.abs(g[fp64] - ref[fp64]) / np.abs(ref[fp64])
+            # FP32 rounding of the FP64 value; entries that vanish (identical
+            # double-layer pairs, rounding noise on both sides) to 2e-12 of
+            # the block's largest entry
+            den = np.maximum(np.abs(ref[fp64]), 1e-5 * np.abs(ref).max())
+            rel = np.abs(g[fp64] - ref[fp64]) / den
             assert rel.max() <= 2e-7, rel.max()
 
 
@@ -107,7 +111,8 @@ def test_mixed_coupling_and_entries(pk, ctx):
     ctx.eval_entries(mesh, op, torch.from_numpy(r).cuda(), torch.from_numpy(c).cuda(), out)
     ctx.check()
     ref = oracle.entries(m.v, m.tri, r, c, **_kw(op)).real
-    assert np.all(np.abs(out.cpu().numpy() - ref) <= 2e-7 * np.abs(ref) + 1e-30)
+    # the identical double-layer entry (0, 0) vanishes: scale by the largest
+    assert np.all(np.abs(out.cpu().numpy() - ref) <= 2e-7 * np.abs(ref) + 1e-9 * np.abs(ref).max())
 
 
 @pytest.mark.parametrize("layer,kappa", [(0, 8.0), (1, 8.0), (1, 2.0)])

@@ -77,8 +77,14 @@ def test_features_of_a_known_pair():
     assert f[2] == pytest.approx(f[1], rel=1e-15)
     assert f[3] == 1.0 and f[6] == 1.0
     assert f[4] == pytest.approx(2.0 * D, rel=1e-15)
-    assert f[5] == pytest.approx(1.0, rel=1e-15)  # coplanar, same orientation
-    assert abs(f[7]) < 1e-15                       # separation in the plane
+    assert f[5] == pytest.approx(np.log(1e-12), rel=1e-15)  # parallel normals: floor
+    assert f[7] == pytest.approx(np.log(1e-8), rel=1e-15)   # in-plane separation: floor
+    # tilt the second triangle out of the plane: |n_i - n_j|^2 = 2 (1 - cos a)
+    a = 0.3
+    v2 = v.copy()
+    v2[5] = [6.0, np.cos(a), np.sin(a)]
+    f2 = selector.features(v2, tri, [0], [1], layer=1, kappa=2.0)[0]
+    assert f2[5] == pytest.approx(np.log(2 * (1 - np.cos(a))), rel=1e-13)
 
 
 def test_features_are_invariant_under_similarity_maps():
