@@ -27,7 +27,9 @@
  * Streams.  `stream` is a hipStream_t (NULL = the null stream).  Calls only
  *   enqueue work and return; completion is observed by synchronising the
  *   stream.  Calls on one context must not run concurrently from several host
- *   threads.
+ *   threads, and work of one context enqueued on different streams must not
+ *   overlap in time: calls share the context's scratch (triangle geometry,
+ *   packed network, selector inputs, gradient partial sums).
  * Output types.  Laplace plain: double; Helmholtz plain: double[2] (re, im)
  *   interleaved; mixed precision: float / float[2].  Sizes and offsets of
  *   outputs count entries (a complex entry is one entry).

@@ -239,6 +239,7 @@ void bem_destroy(bem_ctx *ctx) {
     }
     if (ctx->geo) (void)hipFree(ctx->geo);
     if (ctx->mlp_scratch) (void)hipFree(ctx->mlp_scratch);
+    if (ctx->sel_scratch) (void)hipFree(ctx->sel_scratch);
     if (ctx->flags) (void)hipFree(ctx->flags);
   }
   delete ctx;

@@ -185,7 +185,10 @@ struct SelectArgs {
   const int64_t *out_off;
   int8_t *orders;
   int64_t out_len;
-  const float *params;
+  const void *net;                 // packed network (launch_pack_net)
+  const double *tin_c, *tin_n;     // per-triangle inputs [3][ldt] (launch_tri_inputs)
+  const float *tin_f;              // d, area, aspect [3][ldt]
+  int64_t ldt;
   int32_t layer, q_plain, q_min;
   float margin, log_tol;
   double kappa;
@@ -207,10 +210,15 @@ hipError_t launch_mlp_grad(int n_out, const float *P, int64_t n, const float *x,
                            float *part, float *lpart, float *grad, float *loss, hipStream_t s);
 hipError_t launch_mlp_adam(int64_t np, float *p, const float *g, float *m, float *v, float lr,
                            float b1, float b2, float eps, float c1, float c2, hipStream_t s);
-hipError_t launch_mlp_forward(bool f16, int n_out, const float *P, int64_t n, const float *x,
-                              float *y, hipStream_t s);
+// packed FP16 network for the matrix-core kernels (mlp_packed_bytes bytes)
+size_t mlp_packed_bytes();
+hipError_t launch_pack_net(int n_out, const float *P, void *packed, hipStream_t s);
+hipError_t launch_tri_inputs(const double *geo, int64_t ldg, int nt, double *tc, double *tn,
+                             float *tf, int64_t ldt, hipStream_t s);
+hipError_t launch_mlp_forward(bool f16, int n_out, const float *P, const void *packed, int64_t n,
+                              const float *x, float *y, hipStream_t s);
 hipError_t launch_selector_samples(int kernel, int layer, const SampleArgs &a, hipStream_t s);
-hipError_t launch_select_orders(const SelectArgs &a, hipStream_t s);
+hipError_t launch_select_orders(const SelectArgs &a, int grid, hipStream_t s);
 // x-points per register chunk of the learned kernel for order q
 int learned_chunk(int q, int kernel);
 hipError_t launch_blocks_learned(int kernel, int layer, const BlockArgs &a, const OrderRules &o,
@@ -278,5 +286,7 @@ struct bem_ctx {
   size_t geo_cap = 0;             // doubles
   float *mlp_scratch = nullptr;   // device: per-workgroup gradient partial sums
   size_t mlp_cap = 0;             // floats
+  void *sel_scratch = nullptr;    // device: packed network + per-triangle selector inputs
+  size_t sel_cap = 0;             // bytes
   std::map<std::tuple<int, int, int>, bem::DevRules> rules;
 };

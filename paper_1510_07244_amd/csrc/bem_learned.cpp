@@ -25,6 +25,21 @@ int grow_mlp_scratch(bem_ctx *ctx, size_t floats) {
   return BEM_OK;
 }
 
+int grow_sel_scratch(bem_ctx *ctx, size_t bytes) {
+  if (bytes <= ctx->sel_cap) return BEM_OK;
+  hipError_t e = hipDeviceSynchronize();
+  if (e != hipSuccess) return hip_fail(ctx, e, "hipDeviceSynchronize");
+  if (ctx->sel_scratch) (void)hipFree(ctx->sel_scratch);
+  ctx->sel_scratch = nullptr;
+  ctx->sel_cap = 0;
+  e = hipMalloc(&ctx->sel_scratch, bytes);
+  if (e != hipSuccess) return hip_fail(ctx, e, "hipMalloc(selector scratch)");
+  ctx->sel_cap = bytes;
+  return BEM_OK;
+}
+
+size_t packed_pad() { return (mlp_packed_bytes() + 255) / 256 * 256; }
+
 // Duffy rules of orders 1 .. max (index = order) for an operator.
 int order_rules(bem_ctx *ctx, const bem_op *op, int qmax, const DevRules **r) {
   for (int q = 1; q <= qmax; ++q) {
@@ -64,7 +79,15 @@ int bem_mlp_forward(bem_ctx *ctx, int32_t n_out, int32_t fp16, const float *para
   if (n == 0) return BEM_OK;
   if (!params || !x || !y) return fail(ctx, BEM_EINVAL, "NULL array");
   DeviceGuard g(ctx->device);
-  hipError_t e = launch_mlp_forward(fp16 == 1, n_out, params, n, x, y, static_cast<hipStream_t>(stream));
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  hipError_t e;
+  if (fp16) {
+    int rc = grow_sel_scratch(ctx, packed_pad());
+    if (rc) return rc;
+    if ((e = launch_pack_net(n_out, params, ctx->sel_scratch, s)) != hipSuccess)
+      return hip_fail(ctx, e, "network packing launch");
+  }
+  e = launch_mlp_forward(fp16 == 1, n_out, params, ctx->sel_scratch, n, x, y, s);
   if (e != hipSuccess) return hip_fail(ctx, e, "network forward launch");
   return BEM_OK;
 }
@@ -164,10 +187,23 @@ int bem_select_orders(bem_ctx *ctx, const bem_mesh *mesh, const bem_op *op,
   if (blocks->n == 0) return BEM_OK;
   DeviceGuard g(ctx->device);
   int64_t ldg;
-  if ((rc = ensure_geo(ctx, mesh->nt, &ldg))) return rc;
+  const int64_t ldt = ((int64_t)mesh->nt + 63) / 64 * 64;
+  if ((rc = ensure_geo(ctx, mesh->nt, &ldg)) ||
+      (rc = grow_sel_scratch(ctx, packed_pad() + (size_t)ldt * (6 * sizeof(double) + 3 * sizeof(float)))))
+    return rc;
+  char *base = static_cast<char *>(ctx->sel_scratch);
+  double *tin_c = reinterpret_cast<double *>(base + packed_pad());
+  double *tin_n = tin_c + 3 * ldt;
+  float *tin_f = reinterpret_cast<float *>(tin_n + 3 * ldt);
   hipStream_t s = static_cast<hipStream_t>(stream);
   hipError_t e = launch_geometry(*mesh, ctx->geo, ldg, ctx->flags, s);
-  if (e != hipSuccess) return hip_fail(ctx, e, "geometry kernel launch");
+  if (e == hipSuccess) e = launch_tri_inputs(ctx->geo, ldg, mesh->nt, tin_c, tin_n, tin_f, ldt, s);
+  if (e == hipSuccess) e = launch_pack_net(kSelQ, params, base, s);
+  if (e != hipSuccess) return hip_fail(ctx, e, "geometry / selector input launch");
+  int ncu = 0;
+  if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, ctx->device) != hipSuccess ||
+      ncu <= 0)
+    ncu = 256;
   SelectArgs a{};
   a.tri = mesh->tri;
   a.nt = mesh->nt;
@@ -183,7 +219,11 @@ int bem_select_orders(bem_ctx *ctx, const bem_mesh *mesh, const bem_op *op,
   a.out_off = blocks->out_off;
   a.orders = orders;
   a.out_len = orders_len;
-  a.params = params;
+  a.net = base;
+  a.tin_c = tin_c;
+  a.tin_n = tin_n;
+  a.tin_f = tin_f;
+  a.ldt = ldt;
   a.layer = op->layer;
   a.q_plain = op->q_regular;
   a.q_min = q_min;
@@ -191,7 +231,7 @@ int bem_select_orders(bem_ctx *ctx, const bem_mesh *mesh, const bem_op *op,
   a.log_tol = (float)std::log10(tol);
   a.kappa = op->kernel == BEM_HELMHOLTZ ? op->kappa : 0.0;
   a.flags = ctx->flags;
-  e = launch_select_orders(a, s);
+  e = launch_select_orders(a, 4 * ncu, s);
   if (e != hipSuccess) return hip_fail(ctx, e, "order selection launch");
   return BEM_OK;
 }

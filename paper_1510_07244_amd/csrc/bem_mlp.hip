@@ -226,10 +226,10 @@ struct Net16 {
 // standardisation mu and 1 / sigma (8 each).
 constexpr int kBiasFloats = 3 * kHid + kOutMax + 2 * kIn;
 
-__device__ __forceinline__ void load_net(const float *__restrict__ P, int n_out, Net16 *N,
-                                         float *bias) {
+// A operands of the network for lane l of a wave.
+__device__ __forceinline__ void build_net(const float *__restrict__ P, int n_out, int l, Net16 *N) {
   const Off of = offsets(n_out);
-  const int l = threadIdx.x & 63, g = l >> 4, c = l & 15;
+  const int g = l >> 4, c = l & 15;
   for (int mt = 0; mt < 4; ++mt) {
     const int row = mt * 16 + c;
     for (int j = 0; j < 8; ++j)
@@ -243,14 +243,49 @@ __device__ __forceinline__ void load_net(const float *__restrict__ P, int n_out,
   for (int ks = 0; ks < 2; ++ks)
     for (int j = 0; j < 8; ++j)
       N->a4[ks][j] = (_Float16)(c < n_out ? P[of.w4 + c * kHid + kidx(ks, g, j)] : 0.0f);
-  for (int k = threadIdx.x; k < kBiasFloats; k += blockDim.x) {
+}
+
+// Packed network: kNetSlots FP16 operand vectors per lane, slot-major
+// ([slot][64 lanes], 16 bytes each), then kBiasFloats floats (biases, mu,
+// 1 / sigma).  Built once per call by one wave (k_pack_net) and read by every
+// wave of the inference kernels with 16-byte loads.
+constexpr int kNetSlots = 22;
+
+__global__ void k_pack_net(int n_out, const float *__restrict__ P, h8 *__restrict__ packed) {
+  const int l = threadIdx.x;
+  Net16 N;
+  build_net(P, n_out, l, &N);
+  int k = 0;
+  for (int mt = 0; mt < 4; ++mt) packed[(k++) * 64 + l] = N.a1[mt];
+  for (int mt = 0; mt < 4; ++mt)
+    for (int ks = 0; ks < 2; ++ks) packed[(k++) * 64 + l] = N.a2[mt][ks];
+  for (int mt = 0; mt < 4; ++mt)
+    for (int ks = 0; ks < 2; ++ks) packed[(k++) * 64 + l] = N.a3[mt][ks];
+  for (int ks = 0; ks < 2; ++ks) packed[(k++) * 64 + l] = N.a4[ks];
+  const Off of = offsets(n_out);
+  float *bias = reinterpret_cast<float *>(packed + kNetSlots * 64);
+  for (int q = l; q < kBiasFloats; q += 64) {
     float v;
-    if (k < 3 * kHid) v = P[(k < kHid ? of.b1 : k < 2 * kHid ? of.b2 - kHid : of.b3 - 2 * kHid) + k];
-    else if (k < 3 * kHid + kOutMax) v = k - 3 * kHid < n_out ? P[of.b4 + k - 3 * kHid] : 0.0f;
-    else if (k < 3 * kHid + kOutMax + kIn) v = P[of.mu + k - 3 * kHid - kOutMax];
-    else v = 1.0f / P[of.sigma + k - 3 * kHid - kOutMax - kIn];
-    bias[k] = v;
+    if (q < 3 * kHid) v = P[(q < kHid ? of.b1 : q < 2 * kHid ? of.b2 - kHid : of.b3 - 2 * kHid) + q];
+    else if (q < 3 * kHid + kOutMax) v = q - 3 * kHid < n_out ? P[of.b4 + q - 3 * kHid] : 0.0f;
+    else if (q < 3 * kHid + kOutMax + kIn) v = P[of.mu + q - 3 * kHid - kOutMax];
+    else v = 1.0f / P[of.sigma + q - 3 * kHid - kOutMax - kIn];
+    bias[q] = v;
   }
+}
+
+// This lane's operands from the packed network, the biases into LDS.
+__device__ __forceinline__ void load_net(const h8 *__restrict__ packed, Net16 *N, float *bias) {
+  const int l = threadIdx.x & 63;
+  int k = 0;
+  for (int mt = 0; mt < 4; ++mt) N->a1[mt] = packed[(k++) * 64 + l];
+  for (int mt = 0; mt < 4; ++mt)
+    for (int ks = 0; ks < 2; ++ks) N->a2[mt][ks] = packed[(k++) * 64 + l];
+  for (int mt = 0; mt < 4; ++mt)
+    for (int ks = 0; ks < 2; ++ks) N->a3[mt][ks] = packed[(k++) * 64 + l];
+  for (int ks = 0; ks < 2; ++ks) N->a4[ks] = packed[(k++) * 64 + l];
+  const float *gb = reinterpret_cast<const float *>(packed + kNetSlots * 64);
+  for (int q = threadIdx.x; q < kBiasFloats; q += blockDim.x) bias[q] = gb[q];
 }
 
 __device__ __forceinline__ f4 bias4(const float *bias, int base, int g) {
@@ -301,12 +336,12 @@ __device__ __forceinline__ f4 net16(const Net16 &N, const float *bias, h8 b) {
 }
 
 // Generic inference over stored inputs x[n][8] -> y[n][n_out].
-__global__ __launch_bounds__(kThreads) void k_mlp_infer16(int n_out, const float *__restrict__ P,
+__global__ __launch_bounds__(kThreads) void k_mlp_infer16(int n_out, const h8 *__restrict__ packed,
                                                           int64_t n, const float *__restrict__ x,
                                                           float *__restrict__ y) {
   __shared__ __attribute__((aligned(16))) float bias[kBiasFloats];
   Net16 N;
-  load_net(P, n_out, &N, bias);
+  load_net(packed, &N, bias);
   __syncthreads();
   const int l = threadIdx.x & 63, g = l >> 4;
   const int64_t nwaves = (int64_t)gridDim.x * (kThreads / kWave);
@@ -377,6 +412,20 @@ __device__ __forceinline__ void pair_inputs(const TriIn &ti, const TriIn &tj, in
   f[7] = __logf(fmaxf(dn / r, 1e-8f));
 }
 
+// Per-triangle inputs of a mesh, structure of arrays with leading dimension
+// ldt: c[3][ldt], n[3][ldt] (FP64), d, area, aspect [3][ldt] (FP32).
+__global__ void k_tri_inputs(const double *__restrict__ geo, int64_t L, int nt,
+                             double *__restrict__ tc, double *__restrict__ tn,
+                             float *__restrict__ tf, int64_t ldt) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nt) return;
+  const TriIn t = tri_inputs(geo, L, i);
+  for (int m = 0; m < 3; ++m) tc[m * ldt + i] = t.c[m], tn[m * ldt + i] = t.n[m];
+  tf[i] = t.d;
+  tf[ldt + i] = t.area;
+  tf[2 * ldt + i] = t.aspect;
+}
+
 template <int KERNEL, int LAYER>
 __device__ __forceinline__ double entry_abs_diff(const Acc<KERNEL> &a, const Acc<KERNEL> &b) {
   if constexpr (KERNEL == BEM_LAPLACE) return fabs(a.re - b.re);
@@ -439,7 +488,13 @@ __global__ __launch_bounds__(kThreads) void k_select_orders(const SelectArgs a) 
   __shared__ double sc[2][3][kSelTile], sn[2][3][kSelTile];
   __shared__ float sd[2][3][kSelTile];  // d, area, aspect
   __shared__ int sv[2][3][kSelTile], sbad;
-  const int b = blockIdx.x, tid = threadIdx.x;
+  const int tid = threadIdx.x;
+  Net16 N;
+  load_net(reinterpret_cast<const h8 *>(a.net), &N, bias);
+  const int l = tid & 63, g = l >> 4, wave = tid / kWave;
+  const float kappa = (float)a.kappa;
+  const int64_t T = a.ldt;
+  for (int b = blockIdx.x; b < a.nblocks; b += gridDim.x) {
   const int64_t rp0 = a.row_ptr[b], rp1 = a.row_ptr[b + 1];
   const int64_t cp0 = a.col_ptr[b], cp1 = a.col_ptr[b + 1];
   const int64_t off = a.out_off[b];
@@ -449,12 +504,8 @@ __global__ __launch_bounds__(kThreads) void k_select_orders(const SelectArgs a) 
   ok = ok && (nr == 0 || nc <= (a.out_len - off) / nr);
   if (!ok) {
     if (tid == 0) atomicOr(a.flags, FLAG_EINVAL);
-    return;
+    continue;  // uniform
   }
-  Net16 N;
-  load_net(a.params, kSelQ, &N, bias);
-  const int l = tid & 63, g = l >> 4, wave = tid / kWave;
-  const float kappa = (float)a.kappa;
   for (int64_t r0 = 0; r0 < nr; r0 += kSelTile)
     for (int64_t c0 = 0; c0 < nc; c0 += kSelTile) {
       const int tr = (int)min((int64_t)kSelTile, nr - r0), tc = (int)min((int64_t)kSelTile, nc - c0);
@@ -468,15 +519,12 @@ __global__ __launch_bounds__(kThreads) void k_select_orders(const SelectArgs a) 
           sbad = 1;
           continue;
         }
-        const TriIn t = tri_inputs(a.geo, a.ldg, id);
         for (int m = 0; m < 3; ++m) {
-          sc[side][m][p] = t.c[m];
-          sn[side][m][p] = t.n[m];
+          sc[side][m][p] = a.tin_c[m * T + id];
+          sn[side][m][p] = a.tin_n[m * T + id];
           sv[side][m][p] = a.tri[3 * (int64_t)id + m];
+          sd[side][m][p] = a.tin_f[m * T + id];
         }
-        sd[side][0][p] = t.d;
-        sd[side][1][p] = t.area;
-        sd[side][2][p] = t.aspect;
       }
       __syncthreads();
       if (sbad) {
@@ -538,6 +586,7 @@ __global__ __launch_bounds__(kThreads) void k_select_orders(const SelectArgs a) 
         if (live) a.orders[off + (r0 + rl) + nr * (c0 + cl)] = (int8_t)(cls ? 0 : q);
       }
     }
+  }
 }
 
 }  // namespace
@@ -572,12 +621,28 @@ hipError_t launch_mlp_adam(int64_t np, float *p, const float *g, float *m, float
   return hipGetLastError();
 }
 
-hipError_t launch_mlp_forward(bool f16, int n_out, const float *P, int64_t n, const float *x,
-                              float *y, hipStream_t s) {
+size_t mlp_packed_bytes() { return sizeof(h8) * kNetSlots * 64 + sizeof(float) * kBiasFloats; }
+
+hipError_t launch_pack_net(int n_out, const float *P, void *packed, hipStream_t s) {
+  hipLaunchKernelGGL(k_pack_net, dim3(1), dim3(64), 0, s, n_out, P, static_cast<h8 *>(packed));
+  return hipGetLastError();
+}
+
+hipError_t launch_tri_inputs(const double *geo, int64_t ldg, int nt, double *tc, double *tn,
+                             float *tf, int64_t ldt, hipStream_t s) {
+  if (nt == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_tri_inputs, dim3((nt + 255) / 256), dim3(256), 0, s, geo, ldg, nt, tc, tn,
+                     tf, ldt);
+  return hipGetLastError();
+}
+
+hipError_t launch_mlp_forward(bool f16, int n_out, const float *P, const void *packed, int64_t n,
+                              const float *x, float *y, hipStream_t s) {
   if (f16) {
     const int64_t groups = (n + 15) / 16;
     const unsigned grid = (unsigned)std::min<int64_t>((groups + 3) / 4, 2048);
-    hipLaunchKernelGGL(k_mlp_infer16, dim3(grid), dim3(kThreads), 0, s, n_out, P, n, x, y);
+    hipLaunchKernelGGL(k_mlp_infer16, dim3(grid), dim3(kThreads), 0, s, n_out,
+                       static_cast<const h8 *>(packed), n, x, y);
   } else {
     hipLaunchKernelGGL(k_mlp_fwd32, dim3((unsigned)((n + kThreads - 1) / kThreads)),
                        dim3(kThreads), 0, s, n_out, P, n, x, y);
@@ -597,8 +662,8 @@ hipError_t launch_selector_samples(int kernel, int layer, const SampleArgs &a, h
   return hipGetLastError();
 }
 
-hipError_t launch_select_orders(const SelectArgs &a, hipStream_t s) {
-  hipLaunchKernelGGL(k_select_orders, dim3(a.nblocks), dim3(kThreads), 0, s, a);
+hipError_t launch_select_orders(const SelectArgs &a, int grid, hipStream_t s) {
+  hipLaunchKernelGGL(k_select_orders, dim3(std::min(a.nblocks, grid)), dim3(kThreads), 0, s, a);
   return hipGetLastError();
 }
 
