@@ -350,11 +350,55 @@ __device__ __forceinline__ Acc<KERNEL> ss_pair_lane(const PairGeo &g, const SSAr
                                                     double kappa) {
   const uniform_ptr T = (uniform_ptr)(ss.eta[cls]);
   const int n = ss.np[cls];
-  double are = 0.0, aim = 0.0;
-  for (int p = 0; p < n; ++p)
+  // U eta points per step into U accumulators, written stage by stage so
+  // that the independent chains interleave (the sum order is fixed)
+  constexpr int U = KERNEL == BEM_LAPLACE ? 4 : 2;
+  double are[U], aim[U];
+#pragma unroll
+  for (int u = 0; u < U; ++u) are[u] = 0.0, aim[u] = 0.0;
+  int p = 0;
+  if constexpr (KERNEL == BEM_LAPLACE) {
+    for (; p + U <= n; p += U) {
+      double d0[U], d1[U], d2[U], r2[U], h[U], w[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const double g1 = T[p + u], g2 = T[n + p + u], g3 = T[2 * n + p + u], g4 = T[3 * n + p + u];
+        w[u] = T[4 * n + p + u];
+        d0[u] = fma(g1, g.E1i[0], fma(g2, g.E2i[0], fma(-g3, g.E1j[0], -g4 * g.E2j[0])));
+        d1[u] = fma(g1, g.E1i[1], fma(g2, g.E2i[1], fma(-g3, g.E1j[1], -g4 * g.E2j[1])));
+        d2[u] = fma(g1, g.E1i[2], fma(g2, g.E2i[2], fma(-g3, g.E1j[2], -g4 * g.E2j[2])));
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u) r2[u] = fma(d0[u], d0[u], fma(d1[u], d1[u], d2[u] * d2[u]));
+#pragma unroll
+      for (int u = 0; u < U; ++u) h[u] = __builtin_amdgcn_rsq(r2[u]);
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        // one Newton step: z = h + h (1 - r2 h^2) / 2 ~ 1 / |d|
+        const double z = fma(0.5 * h[u], fma(-(r2[u] * h[u]), h[u], 1.0), h[u]);
+        if constexpr (LAYER == BEM_SLP) {
+          are[u] = fma(w[u], z, are[u]);
+        } else {
+          const double dn = fma(d0[u], g.n[0], fma(d1[u], g.n[1], d2[u] * g.n[2]));
+          are[u] = fma(w[u] * dn, z * z * z, are[u]);
+        }
+      }
+    }
+  } else {
+    for (; p + U <= n; p += U) {
+#pragma unroll
+      for (int u = 0; u < U; ++u)
+        eta_point<KERNEL, LAYER>(g, T[p + u], T[n + p + u], T[2 * n + p + u], T[3 * n + p + u],
+                                 T[4 * n + p + u], ss, kappa, &are[u], &aim[u]);
+    }
+  }
+  for (; p < n; ++p)
     eta_point<KERNEL, LAYER>(g, T[p], T[n + p], T[2 * n + p], T[3 * n + p], T[4 * n + p], ss,
-                             kappa, &are, &aim);
-  return ss_finish<KERNEL, LAYER>(g, ss, are, aim);
+                             kappa, &are[0], &aim[0]);
+  double re = are[0], im = aim[0];
+#pragma unroll
+  for (int u = 1; u < U; ++u) re += are[u], im += aim[u];
+  return ss_finish<KERNEL, LAYER>(g, ss, re, im);
 }
 
 // One singular pair per wave: lanes stride over the eta points, then a

@@ -67,7 +67,14 @@ class H2Setup:
         self.mesh = Mesh(torch.from_numpy(self.v), torch.from_numpy(self.tri))
         t0 = time.perf_counter()
         self.ct = ClusterTree(self.v, self.tri, leaf=leaf)
-        self.near, self.far = block_tree(self.ct, eta=eta)
+        near, self.far = block_tree(self.ct, eta=eta)
+        # near-field blocks in decreasing estimated cost (blocks on the
+        # diagonal carry the identical pairs, then by size): the block kernel
+        # is dispatched in list order, so the largest blocks start first and
+        # the small ones fill the tail (longest-processing-time order)
+        size = (self.ct.end - self.ct.begin).astype(np.int64)
+        key = [(-(int(t) == int(s)), -int(size[t] * size[s])) for t, s in near]
+        self.near = near[sorted(range(len(near)), key=lambda k: key[k])]
         self.t_tree = time.perf_counter() - t0
         # heights: leaves 0, fathers 1 + max(sons)
         n = self.ct.n
