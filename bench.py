@@ -46,6 +46,31 @@ FP32_VALU_PEAK = 157.3e12  # published, with packed FP32 (this build does not us
 MIXED_RATIO = 0.5  # mixed form: pairs with box gap < 0.5 max diameter stay FP64
 
 
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_k_blocks_nearfield_sphere8192.md")
+
+
+def stored_traffic():
+    """HBM bytes per DLP near-field launch from the committed counter passes
+    (FETCH_SIZE and WRITE_SIZE, each scaled by its reading of a copy of known
+    size), or None if the block kernel's sources changed since."""
+    import hashlib
+    try:
+        kv = {}
+        for line in open(TRAFFIC_FILE):
+            if ":" in line and line.startswith("    "):
+                k, v = line.strip().split(":", 1)
+                kv[k.strip()] = v.strip()
+        h = hashlib.sha256()
+        for src in kv["sources"].split():
+            h.update(open(os.path.join(ROOT, src), "rb").read())
+        if h.hexdigest() != kv["source_sha256"]:
+            return None
+        return 1024.0 * (float(kv["fetch_kib_per_launch"]) * float(kv["fetch_scale"]) +
+                         float(kv["write_kib_per_launch"]) * float(kv["write_scale"]))
+    except (OSError, KeyError, ValueError):
+        return None
+
+
 def parse():
     p = argparse.ArgumentParser()
     p.add_argument("--gpus", type=int, default=1)
@@ -452,7 +477,8 @@ def main():
             "kernel": "k_blocks<Laplace, DLP> near field (+ geometry kernel in the same call)",
             "bound": "alu", "achieved": f_dlp / (phase["nd"] * 1e-3) / 1e12,
             "peak": FP64_VALU_PEAK / 1e12, "unit": "TFLOP/s",
-            "frac": f_dlp / (phase["nd"] * 1e-3) / FP64_VALU_PEAK, "traffic": None,
+            "frac": f_dlp / (phase["nd"] * 1e-3) / FP64_VALU_PEAK, "traffic": stored_traffic(),
+            "traffic_unit": "bytes per launch (FETCH_SIZE + WRITE_SIZE, calibrated)",
             "ms_per_launch": phase["nd"], "flops_per_launch": f_dlp,
         },
         "roofline_slp": {
