@@ -168,9 +168,9 @@ int bem_eval_entries(bem_ctx *ctx, const bem_mesh *mesh, const bem_op *op, int64
  * bounded size that worker threads dequeue and run on the GPU (Algorithms
  * add_block / assemble_gpu and schedule_tasks).  Here the lists of many
  * block lists, possibly of many meshes, become one device queue of
- * sub-tiles (at most 64 x 64 entries of one block), sorted by decreasing
- * estimated cost; a fixed grid of workgroups pops sub-tiles from it until
- * it is empty.  The queue, per-mesh geometry and launch are built once by
+ * work items (whole blocks, or sub-tiles of at most 64 x 64 entries),
+ * sorted by decreasing estimated cost; a fixed grid of workgroups pops items
+ * from it until it is empty.  The queue, per-mesh geometry and launch are built once by
  * bem_plan_batched and captured in a HIP graph (a counter-reset kernel,
  * the geometry kernels and the persistent kernel); bem_run_batched replays
  * it.  Entries are bitwise equal to those of bem_assemble_nearfield /
@@ -200,7 +200,11 @@ typedef struct {
   int32_t x_chunk;   /* regular-rule points per register chunk: 4, 5, 7, 8 or 9
                         (default: the per-block kernel's) */
   int32_t autotune;  /* 1: time the candidates of every field left 0 */
-  int32_t reserved[3];
+  int32_t granularity; /* work item of the queue: 1 whole blocks (each
+                          popped block's sub-tiles in turn, like the
+                          per-block kernel), 2 single sub-tiles; 0: the
+                          library's choice (1 unless autotuned) */
+  int32_t reserved[2];
   double tuned_ms;   /* out: time of one launch of the chosen configuration
                         (0 when nothing was timed) */
 } bem_tune;
@@ -226,7 +230,7 @@ int bem_plan_batched(bem_ctx *ctx, const bem_op *op, int32_t nbatch, const bem_b
  * plan's context as for the per-call entry points (see bem_check). */
 int bem_run_batched(bem_plan *plan, void *stream);
 
-/* Sub-tiles in the plan's queue (0 for a NULL plan). */
+/* Work items in the plan's queue (0 for a NULL plan). */
 int64_t bem_plan_tiles(const bem_plan *plan);
 
 /* Release a plan (waits for its device work).  NULL is a no-op. */

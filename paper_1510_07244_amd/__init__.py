@@ -340,7 +340,8 @@ class bem_batch(ctypes.Structure):
 class bem_tune(ctypes.Structure):
     _fields_ = [("grid", ctypes.c_int32), ("tile_rows", ctypes.c_int32),
                 ("tile_cols", ctypes.c_int32), ("x_chunk", ctypes.c_int32),
-                ("autotune", ctypes.c_int32), ("reserved", ctypes.c_int32 * 3),
+                ("autotune", ctypes.c_int32), ("granularity", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 2),
                 ("tuned_ms", ctypes.c_double)]
 
 
@@ -377,7 +378,8 @@ class Plan:
         t = dict(tune or {})
         self.tune = bem_tune(int(t.get("grid", 0)), int(t.get("tile_rows", 0)),
                              int(t.get("tile_cols", 0)), int(t.get("x_chunk", 0)),
-                             int(bool(autotune)), (ctypes.c_int32 * 3)(0, 0, 0), 0.0)
+                             int(bool(autotune)), int(t.get("granularity", 0)),
+                             (ctypes.c_int32 * 2)(0, 0), 0.0)
         h = ctypes.c_void_p()
         path = os.fsencode(cache) if cache else None
         ctx._rc(_lib.bem_plan_batched(ctx.h, ctypes.byref(op), n, self._c, ctypes.byref(self.tune),
@@ -388,7 +390,7 @@ class Plan:
     def config(self):
         t = self.tune
         return dict(grid=t.grid, tile_rows=t.tile_rows, tile_cols=t.tile_cols,
-                    x_chunk=t.x_chunk, tuned_ms=t.tuned_ms)
+                    x_chunk=t.x_chunk, granularity=t.granularity, tuned_ms=t.tuned_ms)
 
     @property
     def tiles(self):

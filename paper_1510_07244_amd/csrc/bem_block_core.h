@@ -104,10 +104,8 @@ __device__ __forceinline__ Acc<KERNEL> regular_entry(const Lds &l, int TR, int T
       WX[a] = w * SG;
       if constexpr (LAYER == BEM_DLP) WN[a] = WX[a] * fma(X0[a], n0, fma(X1[a], n1, X2[a] * n2));
     }
-    const double2 *yp = ycol;
-#pragma unroll 2
-    for (int kb = 0; kb < nqp; ++kb, yp += ystride) {
-      const double2 c0 = yp[0], c1 = yp[1], c2 = yp[2];
+    // one column point: (-2Y, |Y|^2, w sqrt(g_j), <Y, n_j>) as three double2
+    auto point = [&](const double2 c0, const double2 c1, const double2 c2) {
       const double M0 = c0.x, M1 = c0.y, M2 = c1.x, YY = c1.y, WY = c2.x, YN = c2.y;
       // the XC chains are written stage by stage so that they interleave
       double sq[XC], h[XC];
@@ -145,7 +143,23 @@ __device__ __forceinline__ Acc<KERNEL> regular_entry(const Lds &l, int TR, int T
       }
       acc.re = fma(WY, ire, acc.re);
       if constexpr (KERNEL == BEM_HELMHOLTZ) acc.im = fma(WY, iim, acc.im);
+    };
+    // two points per step, the next one's LDS reads issued before the
+    // current one's arithmetic (no register copies between steps)
+    const double2 *yp = ycol;
+    double2 a0 = yp[0], a1 = yp[1], a2 = yp[2];
+    int kb = 0;
+    for (; kb + 2 <= nqp; kb += 2) {
+      const double2 *yn = yp + ystride;
+      const double2 b0 = yn[0], b1 = yn[1], b2 = yn[2];
+      __builtin_amdgcn_sched_barrier(0);  // keep the reads ahead of the arithmetic
+      point(a0, a1, a2);
+      yp = ycol + (kb + 2 < nqp ? kb + 2 : nqp - 1) * ystride;
+      a0 = yp[0], a1 = yp[1], a2 = yp[2];
+      __builtin_amdgcn_sched_barrier(0);
+      point(b0, b1, b2);
     }
+    if (kb < nqp) point(a0, a1, a2);
   }
   return acc;
 }
@@ -193,10 +207,8 @@ __device__ __forceinline__ Acc<KERNEL> regular_entry_f32(const Lds &l, int TR, i
       WX[a] = (float)(w * SG) * (LAYER == BEM_SLP ? 2.0f : 8.0f);
       if constexpr (LAYER == BEM_DLP) WN[a] = WX[a] * fmaf(x0, n0, fmaf(x1, n1, x2 * n2));
     }
-    const float4 *yp = ycol;
-#pragma unroll 2
-    for (int kb = 0; kb < nqp; ++kb, yp += ystride) {
-      const float4 c0 = yp[0], c1 = yp[1];
+    // one column point: (Y, w sqrt(g_j), <Y, n_j>) as two float4
+    auto point = [&](const float4 c0, const float4 c1) {
       const float y0 = d0 + c0.x, y1 = d1 + c0.y, y2 = d2 + c0.z, WY = c0.w;
       const float YY = fmaf(y0, y0, fmaf(y1, y1, y2 * y2));
       const float YN = dn + c1.x;  // <Y', n_j>
@@ -233,7 +245,22 @@ __device__ __forceinline__ Acc<KERNEL> regular_entry_f32(const Lds &l, int TR, i
       }
       are = fmaf(WY, ire, are);
       if constexpr (KERNEL == BEM_HELMHOLTZ) aim = fmaf(WY, iim, aim);
+    };
+    // two points per step, the next one's LDS reads issued first
+    const float4 *yp = ycol;
+    float4 a0 = yp[0], a1 = yp[1];
+    int kb = 0;
+    for (; kb + 2 <= nqp; kb += 2) {
+      const float4 *yn = yp + ystride;
+      const float4 b0 = yn[0], b1 = yn[1];
+      __builtin_amdgcn_sched_barrier(0);  // keep the reads ahead of the arithmetic
+      point(a0, a1);
+      yp = ycol + (kb + 2 < nqp ? kb + 2 : nqp - 1) * ystride;
+      a0 = yp[0], a1 = yp[1];
+      __builtin_amdgcn_sched_barrier(0);
+      point(b0, b1);
     }
+    if (kb < nqp) point(a0, a1);
   }
   Acc<KERNEL> acc;
   acc.re = are;

@@ -398,9 +398,23 @@ __global__ __launch_bounds__(kThreads, 2) void k_blocks(const BlockArgs a, const
       subtile<KERNEL, LAYER, XC, MIXED>(a, l, h, r0, c0, coupling);
 }
 
-// Persistent form: every workgroup pops sub-tiles (batch, block, r0, c0) from
-// a queue sorted by decreasing cost until it is empty; every batch shares the
-// operator (rule, sub-tile shape) and has its own mesh, blocks and output.
+// Persistent form: every workgroup pops work items (batch, block, r0, c0) --
+// one sub-tile, or the whole block when r0 = c0 = -1 -- from a queue sorted by
+// decreasing cost until it is empty; every batch shares the operator (rule,
+// sub-tile shape) and has its own mesh, blocks and output.
+// Copy of a read-only struct at a wave-uniform address by scalar loads.
+template <class T>
+__device__ __forceinline__ T uniform_copy(const T *p) {
+  static_assert(sizeof(T) % 4 == 0, "dword-sized struct");
+  typedef const uint32_t __attribute__((address_space(4))) *cword_t;
+  T v;
+  const cword_t src = (cword_t)p;
+  uint32_t *dst = reinterpret_cast<uint32_t *>(&v);
+#pragma unroll
+  for (int k = 0; k < (int)(sizeof(T) / 4); ++k) dst[k] = src[k];
+  return v;
+}
+
 template <int KERNEL, int LAYER, int XC, bool MIXED>
 __global__ __launch_bounds__(kThreads, 2) void k_persistent(const BlockArgs *batches,
                                                             const int32_t *coupling,
@@ -408,28 +422,42 @@ __global__ __launch_bounds__(kThreads, 2) void k_persistent(const BlockArgs *bat
                                                             int32_t nbatch, int32_t *counter) {
   extern __shared__ double lds_raw[];
   __shared__ int s_tile;
-  const BlockArgs &a0 = batches[0];
+  // the queue and the batch arguments are read-only here: wave-uniform
+  // (scalar) loads keep every argument, pointer and loop bound in scalar
+  // registers as in the per-block kernel
+  typedef const int32_t __attribute__((address_space(4))) *cint_t;
+  const BlockArgs a0 = uniform_copy(batches);
   const Lds l = carve<MIXED>(lds_raw, a0.nq_pad, a0.tr, a0.tc);
   load_rule(a0, l);
   for (;;) {
     __syncthreads();  // everyone has read s_tile and left the previous tile
     if (threadIdx.x == 0) s_tile = atomicAdd(counter, 1);
     __syncthreads();
-    const int t = s_tile;
+    const int t = __builtin_amdgcn_readfirstlane(s_tile);
     if (t >= ntiles) break;  // the counter only grows: every workgroup exits
-    const int4 d = tiles[t];
+    const int4 d = uniform_copy(tiles + t);
     if (d.x < 0 || d.x >= nbatch) {
       if (threadIdx.x == 0) atomicOr(a0.flags, FLAG_EINVAL);
       continue;
     }
-    const BlockArgs &a = batches[d.x];
+    const BlockArgs a = uniform_copy(batches + d.x);
+    const int cp = ((cint_t)coupling)[d.x];
     if (d.y < 0 || d.y >= a.nblocks) {
       if (threadIdx.x == 0) atomicOr(a.flags, FLAG_EINVAL);
       continue;
     }
     BlockHdr h;
-    if (!block_header(a, d.y, &h) || d.z >= h.nr || d.w >= h.nc || d.z < 0 || d.w < 0) continue;
-    subtile<KERNEL, LAYER, XC, MIXED>(a, l, h, d.z, d.w, coupling[d.x]);
+    if (!block_header(a, d.y, &h) || h.nr == 0 || h.nc == 0) continue;
+    if (d.z == -1 && d.w == -1) {  // the whole block, sub-tile by sub-tile
+      for (int64_t r0 = 0; r0 < h.nr; r0 += a.tr)
+        for (int64_t c0 = 0; c0 < h.nc; c0 += a.tc) subtile<KERNEL, LAYER, XC, MIXED>(a, l, h, r0, c0, cp);
+      continue;
+    }
+    if (d.z >= h.nr || d.w >= h.nc || d.z < 0 || d.w < 0) {
+      if (threadIdx.x == 0) atomicOr(a.flags, FLAG_EINVAL);
+      continue;
+    }
+    subtile<KERNEL, LAYER, XC, MIXED>(a, l, h, d.z, d.w, cp);
   }
 }
 

@@ -20,6 +20,7 @@
 #include <new>
 #include <sstream>
 #include <string>
+#include <tuple>
 #include <vector>
 
 #include "bem_internal.h"
@@ -68,9 +69,12 @@ hipError_t d2h(std::vector<T> *dst, const T *src, int64_t n) {
   return hipMemcpy(dst->data(), src, (size_t)n * sizeof(T), hipMemcpyDeviceToHost);
 }
 
-// Estimated cost of one sub-tile in quadrature points: regular entries use
-// nqp^2 points; a pair with k common vertices adds about 2 k q_s^3 points of
-// the Sauter-Schwab rules (2, 5 and 6 regions of q_s^3 for k = 1, 2, 3).
+// Estimated cost of one sub-tile in regular point-pair units: regular
+// entries use nqp^2 point pairs; a pair with k common vertices has 2, 5 or 6
+// regions of q_s^3 eta points (k = 1, 2, 3), each about twice a regular
+// point pair's work and summed one pair per lane: 8 k q_s^3 (measured on the
+// near field of the 8192-triangle sphere, the singular pass takes about 1/6
+// of the launch for 1/40 of its flops).
 struct CostModel {
   int nqp = 0, qs = 0;
   std::vector<int32_t> vcount;  // per vertex: rows of the tile touching it
@@ -87,15 +91,16 @@ double tile_cost(CostModel &cm, const HostBatch &hb, const std::vector<int32_t> 
     for (int m = 0; m < 3; ++m) shared += cm.vcount[tri[3 * (size_t)hb.col_idx[cp0 + c0 + k] + m]];
   for (int k = 0; k < tr; ++k)
     for (int m = 0; m < 3; ++m) cm.vcount[tri[3 * (size_t)hb.row_idx[rp0 + r0 + k] + m]] = 0;
-  return reg + 2.0 * (double)shared * cm.qs * cm.qs * cm.qs;
+  return reg + 8.0 * (double)shared * cm.qs * cm.qs * cm.qs;
 }
 
-// Sub-tiles (batch, block, first row, first column) of every block, sorted
-// by decreasing cost; ties keep the natural order.
+// Work items (batch, block, first row, first column) -- every sub-tile, or
+// with whole = true every block as (batch, block, -1, -1) with the sum of its
+// sub-tiles' costs -- sorted by decreasing cost; ties keep the natural order.
 std::vector<int4> build_tiles(const std::vector<HostBatch> &hbs,
                               const std::vector<std::vector<int32_t>> &tris,
                               const std::vector<bem_mesh> &meshes, int tr, int tc, int nqp,
-                              int qs) {
+                              int qs, bool whole) {
   std::vector<int4> tiles;
   std::vector<double> cost;
   for (size_t e = 0; e < hbs.size(); ++e) {
@@ -107,12 +112,23 @@ std::vector<int4> build_tiles(const std::vector<HostBatch> &hbs,
     for (int32_t b = 0; b < hb.blocks.n; ++b) {
       const int64_t rp0 = hb.row_ptr[b], cp0 = hb.col_ptr[b];
       const int64_t nr = hb.row_ptr[b + 1] - rp0, nc = hb.col_ptr[b + 1] - cp0;
+      if (nr == 0 || nc == 0) continue;
+      double sum = 0.0;
       for (int64_t r0 = 0; r0 < nr; r0 += tr)
         for (int64_t c0 = 0; c0 < nc; c0 += tc) {
           const int etr = (int)std::min<int64_t>(tr, nr - r0), etc = (int)std::min<int64_t>(tc, nc - c0);
-          tiles.push_back(make_int4((int)e, b, (int)r0, (int)c0));
-          cost.push_back(tile_cost(cm, hb, tris[hb.mesh], rp0, cp0, r0, c0, etr, etc));
+          const double c = tile_cost(cm, hb, tris[hb.mesh], rp0, cp0, r0, c0, etr, etc);
+          if (whole) {
+            sum += c;
+          } else {
+            tiles.push_back(make_int4((int)e, b, (int)r0, (int)c0));
+            cost.push_back(c);
+          }
         }
+      if (whole) {
+        tiles.push_back(make_int4((int)e, b, -1, -1));
+        cost.push_back(sum);
+      }
     }
   }
   std::vector<size_t> order(tiles.size());
@@ -152,7 +168,8 @@ int validate(bem_ctx *ctx, const HostBatch &hb, const bem_mesh &m, int e) {
 
 // ---------------------------------------------------------------- tuning cache
 // One JSON object per line:
-//   {"key": "...", "grid": G, "tile_rows": R, "tile_cols": C, "x_chunk": X, "ms": T}
+//   {"key": "...", "grid": G, "tile_rows": R, "tile_cols": C, "x_chunk": X,
+//    "granularity": 1 (blocks) or 2 (sub-tiles), "ms": T}
 bool json_int(const std::string &line, const char *field, long *v) {
   const std::string pat = std::string("\"") + field + "\":";
   const size_t p = line.find(pat);
@@ -171,13 +188,15 @@ bool cache_lookup(const char *path, const std::string &key, bem_tune *t) {
   bool found = false;
   while (std::getline(f, line)) {  // the last matching line wins
     if (line.find(kpat) == std::string::npos) continue;
-    long g, r, c, x;
+    long g, r, c, x, w;
     if (json_int(line, "grid", &g) && json_int(line, "tile_rows", &r) &&
-        json_int(line, "tile_cols", &c) && json_int(line, "x_chunk", &x)) {
+        json_int(line, "tile_cols", &c) && json_int(line, "x_chunk", &x) &&
+        json_int(line, "granularity", &w)) {
       t->grid = (int32_t)g;
       t->tile_rows = (int32_t)r;
       t->tile_cols = (int32_t)c;
       t->x_chunk = (int32_t)x;
+      t->granularity = (int32_t)w;
       found = true;
     }
   }
@@ -190,7 +209,7 @@ void cache_store(const char *path, const std::string &key, const bem_tune &t) {
   if (!f) return;
   f << "{\"key\": \"" << key << "\", \"grid\": " << t.grid << ", \"tile_rows\": " << t.tile_rows
     << ", \"tile_cols\": " << t.tile_cols << ", \"x_chunk\": " << t.x_chunk
-    << ", \"ms\": " << t.tuned_ms << "}\n";
+    << ", \"granularity\": " << t.granularity << ", \"ms\": " << t.tuned_ms << "}\n";
 }
 
 bool valid_chunk(int x) { return x == 4 || x == 5 || x == 7 || x == 8 || x == 9; }
@@ -206,6 +225,7 @@ void release(bem_plan *p) {
 
 struct Candidate {
   int grid, tr, tc, xc;
+  bool whole;  // queue whole blocks instead of sub-tiles
 };
 
 }  // namespace
@@ -224,10 +244,10 @@ int bem_plan_batched(bem_ctx *ctx, const bem_op *op, int32_t nbatch, const bem_b
   if (tune) want = *tune;
   if (want.grid < 0 || want.tile_rows < 0 || want.tile_rows > 64 || want.tile_cols < 0 ||
       want.tile_cols > 64 || (want.x_chunk && !valid_chunk(want.x_chunk)) ||
-      (want.autotune != 0 && want.autotune != 1) || want.reserved[0] || want.reserved[1] ||
-      want.reserved[2])
+      (want.autotune != 0 && want.autotune != 1) || want.granularity < 0 ||
+      want.granularity > 2 || want.reserved[0] || want.reserved[1])
     return fail(ctx, BEM_EINVAL, "tune: grid >= 0, tiles in [0, 64], x_chunk in {0,4,5,7,8,9}, "
-                                 "autotune 0/1, reserved 0");
+                                 "autotune 0/1, granularity 0..2, reserved 0");
   DeviceGuard guard(ctx->device);
   hipStream_t s = static_cast<hipStream_t>(stream);
   bem_plan *p = new (std::nothrow) bem_plan;
@@ -362,20 +382,25 @@ int bem_plan_batched(bem_ctx *ctx, const bem_op *op, int32_t nbatch, const bem_b
     }
     for (auto sh : shapes) {
       if (block_lds_bytes(nqp, sh.first, sh.second, p->mixed) > ctx->lds_budget) continue;
-      for (int g : grids) cands.push_back({g, sh.first, sh.second, xc});
+      for (int g : grids) {
+        if (want.granularity != 2) cands.push_back({g, sh.first, sh.second, xc, true});
+        if (want.granularity == 2 || (want.granularity == 0 && want.autotune))
+          cands.push_back({g, sh.first, sh.second, xc, false});
+      }
     }
   }
   if (cands.empty())
     return bail(fail(ctx, BEM_EUNSUPPORTED, "no sub-tile shape fits the LDS budget"));
 
   // ---- per-candidate device state
-  std::map<std::pair<int, int>, std::vector<int4>> tile_sets;  // by shape (xc-independent)
+  std::map<std::tuple<int, int, bool>, std::vector<int4>> tile_sets;  // xc-independent
   auto tiles_for = [&](const Candidate &c) -> const std::vector<int4> & {
-    auto key = std::make_pair(c.tr, c.tc);
+    auto key = std::make_tuple(c.tr, c.tc, c.whole);
     auto it = tile_sets.find(key);
     if (it == tile_sets.end()) {
       const int nqp = (p->nq + def_xc - 1) / def_xc * def_xc;
-      it = tile_sets.emplace(key, build_tiles(hbs, tris, p->meshes, c.tr, c.tc, nqp, op->q_singular)).first;
+      it = tile_sets.emplace(key, build_tiles(hbs, tris, p->meshes, c.tr, c.tc, nqp, op->q_singular,
+                                              c.whole)).first;
     }
     return it->second;
   };
@@ -468,7 +493,7 @@ int bem_plan_batched(bem_ctx *ctx, const bem_op *op, int32_t nbatch, const bem_b
   ks << arch << "/cu" << ncu << "/k" << op->kernel << "l" << op->layer << "p" << op->precision
      << "r" << op->regular_rule << "q" << op->q_regular << "s" << op->q_singular << "/b" << nbatch
      << "c" << ncoup << "t" << tri_total << "e" << entries << "/fix" << want.grid << ","
-     << want.tile_rows << "," << want.tile_cols << "," << want.x_chunk;
+     << want.tile_rows << "," << want.tile_cols << "," << want.x_chunk << "," << want.granularity;
   const std::string key = ks.str();
   Candidate best = cands[0];
   double best_ms = 0.0;
@@ -479,7 +504,10 @@ int bem_plan_batched(bem_ctx *ctx, const bem_op *op, int32_t nbatch, const bem_b
     hit = nqp > 0 && p->nq % cached.x_chunk == 0 && cached.grid > 0 && cached.tile_rows >= 1 &&
           cached.tile_rows <= 64 && cached.tile_cols >= 1 && cached.tile_cols <= 64 &&
           block_lds_bytes(nqp, cached.tile_rows, cached.tile_cols, p->mixed) <= ctx->lds_budget;
-    if (hit) best = {cached.grid, cached.tile_rows, cached.tile_cols, cached.x_chunk};
+    hit = hit && (cached.granularity == 1 || cached.granularity == 2) &&
+          (want.granularity == 0 || want.granularity == cached.granularity);
+    if (hit)
+      best = {cached.grid, cached.tile_rows, cached.tile_cols, cached.x_chunk, cached.granularity == 1};
   }
   if (!hit && want.autotune && cands.size() > 1) {
     hipEvent_t t0, t1;
@@ -516,6 +544,7 @@ int bem_plan_batched(bem_ctx *ctx, const bem_op *op, int32_t nbatch, const bem_b
   p->cfg.tile_rows = best.tr;
   p->cfg.tile_cols = best.tc;
   p->cfg.x_chunk = best.xc;
+  p->cfg.granularity = best.whole ? 1 : 2;
   p->cfg.autotune = want.autotune;
   p->cfg.tuned_ms = best_ms;
   if (want.autotune && !hit && best_ms > 0) cache_store(cache_path, key, p->cfg);

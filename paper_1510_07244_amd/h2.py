@@ -67,14 +67,17 @@ class H2Setup:
         self.mesh = Mesh(torch.from_numpy(self.v), torch.from_numpy(self.tri))
         t0 = time.perf_counter()
         self.ct = ClusterTree(self.v, self.tri, leaf=leaf)
-        near, self.far = block_tree(self.ct, eta=eta)
-        # near-field blocks in decreasing estimated cost (blocks on the
-        # diagonal carry the identical pairs, then by size): the block kernel
-        # is dispatched in list order, so the largest blocks start first and
-        # the small ones fill the tail (longest-processing-time order)
+        near, far = block_tree(self.ct, eta=eta)
+        # blocks in decreasing estimated cost (near field: blocks on the
+        # diagonal carry the identical pairs, then by size; coupling: by the
+        # clusters' sizes, which their ranks follow): the block kernel is
+        # dispatched in list order, so the largest blocks start first and the
+        # small ones fill the tail (longest-processing-time order)
         size = (self.ct.end - self.ct.begin).astype(np.int64)
         key = [(-(int(t) == int(s)), -int(size[t] * size[s])) for t, s in near]
         self.near = near[sorted(range(len(near)), key=lambda k: key[k])]
+        fkey = [-int(size[t] * size[s]) for t, s in far]
+        self.far = far[sorted(range(len(far)), key=lambda k: fkey[k])]
         self.t_tree = time.perf_counter() - t0
         # heights: leaves 0, fathers 1 + max(sons)
         n = self.ct.n

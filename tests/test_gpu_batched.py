@@ -180,12 +180,16 @@ def test_autotune_and_cache(pk, ctx, batch, tmp_path):
     torch.cuda.synchronize()
 
 
-def test_fixed_configuration_and_small_tiles(pk, ctx, batch):
-    # a ragged sub-tile shape and a small grid still give the per-call bits
+@pytest.mark.parametrize("granularity", [1, 2])
+def test_fixed_configuration_and_small_tiles(pk, ctx, batch, granularity):
+    # a ragged sub-tile shape and a small grid still give the per-call bits,
+    # with whole blocks or single sub-tiles as the queue's work items
     op = pk.make_op(pk.LAPLACE, pk.SLP, q_regular=4, q_singular=4)
     ref = [_per_call(pk, ctx, op, e) for e in batch]
-    plan, outs = _plan(pk, ctx, op, batch, tune=dict(grid=7, tile_rows=24, tile_cols=40))
+    plan, outs = _plan(pk, ctx, op, batch, tune=dict(grid=7, tile_rows=24, tile_cols=40,
+                                                      granularity=granularity))
     assert plan.config["tile_rows"] == 24 and plan.config["grid"] == 7
+    assert plan.config["granularity"] == granularity
     plan.run()
     ctx.check()
     for r, o in zip(ref, outs):
