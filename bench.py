@@ -99,10 +99,15 @@ def class_counts(tri, rows, cols):
 
 
 def near_flops(counts, kernel, layer, q_reg, q_sing):
-    """Laplace: the singular xi sums are moments, q^3 eta points per region."""
+    """Laplace: the singular xi sums are moments, q^3 eta points per region.
+    Identical pairs: the single layer needs 3 of the 6 regions (the others
+    are their mirror images), the double layer none (its entry vanishes on a
+    flat triangle)."""
     f = FLOPS_PER_POINT[(kernel, layer)]
     flops = counts[0] * (q_reg ** 2) ** 2 * f
     for cls, nreg in SS_REGIONS.items():
+        if cls == 3:
+            nreg = 3 if layer == 0 else 0
         pts = nreg * q_sing ** 3 * (1 if kernel == 0 else q_sing)
         flops += counts[cls] * pts * (f + SS_EXTRA)
     return float(flops)

@@ -122,8 +122,9 @@ int get_rules(bem_ctx *ctx, const bem_op *op, const bem::DevRules **out) {
       e = hipMemcpy(d.xi, hx.data(), hx.size() * sizeof(double), hipMemcpyHostToDevice);
       if (e != hipSuccess) return hip_fail(ctx, e, "hipMemcpy(xi rule)");
     }
-    for (int cls = 1; cls <= 3; ++cls) {
-      const bem::SSRule r = bem::ss_rule(cls, op->q_singular);
+    for (int cls = 0; cls <= 3; ++cls) {
+      const bem::SSRule r = cls ? bem::ss_rule(cls, op->q_singular)
+                                : bem::ss_rule_identical_symmetric(op->q_singular);
       d.np[cls] = (int)r.w.size();
       std::vector<double> hs;
       for (const auto *vec : {&r.xs, &r.xt, &r.ys, &r.yt, &r.w}) hs.insert(hs.end(), vec->begin(), vec->end());

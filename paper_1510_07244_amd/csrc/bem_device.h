@@ -345,11 +345,23 @@ __device__ __forceinline__ Acc<KERNEL> ss_finish(const PairGeo &g, const SSArgs 
 
 // One singular pair per lane; all lanes of the wave share the class, so the
 // eta table is read with wave-uniform (scalar) loads.
+// Table of a class for this kernel: identical pairs of a single layer use
+// the symmetric half-table; for a double layer an identical pair's entry
+// vanishes (on a flat triangle <x - y, n> = 0), so no point is summed.
+template <int LAYER>
+__device__ __forceinline__ int ss_table(int cls) {
+  return cls == CLS_IDENTICAL && LAYER == BEM_SLP ? 0 : cls;
+}
+template <int LAYER>
+__device__ __forceinline__ int ss_points(const SSArgs &ss, int cls) {
+  return cls == CLS_IDENTICAL && LAYER == BEM_DLP ? 0 : ss.np[ss_table<LAYER>(cls)];
+}
+
 template <int KERNEL, int LAYER>
 __device__ __forceinline__ Acc<KERNEL> ss_pair_lane(const PairGeo &g, const SSArgs &ss, int cls,
                                                     double kappa) {
-  const uniform_ptr T = (uniform_ptr)(ss.eta[cls]);
-  const int n = ss.np[cls];
+  const uniform_ptr T = (uniform_ptr)(ss.eta[ss_table<LAYER>(cls)]);
+  const int n = ss_points<LAYER>(ss, cls);
   // U eta points per step into U accumulators, written stage by stage so
   // that the independent chains interleave (the sum order is fixed)
   constexpr int U = KERNEL == BEM_LAPLACE ? 4 : 2;
@@ -406,8 +418,8 @@ __device__ __forceinline__ Acc<KERNEL> ss_pair_lane(const PairGeo &g, const SSAr
 template <int KERNEL, int LAYER>
 __device__ Acc<KERNEL> ss_pair_wave(const PairGeo &g, const SSArgs &ss, int cls, double kappa) {
   const int lane = threadIdx.x & (kWave - 1);
-  const double *T = ss.eta[cls];
-  const int n = ss.np[cls];
+  const double *T = ss.eta[ss_table<LAYER>(cls)];
+  const int n = ss_points<LAYER>(ss, cls);
   double are = 0.0, aim = 0.0;
   for (int p = lane; p < n; p += kWave)
     eta_point<KERNEL, LAYER>(g, T[p], T[n + p], T[2 * n + p], T[3 * n + p], T[4 * n + p], ss,

@@ -37,6 +37,7 @@ struct XiRule {
 };
 enum { CLS_DISJOINT = 0, CLS_VERTEX = 1, CLS_EDGE = 2, CLS_IDENTICAL = 3 };
 SSRule ss_rule(int cls, int q);
+SSRule ss_rule_identical_symmetric(int q);  // 3 of the 6 identical regions, weights doubled
 XiRule xi_rule(int q);
 
 // --------------------------------------------------------------- geometry
@@ -59,7 +60,10 @@ enum : unsigned { FLAG_EINVAL = 1u, FLAG_NONFINITE = 2u };
 struct DevRules {
   int nq = 0;         // points per triangle (regular rule)
   double *tri = nullptr;  // [3][nq]: s, t, w
-  int np[4] = {0, 0, 0, 0};  // Sauter-Schwab eta points per class (index = class)
+  // Sauter-Schwab eta tables per class (index = class 1..3); index 0 (no
+  // disjoint table is needed) holds the identical-pair table for kernels
+  // symmetric in x and y (ss_rule_identical_symmetric)
+  int np[4] = {0, 0, 0, 0};
   double *ss[4] = {nullptr, nullptr, nullptr, nullptr};  // [5][np]: xs, xt, ys, yt, w
   int nxi = 0;               // Sauter-Schwab order q
   double *xi = nullptr;      // [3q + 2]: xi, w xi^2, w xi, then M1 = sum w xi, M2 = sum w xi^2
@@ -67,7 +71,7 @@ struct DevRules {
 
 // Device Sauter-Schwab tables as seen by the kernels.
 struct SSArgs {
-  const double *eta[4];  // per class [5][np]
+  const double *eta[4];  // per class [5][np]; [0]: identical pairs, symmetric kernels
   int32_t np[4];
   const double *xi;      // [4][q]
   int32_t q;

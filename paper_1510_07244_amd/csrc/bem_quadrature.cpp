@@ -186,6 +186,25 @@ SSRule ss_rule(int cls, int q) {
   return r;
 }
 
+// Identical pairs with a kernel symmetric in x and y (single layers): the odd
+// regions are the mirror images (x^ <-> y^) of the even ones on the same
+// triangle, so their sums are equal and the even regions with doubled
+// weights give the same rule.
+SSRule ss_rule_identical_symmetric(int q) {
+  const SSRule full = ss_rule(CLS_IDENTICAL, q);
+  const size_t per = (size_t)q * q * q;
+  SSRule r;
+  for (int reg = 0; reg < 6; reg += 2)
+    for (size_t k = reg * per; k < (reg + 1) * per; ++k) {
+      r.xs.push_back(full.xs[k]);
+      r.xt.push_back(full.xt[k]);
+      r.ys.push_back(full.ys[k]);
+      r.yt.push_back(full.yt[k]);
+      r.w.push_back(2.0 * full.w[k]);
+    }
+  return r;
+}
+
 XiRule xi_rule(int q) {
   if (q < 1 || q > BEM_MAX_ORDER) throw std::invalid_argument("order");
   std::vector<double> gx(q), gw(q);
