@@ -166,65 +166,122 @@ __device__ void stage_columns(const BlockArgs &a, const Lds &l, const BlockHdr &
   __syncthreads();
 }
 
-// Phases D and E: the listed pairs (front of l.list, *l.count of them),
-// grouped by class (identical, edge, vertex, near-singular), each group
-// padded to a multiple of 64 so that every wave-sized chunk holds one class,
-// then one pair per lane in FP64.  Expects a barrier after the listing.
-template <int KERNEL, int LAYER, bool MIXED>
-__device__ void singular_pass(const BlockArgs &a, const Lds &l, const BlockHdr &h, int64_t r0,
-                              int64_t c0) {
-  const int tid = threadIdx.x, wave = tid / kWave, lane = tid & (kWave - 1);
+// Phase D: the listed pairs (front of l.list, *l.count of them) grouped by
+// class (identical, edge, vertex, near-singular) into l.sorted, each group
+// padded to a multiple of 64 with kNoPair so that every wave-sized chunk
+// holds one class.  Expects a barrier after the listing; ends with one.
+struct Groups {
+  int seg[4];  // start of the group of class c
+  int total;   // padded length
+};
+
+__device__ __forceinline__ Groups group_listed(const Lds &l) {
+  const int tid = threadIdx.x;
   const int ns = *l.count;
-  if (ns == 0) return;
+  Groups g;
   const int n3 = (l.ccount[3] + 63) & ~63, n2 = (l.ccount[2] + 63) & ~63,
             n1 = (l.ccount[1] + 63) & ~63, n0 = (l.ccount[0] + 63) & ~63;
-  const int seg[4] = {n3 + n2 + n1, n3 + n2, n3, 0};  // start of the group of class c
-  const int total = n3 + n2 + n1 + n0;
-  for (int k = tid; k < total; k += kThreads) l.sorted[k] = kNoPair;
+  g.seg[0] = n3 + n2 + n1;
+  g.seg[1] = n3 + n2;
+  g.seg[2] = n3;
+  g.seg[3] = 0;
+  g.total = n3 + n2 + n1 + n0;
+  if (ns == 0) return g;  // uniform
+  for (int k = tid; k < g.total; k += kThreads) l.sorted[k] = kNoPair;
   __syncthreads();
   for (int k = tid; k < ns; k += kThreads) {
     const uint16_t code = l.list[k];
     const int cls = code >> 12;
-    l.sorted[seg[cls] + atomicAdd(&l.cursor[cls], 1)] = code;
+    l.sorted[g.seg[cls] + atomicAdd(&l.cursor[cls], 1)] = code;
   }
   __syncthreads();
-  for (int chunk = wave; chunk * kWave < total; chunk += kThreads / kWave) {
-    const int pos = chunk * kWave;
-    const int cls = pos < seg[2] ? CLS_IDENTICAL
-                    : pos < seg[1] ? CLS_EDGE
-                    : pos < seg[0] ? CLS_VERTEX : kNearSingular;
-    const uint16_t code = l.sorted[pos + lane];
-    const bool active = code != kNoPair;
-    const int rl = code & 63, cl = (code >> 6) & 63;
-    const int64_t dst = h.off + (r0 + rl) + h.nr * (c0 + cl);
-    if (cls == kNearSingular) {
-      if (active) {
-        const Acc<KERNEL> v = regular_pair_fp64<KERNEL, LAYER>(a.geo, a.ldg, a.rule, a.nq,
-                                                               a.kappa, l.rid[rl], l.cid[cl]);
-        store_as<KERNEL, MIXED>(a.out, dst, v, a.flags);
-      }
-      continue;
+  return g;
+}
+
+// Phase E for one wave-sized chunk of the grouped list (chunk start pos):
+// one pair per lane in FP64.
+template <int KERNEL, int LAYER, bool MIXED>
+__device__ __forceinline__ void singular_chunk(const BlockArgs &a, const Lds &l,
+                                               const BlockHdr &h, int64_t r0, int64_t c0,
+                                               const Groups &gr, int pos) {
+  const int lane = threadIdx.x & (kWave - 1);
+  const int cls = pos < gr.seg[2] ? CLS_IDENTICAL
+                  : pos < gr.seg[1] ? CLS_EDGE
+                  : pos < gr.seg[0] ? CLS_VERTEX : kNearSingular;
+  const uint16_t code = l.sorted[pos + lane];
+  const bool active = code != kNoPair;
+  const int rl = code & 63, cl = (code >> 6) & 63;
+  const int64_t dst = h.off + (r0 + rl) + h.nr * (c0 + cl);
+  if (cls == kNearSingular) {
+    if (active) {
+      const Acc<KERNEL> v = regular_pair_fp64<KERNEL, LAYER>(a.geo, a.ldg, a.rule, a.nq, a.kappa,
+                                                             l.rid[rl], l.cid[cl]);
+      store_as<KERNEL, MIXED>(a.out, dst, v, a.flags);
     }
-    PairGeo g;
-    bool have = false;
-    if (active) have = pair_geometry(a.v, a.tri, a.nv, a.geo, a.ldg, l.rid[rl], l.cid[cl], cls,
-                                     a.flags, &g);
-    if (!have) {  // idle lane: harmless finite geometry, result discarded
-      for (int c = 0; c < 3; ++c)
-        g.E1i[c] = c == 0, g.E2i[c] = c == 1, g.E1j[c] = -(c == 2), g.E2j[c] = 0, g.n[c] = 0;
-      g.scale = 0.0;
-    }
-    const Acc<KERNEL> v = ss_pair_lane<KERNEL, LAYER>(g, a.ss, cls, a.kappa);
-    if (have) store_as<KERNEL, MIXED>(a.out, dst, v, a.flags);
+    return;
   }
+  PairGeo g;
+  bool have = false;
+  if (active) have = pair_geometry(a.v, a.tri, a.nv, a.geo, a.ldg, l.rid[rl], l.cid[cl], cls,
+                                   a.flags, &g);
+  if (!have) {  // idle lane: harmless finite geometry, result discarded
+    for (int c = 0; c < 3; ++c)
+      g.E1i[c] = c == 0, g.E2i[c] = c == 1, g.E1j[c] = -(c == 2), g.E2j[c] = 0, g.n[c] = 0;
+    g.scale = 0.0;
+  }
+  const Acc<KERNEL> v = ss_pair_lane<KERNEL, LAYER>(g, a.ss, cls, a.kappa);
+  if (have) store_as<KERNEL, MIXED>(a.out, dst, v, a.flags);
+}
+
+// Phases D and E with a static assignment of chunks to waves.
+template <int KERNEL, int LAYER, bool MIXED>
+__device__ void singular_pass(const BlockArgs &a, const Lds &l, const BlockHdr &h, int64_t r0,
+                              int64_t c0) {
+  const Groups gr = group_listed(l);
+  const int wave = threadIdx.x / kWave;
+  for (int chunk = wave; chunk * kWave < gr.total; chunk += kThreads / kWave)
+    singular_chunk<KERNEL, LAYER, MIXED>(a, l, h, r0, c0, gr, chunk * kWave);
+}
+
+// Whether entry (rl, cl) of the staged sub-tile goes to the FP64 pass:
+// a common vertex (cls > 0), or in the mixed form a near-singular pair
+// (bounding boxes closer than ratio * the larger box diagonal).
+template <bool MIXED>
+__device__ __forceinline__ bool fp64_pair(const Lds &l, int TR, int TC, int rl, int cl,
+                                          double ratio, int *cls_out) {
+  const int cls = shared_vertex_count(l.rv[rl], l.rv[TR + rl], l.rv[2 * TR + rl], l.cv[cl],
+                                      l.cv[TC + cl], l.cv[2 * TC + cl]);
+  *cls_out = cls;
+  bool fp64 = cls != 0;
+  if constexpr (MIXED) {
+    if (!fp64 && ratio > 0.0) {
+      double gap2 = 0.0, di = 0.0, dj = 0.0;
+      for (int m = 0; m < 3; ++m) {
+        const double rlo = l.rb[m * TR + rl], rhi = l.rb[(3 + m) * TR + rl];
+        const double clo = l.cb[m * TC + cl], chi = l.cb[(3 + m) * TC + cl];
+        const double g = fmax(0.0, fmax(clo - rhi, rlo - chi));
+        gap2 = fma(g, g, gap2);
+        di = fma(rhi - rlo, rhi - rlo, di);
+        dj = fma(chi - clo, chi - clo, dj);
+      }
+      fp64 = gap2 < ratio * ratio * fmax(di, dj);
+    }
+  }
+  return fp64;
 }
 
 // One sub-tile: rows r0 .. r0 + TR, columns c0 .. c0 + TC of the block.
-// Returns early (uniformly) if a triangle id is invalid.
+// After staging, the pairs of the FP64 pass are listed and grouped by class;
+// then every wave takes work from one counter -- first the FP64 chunks
+// (heaviest), then the regular entries 64 at a time in column-major order
+// (lanes of a chunk share a column, so column points are broadcast reads)
+// -- until both are done, so the FP64 work is spread over the waves instead
+// of ending the sub-tile.  Returns early (uniformly) if a triangle id is
+// invalid.
 template <int KERNEL, int LAYER, int XC, bool MIXED>
 __device__ void subtile(const BlockArgs &a, const Lds &l, const BlockHdr &h, int64_t r0,
                         int64_t c0, int coupling) {
-  const int tid = threadIdx.x;
+  const int tid = threadIdx.x, lane = tid & (kWave - 1);
   const int nqp = a.nq_pad, TR = a.tr, TC = a.tc;
   const int64_t nr = h.nr, off = h.off;
   const double kq = 0.25 * a.kappa;
@@ -233,35 +290,35 @@ __device__ void subtile(const BlockArgs &a, const Lds &l, const BlockHdr &h, int
   const int tr = (int)min((int64_t)TR, h.nr - r0), tc = (int)min((int64_t)TC, h.nc - c0);
   if (!stage_tile<MIXED>(a, l, h, r0, c0, tr, tc)) return;
   stage_columns<MIXED>(a, l, h, tc, a.nq, nqp);
-  // phase C: regular entries, one per lane; the rest is listed
+  // phase C: list the pairs of the FP64 pass
   for (int e = tid; e < tr * tc; e += kThreads) {
     const int rl = e % tr, cl = e / tr;
-    const int cls = shared_vertex_count(l.rv[rl], l.rv[TR + rl], l.rv[2 * TR + rl], l.cv[cl],
-                                        l.cv[TC + cl], l.cv[2 * TC + cl]);
-    bool fp64 = cls != 0;
-    if constexpr (MIXED) {
-      if (!fp64 && ratio > 0.0) {  // near-singular: box distance < ratio * max diam
-        double gap2 = 0.0, di = 0.0, dj = 0.0;
-        for (int m = 0; m < 3; ++m) {
-          const double rlo = l.rb[m * TR + rl], rhi = l.rb[(3 + m) * TR + rl];
-          const double clo = l.cb[m * TC + cl], chi = l.cb[(3 + m) * TC + cl];
-          const double g = fmax(0.0, fmax(clo - rhi, rlo - chi));
-          gap2 = fma(g, g, gap2);
-          di = fma(rhi - rlo, rhi - rlo, di);
-          dj = fma(chi - clo, chi - clo, dj);
-        }
-        fp64 = gap2 < ratio * ratio * fmax(di, dj);
-      }
+    int cls;
+    if (!fp64_pair<MIXED>(l, TR, TC, rl, cl, ratio, &cls)) continue;
+    if (coupling && cls) {
+      atomicOr(a.flags, FLAG_EINVAL);
+    } else {
+      l.list[atomicAdd(l.count, 1)] = (uint16_t)(rl | (cl << 6) | (cls << 12));
+      atomicAdd(&l.ccount[cls], 1);
     }
-    if (fp64) {
-      if (coupling && cls) {
-        atomicOr(a.flags, FLAG_EINVAL);
-      } else {
-        l.list[atomicAdd(l.count, 1)] = (uint16_t)(rl | (cl << 6) | (cls << 12));
-        atomicAdd(&l.ccount[cls], 1);
-      }
+  }
+  __syncthreads();
+  const Groups gr = group_listed(l);
+  const int nsc = gr.total / kWave, nrc = (tr * tc + kWave - 1) / kWave;
+  for (;;) {
+    int c = 0;
+    if (lane == 0) c = atomicAdd(l.rcount, 1);
+    c = __shfl(c, 0, kWave);
+    if (c >= nsc + nrc) break;
+    if (c < nsc) {
+      singular_chunk<KERNEL, LAYER, MIXED>(a, l, h, r0, c0, gr, c * kWave);
       continue;
     }
+    const int e = (c - nsc) * kWave + lane;
+    if (e >= tr * tc) continue;
+    const int rl = e % tr, cl = e / tr;
+    int cls;
+    if (fp64_pair<MIXED>(l, TR, TC, rl, cl, ratio, &cls)) continue;
     Acc<KERNEL> v;
     if constexpr (!MIXED) {
       v = regular_entry<KERNEL, LAYER, XC>(l, TR, TC, nqp, rl, cl, kq);
@@ -272,8 +329,6 @@ __device__ void subtile(const BlockArgs &a, const Lds &l, const BlockHdr &h, int
     if constexpr (KERNEL == BEM_HELMHOLTZ) v.im *= scale;
     store_as<KERNEL, MIXED>(a.out, off + (r0 + rl) + nr * (c0 + cl), v, a.flags);
   }
-  __syncthreads();
-  singular_pass<KERNEL, LAYER, MIXED>(a, l, h, r0, c0);
 }
 
 // x-points per register chunk of the learned kernel for order q (q = 2 .. 6);
