@@ -433,7 +433,7 @@ __device__ void subtile_learned(const BlockArgs &a, const OrderRules &o, const L
 template <int KERNEL, int LAYER>
 __global__ __launch_bounds__(kThreads, 2) void k_blocks_learned(const BlockArgs a,
                                                                 const OrderRules o) {
-  extern __shared__ double lds_raw[];
+  extern __shared__ __align__(16) double lds_raw[];  // 16-byte aligned: ds_read_b128 of points
   BlockHdr h;
   if (!block_header(a, blockIdx.x, &h) || h.nr == 0 || h.nc == 0) return;
   const Lds l = carve<false>(lds_raw, a.nq_pad, a.tr, a.tc);
@@ -443,7 +443,7 @@ __global__ __launch_bounds__(kThreads, 2) void k_blocks_learned(const BlockArgs 
 
 template <int KERNEL, int LAYER, int XC, bool MIXED>
 __global__ __launch_bounds__(kThreads, 2) void k_blocks(const BlockArgs a, const int coupling) {
-  extern __shared__ double lds_raw[];
+  extern __shared__ __align__(16) double lds_raw[];  // 16-byte aligned: ds_read_b128 of points
   BlockHdr h;
   if (!block_header(a, blockIdx.x, &h) || h.nr == 0 || h.nc == 0) return;
   const Lds l = carve<MIXED>(lds_raw, a.nq_pad, a.tr, a.tc);
@@ -475,7 +475,7 @@ __global__ __launch_bounds__(kThreads, 2) void k_persistent(const BlockArgs *bat
                                                             const int32_t *coupling,
                                                             const int4 *tiles, int32_t ntiles,
                                                             int32_t nbatch, int32_t *counter) {
-  extern __shared__ double lds_raw[];
+  extern __shared__ __align__(16) double lds_raw[];  // 16-byte aligned: ds_read_b128 of points
   __shared__ int s_tile;
   // the queue and the batch arguments are read-only here: wave-uniform
   // (scalar) loads keep every argument, pointer and loop bound in scalar

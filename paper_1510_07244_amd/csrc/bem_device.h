@@ -352,15 +352,22 @@ template <int LAYER>
 __device__ __forceinline__ int ss_table(int cls) {
   return cls == CLS_IDENTICAL && LAYER == BEM_SLP ? 0 : cls;
 }
+// Element k of a four-entry argument array by selects, not by an index: a
+// kernel that copies its arguments into registers (the persistent form) would
+// otherwise keep the whole copy in scratch memory.
+template <class T>
+__device__ __forceinline__ T pick4(const T (&v)[4], int k) {
+  return k == 0 ? v[0] : k == 1 ? v[1] : k == 2 ? v[2] : v[3];
+}
 template <int LAYER>
 __device__ __forceinline__ int ss_points(const SSArgs &ss, int cls) {
-  return cls == CLS_IDENTICAL && LAYER == BEM_DLP ? 0 : ss.np[ss_table<LAYER>(cls)];
+  return cls == CLS_IDENTICAL && LAYER == BEM_DLP ? 0 : pick4(ss.np, ss_table<LAYER>(cls));
 }
 
 template <int KERNEL, int LAYER>
 __device__ __forceinline__ Acc<KERNEL> ss_pair_lane(const PairGeo &g, const SSArgs &ss, int cls,
                                                     double kappa) {
-  const uniform_ptr T = (uniform_ptr)(ss.eta[ss_table<LAYER>(cls)]);
+  const uniform_ptr T = (uniform_ptr)(pick4(ss.eta, ss_table<LAYER>(cls)));
   const int n = ss_points<LAYER>(ss, cls);
   // U eta points per step into U accumulators, written stage by stage so
   // that the independent chains interleave (the sum order is fixed)
@@ -418,7 +425,7 @@ __device__ __forceinline__ Acc<KERNEL> ss_pair_lane(const PairGeo &g, const SSAr
 template <int KERNEL, int LAYER>
 __device__ Acc<KERNEL> ss_pair_wave(const PairGeo &g, const SSArgs &ss, int cls, double kappa) {
   const int lane = threadIdx.x & (kWave - 1);
-  const double *T = ss.eta[ss_table<LAYER>(cls)];
+  const double *T = pick4(ss.eta, ss_table<LAYER>(cls));
   const int n = ss_points<LAYER>(ss, cls);
   double are = 0.0, aim = 0.0;
   for (int p = lane; p < n; p += kWave)
