@@ -248,8 +248,12 @@ __device__ __forceinline__ void build_net(const float *__restrict__ P, int n_out
 // Packed network: kNetSlots FP16 operand vectors per lane, slot-major
 // ([slot][64 lanes], 16 bytes each), then kBiasFloats floats (biases, mu,
 // 1 / sigma).  Built once per call by one wave (k_pack_net) and read by every
-// wave of the inference kernels with 16-byte loads.
-constexpr int kNetSlots = 22;
+// wave of the inference kernels with 16-byte loads.  Slots 0..21 are Net16;
+// slots 22 + 2 G + ks hold the output layer with its rows rotated by 4 G
+// (output o at row (o + 4 G) mod 16), so that group G of a four-group step
+// leaves outputs 0..3 of its samples in lane group G.
+constexpr int kNetSlots = 30;
+constexpr int kRotSlot = 22;
 
 __global__ void k_pack_net(int n_out, const float *__restrict__ P, h8 *__restrict__ packed) {
   const int l = threadIdx.x;
@@ -263,6 +267,15 @@ __global__ void k_pack_net(int n_out, const float *__restrict__ P, h8 *__restric
     for (int ks = 0; ks < 2; ++ks) packed[(k++) * 64 + l] = N.a3[mt][ks];
   for (int ks = 0; ks < 2; ++ks) packed[(k++) * 64 + l] = N.a4[ks];
   const Off of = offsets(n_out);
+  const int g = l >> 4, c = l & 15;
+  for (int G = 0; G < 4; ++G)
+    for (int ks = 0; ks < 2; ++ks) {
+      const int o = (c - 4 * G) & 15;
+      h8 v;
+      for (int j = 0; j < 8; ++j)
+        v[j] = (_Float16)(o < n_out ? P[of.w4 + o * kHid + kidx(ks, g, j)] : 0.0f);
+      packed[(k++) * 64 + l] = v;
+    }
   float *bias = reinterpret_cast<float *>(packed + kNetSlots * 64);
   for (int q = l; q < kBiasFloats; q += 64) {
     float v;
@@ -292,13 +305,21 @@ __device__ __forceinline__ f4 bias4(const float *bias, int base, int g) {
   return *reinterpret_cast<const f4 *>(bias + base + drow(g, 0));
 }
 
+// ReLU after the FP16 rounding, on the bit patterns: a negative half (sign
+// bit set, -0 included) is a negative int16, so a packed integer max with 0
+// gives exactly the rounding of max(x, 0) for every finite x.
+typedef short s2 __attribute__((ext_vector_type(2)));
+typedef float f2 __attribute__((ext_vector_type(2)));
+typedef _Float16 hf2 __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ uint32_t relu2(float a, float b) {
+  const hf2 h = __builtin_convertvector((f2){a, b}, hf2);
+  const s2 zero = {0, 0};
+  return __builtin_bit_cast(uint32_t, __builtin_elementwise_max(__builtin_bit_cast(s2, h), zero));
+}
 __device__ __forceinline__ h8 relu_pair(f4 lo, f4 hi) {
-  h8 r;
-  for (int j = 0; j < 4; ++j) {
-    r[j] = (_Float16)fmaxf(lo[j], 0.0f);
-    r[j + 4] = (_Float16)fmaxf(hi[j], 0.0f);
-  }
-  return r;
+  const uint32_t w[4] = {relu2(lo[0], lo[1]), relu2(lo[2], lo[3]), relu2(hi[0], hi[1]),
+                         relu2(hi[2], hi[3])};
+  return __builtin_bit_cast(h8, w);
 }
 
 // Standardised FP16 inputs of one sample (the same arithmetic everywhere).
@@ -309,34 +330,71 @@ __device__ __forceinline__ h8 standardise(const float x[8], const float *bias) {
   return b;
 }
 
-// Outputs for 16 samples: lanes 0..15 hold the standardised inputs of sample
-// lane (zeros elsewhere).  Result register r of lane l: output drow(l/16, r)
-// of sample l % 16.
-__device__ __forceinline__ f4 net16(const Net16 &N, const float *bias, h8 b) {
+// Outputs for NG x 16 samples (groups G0 .. G0 + NG - 1 of a wave's 64): in
+// group G, lanes 0..15 hold the standardised inputs of sample 16 G + lane
+// (zeros elsewhere).  Result register r of out[G - G0] in lane l: output
+// drow(l/16, r) of sample 16 G + l % 16 -- with ROT, output
+// (drow(l/16, r) - 4 G) mod 16 (the rotated output layer).  The groups go
+// through each layer together, so that their independent matrix core chains
+// overlap the activations of the others.
+template <bool ROT, int NG, int G0>
+__device__ __forceinline__ void net(const Net16 &N, const h8 *rot, const float *bias, const h8 *b,
+                                    f4 *out) {
   const int g = (threadIdx.x & 63) >> 4;
-  f4 t1[4], t2[4], t3[4];
-  for (int mt = 0; mt < 4; ++mt)
-    t1[mt] = __builtin_amdgcn_mfma_f32_16x16x32_f16(N.a1[mt], b, bias4(bias, mt * 16, g), 0, 0, 0);
-  const h8 h1[2] = {relu_pair(t1[0], t1[1]), relu_pair(t1[2], t1[3])};
+  h8 h[NG][2];
+  f4 t[NG][4];
+#pragma unroll
   for (int mt = 0; mt < 4; ++mt) {
-    f4 acc = bias4(bias, kHid + mt * 16, g);
-    for (int ks = 0; ks < 2; ++ks) acc = __builtin_amdgcn_mfma_f32_16x16x32_f16(N.a2[mt][ks], h1[ks], acc, 0, 0, 0);
-    t2[mt] = acc;
+    const f4 c = bias4(bias, mt * 16, g);
+#pragma unroll
+    for (int G = 0; G < NG; ++G) t[G][mt] = __builtin_amdgcn_mfma_f32_16x16x32_f16(N.a1[mt], b[G], c, 0, 0, 0);
   }
-  const h8 h2[2] = {relu_pair(t2[0], t2[1]), relu_pair(t2[2], t2[3])};
+#pragma unroll
+  for (int G = 0; G < NG; ++G) h[G][0] = relu_pair(t[G][0], t[G][1]), h[G][1] = relu_pair(t[G][2], t[G][3]);
+#pragma unroll
   for (int mt = 0; mt < 4; ++mt) {
-    f4 acc = bias4(bias, 2 * kHid + mt * 16, g);
-    for (int ks = 0; ks < 2; ++ks) acc = __builtin_amdgcn_mfma_f32_16x16x32_f16(N.a3[mt][ks], h2[ks], acc, 0, 0, 0);
-    t3[mt] = acc;
+    const f4 c = bias4(bias, kHid + mt * 16, g);
+#pragma unroll
+    for (int G = 0; G < NG; ++G)
+      t[G][mt] = __builtin_amdgcn_mfma_f32_16x16x32_f16(
+          N.a2[mt][1], h[G][1], __builtin_amdgcn_mfma_f32_16x16x32_f16(N.a2[mt][0], h[G][0], c, 0, 0, 0),
+          0, 0, 0);
   }
-  const h8 h3[2] = {relu_pair(t3[0], t3[1]), relu_pair(t3[2], t3[3])};
-  f4 acc = bias4(bias, 3 * kHid, g);
-  for (int ks = 0; ks < 2; ++ks) acc = __builtin_amdgcn_mfma_f32_16x16x32_f16(N.a4[ks], h3[ks], acc, 0, 0, 0);
-  return acc;
+#pragma unroll
+  for (int G = 0; G < NG; ++G) h[G][0] = relu_pair(t[G][0], t[G][1]), h[G][1] = relu_pair(t[G][2], t[G][3]);
+#pragma unroll
+  for (int mt = 0; mt < 4; ++mt) {
+    const f4 c = bias4(bias, 2 * kHid + mt * 16, g);
+#pragma unroll
+    for (int G = 0; G < NG; ++G)
+      t[G][mt] = __builtin_amdgcn_mfma_f32_16x16x32_f16(
+          N.a3[mt][1], h[G][1], __builtin_amdgcn_mfma_f32_16x16x32_f16(N.a3[mt][0], h[G][0], c, 0, 0, 0),
+          0, 0, 0);
+  }
+#pragma unroll
+  for (int G = 0; G < NG; ++G) h[G][0] = relu_pair(t[G][0], t[G][1]), h[G][1] = relu_pair(t[G][2], t[G][3]);
+  if constexpr (!ROT) {
+    const f4 c = bias4(bias, 3 * kHid, g);
+#pragma unroll
+    for (int G = 0; G < NG; ++G)
+      out[G] = __builtin_amdgcn_mfma_f32_16x16x32_f16(
+          N.a4[1], h[G][1], __builtin_amdgcn_mfma_f32_16x16x32_f16(N.a4[0], h[G][0], c, 0, 0, 0), 0, 0, 0);
+  } else {
+    const int l = threadIdx.x & 63;
+#pragma unroll
+    for (int G = 0; G < NG; ++G) {
+      // rows 4 g + r of group G0 + G hold output (4 (g - G0 - G) + r) mod 16
+      const f4 c = *reinterpret_cast<const f4 *>(bias + 3 * kHid + ((4 * (g - G0 - G)) & 15));
+      const h8 w0 = rot[(2 * (G0 + G)) * 64 + l];
+      const h8 w1 = rot[(2 * (G0 + G) + 1) * 64 + l];
+      out[G] = __builtin_amdgcn_mfma_f32_16x16x32_f16(
+          w1, h[G][1], __builtin_amdgcn_mfma_f32_16x16x32_f16(w0, h[G][0], c, 0, 0, 0), 0, 0, 0);
+    }
+  }
 }
 
 // Generic inference over stored inputs x[n][8] -> y[n][n_out].
-__global__ __launch_bounds__(kThreads) void k_mlp_infer16(int n_out, const h8 *__restrict__ packed,
+__global__ __launch_bounds__(kThreads, 2) void k_mlp_infer16(int n_out, const h8 *__restrict__ packed,
                                                           int64_t n, const float *__restrict__ x,
                                                           float *__restrict__ y) {
   __shared__ __attribute__((aligned(16))) float bias[kBiasFloats];
@@ -346,18 +404,26 @@ __global__ __launch_bounds__(kThreads) void k_mlp_infer16(int n_out, const h8 *_
   const int l = threadIdx.x & 63, g = l >> 4;
   const int64_t nwaves = (int64_t)gridDim.x * (kThreads / kWave);
   const int64_t w0 = (int64_t)blockIdx.x * (kThreads / kWave) + threadIdx.x / kWave;
-  for (int64_t s0 = w0 * 16; s0 < n; s0 += nwaves * 16) {
-    const int64_t s = s0 + (l & 15);
-    h8 b = {0, 0, 0, 0, 0, 0, 0, 0};
-    if (g == 0 && s < n) {
-      float f[8];
-      for (int j = 0; j < 8; ++j) f[j] = x[s * kIn + j];
-      b = standardise(f, bias);
+  for (int64_t s0 = w0 * 64; s0 < n; s0 += nwaves * 64) {
+    h8 b[4];
+    for (int G = 0; G < 4; ++G) {
+      const int64_t s = s0 + 16 * G + (l & 15);
+      b[G] = (h8){0, 0, 0, 0, 0, 0, 0, 0};
+      if (g == 0 && s < n) {
+        float f[8];
+        for (int j = 0; j < 8; ++j) f[j] = x[s * kIn + j];
+        b[G] = standardise(f, bias);
+      }
     }
-    const f4 out = net16(N, bias, b);
-    for (int r = 0; r < 4; ++r) {
-      const int o = drow(g, r);
-      if (s < n && o < n_out) y[s * n_out + o] = out[r];
+    f4 out[4];
+    net<false, 2, 0>(N, nullptr, bias, b, out);
+    net<false, 2, 2>(N, nullptr, bias, b + 2, out + 2);
+    for (int G = 0; G < 4; ++G) {
+      const int64_t s = s0 + 16 * G + (l & 15);
+      for (int r = 0; r < 4; ++r) {
+        const int o = drow(g, r);
+        if (s < n && o < n_out) y[s * n_out + o] = out[G][r];
+      }
     }
   }
 }
@@ -390,26 +456,40 @@ __device__ __forceinline__ TriIn tri_inputs(const double *g, int64_t L, int i) {
   return t;
 }
 
+// Larger / smaller of two non-negative floats by their bit patterns (which
+// order like integers), without the NaN quieting of fmaxf / fminf.
+__device__ __forceinline__ float nonneg_max(float a, float b) {
+  return __int_as_float(max(__float_as_int(a), __float_as_int(b)));
+}
+__device__ __forceinline__ float nonneg_min(float a, float b) {
+  return __int_as_float(min(__float_as_int(a), __float_as_int(b)));
+}
+// ln x for a normal x > 0 (v_log_f32 gives log2).
+__device__ __forceinline__ float ln_normal(float x) {
+  return 0.69314718055994531f * __builtin_amdgcn_logf(x);
+}
+
 // Inputs of the pair (i, j): x0 = ln(r / D), x1, x2 aspects, x3 area ratio,
 // x4 = kappa D, x5 = ln max(|n_i - n_j|^2, 1e-12), x6 = layer,
 // x7 = ln max(|<c_i - c_j, n_j>| / r, 1e-8).  Differences in FP64, the rest
-// in FP32.
+// in FP32: ratios by v_rcp_f32 / v_rsq_f32, logarithms of ratios (no
+// cancellation), x0 as ln(r^2 / D^2) / 2.
 __device__ __forceinline__ void pair_inputs(const TriIn &ti, const TriIn &tj, int layer,
                                             float kappa, float f[8]) {
   const double s0 = ti.c[0] - tj.c[0], s1 = ti.c[1] - tj.c[1], s2 = ti.c[2] - tj.c[2];
   const double m0 = ti.n[0] - tj.n[0], m1 = ti.n[1] - tj.n[1], m2 = ti.n[2] - tj.n[2];
-  const float r = sqrtf((float)fma(s0, s0, fma(s1, s1, s2 * s2)));
+  const float r2 = (float)fma(s0, s0, fma(s1, s1, s2 * s2));
   const float dn = (float)fabs(fma(s0, tj.n[0], fma(s1, tj.n[1], s2 * tj.n[2])));
   const float nn = (float)fma(m0, m0, fma(m1, m1, m2 * m2));
-  const float D = fmaxf(ti.d, tj.d);
-  f[0] = __logf(r / D);
+  const float D = nonneg_max(ti.d, tj.d);
+  f[0] = 0.5f * ln_normal(r2 * __builtin_amdgcn_rcpf(D * D));
   f[1] = ti.aspect;
   f[2] = tj.aspect;
-  f[3] = fminf(ti.area, tj.area) / fmaxf(ti.area, tj.area);
+  f[3] = nonneg_min(ti.area, tj.area) * __builtin_amdgcn_rcpf(nonneg_max(ti.area, tj.area));
   f[4] = kappa * D;
-  f[5] = __logf(fmaxf(nn, 1e-12f));
+  f[5] = ln_normal(nonneg_max(nn, 1e-12f));
   f[6] = (float)layer;
-  f[7] = __logf(fmaxf(dn / r, 1e-8f));
+  f[7] = ln_normal(nonneg_max(dn * __builtin_amdgcn_rsqf(r2), 1e-8f));
 }
 
 // Per-triangle inputs of a mesh, structure of arrays with leading dimension
@@ -483,14 +563,16 @@ __global__ __launch_bounds__(kThreads) void k_selector_samples(const SampleArgs 
 // shuffles).
 constexpr int kSelTile = 64;
 
-__global__ __launch_bounds__(kThreads) void k_select_orders(const SelectArgs a) {
+__global__ __launch_bounds__(kThreads, 2) void k_select_orders(const SelectArgs a) {
   __shared__ __attribute__((aligned(16))) float bias[kBiasFloats];
   __shared__ double sc[2][3][kSelTile], sn[2][3][kSelTile];
   __shared__ float sd[2][3][kSelTile];  // d, area, aspect
   __shared__ int sv[2][3][kSelTile], sbad;
+  __shared__ h8 srot[8 * 64];  // the rotated output layer (slots kRotSlot ..)
   const int tid = threadIdx.x;
   Net16 N;
   load_net(reinterpret_cast<const h8 *>(a.net), &N, bias);
+  for (int k = tid; k < 8 * 64; k += kThreads) srot[k] = reinterpret_cast<const h8 *>(a.net)[kRotSlot * 64 + k];
   const int l = tid & 63, g = l >> 4, wave = tid / kWave;
   const float kappa = (float)a.kappa;
   const int64_t T = a.ldt;
@@ -532,10 +614,14 @@ __global__ __launch_bounds__(kThreads) void k_select_orders(const SelectArgs a) 
         continue;  // uniform
       }
       const int ne = tr * tc;
+      // e / tr by a float reciprocal: e < 4096 and tr <= 64 keep (e + 1/2) / tr
+      // at least 1 / 128 away from an integer, far above the rounding error
+      const float itr = 1.0f / (float)tr;
       for (int e0 = wave * 64; e0 < ne; e0 += kThreads) {  // no barrier inside: trip counts differ
         const int e = e0 + l;
         const bool live = e < ne;
-        const int rl = live ? e % tr : 0, cl = live ? e / tr : 0;
+        const int cq = (int)(((float)e + 0.5f) * itr);
+        const int rl = live ? e - cq * tr : 0, cl = live ? cq : 0;
         const int cls = shared_vertex_count(sv[0][0][rl], sv[0][1][rl], sv[0][2][rl], sv[1][0][cl],
                                             sv[1][1][cl], sv[1][2][cl]);
         // standardised inputs of this lane's entry, packed as four half2 words
@@ -557,31 +643,43 @@ __global__ __launch_bounds__(kThreads) void k_select_orders(const SelectArgs a) 
                    ((uint32_t)__builtin_bit_cast(uint16_t, hi) << 16);
           }
         }
-        int q = 0;
-        for (int grp = 0; grp < 4; ++grp) {
-          // lanes 0..15 take the inputs of entry grp * 16 + lane
-          h8 bop = {0, 0, 0, 0, 0, 0, 0, 0};
+        // group G of the network: every lane takes the inputs of entry
+        // 16 G + l % 16; only lanes 0..15 meet nonzero first-layer weights
+        // (the other lanes' k-slots multiply zeros, exactly)
+        h8 bop[4];
+        for (int G = 0; G < 4; ++G) {
           uint32_t v[4];
-          for (int k = 0; k < 4; ++k) v[k] = (uint32_t)__shfl((int)w[k], grp * 16 + (l & 15), kWave);
-          if (g == 0)
-            for (int k = 0; k < 4; ++k) {
-              bop[2 * k] = __builtin_bit_cast(_Float16, (uint16_t)(v[k] & 0xffff));
-              bop[2 * k + 1] = __builtin_bit_cast(_Float16, (uint16_t)(v[k] >> 16));
-            }
-          const f4 out = net16(N, bias, bop);
-          // outputs 0..5 of entry grp * 16 + (l & 15) into lane group 0
-          float pred[kSelQ];
-          for (int o = 0; o < kSelQ; ++o)
-            pred[o] = __shfl(out[o & 3], (o >> 2) * 16 + (l & 15), kWave);
-          int qq = a.q_plain;
-          bool run = true;
-          for (int t = a.q_plain - 1; t >= a.q_min; --t) {
+          for (int k = 0; k < 4; ++k) v[k] = (uint32_t)__shfl((int)w[k], G * 16 + (l & 15), kWave);
+          bop[G] = __builtin_bit_cast(h8, v);
+        }
+        f4 out[4];
+        net<true, 2, 0>(N, srot, bias, bop, out);
+        net<true, 2, 2>(N, srot, bias, bop + 2, out + 2);
+        // This lane's entry is sample l % 16 of group g: its outputs 0..3 are
+        // out[g][0..3] here, output 4 is out[g][0] of lane l + 16 (mod 64).
+        // Only outputs q_min - 1 .. q_plain - 2 are needed (uniform).
+        float pred[5];
+#pragma unroll
+        for (int o = 0; o < 4; ++o) {
+          pred[o] = 0.0f;
+          if (o >= a.q_min - 1 && o <= a.q_plain - 2)
+            pred[o] = g == 0 ? out[0][o] : g == 1 ? out[1][o] : g == 2 ? out[2][o] : out[3][o];
+        }
+        pred[4] = 0.0f;
+        if (a.q_plain >= 6) {  // the next lane group's copy for group g - 1
+          const int gs = (g + 3) & 3;
+          const float v = gs == 0 ? out[0][0] : gs == 1 ? out[1][0] : gs == 2 ? out[2][0] : out[3][0];
+          pred[4] = __shfl(v, (l + 16) & 63, kWave);
+        }
+        // t = q_plain - 1 down to q_min while e_t + margin <= log10 tol
+        int q = a.q_plain;
+        bool run = true;
+#pragma unroll
+        for (int t = kSelQ - 1; t >= 1; --t) {
+          if (t <= a.q_plain - 1 && t >= a.q_min) {  // uniform
             run = run && pred[t - 1] + a.margin <= a.log_tol;
-            if (run) qq = t;
+            q = run ? t : q;
           }
-          // back to the lane that owns the entry
-          const int got = __shfl(qq, l & 15, kWave);
-          if ((l >> 4) == grp) q = got;
         }
         if (live) a.orders[off + (r0 + rl) + nr * (c0 + cl)] = (int8_t)(cls ? 0 : q);
       }
@@ -639,8 +737,8 @@ hipError_t launch_tri_inputs(const double *geo, int64_t ldg, int nt, double *tc,
 hipError_t launch_mlp_forward(bool f16, int n_out, const float *P, const void *packed, int64_t n,
                               const float *x, float *y, hipStream_t s) {
   if (f16) {
-    const int64_t groups = (n + 15) / 16;
-    const unsigned grid = (unsigned)std::min<int64_t>((groups + 3) / 4, 2048);
+    const int64_t waves = (n + 63) / 64;  // 64 samples per wave and step
+    const unsigned grid = (unsigned)std::min<int64_t>((waves + 3) / 4, 2048);
     hipLaunchKernelGGL(k_mlp_infer16, dim3(grid), dim3(kThreads), 0, s, n_out,
                        static_cast<const h8 *>(packed), n, x, y);
   } else {
