@@ -82,7 +82,31 @@ def parse():
     p.add_argument("--batched-meshes", type=int, default=64)
     p.add_argument("--learned-n", type=int, default=128,
                    help="octahedron subdivision of the learned-form sphere (nt = 8 n^2)")
+    p.add_argument("--counter-pass", action="store_true",
+                   help="for hardware-counter runs: one near-field launch of the Laplace SLP "
+                        "and one of the DLP on the 8192-triangle sphere, then a 512 MiB device "
+                        "copy that calibrates FETCH_SIZE / WRITE_SIZE; prints no JSON")
     return p.parse_args()
+
+
+def counter_pass(torch, pk, ctx, m):
+    """The launches the committed traffic counters are read from: the same
+    near-field calls the step times (SLP, then DLP), then a copy of known size."""
+    ct = pk.ClusterTree(m.v, m.tri, leaf=64)
+    near, _ = pk.block_tree(ct, eta=2.0)
+    mesh = pk.Mesh(torch.from_numpy(m.v), torch.from_numpy(m.tri))
+    blocks, total = pk.Blocks.from_lists([ct.idx(t) for t, s in near],
+                                         [ct.idx(s) for t, s in near])
+    out = torch.empty(total, dtype=torch.float64, device="cuda")
+    for layer in (pk.SLP, pk.DLP):
+        ctx.assemble_nearfield(mesh, pk.make_op(pk.LAPLACE, layer, q_regular=Q, q_singular=Q),
+                               blocks, out)
+    ctx.check()
+    a = torch.ones(1 << 26, dtype=torch.float64, device="cuda")  # 512 MiB
+    b = torch.empty_like(a)
+    b.copy_(a)
+    torch.cuda.synchronize()
+    print(f"near-field entries per launch {total}, copy bytes {a.numel() * 8}", flush=True)
 
 
 def class_counts(tri, rows, cols):
@@ -419,6 +443,9 @@ def main():
 
     m = octahedron_sphere(32)
     ctx = pk.Context(0)
+    if args.counter_pass:
+        counter_pass(torch, pk, ctx, m)
+        return
     setups = []
     hb = None
     for _ in range(max(1, args.setup_repeats)):
