@@ -115,8 +115,9 @@ class H2Setup:
             rp[1:] = np.cumsum(nrows)
             a_off = np.zeros(cls.size, dtype=np.int64)
             a_off[1:] = np.cumsum(nrows.astype(np.int64) * 2 * m)[:-1]
+            lv.row_idx_h = np.concatenate(rows)
             lv.row_ptr = _dev(rp, torch.int32)
-            lv.row_idx = _dev(np.concatenate(rows), torch.int32)
+            lv.row_idx = _dev(lv.row_idx_h, torch.int32)
             lv.z = _dev(self.z[cls], torch.float64)
             lv.zn = _dev(self.zn[cls], torch.float64)
             lv.zw = _dev(self.zw[cls], torch.float64)
@@ -141,6 +142,7 @@ class H2Setup:
             v_off = np.zeros(cls.size, dtype=np.int64)
             v_off[1:] = np.cumsum(nrows.astype(np.int64) * rank)[:-1]
             lv.nrows_h, lv.v_off_h = nrows, v_off
+            lv.rank_h, lv.pcol_h, lv.pinv_h = rank, pcol, pinv
             lv.nrows = _dev(nrows, torch.int32)
             lv.rank = _dev(rank, torch.int32)
             lv.piv_cols = _dev(pcol, torch.int32)
@@ -153,19 +155,67 @@ class H2Setup:
                                     lv.A, lv.a_off, 2 * m, lv.V, lv.v_off, max_rows=lv.max_rows)
             B.levels.append(lv)
         self.ctx.check()
+        B.replay = self._replay_plan(B)
         return B
+
+    def _replay_plan(self, B):
+        """Inputs of all levels concatenated (level by level), so that a replay
+        is one Green-matrix launch and one contraction launch: with the pivots
+        fixed, no level depends on another's results.  The levels' A and V
+        become views of the combined buffers."""
+        import torch
+        Ls, m2 = B.levels, 2 * self.m
+        rp = LevelPlan()
+        cls = np.concatenate([lv.cls for lv in Ls])
+        nrows = np.concatenate([lv.nrows_h for lv in Ls]).astype(np.int64)
+        ptr = np.zeros(cls.size + 1, dtype=np.int32)
+        ptr[1:] = np.cumsum(nrows)
+        a_off = np.zeros(cls.size, dtype=np.int64)
+        a_off[1:] = np.cumsum(nrows * m2)[:-1]
+        rank = np.concatenate([lv.rank_h for lv in Ls]).astype(np.int32)
+        v_off = np.zeros(cls.size, dtype=np.int64)
+        v_off[1:] = np.cumsum(nrows * rank)[:-1]
+        K = max(lv.max_rank for lv in Ls)
+        f = 2 if self.cplx else 1
+        pcol = np.zeros((cls.size, K), dtype=np.int32)
+        pinv = np.zeros((cls.size, K * K * f), dtype=np.float64)
+        i = 0
+        for lv in Ls:
+            for p in range(lv.cls.size):
+                k = int(lv.rank_h[p])
+                pcol[i, :k] = lv.pcol_h[p, :k]
+                pinv[i, :k * k * f] = lv.pinv_h[p, :k * k * f]
+                i += 1
+        rp.ncl = int(cls.size)
+        rp.row_ptr = _dev(ptr, torch.int32)
+        rp.row_idx = _dev(np.concatenate([lv.row_idx_h for lv in Ls]), torch.int32)
+        rp.z, rp.zn = _dev(self.z[cls], torch.float64), _dev(self.zn[cls], torch.float64)
+        rp.zw, rp.delta = _dev(self.zw[cls], torch.float64), _dev(self.delta[cls], torch.float64)
+        rp.a_off, rp.v_off = _dev(a_off, torch.int64), _dev(v_off, torch.int64)
+        rp.nrows, rp.rank = _dev(nrows, torch.int32), _dev(rank, torch.int32)
+        rp.piv_cols, rp.pinv, rp.max_rank = _dev(pcol, torch.int32), _dev(pinv, torch.float64), K
+        rp.max_rows = int(nrows.max())
+        rp.A = torch.empty(int((nrows * m2).sum()), dtype=self.adtype, device="cuda")
+        rp.V = torch.empty(int((nrows * rank).sum()), dtype=self.adtype, device="cuda")
+        ao = vo = 0
+        for lv in Ls:
+            na, nv = lv.A.numel(), lv.V.numel()
+            rp.A[ao:ao + na].copy_(lv.A)
+            rp.V[vo:vo + nv].copy_(lv.V)
+            lv.A, lv.V = rp.A[ao:ao + na], rp.V[vo:vo + nv]
+            ao, vo = ao + na, vo + nv
+        return rp
 
     def basis_replay(self, B, stream=None):
         """Enqueue the GPU part of a basis construction again (Green matrices
-        and contractions) with the pivots and inverses already chosen."""
-        op = self.op(SLP)
-        for lv in B.levels:
-            self.ctx.green_matrix(self.mesh, op, B.side, lv.row_ptr, lv.row_idx, lv.z, lv.zn,
-                                  lv.zw, lv.delta, lv.a_off, lv.A, max_rows=lv.max_rows,
-                                  stream=stream)
-            self.ctx.basis_contract(self.cplx, lv.nrows, lv.rank, lv.max_rank, lv.piv_cols,
-                                    lv.pinv, lv.A, lv.a_off, 2 * self.m, lv.V, lv.v_off,
-                                    max_rows=lv.max_rows, stream=stream)
+        and contractions of every level, one launch each) with the pivots and
+        inverses already chosen."""
+        rp = B.replay
+        self.ctx.green_matrix(self.mesh, self.op(SLP), B.side, rp.row_ptr, rp.row_idx, rp.z, rp.zn,
+                              rp.zw, rp.delta, rp.a_off, rp.A, max_rows=rp.max_rows, stream=stream)
+        self.ctx.basis_contract(self.cplx, rp.nrows, rp.rank, rp.max_rank, rp.piv_cols, rp.pinv,
+                                rp.A, rp.a_off, 2 * self.m, rp.V, rp.v_off, max_rows=rp.max_rows,
+                                stream=stream)
 
     def full_basis(self, B, c):
         """V_t (rows ordered like the cluster's triangles) as a host array."""

@@ -148,3 +148,28 @@ def test_h2_sphere8192_laplace_accuracy(pk, ctx, layer):
 def test_h2_helmholtz_accuracy(pk, ctx):
     errs, _, _ = _h2_errors(pk, ctx, octahedron_sphere(16), pk.HELMHOLTZ, 4.0, pk.DLP, 30, seed=5)
     assert errs.max() <= 1e-6, errs.max()
+
+
+@pytest.mark.parametrize("kernel,kappa,side", [(0, 0.0, 0), (0, 0.0, 1), (1, 4.0, 1)])
+def test_basis_replay_equals_setup_bitwise(pk, ctx, kernel, kappa, side):
+    # the replay recomputes every level's Green matrices and transfer matrices
+    # in one launch each; with the pivots fixed they are the setup's, bit for bit
+    from paper_1510_07244_amd.h2 import H2Setup
+    import torch
+    m = octahedron_sphere(16)
+    h = H2Setup(ctx, m.v, m.tri, kernel=kernel, kappa=kappa, q_regular=4, q_singular=4)
+    B = h.basis(side)
+    assert len(B.levels) > 2
+    A0, V0 = B.replay.A.clone(), B.replay.V.clone()
+    B.replay.A.fill_(float("nan"))
+    B.replay.V.fill_(float("nan"))
+    h.basis_replay(B)
+    ctx.check()
+    for x, y in ((A0, B.replay.A), (V0, B.replay.V)):
+        a, b = x.cpu(), y.cpu()
+        if a.is_complex():
+            a, b = torch.view_as_real(a), torch.view_as_real(b)
+        assert np.array_equal(a.numpy().view(np.uint8), b.numpy().view(np.uint8))
+    # the levels' views see the replayed values
+    leaf = next(c for c in range(h.ct.n) if h.ct.sons[c, 0] < 0)
+    assert np.all(np.isfinite(B.vhat(leaf)))
