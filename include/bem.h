@@ -233,7 +233,10 @@ int bem_run_batched(bem_plan *plan, void *stream);
 /* Work items in the plan's queue (0 for a NULL plan). */
 int64_t bem_plan_tiles(const bem_plan *plan);
 
-/* Release a plan (waits for its device work).  NULL is a no-op. */
+/* Release a plan (waits for its device work).  NULL is a no-op.  Plans may
+ * be destroyed before or after their context: bem_destroy releases the
+ * device resources of the context's live plans, which then only accept
+ * bem_plan_destroy (bem_run_batched returns BEM_EINVAL). */
 void bem_plan_destroy(bem_plan *plan);
 
 /* ---------------------------------------------------------------------

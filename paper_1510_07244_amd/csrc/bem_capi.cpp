@@ -232,6 +232,7 @@ void bem_destroy(bem_ctx *ctx) {
   {
     DeviceGuard g(ctx->device);
     (void)hipDeviceSynchronize();
+    bem::detach_plans(ctx);
     for (auto &kv : ctx->rules) {
       (void)hipFree(kv.second.tri);
       if (kv.second.xi) (void)hipFree(kv.second.xi);

@@ -5,6 +5,7 @@
 
 #include <cstdint>
 #include <map>
+#include <set>
 #include <string>
 #include <tuple>
 #include <vector>
@@ -278,6 +279,9 @@ int check_blocks(bem_ctx *ctx, const bem_blocks *b, const void *out, int64_t out
 int get_rules(bem_ctx *ctx, const bem_op *op, const DevRules **out);
 // geometry scratch of the context for nt triangles; leading dimension out
 int ensure_geo(bem_ctx *ctx, int32_t nt, int64_t *ldg);
+// release the device resources of the context's live plans and detach them
+// (bem_plan.cpp; called by bem_destroy)
+void detach_plans(bem_ctx *ctx);
 
 }  // namespace bem
 
@@ -293,4 +297,5 @@ struct bem_ctx {
   void *sel_scratch = nullptr;    // device: packed network + per-triangle selector inputs
   size_t sel_cap = 0;             // bytes
   std::map<std::tuple<int, int, int>, bem::DevRules> rules;
+  std::set<bem_plan *> plans;     // live batched plans (released with the context)
 };

@@ -28,7 +28,8 @@
 using namespace bem;
 
 struct bem_plan {
-  bem_ctx *ctx = nullptr;
+  bem_ctx *ctx = nullptr;  // null once the context is destroyed
+  int device = 0;
   int kernel = 0, layer = 0;
   bool mixed = false;
   int32_t nq = 0;
@@ -214,6 +215,7 @@ void cache_store(const char *path, const std::string &key, const bem_tune &t) {
 
 bool valid_chunk(int x) { return x == 4 || x == 5 || x == 7 || x == 8 || x == 9; }
 
+// Device resources of a plan; idempotent.
 void release(bem_plan *p) {
   if (p->exec) (void)hipGraphExecDestroy(p->exec);
   if (p->graph) (void)hipGraphDestroy(p->graph);
@@ -221,6 +223,14 @@ void release(bem_plan *p) {
   for (void *m : {(void *)p->geo, (void *)p->dbatch, (void *)p->dcoupling, (void *)p->dtiles,
                   (void *)p->counter})
     if (m) (void)hipFree(m);
+  p->exec = nullptr;
+  p->graph = nullptr;
+  p->cap = nullptr;
+  p->geo = nullptr;
+  p->dbatch = nullptr;
+  p->dcoupling = nullptr;
+  p->dtiles = nullptr;
+  p->counter = nullptr;
 }
 
 struct Candidate {
@@ -229,6 +239,14 @@ struct Candidate {
 };
 
 }  // namespace
+
+void bem::detach_plans(bem_ctx *ctx) {
+  for (bem_plan *p : ctx->plans) {
+    release(p);
+    p->ctx = nullptr;
+  }
+  ctx->plans.clear();
+}
 
 extern "C" {
 
@@ -253,6 +271,7 @@ int bem_plan_batched(bem_ctx *ctx, const bem_op *op, int32_t nbatch, const bem_b
   bem_plan *p = new (std::nothrow) bem_plan;
   if (!p) return fail(ctx, BEM_ENOMEM, "host allocation failed");
   p->ctx = ctx;
+  p->device = ctx->device;
   p->kernel = op->kernel;
   p->layer = op->layer;
   p->mixed = op->precision == BEM_MIXED;
@@ -568,12 +587,13 @@ int bem_plan_batched(bem_ctx *ctx, const bem_op *op, int32_t nbatch, const bem_b
   e = hipGraphInstantiate(&p->exec, p->graph, nullptr, nullptr, 0);
   if (e != hipSuccess) return bail(hip_fail(ctx, e, "hipGraphInstantiate"));
   if (tune) *tune = p->cfg;
+  ctx->plans.insert(p);
   *plan_out = p;
   return BEM_OK;
 }
 
 int bem_run_batched(bem_plan *plan, void *stream) {
-  if (!plan) return BEM_EINVAL;
+  if (!plan || !plan->ctx) return BEM_EINVAL;  // null, or its context is gone
   DeviceGuard guard(plan->ctx->device);
   const hipError_t e = hipGraphLaunch(plan->exec, static_cast<hipStream_t>(stream));
   if (e != hipSuccess) return hip_fail(plan->ctx, e, "hipGraphLaunch");
@@ -584,8 +604,9 @@ int64_t bem_plan_tiles(const bem_plan *plan) { return plan ? plan->ntiles : 0; }
 
 void bem_plan_destroy(bem_plan *plan) {
   if (!plan) return;
+  if (plan->ctx) plan->ctx->plans.erase(plan);
   {
-    DeviceGuard guard(plan->ctx->device);
+    DeviceGuard guard(plan->device);
     (void)hipDeviceSynchronize();
     release(plan);
   }

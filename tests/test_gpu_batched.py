@@ -215,3 +215,24 @@ def test_plan_rejects_bad_ids_before_launch(pk, ctx):
     empty.run()
     ctx.check()
     empty.close()
+
+
+def test_plan_outliving_its_context(pk, batch):
+    # destroying the context first releases the plan's device resources; the
+    # plan then refuses to run, and destroying it afterwards is safe (no use
+    # of the freed context, no HIP error left behind for later calls)
+    import torch
+    c2 = pk.Context(0)
+    op = pk.make_op(pk.LAPLACE, pk.SLP, q_regular=4, q_singular=4)
+    outs = [torch.zeros(e["total"], dtype=torch.float64, device="cuda") for e in batch[:2]]
+    plan = pk.Plan(c2, op, [(e["mesh"], e["blocks"], o, e["coupling"]) for e, o in zip(batch, outs)])
+    plan.run()
+    c2.check()
+    c2.close()
+    with pytest.raises(pk.BemError) as ei:
+        plan.run()
+    assert ei.value.code == pk.BEM_EINVAL
+    plan.close()
+    x = torch.ones(1024, device="cuda")
+    assert float(x.sum()) == 1024.0
+    torch.cuda.synchronize()
