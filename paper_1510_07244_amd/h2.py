@@ -155,7 +155,7 @@ class H2Setup:
                                     lv.A, lv.a_off, 2 * m, lv.V, lv.v_off, max_rows=lv.max_rows)
             B.levels.append(lv)
         self.ctx.check()
-        B.replay = self._replay_plan(B)
+        B.replay = None  # built by the first basis_replay
         return B
 
     def _replay_plan(self, B):
@@ -210,6 +210,8 @@ class H2Setup:
         """Enqueue the GPU part of a basis construction again (Green matrices
         and contractions of every level, one launch each) with the pivots and
         inverses already chosen."""
+        if B.replay is None:
+            B.replay = self._replay_plan(B)
         rp = B.replay
         self.ctx.green_matrix(self.mesh, self.op(SLP), B.side, rp.row_ptr, rp.row_idx, rp.z, rp.zn,
                               rp.zw, rp.delta, rp.a_off, rp.A, max_rows=rp.max_rows, stream=stream)

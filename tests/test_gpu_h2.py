@@ -160,6 +160,7 @@ def test_basis_replay_equals_setup_bitwise(pk, ctx, kernel, kappa, side):
     h = H2Setup(ctx, m.v, m.tri, kernel=kernel, kappa=kappa, q_regular=4, q_singular=4)
     B = h.basis(side)
     assert len(B.levels) > 2
+    B.replay = h._replay_plan(B)  # as the first basis_replay would
     A0, V0 = B.replay.A.clone(), B.replay.V.clone()
     B.replay.A.fill_(float("nan"))
     B.replay.V.fill_(float("nan"))

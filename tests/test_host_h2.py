@@ -67,3 +67,16 @@ def test_aca_rejects_bad_arguments():
     import paper_1510_07244_amd as pk
     with pytest.raises(pk.BemError):
         pk.aca(np.zeros(4), [0], [2], 2, -1.0, 2)
+
+
+def test_aca_nan_columns_stay_in_bounds():
+    # a column of NaN has no entry equal to its (NaN-ignoring) maximum: the
+    # pivot search must stop at the column's end; an all-NaN matrix has rank 0
+    import paper_1510_07244_amd as pk
+    A = np.full((5, 4), np.nan)
+    rank, _, _, _ = pk.aca(A.T.ravel().copy(), [0], [5], 4, 1e-12, 4)
+    assert rank[0] == 0
+    B = np.random.default_rng(0).standard_normal((8, 6))
+    B[:, 2] = np.nan
+    rank, _, pcol, _ = pk.aca(B.T.ravel().copy(), [0], [8], 6, 1e-12, 6)
+    assert 0 < rank[0] <= 6 and 2 not in pcol[0, :rank[0]]
