@@ -147,8 +147,7 @@ class H2Bench:
         t0 = time.perf_counter()
         self.h = h = H2Setup(ctx, m.v, m.tri, kernel=pk.LAPLACE, q_regular=Q, q_singular=Q)
         t1 = time.perf_counter()
-        self.V = h.basis(0)
-        self.W = h.basis(1)
+        self.V, self.W = h.bases((0, 1))
         sync()
         t2 = time.perf_counter()
         self.near, self.n_near = h.near_blocks()

@@ -96,67 +96,93 @@ class H2Setup:
     # ----------------------------------------------------------- bases
     def basis(self, side):
         """Construct the nested cluster basis of one side, level by level."""
+        return self.bases((side,))[0]
+
+    def bases(self, sides=(0, 1)):
+        """Construct the nested cluster bases of several sides together, level
+        by level: per level one Green-matrix launch per side into one buffer,
+        one copy to the host, one pivot search over the clusters of every side
+        (twice the clusters per call keep the host threads busy at the top
+        levels), then one contraction launch per side."""
         import torch
         ct, m = self.ct, self.m
-        B = ClusterBasis(side, ct.n)
+        Bs = [ClusterBasis(side, ct.n) for side in sides]
         op = self.op(SLP)
         for h in range(int(self.height.max()) + 1):
             cls = np.nonzero(self.height == h)[0]
-            lv = LevelPlan()
-            lv.cls = cls
-            rows = []
-            for c in cls:
-                s = ct.sons[c]
-                r = ct.idx(c) if s[0] < 0 else np.concatenate([B.piv[s[0]], B.piv[s[1]]])
-                B.rows[c] = r.astype(np.int32)
-                rows.append(B.rows[c])
-            nrows = np.array([r.size for r in rows], dtype=np.int32)
-            rp = np.zeros(cls.size + 1, dtype=np.int32)
-            rp[1:] = np.cumsum(nrows)
-            a_off = np.zeros(cls.size, dtype=np.int64)
-            a_off[1:] = np.cumsum(nrows.astype(np.int64) * 2 * m)[:-1]
-            lv.row_idx_h = np.concatenate(rows)
-            lv.row_ptr = _dev(rp, torch.int32)
-            lv.row_idx = _dev(lv.row_idx_h, torch.int32)
-            lv.z = _dev(self.z[cls], torch.float64)
-            lv.zn = _dev(self.zn[cls], torch.float64)
-            lv.zw = _dev(self.zw[cls], torch.float64)
-            lv.delta = _dev(self.delta[cls], torch.float64)
-            lv.a_off = _dev(a_off, torch.int64)
-            lv.A = torch.empty(int(nrows.astype(np.int64).sum() * 2 * m), dtype=self.adtype,
-                               device="cuda")
-            lv.max_rows = int(nrows.max())
-            self.ctx.green_matrix(self.mesh, op, side, lv.row_ptr, lv.row_idx, lv.z, lv.zn, lv.zw,
-                                  lv.delta, lv.a_off, lv.A, max_rows=lv.max_rows)
+            lvs, nrows_all = [], []
+            for B in Bs:
+                lv = LevelPlan()
+                lv.cls = cls
+                rows = []
+                for c in cls:
+                    s = ct.sons[c]
+                    r = ct.idx(c) if s[0] < 0 else np.concatenate([B.piv[s[0]], B.piv[s[1]]])
+                    B.rows[c] = r.astype(np.int32)
+                    rows.append(B.rows[c])
+                lv.nrows_h = np.array([r.size for r in rows], dtype=np.int32)
+                lv.row_idx_h = np.concatenate(rows)
+                lvs.append(lv)
+                nrows_all.append(lv.nrows_h)
+            nrows_all = np.concatenate(nrows_all)
+            a_all = np.zeros(nrows_all.size, dtype=np.int64)  # offsets into the level's buffer
+            a_all[1:] = np.cumsum(nrows_all.astype(np.int64) * 2 * m)[:-1]
+            A_all = torch.empty(int(nrows_all.astype(np.int64).sum() * 2 * m), dtype=self.adtype,
+                                device="cuda")
+            base = 0
+            for B, lv in zip(Bs, lvs):
+                nrows = lv.nrows_h
+                rp = np.zeros(cls.size + 1, dtype=np.int32)
+                rp[1:] = np.cumsum(nrows)
+                a_off = np.zeros(cls.size, dtype=np.int64)
+                a_off[1:] = np.cumsum(nrows.astype(np.int64) * 2 * m)[:-1]
+                size = int(nrows.astype(np.int64).sum() * 2 * m)
+                lv.row_ptr = _dev(rp, torch.int32)
+                lv.row_idx = _dev(lv.row_idx_h, torch.int32)
+                lv.z = _dev(self.z[cls], torch.float64)
+                lv.zn = _dev(self.zn[cls], torch.float64)
+                lv.zw = _dev(self.zw[cls], torch.float64)
+                lv.delta = _dev(self.delta[cls], torch.float64)
+                lv.a_off = _dev(a_off, torch.int64)
+                lv.A = A_all[base:base + size]
+                lv.max_rows = int(nrows.max())
+                self.ctx.green_matrix(self.mesh, op, B.side, lv.row_ptr, lv.row_idx, lv.z, lv.zn,
+                                      lv.zw, lv.delta, lv.a_off, lv.A, max_rows=lv.max_rows)
+                base += size
             self.ctx.check()
-            A_h = lv.A.cpu().numpy()
+            A_h = A_all.cpu().numpy()
             Af = A_h.view(np.float64) if self.cplx else A_h
-            max_rank = int(min(nrows.max(), 2 * m))
-            rank, prow, pcol, pinv = aca(Af, a_off, nrows, 2 * m, self.eps, max_rank,
-                                         is_complex=self.cplx)
-            for p, c in enumerate(cls):
-                k = rank[p]
-                B.rank[c] = k
-                B.piv[c] = B.rows[c][prow[p, :k]]
-                B.where[c] = (len(B.levels), p)
-            v_off = np.zeros(cls.size, dtype=np.int64)
-            v_off[1:] = np.cumsum(nrows.astype(np.int64) * rank)[:-1]
-            lv.nrows_h, lv.v_off_h = nrows, v_off
-            lv.rank_h, lv.pcol_h, lv.pinv_h = rank, pcol, pinv
-            lv.nrows = _dev(nrows, torch.int32)
-            lv.rank = _dev(rank, torch.int32)
-            lv.piv_cols = _dev(pcol, torch.int32)
-            lv.pinv = _dev(pinv, torch.float64)
-            lv.max_rank = max_rank
-            lv.v_off = _dev(v_off, torch.int64)
-            lv.V = torch.empty(int((nrows.astype(np.int64) * rank).sum()), dtype=self.adtype,
-                               device="cuda")
-            self.ctx.basis_contract(self.cplx, lv.nrows, lv.rank, max_rank, lv.piv_cols, lv.pinv,
-                                    lv.A, lv.a_off, 2 * m, lv.V, lv.v_off, max_rows=lv.max_rows)
-            B.levels.append(lv)
+            max_rank = int(min(nrows_all.max(), 2 * m))
+            rank_all, prow, pcol, pinv = aca(Af, a_all, nrows_all, 2 * m, self.eps, max_rank,
+                                             is_complex=self.cplx)
+            for si, (B, lv) in enumerate(zip(Bs, lvs)):
+                sl = slice(si * cls.size, (si + 1) * cls.size)
+                nrows, rank = lv.nrows_h, rank_all[sl]
+                for p, c in enumerate(cls):
+                    k = rank[p]
+                    B.rank[c] = k
+                    B.piv[c] = B.rows[c][prow[sl][p, :k]]
+                    B.where[c] = (len(B.levels), p)
+                v_off = np.zeros(cls.size, dtype=np.int64)
+                v_off[1:] = np.cumsum(nrows.astype(np.int64) * rank)[:-1]
+                lv.v_off_h = v_off
+                lv.rank_h, lv.pcol_h, lv.pinv_h = rank, pcol[sl], pinv[sl]
+                lv.nrows = _dev(nrows, torch.int32)
+                lv.rank = _dev(rank, torch.int32)
+                lv.piv_cols = _dev(pcol[sl], torch.int32)
+                lv.pinv = _dev(pinv[sl], torch.float64)
+                lv.max_rank = max_rank
+                lv.v_off = _dev(v_off, torch.int64)
+                lv.V = torch.empty(int((nrows.astype(np.int64) * rank).sum()), dtype=self.adtype,
+                                   device="cuda")
+                self.ctx.basis_contract(self.cplx, lv.nrows, lv.rank, max_rank, lv.piv_cols,
+                                        lv.pinv, lv.A, lv.a_off, 2 * m, lv.V, lv.v_off,
+                                        max_rows=lv.max_rows)
+                B.levels.append(lv)
         self.ctx.check()
-        B.replay = None  # built by the first basis_replay
-        return B
+        for B in Bs:
+            B.replay = None  # built by the first basis_replay
+        return Bs
 
     def _replay_plan(self, B):
         """Inputs of all levels concatenated (level by level), so that a replay

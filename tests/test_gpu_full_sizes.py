@@ -101,7 +101,7 @@ def test_helmholtz_h2_coupling_sphere32768(pk, ctx):
     from paper_1510_07244_amd.h2 import H2Setup
     m = octahedron_sphere(64)
     h = H2Setup(ctx, m.v, m.tri, kernel=pk.HELMHOLTZ, kappa=8.0, q_regular=5, q_singular=5)
-    V, W = h.basis(0), h.basis(1)
+    V, W = h.bases((0, 1))
     blocks, total = h.coupling_blocks(V, W)
     op = h.op(pk.DLP)
     out = torch.full((total,), float("nan"), dtype=pk.out_dtype(op), device="cuda")
