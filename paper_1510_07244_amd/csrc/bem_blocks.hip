@@ -568,27 +568,42 @@ int rule_chunk(int nq, int kernel) {
   return 4;
 }
 
-size_t block_lds_bytes(int nq_pad, int tr, int tc, bool mixed) {
+// LDS of a sub-tile; without the pair lists (coupling launches: every pair is
+// regular, phase C only flags, and the lists sit past the allocation unread).
+size_t block_lds_bytes(int nq_pad, int tr, int tc, bool mixed, bool lists) {
   size_t dbl = (size_t)blk::ypoint_doubles(mixed) * nq_pad * tc + 10 * (size_t)tr +
                3 * (size_t)nq_pad + 3 * (size_t)tc;
   if (mixed) dbl += 3 * (size_t)tc + 6 * (size_t)tr + 6 * (size_t)tc;
   const size_t ints = (size_t)4 * tr + 4 * (size_t)tc + 36;
-  return dbl * 8 + ints * 4 + (size_t)2 * (2 * (size_t)tr * tc + blk::kSortPad);
+  return dbl * 8 + ints * 4 + (lists ? (size_t)2 * (2 * (size_t)tr * tc + blk::kSortPad) : 0);
 }
 
+// Largest sub-tile within the LDS budget.  Near-field sub-tiles carry the
+// pair lists, whose entries pack row and column in 6 bits each (at most
+// 64 x 64); so do mixed-precision coupling sub-tiles (their near-singular
+// pairs go to the FP64 pass through the lists).  Plain coupling sub-tiles
+// have no lists and take up to 128 rows and 96 columns, so that most coupling
+// blocks (ranks up to ~100) are one sub-tile.
 bool block_tile_shape(int nq_pad, bool mixed, size_t lds_budget, int *tr, int *tc,
-                      size_t *lds_bytes) {
-  static const int shapes[][2] = {{64, 64}, {64, 32}, {64, 16}, {64, 8}, {32, 8}, {16, 8}, {8, 8}};
-  for (auto &sh : shapes) {
-    const size_t bytes = block_lds_bytes(nq_pad, sh[0], sh[1], mixed);
-    if (bytes <= lds_budget) {
-      *tr = sh[0];
-      *tc = sh[1];
-      *lds_bytes = bytes;
-      return true;
+                      size_t *lds_bytes, bool coupling) {
+  static const int near_shapes[][2] = {{64, 64}, {64, 32}, {64, 16}, {64, 8}, {32, 8}, {16, 8},
+                                       {8, 8}};
+  static const int coupling_shapes[][2] = {{128, 96}, {128, 80}, {96, 80}, {128, 64}, {64, 64},
+                                           {64, 32}, {64, 16}, {64, 8}, {32, 8}, {16, 8}, {8, 8}};
+  const bool lists = !coupling || mixed;
+  auto try_list = [&](const int(*shapes)[2], int n) {
+    for (int k = 0; k < n; ++k) {
+      const size_t bytes = block_lds_bytes(nq_pad, shapes[k][0], shapes[k][1], mixed, lists);
+      if (bytes <= lds_budget) {
+        *tr = shapes[k][0];
+        *tc = shapes[k][1];
+        *lds_bytes = bytes;
+        return true;
+      }
     }
-  }
-  return false;
+    return false;
+  };
+  return lists ? try_list(near_shapes, 7) : try_list(coupling_shapes, 11);
 }
 
 hipError_t launch_blocks(int kernel, int layer, bool coupling, bool mixed, const BlockArgs &a,

@@ -183,7 +183,7 @@ int assemble_blocks(bem_ctx *ctx, const bem_mesh *mesh, const bem_op *op,
   a.nq_pad = (rules->nq + xc - 1) / xc * xc;
   size_t lds;
   const bool mixed = op->precision == BEM_MIXED;
-  if (!bem::block_tile_shape(a.nq_pad, mixed, ctx->lds_budget, &a.tr, &a.tc, &lds))
+  if (!bem::block_tile_shape(a.nq_pad, mixed, ctx->lds_budget, &a.tr, &a.tc, &lds, coupling))
     return fail(ctx, BEM_EUNSUPPORTED, "quadrature order too high for the LDS budget");
   a.near_ratio = op->near_singular_ratio;
   for (int c = 0; c < 4; ++c) a.ss.eta[c] = rules->ss[c], a.ss.np[c] = rules->np[c];

@@ -247,8 +247,8 @@ hipError_t launch_entries(int kernel, int layer, bool mixed, const EntryArgs &a,
 // sub-tile shape (rows, columns) and LDS bytes of the block kernel for a
 // padded rule size within an LDS budget; false if nothing fits
 bool block_tile_shape(int nq_pad, bool mixed, size_t lds_budget, int *tr, int *tc,
-                      size_t *lds_bytes);
-size_t block_lds_bytes(int nq_pad, int tr, int tc, bool mixed);
+                      size_t *lds_bytes, bool coupling = false);
+size_t block_lds_bytes(int nq_pad, int tr, int tc, bool mixed, bool lists = true);
 int rule_chunk(int nq, int kernel);  // x-points per register chunk
 
 }  // namespace bem
