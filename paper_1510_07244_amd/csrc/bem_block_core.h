@@ -15,7 +15,7 @@ using namespace dev;
 constexpr double kPad = 1.0e4;       // coordinate of column padding points (weight 0)
 constexpr uint16_t kNoPair = 0xffff; // empty slot of the sorted singular list
 constexpr int kNearSingular = 0;     // list class of near-singular regular pairs (mixed)
-constexpr int kSortPad = 384;        // room for the padding of up to 6 groups
+constexpr int kSortPad = 512;        // room for the padding of up to 8 groups
 
 // LDS layout of one sub-tile (up to TR rows x TC columns; triangle rule of nq
 // points padded to nqp with zero weights):

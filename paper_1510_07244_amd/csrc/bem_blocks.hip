@@ -233,16 +233,6 @@ __device__ __forceinline__ void singular_chunk(const BlockArgs &a, const Lds &l,
   if (have) store_as<KERNEL, MIXED>(a.out, dst, v, a.flags);
 }
 
-// Phases D and E with a static assignment of chunks to waves.
-template <int KERNEL, int LAYER, bool MIXED>
-__device__ void singular_pass(const BlockArgs &a, const Lds &l, const BlockHdr &h, int64_t r0,
-                              int64_t c0) {
-  const Groups gr = group_listed(l);
-  const int wave = threadIdx.x / kWave;
-  for (int chunk = wave; chunk * kWave < gr.total; chunk += kThreads / kWave)
-    singular_chunk<KERNEL, LAYER, MIXED>(a, l, h, r0, c0, gr, chunk * kWave);
-}
-
 // Whether entry (rl, cl) of the staged sub-tile goes to the FP64 pass:
 // a common vertex (cls > 0), or in the mixed form a near-singular pair
 // (bounding boxes closer than ratio * the larger box diagonal).
@@ -359,7 +349,7 @@ __device__ __forceinline__ Acc<KERNEL> regular_entry_q(int q, const Lds &l, int 
 template <int KERNEL, int LAYER>
 __device__ void subtile_learned(const BlockArgs &a, const OrderRules &o, const Lds &l,
                                 const BlockHdr &h, int64_t r0, int64_t c0) {
-  const int tid = threadIdx.x, wave = tid / kWave, lane = tid & (kWave - 1);
+  const int tid = threadIdx.x, lane = tid & (kWave - 1);
   const int TR = a.tr, TC = a.tc;
   const int64_t nr = h.nr, off = h.off;
   const double kq = 0.25 * a.kappa;
@@ -387,37 +377,53 @@ __device__ void subtile_learned(const BlockArgs &a, const OrderRules &o, const L
     atomicAdd(&l.ccount[8 + q], 1);
   }
   __syncthreads();
+  // the singular pairs grouped by class at the front of sorted[], then the
+  // regular ones by order (each group padded to a multiple of 64)
+  const Groups gr = group_listed(l);
   const int nreg = *l.rcount;
   int seg[7];
-  int total = 0;
+  int total = gr.total;
   for (int q = o.q_max; q >= 2; --q) {
     seg[q] = total;
     total += (l.ccount[8 + q] + 63) & ~63;
   }
-  for (int k = tid; k < total; k += kThreads) l.sorted[k] = kNoPair;
+  for (int k = gr.total + tid; k < total; k += kThreads) l.sorted[k] = kNoPair;
   __syncthreads();
   for (int k = tid; k < nreg; k += kThreads) {
     const uint16_t code = l.list[cap - 1 - k];
     const int q = code >> 12;
     l.sorted[seg[q] + atomicAdd(&l.cursor[8 + q], 1)] = code;
   }
-  __syncthreads();
-  for (int q = o.q_max; q >= 2; --q) {
-    const int n = l.ccount[8 + q];
-    if (n == 0) continue;
-    const int xc = learned_xc(KERNEL, q);
-    const int nq = o.nq[q], nqp = (nq + xc - 1) / xc * xc;
-    for (int k = tid; k < nqp; k += kThreads) {
-      const bool real = k < nq;
-      l.rule[k] = real ? o.rule[q][k] : 0.0;
-      l.rule[nqp + k] = real ? o.rule[q][nq + k] : 0.0;
-      l.rule[2 * nqp + k] = real ? o.rule[q][2 * nq + k] : 0.0;
+  // one phase per order present (its column points staged), the singular
+  // chunks joining the first phase; the waves take chunks from a counter
+  int nsc = gr.total / kWave;
+  for (int q = o.q_max; q >= 1; --q) {
+    const int n = q >= 2 ? l.ccount[8 + q] : 0;
+    if (n == 0 && !(q == 1 && nsc > 0)) continue;  // q = 1: singular chunks alone
+    if (tid == 0) l.cursor[15] = 0;
+    const int xc = q >= 2 ? learned_xc(KERNEL, q) : 1;
+    const int nq = q >= 2 ? o.nq[q] : 0, nqp = (nq + xc - 1) / xc * xc;
+    if (n > 0) {
+      for (int k = tid; k < nqp; k += kThreads) {
+        const bool real = k < nq;
+        l.rule[k] = real ? o.rule[q][k] : 0.0;
+        l.rule[nqp + k] = real ? o.rule[q][nq + k] : 0.0;
+        l.rule[2 * nqp + k] = real ? o.rule[q][2 * nq + k] : 0.0;
+      }
     }
-    __syncthreads();
-    stage_columns<false>(a, l, h, tc, nq, nqp);
-    const int span = (n + 63) & ~63;
-    for (int chunk = wave; chunk * kWave < span; chunk += kThreads / kWave) {
-      const uint16_t code = l.sorted[seg[q] + chunk * kWave + lane];
+    __syncthreads();  // sorted[], the counter and the rule are in place
+    if (n > 0) stage_columns<false>(a, l, h, tc, nq, nqp);
+    const int nrc = ((n + 63) & ~63) / kWave;
+    for (;;) {
+      int c = 0;
+      if (lane == 0) c = atomicAdd(&l.cursor[15], 1);
+      c = __shfl(c, 0, kWave);
+      if (c >= nsc + nrc) break;
+      if (c < nsc) {
+        singular_chunk<KERNEL, LAYER, false>(a, l, h, r0, c0, gr, c * kWave);
+        continue;
+      }
+      const uint16_t code = l.sorted[seg[q] + (c - nsc) * kWave + lane];
       if (code == kNoPair) continue;
       const int rl = code & 63, cl = (code >> 6) & 63;
       Acc<KERNEL> v = regular_entry_q<KERNEL, LAYER>(q, l, TR, TC, nqp, rl, cl, kq);
@@ -425,9 +431,9 @@ __device__ void subtile_learned(const BlockArgs &a, const OrderRules &o, const L
       if constexpr (KERNEL == BEM_HELMHOLTZ) v.im *= scale;
       store_as<KERNEL, false>(a.out, off + (r0 + rl) + nr * (c0 + cl), v, a.flags);
     }
-    __syncthreads();  // before the next order's points replace these
+    nsc = 0;
+    __syncthreads();  // before the next order's points and counter replace these
   }
-  singular_pass<KERNEL, LAYER, false>(a, l, h, r0, c0);
 }
 
 template <int KERNEL, int LAYER>
