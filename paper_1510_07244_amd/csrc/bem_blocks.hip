@@ -1,7 +1,8 @@
 // Block assembly kernels (gfx950, wave64).  One sub-tile (up to 64 x 64
-// entries of one block G[t x s]) is processed by one workgroup: regular pairs
-// one entry per lane, the rest (singular pairs; near-singular pairs in the
-// mixed form) grouped by class in LDS and done one pair per lane in FP64.
+// entries of one block G[t x s]; up to 128 x 80 for a plain coupling block)
+// is processed by one workgroup: regular pairs one entry per lane, the rest
+// (singular pairs; near-singular pairs in the mixed form) grouped by class in
+// LDS and done one pair per lane in FP64.
 //   k_blocks      one workgroup per block, looping over its sub-tiles;
 //   k_persistent  a fixed grid of workgroups popping sub-tiles of many
 //                 blocks (of many meshes) from a cost-sorted global queue.
@@ -169,7 +170,8 @@ __device__ void stage_columns(const BlockArgs &a, const Lds &l, const BlockHdr &
 // Phase D: the listed pairs (front of l.list, *l.count of them) grouped by
 // class (identical, edge, vertex, near-singular) into l.sorted, each group
 // padded to a multiple of 64 with kNoPair so that every wave-sized chunk
-// holds one class.  Expects a barrier after the listing; ends with one.
+// holds one class.  Expects a barrier after the listing; ends with one
+// unless nothing is listed.
 struct Groups {
   int seg[4];  // start of the group of class c
   int total;   // padded length
