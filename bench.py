@@ -14,8 +14,10 @@ near-field and coupling blocks of both operators.
 
 One step (the data-parallel hot path, inputs resident in HBM, pivots as
 chosen by the setup): Green matrices and basis contractions of both bases,
-near-field blocks of SLP and DLP, coupling blocks of SLP and DLP.  value =
-Galerkin entries (near field + coupling) per second.  The roofline object is
+near-field blocks of SLP and DLP, coupling blocks of SLP and DLP (the single
+layer's coupling blocks of a pair (t, s), (s, t) evaluated once, the other
+written as the transpose).  value = Galerkin entries written (near field +
+coupling) per second; entries_evaluated_per_step counts those evaluated.  The roofline object is
 for the dominant kernel, the DLP near-field block kernel (VALU-bound FP64),
 measured with HIP events on its launch stream; cpu_baseline is the FP64 CPU
 oracle on a bounded sample of the same blocks.
@@ -151,7 +153,9 @@ class H2Bench:
         sync()
         t2 = time.perf_counter()
         self.near, self.n_near = h.near_blocks()
-        self.cs, self.n_cs = h.coupling_blocks(self.V, self.V)
+        # single layer: of (t, s), (s, t) only t < s is evaluated, the other
+        # block is written as its transpose
+        self.cs, self.n_cs = h.coupling_blocks(self.V, self.V, mirror=True)
         self.cd, self.n_cd = h.coupling_blocks(self.V, self.W)
         self.ops = [h.op(pk.SLP), h.op(pk.DLP)]
         if mixed:  # regular pairs in FP32, singular and near-singular in FP64
@@ -192,6 +196,10 @@ class H2Bench:
     def entries(self):
         return 2 * self.n_near + self.n_cs + self.n_cd
 
+    def entries_evaluated(self):
+        # the single layer's mirrored coupling blocks are written, not evaluated
+        return 2 * self.n_near + self.n_cs // 2 + self.n_cd
+
 
 class BatchedBench:
     """Batched form: near-field and coupling blocks of the Laplace single
@@ -211,7 +219,7 @@ class BatchedBench:
             h = H2Setup(ctx, m.v, m.tri, kernel=pk.LAPLACE, q_regular=Q, q_singular=Q)
             V = h.basis(0)
             near, n_near = h.near_blocks()
-            cs, n_cs = h.coupling_blocks(V, V)
+            cs, n_cs = h.coupling_blocks(V, V, mirror=True)
             self.items.append((h, near, n_near, cs, n_cs))
         torch.cuda.synchronize()
         self.t_bases = time.perf_counter() - t0
@@ -494,6 +502,9 @@ def main():
                         "plain FP64",
             "triangles": int(m.nt), "near_blocks": int(len(h.near)), "far_blocks": int(len(h.far)),
             "entries_per_step": int(hb.entries()),
+            "entries_evaluated_per_step": int(hb.entries_evaluated()),
+            "single_layer_coupling": "of each admissible pair (t, s), (s, t) the block with "
+                                     "t < s is evaluated, the other written as its transpose",
             "near_entries_per_operator": int(hb.n_near),
             "coupling_entries": {"slp": int(hb.n_cs), "dlp": int(hb.n_cd)},
             "rank_mean": {"row_basis": float(ranks_v.mean()), "dlp_column_basis": float(ranks_w.mean())},

@@ -112,7 +112,13 @@ typedef struct {
  * n + 1 nondecreasing entries with row_ptr[n] <= row_len, col_ptr[n] <=
  * col_len).  Its entries go to out[out_off[b] + r + nrows_b * c] (column-major,
  * leading dimension nrows_b) with out_off[b] >= 0 and
- * out_off[b] + nrows_b * ncols_b <= out_len.  Blocks must not overlap in out. */
+ * out_off[b] + nrows_b * ncols_b <= out_len.  Blocks must not overlap in out.
+ * mirror_off (coupling lists of single layers only, else NULL): the kernels
+ * g(x, y) = g(y, x) give G_ij = G_ji for disjoint pairs (up to rounding), so
+ * block b is also written transposed, entry (r, c) to
+ * out[mirror_off[b] + c + ncols_b * r] (the block G[cols_b x rows_b],
+ * column-major); mirror_off[b] < 0: no mirror.  A mirror that does not fit in
+ * out raises the device flag and is not written.  NULL: no mirrors. */
 typedef struct {
     int32_t n;
     const int32_t *row_ptr;
@@ -122,6 +128,7 @@ typedef struct {
     const int32_t *col_idx;
     int64_t col_len;
     const int64_t *out_off;
+    const int64_t *mirror_off;
 } bem_blocks;
 
 /* Create a context on HIP device `device` (tables, scratch, flags). */
@@ -150,7 +157,10 @@ int bem_assemble_nearfield(bem_ctx *ctx, const bem_mesh *mesh, const bem_op *op,
  * bem_assemble_nearfield, with the pivot triangle lists as rows and columns.
  * Only the regular rule is used: admissible blocks are separated, so every
  * pair must be disjoint; a pair that shares a vertex is left unwritten and
- * raises the device flag (BEM_EINVAL at bem_check). */
+ * raises the device flag (BEM_EINVAL at bem_check).  With pivots->mirror_off
+ * (single layers only; BEM_EINVAL for a double layer) each block is also
+ * written transposed, so that of an admissible pair (t, s), (s, t) with the
+ * same bases one block is evaluated for both. */
 int bem_assemble_coupling(bem_ctx *ctx, const bem_mesh *mesh, const bem_op *op,
                           const bem_blocks *pivots, void *out, int64_t out_len,
                           void *stream);

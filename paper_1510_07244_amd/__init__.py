@@ -45,7 +45,7 @@ class bem_blocks(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int32), ("row_ptr", ctypes.c_void_p), ("row_idx", ctypes.c_void_p),
                 ("row_len", ctypes.c_int64), ("col_ptr", ctypes.c_void_p),
                 ("col_idx", ctypes.c_void_p), ("col_len", ctypes.c_int64),
-                ("out_off", ctypes.c_void_p)]
+                ("out_off", ctypes.c_void_p), ("mirror_off", ctypes.c_void_p)]
 
 
 def _load():
@@ -109,7 +109,7 @@ class Mesh:
 class Blocks:
     """Device block list (CSR row/column triangle lists and output offsets)."""
 
-    def __init__(self, row_ptr, row_idx, col_ptr, col_idx, out_off):
+    def __init__(self, row_ptr, row_idx, col_ptr, col_idx, out_off, mirror_off=None):
         import torch
         dev = dict(device="cuda")
         self.row_ptr = torch.as_tensor(row_ptr, dtype=torch.int32).to(**dev).contiguous()
@@ -117,10 +117,13 @@ class Blocks:
         self.col_ptr = torch.as_tensor(col_ptr, dtype=torch.int32).to(**dev).contiguous()
         self.col_idx = torch.as_tensor(col_idx, dtype=torch.int32).to(**dev).contiguous()
         self.out_off = torch.as_tensor(out_off, dtype=torch.int64).to(**dev).contiguous()
+        self.mirror_off = (None if mirror_off is None else
+                           torch.as_tensor(mirror_off, dtype=torch.int64).to(**dev).contiguous())
         self.n = self.out_off.numel()
         self.c = bem_blocks(self.n, _ptr(self.row_ptr), _ptr(self.row_idx), self.row_idx.numel(),
                             _ptr(self.col_ptr), _ptr(self.col_idx), self.col_idx.numel(),
-                            _ptr(self.out_off))
+                            _ptr(self.out_off),
+                            None if self.mirror_off is None else _ptr(self.mirror_off))
 
     @classmethod
     def from_lists(cls, rows, cols):

@@ -18,6 +18,7 @@ using namespace blk;
 
 struct BlockHdr {
   int64_t rp0, cp0, nr, nc, off;
+  int64_t moff;       // transposed copy (coupling of a single layer), -1: none
   double cx, cy, cz;  // block-local origin: first vertex of the first row triangle
 };
 
@@ -45,6 +46,11 @@ __device__ __forceinline__ bool block_header(const BlockArgs &a, int b, BlockHdr
   h->nr = nr;
   h->nc = nc;
   h->off = off;
+  h->moff = a.mirror_off ? a.mirror_off[b] : -1;
+  if (h->moff >= 0 && nr > 0 && (h->moff > a.out_len || nc > (a.out_len - h->moff) / nr)) {
+    if (threadIdx.x == 0) atomicOr(a.flags, FLAG_EINVAL);  // the mirror does not fit
+    h->moff = -1;
+  }
   if (nr > 0 && nc > 0) {
     h->cx = a.geo[G_V0X * a.ldg + i0];
     h->cy = a.geo[G_V0Y * a.ldg + i0];
@@ -219,6 +225,7 @@ __device__ __forceinline__ void singular_chunk(const BlockArgs &a, const Lds &l,
       const Acc<KERNEL> v = regular_pair_fp64<KERNEL, LAYER>(a.geo, a.ldg, a.rule, a.nq, a.kappa,
                                                              l.rid[rl], l.cid[cl]);
       store_as<KERNEL, MIXED>(a.out, dst, v, a.flags);
+      if (h.moff >= 0) store_as<KERNEL, MIXED>(a.out, h.moff + (c0 + cl) + h.nc * (r0 + rl), v, a.flags);
     }
     return;
   }
@@ -320,6 +327,7 @@ __device__ void subtile(const BlockArgs &a, const Lds &l, const BlockHdr &h, int
     v.re *= scale;
     if constexpr (KERNEL == BEM_HELMHOLTZ) v.im *= scale;
     store_as<KERNEL, MIXED>(a.out, off + (r0 + rl) + nr * (c0 + cl), v, a.flags);
+    if (h.moff >= 0) store_as<KERNEL, MIXED>(a.out, h.moff + (c0 + cl) + h.nc * (r0 + rl), v, a.flags);
   }
 }
 

@@ -151,6 +151,8 @@ int assemble_blocks(bem_ctx *ctx, const bem_mesh *mesh, const bem_op *op,
   if ((rc = check_mesh(ctx, mesh)) || (rc = check_op(ctx, op)) ||
       (rc = check_blocks(ctx, blocks, out, out_len)))
     return rc;
+  if (blocks->mirror_off && (!coupling || op->layer != BEM_SLP))
+    return fail(ctx, BEM_EINVAL, "mirror_off is for coupling lists of single layers only");
   if (blocks->n == 0) return BEM_OK;
   if (mesh->nt == 0) return fail(ctx, BEM_EINVAL, "blocks given for an empty mesh");
   DeviceGuard g(ctx->device);
@@ -175,6 +177,7 @@ int assemble_blocks(bem_ctx *ctx, const bem_mesh *mesh, const bem_op *op,
   a.row_len = blocks->row_len;
   a.col_len = blocks->col_len;
   a.out_off = blocks->out_off;
+  a.mirror_off = blocks->mirror_off;
   a.out = out;
   a.out_len = out_len;
   a.rule = rules->tri;

@@ -89,6 +89,7 @@ struct BlockArgs {
   const int32_t *row_ptr, *row_idx, *col_ptr, *col_idx;
   int64_t row_len, col_len;
   const int64_t *out_off;
+  const int64_t *mirror_off;  // coupling of a single layer: transposed copies (or null)
   void *out;
   int64_t out_len;
   const double *rule;  // [3][nq]

@@ -262,7 +262,31 @@ class H2Setup:
         cols = [self.ct.idx(s) for t, s in self.near]
         return Blocks.from_lists(rows, cols)
 
-    def coupling_blocks(self, row_basis, col_basis):
+    def coupling_blocks(self, row_basis, col_basis, mirror=False):
+        """Pivot lists of the admissible blocks, outputs back to back in the
+        order of self.far.  mirror (a single layer with one basis for rows and
+        columns): of each pair (t, s), (s, t) only the block with t < s is
+        evaluated and the other is written as its transpose."""
         rows = [row_basis.piv[t] for t, s in self.far]
         cols = [col_basis.piv[s] for t, s in self.far]
-        return Blocks.from_lists(rows, cols)
+        if not mirror:
+            return Blocks.from_lists(rows, cols)
+        if row_basis is not col_basis:
+            raise ValueError("mirrored coupling blocks need one basis for rows and columns")
+        sizes = np.array([len(r) * len(c) for r, c in zip(rows, cols)], dtype=np.int64)
+        off = np.zeros(len(rows), dtype=np.int64)
+        off[1:] = np.cumsum(sizes)[:-1]
+        pos = {(int(t), int(s)): k for k, (t, s) in enumerate(self.far)}
+        keep = [k for k, (t, s) in enumerate(self.far) if t < s]
+        if 2 * len(keep) != len(self.far):
+            raise ValueError("the admissible blocks are not symmetric")
+        mirror_off = np.array([off[pos[(int(self.far[k][1]), int(self.far[k][0]))]] for k in keep],
+                              dtype=np.int64)
+        kr = [rows[k] for k in keep]
+        kc = [cols[k] for k in keep]
+        rp = np.zeros(len(keep) + 1, dtype=np.int32)
+        cp = np.zeros(len(keep) + 1, dtype=np.int32)
+        rp[1:] = np.cumsum([len(r) for r in kr])
+        cp[1:] = np.cumsum([len(c) for c in kc])
+        cat = lambda xs: np.concatenate(xs).astype(np.int32) if xs else np.zeros(0, np.int32)
+        return Blocks(rp, cat(kr), cp, cat(kc), off[keep], mirror_off), int(sizes.sum())

@@ -114,7 +114,7 @@ def _h2_errors(pk, ctx, m, kernel, kappa, layer, nblocks, seed):
     h = H2Setup(ctx, m.v, m.tri, kernel=kernel, kappa=kappa, q_regular=4, q_singular=4)
     V = h.basis(0)
     W = V if layer == pk.SLP else h.basis(1)
-    blocks, total = h.coupling_blocks(V, W)
+    blocks, total = h.coupling_blocks(V, W, mirror=layer == pk.SLP)  # single layer: mirrored
     op = h.op(layer)
     out = torch.full((total,), float("nan"), dtype=pk.out_dtype(op), device="cuda")
     ctx.assemble_coupling(h.mesh, op, blocks, out)
@@ -174,3 +174,57 @@ def test_basis_replay_equals_setup_bitwise(pk, ctx, kernel, kappa, side):
     # the levels' views see the replayed values
     leaf = next(c for c in range(h.ct.n) if h.ct.sons[c, 0] < 0)
     assert np.all(np.isfinite(B.vhat(leaf)))
+
+
+@pytest.mark.parametrize("kernel,kappa,precision", [(0, 0.0, 0), (1, 4.0, 0), (0, 0.0, 1)])
+def test_mirrored_coupling_equals_full(pk, ctx, kernel, kappa, precision):
+    # of each admissible pair (t, s), (s, t) of a single layer only t < s is
+    # evaluated; its transpose fills (s, t).  Evaluated blocks equal the full
+    # list's bit for bit, mirrored ones agree to rounding (G_ij = G_ji)
+    from paper_1510_07244_amd.h2 import H2Setup
+    import torch
+    m = octahedron_sphere(16)
+    h = H2Setup(ctx, m.v, m.tri, kernel=kernel, kappa=kappa, q_regular=4, q_singular=4)
+    V = h.basis(0)
+    full, total = h.coupling_blocks(V, V)
+    half, total2 = h.coupling_blocks(V, V, mirror=True)
+    assert total2 == total and half.n * 2 == full.n
+    op = h.op(pk.SLP)
+    if precision:
+        op.precision, op.near_singular_ratio = pk.MIXED, 0.5
+    outs = []
+    for blocks in (full, half):
+        out = torch.full((total,), float("nan"), dtype=pk.out_dtype(op), device="cuda")
+        ctx.assemble_coupling(h.mesh, op, blocks, out)
+        ctx.check()
+        outs.append(out.cpu().numpy())
+    a, b = outs
+    assert np.all(np.isfinite(b))  # every entry written
+    o = 0
+    for t, s in h.far:
+        kt, ks = V.piv[t].size, V.piv[s].size
+        x, y = a[o:o + kt * ks], b[o:o + kt * ks]
+        if t < s:
+            assert np.array_equal(x, y)
+        elif precision:
+            assert np.linalg.norm(x - y) <= 1e-6 * np.linalg.norm(x)
+        else:
+            assert np.abs(x - y).max() <= 1e-13 * np.abs(x).max()
+        o += kt * ks
+
+
+def test_mirror_rejected_outside_single_layer_coupling(pk, ctx):
+    from paper_1510_07244_amd.h2 import H2Setup
+    import torch
+    m = octahedron_sphere(16)
+    h = H2Setup(ctx, m.v, m.tri)
+    V = h.basis(0)
+    half, total = h.coupling_blocks(V, V, mirror=True)
+    assert half.n > 0
+    out = torch.zeros(total, dtype=torch.float64, device="cuda")
+    with pytest.raises(pk.BemError) as e:
+        ctx.assemble_coupling(h.mesh, h.op(pk.DLP), half, out)
+    assert e.value.code == pk.BEM_EINVAL
+    with pytest.raises(pk.BemError) as e:
+        ctx.assemble_nearfield(h.mesh, h.op(pk.SLP), half, out)
+    assert e.value.code == pk.BEM_EINVAL
