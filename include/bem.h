@@ -113,12 +113,15 @@ typedef struct {
  * col_len).  Its entries go to out[out_off[b] + r + nrows_b * c] (column-major,
  * leading dimension nrows_b) with out_off[b] >= 0 and
  * out_off[b] + nrows_b * ncols_b <= out_len.  Blocks must not overlap in out.
- * mirror_off (coupling lists of single layers only, else NULL): the kernels
- * g(x, y) = g(y, x) give G_ij = G_ji for disjoint pairs (up to rounding), so
- * block b is also written transposed, entry (r, c) to
- * out[mirror_off[b] + c + ncols_b * r] (the block G[cols_b x rows_b],
- * column-major); mirror_off[b] < 0: no mirror.  A mirror that does not fit in
- * out raises the device flag and is not written.  NULL: no mirrors. */
+ * mirror_off (single layers only, else NULL): the kernels g(x, y) = g(y, x)
+ * give G_ji = G_ij, so block b also fills its transpose G[cols_b x rows_b]
+ * at out[mirror_off[b] + c + ncols_b * r] (column-major); mirror_off[b] < 0:
+ * no mirror.  Disjoint and vertex-adjacent pairs are written once evaluated
+ * (equal up to rounding); an edge-adjacent pair's mirror entry is evaluated
+ * as the pair (j, i), the Sauter-Schwab rule for a shared edge not being
+ * symmetric.  A mirror onto the block itself (a block on the diagonal) or
+ * one that does not fit in out raises the device flag and is not written;
+ * mirrors must not overlap other outputs.  NULL: no mirrors. */
 typedef struct {
     int32_t n;
     const int32_t *row_ptr;
@@ -160,7 +163,8 @@ int bem_assemble_nearfield(bem_ctx *ctx, const bem_mesh *mesh, const bem_op *op,
  * raises the device flag (BEM_EINVAL at bem_check).  With pivots->mirror_off
  * (single layers only; BEM_EINVAL for a double layer) each block is also
  * written transposed, so that of an admissible pair (t, s), (s, t) with the
- * same bases one block is evaluated for both. */
+ * same bases one block is evaluated for both (likewise for near-field
+ * lists: one of the blocks (t, s), (s, t), t != s). */
 int bem_assemble_coupling(bem_ctx *ctx, const bem_mesh *mesh, const bem_op *op,
                           const bem_blocks *pivots, void *out, int64_t out_len,
                           void *stream);

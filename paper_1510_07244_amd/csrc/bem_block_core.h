@@ -14,6 +14,7 @@ using namespace dev;
 
 constexpr double kPad = 1.0e4;       // coordinate of column padding points (weight 0)
 constexpr uint16_t kNoPair = 0xffff; // empty slot of the sorted singular list
+constexpr uint16_t kSwapped = 0x4000; // listed code: the mirror block's entry (j, i)
 constexpr int kNearSingular = 0;     // list class of near-singular regular pairs (mixed)
 constexpr int kSortPad = 512;        // room for the padding of up to 8 groups
 
@@ -31,7 +32,7 @@ constexpr int kSortPad = 512;        // room for the padding of up to 8 groups
 //   ints           rid[TR], rv[3][TR], cid[TC], cv[3][TC], count, bad,
 //                  rcount, pad, per-group counts[16] and cursors[16]
 //                  (classes at 0 .. 3, orders q at 8 + q)
-//   list[TR*TC]    uint16 codes (row | col << 6 | group << 12) of the pairs
+//   list[TR*TC]    uint16 codes (row | col << 6 | group << 12, kSwapped) of the pairs
 //                  left to the FP64 pass (singular; near-singular if mixed),
 //                  from the front; with per-entry orders, the regular pairs
 //                  (group = order) from the back

@@ -47,8 +47,9 @@ __device__ __forceinline__ bool block_header(const BlockArgs &a, int b, BlockHdr
   h->nc = nc;
   h->off = off;
   h->moff = a.mirror_off ? a.mirror_off[b] : -1;
-  if (h->moff >= 0 && nr > 0 && (h->moff > a.out_len || nc > (a.out_len - h->moff) / nr)) {
-    if (threadIdx.x == 0) atomicOr(a.flags, FLAG_EINVAL);  // the mirror does not fit
+  if (h->moff >= 0 && nr > 0 &&
+      (h->moff == off || h->moff > a.out_len || nc > (a.out_len - h->moff) / nr)) {
+    if (threadIdx.x == 0) atomicOr(a.flags, FLAG_EINVAL);  // onto itself, or does not fit
     h->moff = -1;
   }
   if (nr > 0 && nc > 0) {
@@ -199,7 +200,7 @@ __device__ __forceinline__ Groups group_listed(const Lds &l) {
   __syncthreads();
   for (int k = tid; k < ns; k += kThreads) {
     const uint16_t code = l.list[k];
-    const int cls = code >> 12;
+    const int cls = (code >> 12) & 3;
     l.sorted[g.seg[cls] + atomicAdd(&l.cursor[cls], 1)] = code;
   }
   __syncthreads();
@@ -218,28 +219,37 @@ __device__ __forceinline__ void singular_chunk(const BlockArgs &a, const Lds &l,
                   : pos < gr.seg[0] ? CLS_VERTEX : kNearSingular;
   const uint16_t code = l.sorted[pos + lane];
   const bool active = code != kNoPair;
+  const bool swapped = active && (code & kSwapped);
   const int rl = code & 63, cl = (code >> 6) & 63;
-  const int64_t dst = h.off + (r0 + rl) + h.nr * (c0 + cl);
+  // a swapped code is the mirror block's entry: the pair (j, i) to (c, r)
+  const int64_t dst = swapped ? h.moff + (c0 + cl) + h.nc * (r0 + rl)
+                              : h.off + (r0 + rl) + h.nr * (c0 + cl);
+  const int64_t mdst = h.moff >= 0 && !swapped && cls != CLS_EDGE
+                           ? h.moff + (c0 + cl) + h.nc * (r0 + rl) : -1;
   if (cls == kNearSingular) {
     if (active) {
       const Acc<KERNEL> v = regular_pair_fp64<KERNEL, LAYER>(a.geo, a.ldg, a.rule, a.nq, a.kappa,
                                                              l.rid[rl], l.cid[cl]);
       store_as<KERNEL, MIXED>(a.out, dst, v, a.flags);
-      if (h.moff >= 0) store_as<KERNEL, MIXED>(a.out, h.moff + (c0 + cl) + h.nc * (r0 + rl), v, a.flags);
+      if (mdst >= 0) store_as<KERNEL, MIXED>(a.out, mdst, v, a.flags);
     }
     return;
   }
   PairGeo g;
   bool have = false;
-  if (active) have = pair_geometry(a.v, a.tri, a.nv, a.geo, a.ldg, l.rid[rl], l.cid[cl], cls,
-                                   a.flags, &g);
+  if (active)
+    have = pair_geometry(a.v, a.tri, a.nv, a.geo, a.ldg, swapped ? l.cid[cl] : l.rid[rl],
+                         swapped ? l.rid[rl] : l.cid[cl], cls, a.flags, &g);
   if (!have) {  // idle lane: harmless finite geometry, result discarded
     for (int c = 0; c < 3; ++c)
       g.E1i[c] = c == 0, g.E2i[c] = c == 1, g.E1j[c] = -(c == 2), g.E2j[c] = 0, g.n[c] = 0;
     g.scale = 0.0;
   }
   const Acc<KERNEL> v = ss_pair_lane<KERNEL, LAYER>(g, a.ss, cls, a.kappa);
-  if (have) store_as<KERNEL, MIXED>(a.out, dst, v, a.flags);
+  if (have) {
+    store_as<KERNEL, MIXED>(a.out, dst, v, a.flags);
+    if (mdst >= 0) store_as<KERNEL, MIXED>(a.out, mdst, v, a.flags);
+  }
 }
 
 // Whether entry (rl, cl) of the staged sub-tile goes to the FP64 pass:
@@ -299,6 +309,10 @@ __device__ void subtile(const BlockArgs &a, const Lds &l, const BlockHdr &h, int
     } else {
       l.list[atomicAdd(l.count, 1)] = (uint16_t)(rl | (cl << 6) | (cls << 12));
       atomicAdd(&l.ccount[cls], 1);
+      if (h.moff >= 0 && cls == CLS_EDGE) {  // the mirror's entry, evaluated as (j, i)
+        l.list[atomicAdd(l.count, 1)] = (uint16_t)(rl | (cl << 6) | (cls << 12) | kSwapped);
+        atomicAdd(&l.ccount[cls], 1);
+      }
     }
   }
   __syncthreads();

@@ -151,8 +151,8 @@ int assemble_blocks(bem_ctx *ctx, const bem_mesh *mesh, const bem_op *op,
   if ((rc = check_mesh(ctx, mesh)) || (rc = check_op(ctx, op)) ||
       (rc = check_blocks(ctx, blocks, out, out_len)))
     return rc;
-  if (blocks->mirror_off && (!coupling || op->layer != BEM_SLP))
-    return fail(ctx, BEM_EINVAL, "mirror_off is for coupling lists of single layers only");
+  if (blocks->mirror_off && op->layer != BEM_SLP)
+    return fail(ctx, BEM_EINVAL, "mirror_off is for single layers only");
   if (blocks->n == 0) return BEM_OK;
   if (mesh->nt == 0) return fail(ctx, BEM_EINVAL, "blocks given for an empty mesh");
   DeviceGuard g(ctx->device);

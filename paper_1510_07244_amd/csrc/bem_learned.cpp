@@ -59,7 +59,7 @@ int block_list_args(bem_ctx *ctx, const bem_mesh *mesh, const bem_op *op, const 
       (rc = check_blocks(ctx, b, out, out_len)))
     return rc;
   if (b->n > 0 && mesh->nt == 0) return fail(ctx, BEM_EINVAL, "blocks given for an empty mesh");
-  if (b->mirror_off) return fail(ctx, BEM_EINVAL, "mirror_off is for coupling lists only");
+  if (b->mirror_off) return fail(ctx, BEM_EINVAL, "mirror_off is not supported by the learned form");
   return BEM_OK;
 }
 

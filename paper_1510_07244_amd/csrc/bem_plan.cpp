@@ -295,8 +295,8 @@ int bem_plan_batched(bem_ctx *ctx, const bem_op *op, int32_t nbatch, const bem_b
         return bail(rc);
       if ((bt.coupling != 0 && bt.coupling != 1) || bt.reserved)
         return bail(fail(ctx, BEM_EINVAL, "bem_batch.coupling must be 0/1, reserved 0"));
-      if (bt.blocks->mirror_off && (!bt.coupling || op->layer != BEM_SLP))
-        return bail(fail(ctx, BEM_EINVAL, "mirror_off is for coupling lists of single layers only"));
+      if (bt.blocks->mirror_off && op->layer != BEM_SLP)
+        return bail(fail(ctx, BEM_EINVAL, "mirror_off is for single layers only"));
       if (bt.blocks->n > 0 && bt.mesh->nt == 0)
         return bail(fail(ctx, BEM_EINVAL, "blocks given for an empty mesh"));
       hb.coupling = bt.coupling;

@@ -257,10 +257,38 @@ class H2Setup:
         return D @ B.vhat(c)
 
     # ----------------------------------------------------------- blocks
-    def near_blocks(self):
+    def near_blocks(self, mirror=False):
+        """Triangle lists of the inadmissible blocks, outputs back to back in
+        the order of self.near.  mirror (a single layer): of each pair (t, s),
+        (s, t) with t != s only t < s is evaluated, the other written as its
+        transpose (edge-adjacent entries evaluated as (j, i))."""
         rows = [self.ct.idx(t) for t, s in self.near]
         cols = [self.ct.idx(s) for t, s in self.near]
-        return Blocks.from_lists(rows, cols)
+        if not mirror:
+            return Blocks.from_lists(rows, cols)
+        keep = [k for k, (t, s) in enumerate(self.near) if t <= s]
+        return self._mirrored(self.near, rows, cols, keep)
+
+    @staticmethod
+    def _mirrored(pairs, rows, cols, keep):
+        """Blocks `keep` of the list (t, s) -> rows, cols, each with the output
+        offset of (s, t) as its mirror (-1 for t == s); the output layout is
+        that of the whole list."""
+        sizes = np.array([len(r) * len(c) for r, c in zip(rows, cols)], dtype=np.int64)
+        off = np.zeros(len(rows), dtype=np.int64)
+        off[1:] = np.cumsum(sizes)[:-1]
+        pos = {(int(t), int(s)): k for k, (t, s) in enumerate(pairs)}
+        mirror_off = np.array([-1 if pairs[k][0] == pairs[k][1] else
+                               off[pos[(int(pairs[k][1]), int(pairs[k][0]))]] for k in keep],
+                              dtype=np.int64)
+        kr = [rows[k] for k in keep]
+        kc = [cols[k] for k in keep]
+        rp = np.zeros(len(keep) + 1, dtype=np.int32)
+        cp = np.zeros(len(keep) + 1, dtype=np.int32)
+        rp[1:] = np.cumsum([len(r) for r in kr])
+        cp[1:] = np.cumsum([len(c) for c in kc])
+        cat = lambda xs: np.concatenate(xs).astype(np.int32) if xs else np.zeros(0, np.int32)
+        return Blocks(rp, cat(kr), cp, cat(kc), off[keep], mirror_off), int(sizes.sum())
 
     def coupling_blocks(self, row_basis, col_basis, mirror=False):
         """Pivot lists of the admissible blocks, outputs back to back in the
@@ -273,20 +301,7 @@ class H2Setup:
             return Blocks.from_lists(rows, cols)
         if row_basis is not col_basis:
             raise ValueError("mirrored coupling blocks need one basis for rows and columns")
-        sizes = np.array([len(r) * len(c) for r, c in zip(rows, cols)], dtype=np.int64)
-        off = np.zeros(len(rows), dtype=np.int64)
-        off[1:] = np.cumsum(sizes)[:-1]
-        pos = {(int(t), int(s)): k for k, (t, s) in enumerate(self.far)}
         keep = [k for k, (t, s) in enumerate(self.far) if t < s]
         if 2 * len(keep) != len(self.far):
             raise ValueError("the admissible blocks are not symmetric")
-        mirror_off = np.array([off[pos[(int(self.far[k][1]), int(self.far[k][0]))]] for k in keep],
-                              dtype=np.int64)
-        kr = [rows[k] for k in keep]
-        kc = [cols[k] for k in keep]
-        rp = np.zeros(len(keep) + 1, dtype=np.int32)
-        cp = np.zeros(len(keep) + 1, dtype=np.int32)
-        rp[1:] = np.cumsum([len(r) for r in kr])
-        cp[1:] = np.cumsum([len(c) for c in kc])
-        cat = lambda xs: np.concatenate(xs).astype(np.int32) if xs else np.zeros(0, np.int32)
-        return Blocks(rp, cat(kr), cp, cat(kc), off[keep], mirror_off), int(sizes.sum())
+        return self._mirrored(self.far, rows, cols, keep)

@@ -213,7 +213,7 @@ def test_mirrored_coupling_equals_full(pk, ctx, kernel, kappa, precision):
         o += kt * ks
 
 
-def test_mirror_rejected_outside_single_layer_coupling(pk, ctx):
+def test_mirror_rejected_for_double_layers(pk, ctx):
     from paper_1510_07244_amd.h2 import H2Setup
     import torch
     m = octahedron_sphere(16)
@@ -225,6 +225,49 @@ def test_mirror_rejected_outside_single_layer_coupling(pk, ctx):
     with pytest.raises(pk.BemError) as e:
         ctx.assemble_coupling(h.mesh, h.op(pk.DLP), half, out)
     assert e.value.code == pk.BEM_EINVAL
+    near, ntot = h.near_blocks(mirror=True)
+    nout = torch.zeros(ntot, dtype=torch.float64, device="cuda")
     with pytest.raises(pk.BemError) as e:
-        ctx.assemble_nearfield(h.mesh, h.op(pk.SLP), half, out)
+        ctx.assemble_nearfield(h.mesh, h.op(pk.DLP), near, nout)
     assert e.value.code == pk.BEM_EINVAL
+
+
+@pytest.mark.parametrize("kernel,kappa,precision", [(0, 0.0, 0), (1, 4.0, 0), (0, 0.0, 1)])
+def test_mirrored_nearfield_equals_full(pk, ctx, kernel, kappa, precision):
+    # of each near-field pair (t, s), (s, t), t != s, of a single layer only
+    # t < s is evaluated; the transpose fills (s, t), its edge-adjacent
+    # entries evaluated as (j, i).  Evaluated blocks and those entries equal
+    # the full list's bit for bit; the rest agree to rounding
+    from paper_1510_07244_amd.h2 import H2Setup
+    import torch
+    m = octahedron_sphere(16)
+    h = H2Setup(ctx, m.v, m.tri, kernel=kernel, kappa=kappa, q_regular=4, q_singular=4)
+    full, total = h.near_blocks()
+    half, total2 = h.near_blocks(mirror=True)
+    assert total2 == total and half.n < full.n
+    op = h.op(pk.SLP)
+    if precision:
+        op.precision, op.near_singular_ratio = pk.MIXED, 0.5
+    outs = []
+    for blocks in (full, half):
+        out = torch.full((total,), float("nan"), dtype=pk.out_dtype(op), device="cuda")
+        ctx.assemble_nearfield(h.mesh, op, blocks, out)
+        ctx.check()
+        outs.append(out.cpu().numpy())
+    a, b = outs
+    assert np.all(np.isfinite(b))  # every entry written
+    o = 0
+    for t, s in h.near:
+        r, c = h.ct.idx(t), h.ct.idx(s)
+        x, y = a[o:o + r.size * c.size], b[o:o + r.size * c.size]
+        o += r.size * c.size
+        if t <= s:
+            assert np.array_equal(x, y)
+            continue
+        X, Y = x.reshape(c.size, r.size).T, y.reshape(c.size, r.size).T
+        edge = np.array([[len(set(m.tri[i]) & set(m.tri[j])) == 2 for j in c] for i in r])
+        assert np.array_equal(X[edge], Y[edge])
+        if precision:
+            assert np.linalg.norm(X - Y) <= 1e-6 * np.linalg.norm(X)
+        else:
+            assert np.abs(X - Y).max() <= 1e-13 * np.abs(X).max()
