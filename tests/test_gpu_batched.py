@@ -236,3 +236,29 @@ def test_plan_outliving_its_context(pk, batch):
     x = torch.ones(1024, device="cuda")
     assert float(x.sum()) == 1024.0
     torch.cuda.synchronize()
+
+
+def test_batched_mirrored_lists_equal_per_call(pk, ctx):
+    # single-layer lists that write the transposed blocks too (near field and
+    # coupling of an H2 setup): the persistent form gives the per-call bits
+    import torch
+    from paper_1510_07244_amd.h2 import H2Setup
+    m = perturbed_sphere(41, n_min=16, n_max=16)
+    h = H2Setup(ctx, m.v, m.tri, q_regular=4, q_singular=4)
+    V = h.basis(0)
+    lists = [(h.near_blocks(mirror=True), 0), (h.coupling_blocks(V, V, mirror=True), 1)]
+    op = h.op(pk.SLP)
+    ref, outs = [], []
+    for (blocks, total), coupling in lists:
+        r = torch.full((total,), float("nan"), dtype=torch.float64, device="cuda")
+        (ctx.assemble_coupling if coupling else ctx.assemble_nearfield)(h.mesh, op, blocks, r)
+        ctx.check()
+        ref.append(r)
+        outs.append(torch.full((total,), float("nan"), dtype=torch.float64, device="cuda"))
+    plan = pk.Plan(ctx, op, [(h.mesh, b, o, c) for ((b, _), c), o in zip(lists, outs)])
+    plan.run()
+    ctx.check()
+    for r, o in zip(ref, outs):
+        assert np.all(np.isfinite(r.cpu().numpy()))
+        assert np.array_equal(_bits(o), _bits(r))
+    plan.close()
