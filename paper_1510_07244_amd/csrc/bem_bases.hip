@@ -20,13 +20,18 @@ using namespace dev;
 //   side 1:  sqrt(w) int d/dn(x) g(x, z) dx, sqrt(w) delta int d/dn(x) d/dn(z) g(x, z) dx
 // (side 1 is the column basis of the double layer).  Triangle integrals use
 // the Duffy rule: int_tau f = sqrt(g) sum_k w_k f(Phi(s_k, t_k)).
+// A thread takes one row triangle and kGreenPerThread Green points: the rule
+// points x_k on the triangle are formed once and used for every Green point.
+constexpr int kGreenPerThread = 4;
+
 template <int KERNEL, int SIDE>
 __global__ __launch_bounds__(kThreads) void k_green(const GreenArgs a) {
+  constexpr int J = kGreenPerThread;
   const int c = blockIdx.x;
   const int64_t rp0 = a.row_ptr[c], rp1 = a.row_ptr[c + 1];
   const int64_t off = a.out_off[c];
   const int64_t n = rp1 - rp0;
-  const int m = a.m;
+  const int m = a.m, mg = (m + J - 1) / J;
   const bool ok = rp0 >= 0 && rp0 <= rp1 && rp1 <= a.row_len && off >= 0 && off <= a.out_len &&
                   (n == 0 || 2 * (int64_t)m <= (a.out_len - off) / n);
   if (!ok) {
@@ -35,80 +40,96 @@ __global__ __launch_bounds__(kThreads) void k_green(const GreenArgs a) {
   }
   const double delta = a.delta[c];
   const int64_t L = a.ldg;
-  // the entries of one cluster are spread over gridDim.y workgroups
-  for (int64_t e = (int64_t)blockIdx.y * kThreads + threadIdx.x; e < n * m;
+  // the work items (row, group of J Green points) of one cluster are spread
+  // over gridDim.y workgroups; consecutive threads take consecutive rows
+  for (int64_t e = (int64_t)blockIdx.y * kThreads + threadIdx.x; e < n * mg;
        e += (int64_t)gridDim.y * kThreads) {
     const int64_t r = e % n;
-    const int nu = (int)(e / n);
+    const int nu0 = (int)(e / n) * J;
     const int id = a.row_idx[rp0 + r];
     if (id < 0 || id >= a.nt) {
       atomicOr(a.flags, FLAG_EINVAL);
       continue;
     }
-    const double *zp = a.z + 3 * ((int64_t)c * m + nu);
-    const double *np = a.zn + 3 * ((int64_t)c * m + nu);
-    const double zx = zp[0], zy = zp[1], zz = zp[2];
-    const double mx = np[0], my = np[1], mz = np[2];
-    const double wz = a.zw[(int64_t)c * m + nu];
-    // x - z at the rule points: (v0 - z) + s e1 + t e2
-    const double dx0 = a.geo[G_V0X * L + id] - zx, dy0 = a.geo[G_V0Y * L + id] - zy,
-                 dz0 = a.geo[G_V0Z * L + id] - zz;
+    double zx[J], zy[J], zz[J], mx[J], my[J], mz[J], wz[J];
+#pragma unroll
+    for (int j = 0; j < J; ++j) {
+      const int nu = min(nu0 + j, m - 1);  // past m: a copy, not written
+      const double *zp = a.z + 3 * ((int64_t)c * m + nu);
+      const double *np = a.zn + 3 * ((int64_t)c * m + nu);
+      zx[j] = zp[0], zy[j] = zp[1], zz[j] = zp[2];
+      mx[j] = np[0], my[j] = np[1], mz[j] = np[2];
+      wz[j] = a.zw[(int64_t)c * m + nu];
+    }
+    const double v0x = a.geo[G_V0X * L + id], v0y = a.geo[G_V0Y * L + id], v0z = a.geo[G_V0Z * L + id];
     const double e1x = a.geo[G_E1X * L + id], e1y = a.geo[G_E1Y * L + id], e1z = a.geo[G_E1Z * L + id];
     const double e2x = a.geo[G_E2X * L + id], e2y = a.geo[G_E2Y * L + id], e2z = a.geo[G_E2Z * L + id];
     const double nx = a.geo[G_NX * L + id], ny = a.geo[G_NY * L + id], nz = a.geo[G_NZ * L + id];
-    double pr = 0, pi = 0, qr = 0, qi = 0;  // + and - columns
+    double pr[J], pi[J], qr[J], qi[J];  // + and - columns
+#pragma unroll
+    for (int j = 0; j < J; ++j) pr[j] = pi[j] = qr[j] = qi[j] = 0.0;
     for (int k = 0; k < a.nq; ++k) {
       const double s = a.rule[k], t = a.rule[a.nq + k], w = a.rule[2 * a.nq + k];
-      const double dx = fma(s, e1x, fma(t, e2x, dx0));
-      const double dy = fma(s, e1y, fma(t, e2y, dy0));
-      const double dz = fma(s, e1z, fma(t, e2z, dz0));
-      const double r2 = fma(dx, dx, fma(dy, dy, dz * dz));
-      const double iz = rsqrt_newton(r2);  // 1 / r
-      const double i3 = iz * iz * iz;
-      const double dnz = fma(dx, mx, fma(dy, my, dz * mz));  // <x - z, n_z>
-      const double dnx = fma(dx, nx, fma(dy, ny, dz * nz));  // <x - z, n_x>
-      if constexpr (KERNEL == BEM_LAPLACE) {
-        if constexpr (SIDE == 0) {
-          pr = fma(w, iz, pr);
-          qr = fma(w, dnz * i3, qr);
+      // the rule point x = v0 + s e1 + t e2 on the triangle
+      const double px = fma(s, e1x, fma(t, e2x, v0x));
+      const double py = fma(s, e1y, fma(t, e2y, v0y));
+      const double pz = fma(s, e1z, fma(t, e2z, v0z));
+#pragma unroll
+      for (int j = 0; j < J; ++j) {
+        const double dx = px - zx[j], dy = py - zy[j], dz = pz - zz[j];
+        const double r2 = fma(dx, dx, fma(dy, dy, dz * dz));
+        const double iz = rsqrt_newton(r2);  // 1 / r
+        const double i3 = iz * iz * iz;
+        const double dnz = fma(dx, mx[j], fma(dy, my[j], dz * mz[j]));  // <x - z, n_z>
+        const double dnx = fma(dx, nx, fma(dy, ny, dz * nz));           // <x - z, n_x>
+        if constexpr (KERNEL == BEM_LAPLACE) {
+          if constexpr (SIDE == 0) {
+            pr[j] = fma(w, iz, pr[j]);
+            qr[j] = fma(w, dnz * i3, qr[j]);
+          } else {
+            const double nn = fma(nx, mx[j], fma(ny, my[j], nz * mz[j]));
+            pr[j] = fma(w, -dnx * i3, pr[j]);
+            qr[j] = fma(w, fma(-3.0 * dnx * dnz, iz * iz, nn) * i3, qr[j]);
+          }
         } else {
-          const double nn = fma(nx, mx, fma(ny, my, nz * mz));
-          pr = fma(w, -dnx * i3, pr);
-          qr = fma(w, fma(-3.0 * dnx * dnz, iz * iz, nn) * i3, qr);
-        }
-      } else {
-        const double r = r2 * iz, kr = a.kappa * r;
-        double sn, cs;
-        sincos_cw(kr, &sn, &cs);
-        // e^{ikr} (1 - i kr) = (cs + kr sn) + i (sn - kr cs)
-        const double ar = fma(kr, sn, cs), ai = fma(-kr, cs, sn);
-        if constexpr (SIDE == 0) {
-          pr = fma(w * iz, cs, pr);
-          pi = fma(w * iz, sn, pi);
-          qr = fma(w * dnz * i3, ar, qr);
-          qi = fma(w * dnz * i3, ai, qi);
-        } else {
-          const double nn = fma(nx, mx, fma(ny, my, nz * mz));
-          pr = fma(-w * dnx * i3, ar, pr);
-          pi = fma(-w * dnx * i3, ai, pi);
-          // e^{ikr} [ (1 - i kr) nn / r^3 + (k^2 r^2 - 3 + 3 i kr) dnx dnz / r^5 ]
-          const double u = dnx * dnz * iz * iz;
-          const double br = fma(kr, kr, -3.0), bi = 3.0 * kr;
-          const double tr = fma(nn, 1.0, u * br), ti = fma(-nn, kr, u * bi);  // (1 - i kr) nn + u (br + i bi)
-          qr = fma(w * i3, cs * tr - sn * ti, qr);
-          qi = fma(w * i3, sn * tr + cs * ti, qi);
+          const double r = r2 * iz, kr = a.kappa * r;
+          double sn, cs;
+          sincos_cw(kr, &sn, &cs);
+          // e^{ikr} (1 - i kr) = (cs + kr sn) + i (sn - kr cs)
+          const double ar = fma(kr, sn, cs), ai = fma(-kr, cs, sn);
+          if constexpr (SIDE == 0) {
+            pr[j] = fma(w * iz, cs, pr[j]);
+            pi[j] = fma(w * iz, sn, pi[j]);
+            qr[j] = fma(w * dnz * i3, ar, qr[j]);
+            qi[j] = fma(w * dnz * i3, ai, qi[j]);
+          } else {
+            const double nn = fma(nx, mx[j], fma(ny, my[j], nz * mz[j]));
+            pr[j] = fma(-w * dnx * i3, ar, pr[j]);
+            pi[j] = fma(-w * dnx * i3, ai, pi[j]);
+            // e^{ikr} [ (1 - i kr) nn / r^3 + (k^2 r^2 - 3 + 3 i kr) dnx dnz / r^5 ]
+            const double u = dnx * dnz * iz * iz;
+            const double br = fma(kr, kr, -3.0), bi = 3.0 * kr;
+            const double tr = fma(nn, 1.0, u * br), ti = fma(-nn, kr, u * bi);  // (1 - i kr) nn + u (br + i bi)
+            qr[j] = fma(w * i3, cs * tr - sn * ti, qr[j]);
+            qi[j] = fma(w * i3, sn * tr + cs * ti, qi[j]);
+          }
         }
       }
     }
     const double sg = a.geo[G_SG * L + id];
-    const double sp = sqrt(wz) * sg * kInv4Pi, sm = sp * delta;
-    const int64_t ip = off + r + n * nu, im = off + r + n * (m + nu);
-    if constexpr (KERNEL == BEM_LAPLACE) {
-      static_cast<double *>(a.out)[ip] = pr * sp;
-      static_cast<double *>(a.out)[im] = qr * sm;
-    } else {
-      static_cast<double2 *>(a.out)[ip] = make_double2(pr * sp, pi * sp);
-      static_cast<double2 *>(a.out)[im] = make_double2(qr * sm, qi * sm);
+#pragma unroll
+    for (int j = 0; j < J; ++j) {
+      const int nu = nu0 + j;
+      if (nu >= m) break;
+      const double sp = sqrt(wz[j]) * sg * kInv4Pi, sm = sp * delta;
+      const int64_t ip = off + r + n * nu, im = off + r + n * (m + nu);
+      if constexpr (KERNEL == BEM_LAPLACE) {
+        static_cast<double *>(a.out)[ip] = pr[j] * sp;
+        static_cast<double *>(a.out)[im] = qr[j] * sm;
+      } else {
+        static_cast<double2 *>(a.out)[ip] = make_double2(pr[j] * sp, pi[j] * sp);
+        static_cast<double2 *>(a.out)[im] = make_double2(qr[j] * sm, qi[j] * sm);
+      }
     }
   }
 }

@@ -321,7 +321,7 @@ int bem_green_matrix(bem_ctx *ctx, const bem_mesh *mesh, const bem_op *op, int32
   a.kappa = op->kernel == BEM_HELMHOLTZ ? op->kappa : 0.0;
   a.flags = ctx->flags;
   // workgroups per cluster from the row-count hint (any hint is correct)
-  const int64_t per = ((int64_t)std::max(max_rows, 1) * m + 255) / 256;
+  const int64_t per = ((int64_t)std::max(max_rows, 1) * ((m + 3) / 4) + 255) / 256;  // 4 points a thread
   e = bem::launch_green(op->kernel, side, a, (int)std::min<int64_t>(per, 64), s);
   if (e != hipSuccess) return hip_fail(ctx, e, "green kernel launch");
   return BEM_OK;
