@@ -14,9 +14,10 @@ near-field and coupling blocks of both operators.
 
 One step (the data-parallel hot path, inputs resident in HBM, pivots as
 chosen by the setup): Green matrices and basis contractions of both bases,
-near-field blocks of SLP and DLP, coupling blocks of SLP and DLP (the single
-layer's blocks of a pair (t, s), (s, t), t != s, evaluated once, the other
-written as the transpose).  value = Galerkin entries written (near field +
+near-field blocks of SLP and DLP (one pass for both layers over the blocks
+with t <= s), coupling blocks of SLP and DLP (the single layer's blocks of a
+pair (t, s), (s, t), t != s, evaluated once, the other written as the
+transpose).  value = Galerkin entries written (near field +
 coupling) per second; entries_evaluated_per_step counts those evaluated.  The roofline object is
 for the dominant kernel, the double layer's coupling launch (VALU-bound
 FP64, the step's longest), measured with HIP events on its launch stream; cpu_baseline is the FP64 CPU
@@ -92,9 +93,11 @@ def parse():
 
 
 def counter_pass(torch, pk, ctx, m):
-    """The launches the committed traffic counters are read from: the same
-    near-field calls the step times with the full lists (SLP, then DLP), the
-    double layer's coupling launch of the H2 setup, then a copy of known size."""
+    """The launches the committed traffic counters are read from: the
+    per-layer near-field calls with the full lists (SLP, then DLP), the
+    double layer's coupling launch of the H2 setup, the one-pass near field of
+    both layers on the mirrored list (as the step makes it), then a copy of
+    known size."""
     from paper_1510_07244_amd.h2 import H2Setup
     ct = pk.ClusterTree(m.v, m.tri, leaf=64)
     near, _ = pk.block_tree(ct, eta=2.0)
@@ -111,6 +114,10 @@ def counter_pass(torch, pk, ctx, m):
     cd, n_cd = h.coupling_blocks(V, W)
     cout = torch.empty(n_cd, dtype=torch.float64, device="cuda")
     ctx.assemble_coupling(h.mesh, h.op(pk.DLP), cd, cout)
+    half, tot = h.near_blocks(mirror=True)
+    o1 = torch.empty(tot, dtype=torch.float64, device="cuda")
+    o2 = torch.empty_like(o1)
+    ctx.assemble_nearfield_both(h.mesh, h.op(pk.SLP), half, o1, o2)
     ctx.check()
     a = torch.ones(1 << 26, dtype=torch.float64, device="cuda")  # 512 MiB
     b = torch.empty_like(a)
@@ -177,18 +184,30 @@ class H2Bench:
         dt = dict(dtype=torch.float32 if mixed else torch.float64, device="cuda")
         self.out = {k: torch.empty(n, **dt) for k, n in
                     (("ns", self.n_near), ("nd", self.n_near), ("cs", self.n_cs), ("cd", self.n_cd))}
+        # plain FP64: the near field of both layers in one pass over the
+        # mirrored list; the mixed form has per-layer near-field passes
+        self.phases = ["bases"] + (["ns", "nd"] if mixed else ["nb"]) + ["cs", "cd"]
         self.assemble()
         ctx.check()
         t3 = time.perf_counter()
         self.t_tree, self.t_bases, self.t_assembly = t1 - t0, t2 - t1, t3 - t2
         self.t_setup = t3 - t0
 
+    def near_calls(self, stream=None):
+        ctx, h, o = self.ctx, self.h, self.out
+        return {
+            "nb": lambda: ctx.assemble_nearfield_both(h.mesh, self.ops[0], self.near_s, o["ns"],
+                                                      o["nd"], stream),
+            "ns": lambda: ctx.assemble_nearfield(h.mesh, self.ops[0], self.near_s, o["ns"], stream),
+            "nd": lambda: ctx.assemble_nearfield(h.mesh, self.ops[1], self.near, o["nd"], stream),
+        }
+
     def assemble(self, stream=None, ev=None):
         ctx, h, o = self.ctx, self.h, self.out
-        seq = [("ns", lambda: ctx.assemble_nearfield(h.mesh, self.ops[0], self.near_s, o["ns"], stream)),
-               ("nd", lambda: ctx.assemble_nearfield(h.mesh, self.ops[1], self.near, o["nd"], stream)),
-               ("cs", lambda: ctx.assemble_coupling(h.mesh, self.ops[0], self.cs, o["cs"], stream)),
-               ("cd", lambda: ctx.assemble_coupling(h.mesh, self.ops[1], self.cd, o["cd"], stream))]
+        near = self.near_calls(stream)
+        seq = [(k, near[k]) for k in self.phases if k in near]
+        seq += [("cs", lambda: ctx.assemble_coupling(h.mesh, self.ops[0], self.cs, o["cs"], stream)),
+                ("cd", lambda: ctx.assemble_coupling(h.mesh, self.ops[1], self.cd, o["cd"], stream))]
         for name, call in seq:
             if ev:
                 ev[name][0].record(stream)
@@ -407,7 +426,7 @@ class LearnedBench:
 
 def run_leg(torch, ctx, hb, stream, steps, warmup):
     """Time `steps` steps after `warmup`; per-phase HIP-event means."""
-    names = ["bases", "ns", "nd", "cs", "cd"]
+    names = hb.phases
     evs = [{k: (torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
             for k in names} for _ in range(steps)]
     for _ in range(warmup):
@@ -422,6 +441,25 @@ def run_leg(torch, ctx, hb, stream, steps, warmup):
     ctx.check(stream)
     phase = {k: float(np.mean([e[k][0].elapsed_time(e[k][1]) for e in evs])) for k in names}
     return (t1 - t0) * 1e3 / steps, phase
+
+
+def per_layer_near(torch, hb, stream, reps):
+    """HIP-event means of the per-layer near-field passes (mirrored single
+    layer, full double layer) that the one-pass call replaces."""
+    calls = hb.near_calls(stream)
+    out = {}
+    for k in ("ns", "nd"):
+        calls[k]()
+        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+              for _ in range(reps)]
+        for a, b in ev:
+            a.record(stream)
+            calls[k]()
+            b.record(stream)
+        torch.cuda.synchronize()
+        out[k] = float(np.mean([a.elapsed_time(b) for a, b in ev]))
+    hb.ctx.check(stream)
+    return out
 
 
 def cpu_baseline(m, hb, seconds):
@@ -474,6 +512,7 @@ def main():
         setups.append((hb.t_setup, hb.t_tree, hb.t_bases, hb.t_assembly))
     stream = torch.cuda.current_stream()
     ms_step, phase = run_leg(torch, ctx, hb, stream, args.steps, args.warmup)
+    per_layer = per_layer_near(torch, hb, stream, max(5, min(args.steps, 20)))
     hm = H2Bench(pk, ctx, m, mixed=True)
     ms_step_m, phase_m = run_leg(torch, ctx, hm, stream, args.steps, args.warmup)
     batched = None
@@ -502,6 +541,17 @@ def main():
     counts_s[2] += edges_lo
     f_slp = near_flops(counts_s, 0, 0, Q, Q)
     hb.near_evaluated_slp = int(sum(rows[k].size * cols[k].size for k in up)) + edges_lo
+    # one pass over the blocks with t <= s: per regular pair the double
+    # layer's work plus the single layer's accumulation (the transposed
+    # pair's double layer costs per-point work only); singular pairs: both
+    # layers of (i, j), the double layer of (j, i) and the single layer of
+    # edge-adjacent (j, i)
+    cu = class_counts(m.tri, [rows[k] for k in up], [cols[k] for k in up])
+    cl_ = class_counts(m.tri, [rows[k] for k in lo], [cols[k] for k in lo])
+    sing = lambda c: [0] + list(c[1:])
+    f_both = (float(cu[0]) * (Q ** 2) ** 2 * (FLOPS_PER_POINT[(0, 1)] + 2) +
+              near_flops(sing(cu), 0, 0, Q, Q) + near_flops(sing(cu), 0, 1, Q, Q) +
+              near_flops(sing(cl_), 0, 1, Q, Q) + near_flops([0, 0, cl_[2], 0], 0, 0, Q, Q))
     st = np.array(setups)
     best = int(np.argmin(st[:, 0]))
     ranks_v = hb.V.rank[hb.V.rank > 0]
@@ -530,6 +580,9 @@ def main():
                                      "single layer (near field and coupling) the block with t < s "
                                      "is evaluated, the other written as its transpose (near-field "
                                      "edge-adjacent entries evaluated as (j, i))",
+            "near_field": "one pass for both layers over the blocks with t <= s: each point "
+                          "pair's distance and reciprocal root serve the single layer of (i, j) "
+                          "and the double layer of (i, j) and (j, i)",
             "near_entries_per_operator": int(hb.n_near),
             "coupling_entries": {"slp": int(hb.n_cs), "dlp": int(hb.n_cd)},
             "rank_mean": {"row_basis": float(ranks_v.mean()), "dlp_column_basis": float(ranks_w.mean())},
@@ -549,17 +602,26 @@ def main():
             "traffic_unit": "bytes per launch (FETCH_SIZE + WRITE_SIZE, calibrated)",
             "ms_per_launch": phase["cd"], "flops_per_launch": f_cd,
         },
-        "roofline_near_dlp": {
-            "kernel": "k_blocks<Laplace, DLP> near field", "bound": "alu",
-            "achieved": f_dlp / (phase["nd"] * 1e-3) / 1e12, "peak": FP64_VALU_PEAK / 1e12,
-            "unit": "TFLOP/s", "frac": f_dlp / (phase["nd"] * 1e-3) / FP64_VALU_PEAK,
-            "ms_per_launch": phase["nd"], "flops_per_launch": f_dlp,
+        "roofline_near_both": {
+            "kernel": "k_blocks<Laplace, SLP+DLP> near field, one pass over the blocks with "
+                      "t <= s (both layers of (t, s) and (s, t))", "bound": "alu",
+            "achieved": f_both / (phase["nb"] * 1e-3) / 1e12, "peak": FP64_VALU_PEAK / 1e12,
+            "unit": "TFLOP/s", "frac": f_both / (phase["nb"] * 1e-3) / FP64_VALU_PEAK,
+            "ms_per_launch": phase["nb"], "flops_per_launch": f_both,
         },
-        "roofline_slp": {
-            "kernel": "k_blocks<Laplace, SLP> near field (mirrored: blocks with t <= s)", "bound": "alu",
-            "achieved": f_slp / (phase["ns"] * 1e-3) / 1e12, "peak": FP64_VALU_PEAK / 1e12,
-            "unit": "TFLOP/s", "frac": f_slp / (phase["ns"] * 1e-3) / FP64_VALU_PEAK,
-            "ms_per_launch": phase["ns"], "flops_per_launch": f_slp,
+        "near_per_layer": {
+            "ms": per_layer, "one_pass_ms": phase["nb"],
+            "speedup": (per_layer["ns"] + per_layer["nd"]) / phase["nb"],
+            "roofline_dlp": {
+                "kernel": "k_blocks<Laplace, DLP> near field (all blocks)", "bound": "alu",
+                "achieved": f_dlp / (per_layer["nd"] * 1e-3) / 1e12,
+                "frac": f_dlp / (per_layer["nd"] * 1e-3) / FP64_VALU_PEAK,
+                "flops_per_launch": f_dlp},
+            "roofline_slp": {
+                "kernel": "k_blocks<Laplace, SLP> near field (mirrored: blocks with t <= s)",
+                "bound": "alu", "achieved": f_slp / (per_layer["ns"] * 1e-3) / 1e12,
+                "frac": f_slp / (per_layer["ns"] * 1e-3) / FP64_VALU_PEAK,
+                "flops_per_launch": f_slp},
         },
         "forms": {
             "plain_fp64": {"value": hb.entries() / (ms_step * 1e-3), "ms_per_step": ms_step},

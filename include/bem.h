@@ -169,6 +169,23 @@ int bem_assemble_coupling(bem_ctx *ctx, const bem_mesh *mesh, const bem_op *op,
                           const bem_blocks *pivots, void *out, int64_t out_len,
                           void *stream);
 
+/* Near field of the single and the double layer potential operators V and K
+ * in one pass (both enter the Laplace formulation and the Brakhage-Werner
+ * formulation of Sec. 4; entries as bem_assemble_nearfield's for
+ * op->layer = BEM_SLP and BEM_DLP, up to rounding).  Every point pair's
+ * distance, reciprocal root (and for Helmholtz its sine and cosine) serve
+ * both kernels.  out_slp, out_dlp: device, out_len entries each, same layout,
+ * distinct buffers; op->layer (BEM_SLP or BEM_DLP) is not used; plain FP64 only
+ * (BEM_EUNSUPPORTED for BEM_MIXED).  With blocks->mirror_off, block b also
+ * fills its transpose at mirror_off[b] in both outputs: the single layer as
+ * for bem_assemble_nearfield, the double layer of every transposed pair
+ * (j, i) evaluated from the same point pairs as (i, j) (regular pairs) or by
+ * its own Sauter-Schwab rule (singular pairs) -- so one of the blocks (t, s),
+ * (s, t) gives both layers of both. */
+int bem_assemble_nearfield_both(bem_ctx *ctx, const bem_mesh *mesh, const bem_op *op,
+                                const bem_blocks *blocks, void *out_slp, void *out_dlp,
+                                int64_t out_len, void *stream);
+
 /* Arbitrary entries: out[k] = G(rows[k], cols[k]) for 0 <= k < n, each pair
  * classified and integrated by its rule (Sec. 2.1 eq. matrix_entry, Sec. 2.2).
  * rows, cols: device int32[n]; out: device, n entries. */

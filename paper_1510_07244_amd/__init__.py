@@ -63,6 +63,8 @@ def _load():
     for name in ("bem_assemble_nearfield", "bem_assemble_coupling"):
         getattr(L, name).argtypes = [P, ctypes.POINTER(bem_mesh), ctypes.POINTER(bem_op),
                                      ctypes.POINTER(bem_blocks), P, ctypes.c_int64, P]
+    L.bem_assemble_nearfield_both.argtypes = [P, ctypes.POINTER(bem_mesh), ctypes.POINTER(bem_op),
+                                              ctypes.POINTER(bem_blocks), P, P, ctypes.c_int64, P]
     L.bem_eval_entries.argtypes = [P, ctypes.POINTER(bem_mesh), ctypes.POINTER(bem_op),
                                    ctypes.c_int64, P, P, P, P]
     L.bem_cluster_tree.argtypes = [P, ctypes.c_int32, P, ctypes.c_int32, ctypes.c_int32,
@@ -178,6 +180,15 @@ class Context:
         self._rc(_lib.bem_assemble_nearfield(self.h, ctypes.byref(mesh.c), ctypes.byref(op),
                                              ctypes.byref(blocks.c), _ptr(out), out.numel(),
                                              _stream(stream)))
+
+    def assemble_nearfield_both(self, mesh, op, blocks, out_slp, out_dlp, stream=None):
+        """bem_assemble_nearfield_both: single layer to out_slp, double layer
+        to out_dlp (same length and type), one pass."""
+        if out_slp.numel() != out_dlp.numel() or out_slp.dtype != out_dlp.dtype:
+            raise ValueError("out_slp and out_dlp must have the same length and dtype")
+        self._rc(_lib.bem_assemble_nearfield_both(self.h, ctypes.byref(mesh.c), ctypes.byref(op),
+                                                  ctypes.byref(blocks.c), _ptr(out_slp),
+                                                  _ptr(out_dlp), out_slp.numel(), _stream(stream)))
 
     def assemble_coupling(self, mesh, op, pivots, out, stream=None):
         self._rc(_lib.bem_assemble_coupling(self.h, ctypes.byref(mesh.c), ctypes.byref(op),

@@ -17,6 +17,7 @@ constexpr uint16_t kNoPair = 0xffff; // empty slot of the sorted singular list
 constexpr uint16_t kSwapped = 0x4000; // listed code: the mirror block's entry (j, i)
 constexpr int kNearSingular = 0;     // list class of near-singular regular pairs (mixed)
 constexpr int kSortPad = 512;        // room for the padding of up to 8 groups
+constexpr int kBoth = 2;             // layer template value: single and double layer in one pass
 
 // LDS layout of one sub-tile (up to TR rows x TC columns; triangle rule of nq
 // points padded to nqp with zero weights):
@@ -28,6 +29,7 @@ constexpr int kSortPad = 512;        // room for the padding of up to 8 groups
 //   rg[10][TR]     row geometry 2 (v0 - c), 2 e1, 2 e2, sqrt(g_i)
 //   rule[3][nqp]   s, t, w of the triangle rule
 //   cn[3][TC]      column normals
+//   both layers:   rn[3][TR] row normals
 //   mixed only:    cg[3][TC] = 2 (v0_j - c); rb[6][TR], cb[6][TC] boxes
 //   ints           rid[TR], rv[3][TR], cid[TC], cv[3][TC], count, bad,
 //                  rcount, pad, per-group counts[16] and cursors[16]
@@ -39,7 +41,7 @@ constexpr int kSortPad = 512;        // room for the padding of up to 8 groups
 //   sorted[TR*TC + kSortPad]  codes grouped (by class or by order), each
 //                  group padded to a multiple of 64 with kNoPair
 struct Lds {
-  double *ys, *rg, *rule, *cn, *cg, *rb, *cb;
+  double *ys, *rg, *rule, *cn, *rn, *cg, *rb, *cb;
   int *rid, *rv, *cid, *cv, *count, *bad, *rcount, *ccount, *cursor;
   uint16_t *list, *sorted;
 };
@@ -47,13 +49,14 @@ struct Lds {
 __host__ __device__ __forceinline__ int ypoint_doubles(bool mixed) { return mixed ? 4 : 6; }
 
 template <bool MIXED>
-__device__ __forceinline__ Lds carve(double *base, int nqp, int TR, int TC) {
+__device__ __forceinline__ Lds carve(double *base, int nqp, int TR, int TC, bool both = false) {
   Lds l;
   l.ys = base;
   l.rg = l.ys + ypoint_doubles(MIXED) * nqp * TC;
   l.rule = l.rg + 10 * TR;
   l.cn = l.rule + 3 * nqp;
-  l.cg = l.cn + 3 * TC;
+  l.rn = both ? l.cn + 3 * TC : nullptr;
+  l.cg = l.cn + 3 * TC + (both ? 3 * TR : 0);
   l.rb = l.cg + (MIXED ? 3 * TC : 0);
   l.cb = l.rb + (MIXED ? 6 * TR : 0);
   int *ib = reinterpret_cast<int *>(l.cb + (MIXED ? 6 * TC : 0));
@@ -163,6 +166,107 @@ __device__ __forceinline__ Acc<KERNEL> regular_entry(const Lds &l, int TR, int T
     if (kb < nqp) point(a0, a1, a2);
   }
   return acc;
+}
+
+// One pass over the point pairs of regular entry (rl, cl) for both layers
+// and for the double layer of the transposed pair (j, i), with k' as in
+// regular_entry.  The distance, its reciprocal root (and for Helmholtz the
+// sine and cosine) of a pair serve all three; with k3 the double layer's
+// radial factor and, per column point b,
+//   t1_b = sum_a wx_a k3_ab,   t2_b = sum_a wx_a <X_a, n_j> k3_ab,
+//   SLP(i, j) = sum_b wy_b sum_a wx_a k_ab,
+//   DLP(i, j) = sum_b wy_b (t2_b - <Y_b, n_j> t1_b),
+//   DLP(j, i) = sum_b wy_b (<Y_b, n_i> - <X, n_i>) t1_b,
+// since <X_a, n_i> takes one value on the row triangle's plane (and <Y_b, n_j>
+// one on the column triangle's).  The point pairs of (j, i) are those of
+// (i, j) with the roles of x and y exchanged: the same triangle rule on both.
+template <int KERNEL, int XC>
+__device__ __forceinline__ void regular_entry_both(const Lds &l, int TR, int TC, int nqp, int rl,
+                                                   int cl, double kq, Acc<KERNEL> *gs,
+                                                   Acc<KERNEL> *gd, Acc<KERNEL> *gm) {
+  const double D0 = l.rg[0 * TR + rl], D1 = l.rg[1 * TR + rl], D2 = l.rg[2 * TR + rl];
+  const double A0 = l.rg[3 * TR + rl], A1 = l.rg[4 * TR + rl], A2 = l.rg[5 * TR + rl];
+  const double B0 = l.rg[6 * TR + rl], B1 = l.rg[7 * TR + rl], B2 = l.rg[8 * TR + rl];
+  const double SG = l.rg[9 * TR + rl];
+  const double n0 = l.cn[cl], n1 = l.cn[TC + cl], n2 = l.cn[2 * TC + cl];
+  const double m0 = l.rn[rl], m1 = l.rn[TR + rl], m2 = l.rn[2 * TR + rl];
+  const double XN = fma(D0, m0, fma(D1, m1, D2 * m2));  // <X, n_i>
+  // -n_i / 2: <-2Y, -n_i / 2> = <Y, n_i>
+  const double p0 = -0.5 * m0, p1 = -0.5 * m1, p2 = -0.5 * m2;
+  const double2 *ycol = reinterpret_cast<const double2 *>(l.ys) + 3 * cl;
+  const int ystride = 3 * TC;
+  Acc<KERNEL> s, d, m;
+  for (int ch = 0; ch < nqp; ch += XC) {
+    double X0[XC], X1[XC], X2[XC], XX[XC], WX[XC], WN[XC];
+#pragma unroll
+    for (int a = 0; a < XC; ++a) {
+      const double u = l.rule[ch + a], t = l.rule[nqp + ch + a], w = l.rule[2 * nqp + ch + a];
+      X0[a] = fma(u, A0, fma(t, B0, D0));
+      X1[a] = fma(u, A1, fma(t, B1, D1));
+      X2[a] = fma(u, A2, fma(t, B2, D2));
+      XX[a] = fma(X0[a], X0[a], fma(X1[a], X1[a], X2[a] * X2[a]));
+      WX[a] = w * SG;
+      WN[a] = WX[a] * fma(X0[a], n0, fma(X1[a], n1, X2[a] * n2));
+    }
+    auto point = [&](const double2 c0, const double2 c1, const double2 c2) {
+      const double M0 = c0.x, M1 = c0.y, M2 = c1.x, YY = c1.y, WY = c2.x, YN = c2.y;
+      double sq[XC], h[XC];
+#pragma unroll
+      for (int a = 0; a < XC; ++a)
+        sq[a] = fma(X2[a], M2, fma(X1[a], M1, fma(X0[a], M0, XX[a] + YY)));  // 4 r^2
+#pragma unroll
+      for (int a = 0; a < XC; ++a) h[a] = __builtin_amdgcn_rsq(sq[a]);
+      double sre = 0.0, sim = 0.0, t1r = 0.0, t1i = 0.0, t2r = 0.0, t2i = 0.0;
+#pragma unroll
+      for (int a = 0; a < XC; ++a) {
+        const double z = h[a] * fma(-(sq[a] * h[a]), h[a], 3.0);  // ~ 1/r
+        const double z3 = z * z * z;
+        if constexpr (KERNEL == BEM_LAPLACE) {
+          sre = fma(WX[a], z, sre);
+          t1r = fma(WX[a], z3, t1r);
+          t2r = fma(WN[a], z3, t2r);
+        } else {
+          const double kr = kq * sq[a] * z;
+          double sn, cs;
+          sincos_cw(kr, &sn, &cs);
+          const double wz = WX[a] * z;
+          sre = fma(wz, cs, sre);
+          sim = fma(wz, sn, sim);
+          const double fr = z3 * fma(kr, sn, cs), fi = z3 * fma(-kr, cs, sn);
+          t1r = fma(WX[a], fr, t1r);
+          t1i = fma(WX[a], fi, t1i);
+          t2r = fma(WN[a], fr, t2r);
+          t2i = fma(WN[a], fi, t2i);
+        }
+      }
+      const double wm = WY * (fma(M0, p0, fma(M1, p1, M2 * p2)) - XN);  // wy 2 <y - x, n_i>
+      s.re = fma(WY, sre, s.re);
+      d.re = fma(WY, fma(-YN, t1r, t2r), d.re);
+      m.re = fma(wm, t1r, m.re);
+      if constexpr (KERNEL == BEM_HELMHOLTZ) {
+        s.im = fma(WY, sim, s.im);
+        d.im = fma(WY, fma(-YN, t1i, t2i), d.im);
+        m.im = fma(wm, t1i, m.im);
+      }
+    };
+    const double2 *yp = ycol;
+    double2 a0 = yp[0], a1 = yp[1], a2 = yp[2];
+    int kb = 0;
+    for (; kb + 2 <= nqp; kb += 2) {
+      const double2 *yn = yp + ystride;
+      const double2 b0 = yn[0], b1 = yn[1], b2 = yn[2];
+      __builtin_amdgcn_sched_barrier(0);
+      point(a0, a1, a2);
+      yp = ycol + (kb + 2 < nqp ? kb + 2 : nqp - 1) * ystride;
+      a0 = yp[0], a1 = yp[1], a2 = yp[2];
+      __builtin_amdgcn_sched_barrier(0);
+      point(b0, b1, b2);
+    }
+    if (kb < nqp) point(a0, a1, a2);
+  }
+  *gs = s;
+  *gd = d;
+  *gm = m;
 }
 
 // FP32 sum of one regular entry of the mixed form, in coordinates local to

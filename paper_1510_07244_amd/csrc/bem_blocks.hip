@@ -3,7 +3,8 @@
 // is processed by one workgroup: regular pairs one entry per lane, the rest
 // (singular pairs; near-singular pairs in the mixed form) grouped by class in
 // LDS and done one pair per lane in FP64.
-//   k_blocks      one workgroup per block, looping over its sub-tiles;
+//   k_blocks      one workgroup per block, looping over its sub-tiles (one
+//                 layer, or the single and the double layer in one pass);
 //   k_persistent  a fixed grid of workgroups popping sub-tiles of many
 //                 blocks (of many meshes) from a cost-sorted global queue.
 // Both call the same sub-tile code, so their results are bitwise equal.
@@ -101,6 +102,11 @@ __device__ bool stage_tile(const BlockArgs &a, const Lds &l, const BlockHdr &h, 
       l.rg[2 * TR + k] = 2.0 * (a.geo[G_V0Z * L + id] - cz);
       for (int m = 0; m < 6; ++m) l.rg[(3 + m) * TR + k] = 2.0 * a.geo[(G_E1X + m) * L + id];
       l.rg[9 * TR + k] = a.geo[G_SG * L + id];
+      if (l.rn) {
+        l.rn[k] = a.geo[G_NX * L + id];
+        l.rn[TR + k] = a.geo[G_NY * L + id];
+        l.rn[2 * TR + k] = a.geo[G_NZ * L + id];
+      }
       if constexpr (MIXED)
         for (int m = 0; m < 6; ++m) l.rb[m * TR + k] = a.geo[(G_LOX + m) * L + id];
     } else {
@@ -252,6 +258,53 @@ __device__ __forceinline__ void singular_chunk(const BlockArgs &a, const Lds &l,
   }
 }
 
+// Phase E of the one-pass form (both layers; plain FP64, singular pairs
+// only): the pair (i, j) of a listed code in both layers and, if the block
+// has a mirror, the transposed pair (j, i): its double layer evaluated as
+// (j, i), its single layer copied (vertex pairs: equal up to rounding) or
+// evaluated as (j, i) (edge pairs: that rule is not symmetric).  The class
+// is uniform across the chunk.
+template <int KERNEL>
+__device__ __forceinline__ void singular_chunk_both(const BlockArgs &a, const Lds &l,
+                                                    const BlockHdr &h, int64_t r0, int64_t c0,
+                                                    const Groups &gr, int pos) {
+  const int lane = threadIdx.x & (kWave - 1);
+  const int cls = pos < gr.seg[2] ? CLS_IDENTICAL : pos < gr.seg[1] ? CLS_EDGE : CLS_VERTEX;
+  const uint16_t code = l.sorted[pos + lane];
+  const bool active = code != kNoPair;
+  const int rl = code & 63, cl = (code >> 6) & 63;
+  auto idle = [](PairGeo *g) {  // harmless finite geometry, result discarded
+    for (int c = 0; c < 3; ++c)
+      g->E1i[c] = c == 0, g->E2i[c] = c == 1, g->E1j[c] = -(c == 2), g->E2j[c] = 0, g->n[c] = 0;
+    g->scale = 0.0;
+  };
+  PairGeo g;
+  bool have = false;
+  if (active)
+    have = pair_geometry(a.v, a.tri, a.nv, a.geo, a.ldg, l.rid[rl], l.cid[cl], cls, a.flags, &g);
+  if (!have) idle(&g);
+  const Acc<KERNEL> vs = ss_pair_lane<KERNEL, BEM_SLP>(g, a.ss, cls, a.kappa);
+  const Acc<KERNEL> vd = ss_pair_lane<KERNEL, BEM_DLP>(g, a.ss, cls, a.kappa);
+  if (have) {
+    const int64_t dst = h.off + (r0 + rl) + h.nr * (c0 + cl);
+    store<KERNEL>(a.out, dst, vs, a.flags);
+    store<KERNEL>(a.out2, dst, vd, a.flags);
+  }
+  if (h.moff < 0) return;  // uniform
+  have = false;
+  if (active)
+    have = pair_geometry(a.v, a.tri, a.nv, a.geo, a.ldg, l.cid[cl], l.rid[rl], cls, a.flags, &g);
+  if (!have) idle(&g);
+  const Acc<KERNEL> md = ss_pair_lane<KERNEL, BEM_DLP>(g, a.ss, cls, a.kappa);
+  Acc<KERNEL> ms = vs;
+  if (cls == CLS_EDGE) ms = ss_pair_lane<KERNEL, BEM_SLP>(g, a.ss, cls, a.kappa);
+  if (have) {
+    const int64_t mdst = h.moff + (c0 + cl) + h.nc * (r0 + rl);
+    store<KERNEL>(a.out, mdst, ms, a.flags);
+    store<KERNEL>(a.out2, mdst, md, a.flags);
+  }
+}
+
 // Whether entry (rl, cl) of the staged sub-tile goes to the FP64 pass:
 // a common vertex (cls > 0), or in the mixed form a near-singular pair
 // (bounding boxes closer than ratio * the larger box diagonal).
@@ -279,7 +332,8 @@ __device__ __forceinline__ bool fp64_pair(const Lds &l, int TR, int TC, int rl, 
   return fp64;
 }
 
-// One sub-tile: rows r0 .. r0 + TR, columns c0 .. c0 + TC of the block.
+// One sub-tile: rows r0 .. r0 + TR, columns c0 .. c0 + TC of the block
+// (LAYER = kBoth: the single layer to a.out and the double layer to a.out2).
 // After staging, the pairs of the FP64 pass are listed and grouped by class;
 // then every wave takes work from one counter -- first the FP64 chunks
 // (heaviest), then the regular entries 64 at a time in column-major order
@@ -309,7 +363,7 @@ __device__ void subtile(const BlockArgs &a, const Lds &l, const BlockHdr &h, int
     } else {
       l.list[atomicAdd(l.count, 1)] = (uint16_t)(rl | (cl << 6) | (cls << 12));
       atomicAdd(&l.ccount[cls], 1);
-      if (h.moff >= 0 && cls == CLS_EDGE) {  // the mirror's entry, evaluated as (j, i)
+      if (LAYER != kBoth && h.moff >= 0 && cls == CLS_EDGE) {  // the mirror's entry, as (j, i)
         l.list[atomicAdd(l.count, 1)] = (uint16_t)(rl | (cl << 6) | (cls << 12) | kSwapped);
         atomicAdd(&l.ccount[cls], 1);
       }
@@ -324,7 +378,11 @@ __device__ void subtile(const BlockArgs &a, const Lds &l, const BlockHdr &h, int
     c = __shfl(c, 0, kWave);
     if (c >= nsc + nrc) break;
     if (c < nsc) {
-      singular_chunk<KERNEL, LAYER, MIXED>(a, l, h, r0, c0, gr, c * kWave);
+      if constexpr (LAYER == kBoth) {
+        singular_chunk_both<KERNEL>(a, l, h, r0, c0, gr, c * kWave);
+      } else {
+        singular_chunk<KERNEL, LAYER, MIXED>(a, l, h, r0, c0, gr, c * kWave);
+      }
       continue;
     }
     const int e = (c - nsc) * kWave + lane;
@@ -332,6 +390,24 @@ __device__ void subtile(const BlockArgs &a, const Lds &l, const BlockHdr &h, int
     const int rl = e % tr, cl = e / tr;
     int cls;
     if (fp64_pair<MIXED>(l, TR, TC, rl, cl, ratio, &cls)) continue;
+    if constexpr (LAYER == kBoth) {
+      Acc<KERNEL> vs, vd, vm;
+      regular_entry_both<KERNEL, XC>(l, TR, TC, nqp, rl, cl, kq, &vs, &vd, &vm);
+      const double fs = kInv4Pi, fd = 0.5 * kInv4Pi;
+      vs.re *= fs;
+      vd.re *= fd;
+      vm.re *= fd;
+      if constexpr (KERNEL == BEM_HELMHOLTZ) vs.im *= fs, vd.im *= fd, vm.im *= fd;
+      const int64_t dst = off + (r0 + rl) + nr * (c0 + cl);
+      store<KERNEL>(a.out, dst, vs, a.flags);
+      store<KERNEL>(a.out2, dst, vd, a.flags);
+      if (h.moff >= 0) {
+        const int64_t mdst = h.moff + (c0 + cl) + h.nc * (r0 + rl);
+        store<KERNEL>(a.out, mdst, vs, a.flags);
+        store<KERNEL>(a.out2, mdst, vm, a.flags);
+      }
+      continue;
+    }
     Acc<KERNEL> v;
     if constexpr (!MIXED) {
       v = regular_entry<KERNEL, LAYER, XC>(l, TR, TC, nqp, rl, cl, kq);
@@ -476,7 +552,7 @@ __global__ __launch_bounds__(kThreads, 2) void k_blocks(const BlockArgs a, const
   extern __shared__ __align__(16) double lds_raw[];  // 16-byte aligned: ds_read_b128 of points
   BlockHdr h;
   if (!block_header(a, blockIdx.x, &h) || h.nr == 0 || h.nc == 0) return;
-  const Lds l = carve<MIXED>(lds_raw, a.nq_pad, a.tr, a.tc);
+  const Lds l = carve<MIXED>(lds_raw, a.nq_pad, a.tr, a.tc, LAYER == kBoth);
   load_rule(a, l);
   for (int64_t r0 = 0; r0 < h.nr; r0 += a.tr)
     for (int64_t c0 = 0; c0 < h.nc; c0 += a.tc)
@@ -580,6 +656,19 @@ hipError_t launch_pers(int xc, const PersistentArgs &p, size_t lds, hipStream_t 
   return hipGetLastError();
 }
 
+template <int KERNEL>
+hipError_t launch_both(const BlockArgs &a, size_t lds, hipStream_t s) {
+  const dim3 grid(a.nblocks), block(kThreads);
+  switch (rule_chunk(a.nq, KERNEL)) {
+    case 4: hipLaunchKernelGGL((k_blocks<KERNEL, kBoth, 4, false>), grid, block, lds, s, a, 0); break;
+    case 5: hipLaunchKernelGGL((k_blocks<KERNEL, kBoth, 5, false>), grid, block, lds, s, a, 0); break;
+    case 7: hipLaunchKernelGGL((k_blocks<KERNEL, kBoth, 7, false>), grid, block, lds, s, a, 0); break;
+    case 8: hipLaunchKernelGGL((k_blocks<KERNEL, kBoth, 8, false>), grid, block, lds, s, a, 0); break;
+    default: hipLaunchKernelGGL((k_blocks<KERNEL, kBoth, 9, false>), grid, block, lds, s, a, 0); break;
+  }
+  return hipGetLastError();
+}
+
 template <int KERNEL, int LAYER>
 hipError_t launch_kl(bool coupling, bool mixed, const BlockArgs &a, size_t lds, hipStream_t s) {
   return mixed ? launch_klm<KERNEL, LAYER, true>(coupling, a, lds, s)
@@ -600,9 +689,9 @@ int rule_chunk(int nq, int kernel) {
 
 // LDS of a sub-tile; without the pair lists (coupling launches: every pair is
 // regular, phase C only flags, and the lists sit past the allocation unread).
-size_t block_lds_bytes(int nq_pad, int tr, int tc, bool mixed, bool lists) {
+size_t block_lds_bytes(int nq_pad, int tr, int tc, bool mixed, bool lists, bool both) {
   size_t dbl = (size_t)blk::ypoint_doubles(mixed) * nq_pad * tc + 10 * (size_t)tr +
-               3 * (size_t)nq_pad + 3 * (size_t)tc;
+               3 * (size_t)nq_pad + 3 * (size_t)tc + (both ? 3 * (size_t)tr : 0);
   if (mixed) dbl += 3 * (size_t)tc + 6 * (size_t)tr + 6 * (size_t)tc;
   const size_t ints = (size_t)4 * tr + 4 * (size_t)tc + 36;
   return dbl * 8 + ints * 4 + (lists ? (size_t)2 * (2 * (size_t)tr * tc + blk::kSortPad) : 0);
@@ -615,7 +704,7 @@ size_t block_lds_bytes(int nq_pad, int tr, int tc, bool mixed, bool lists) {
 // have no lists and take up to 128 rows and 96 columns, so that most coupling
 // blocks (ranks up to ~100) are one sub-tile.
 bool block_tile_shape(int nq_pad, bool mixed, size_t lds_budget, int *tr, int *tc,
-                      size_t *lds_bytes, bool coupling) {
+                      size_t *lds_bytes, bool coupling, bool both) {
   static const int near_shapes[][2] = {{64, 64}, {64, 32}, {64, 16}, {64, 8}, {32, 8}, {16, 8},
                                        {8, 8}};
   static const int coupling_shapes[][2] = {{128, 96}, {128, 80}, {96, 80}, {128, 64}, {64, 64},
@@ -623,7 +712,7 @@ bool block_tile_shape(int nq_pad, bool mixed, size_t lds_budget, int *tr, int *t
   const bool lists = !coupling || mixed;
   auto try_list = [&](const int(*shapes)[2], int n) {
     for (int k = 0; k < n; ++k) {
-      const size_t bytes = block_lds_bytes(nq_pad, shapes[k][0], shapes[k][1], mixed, lists);
+      const size_t bytes = block_lds_bytes(nq_pad, shapes[k][0], shapes[k][1], mixed, lists, both);
       if (bytes <= lds_budget) {
         *tr = shapes[k][0];
         *tc = shapes[k][1];
@@ -644,6 +733,12 @@ hipError_t launch_blocks(int kernel, int layer, bool coupling, bool mixed, const
                             : launch_kl<BEM_LAPLACE, BEM_DLP>(coupling, mixed, a, lds, s);
   return layer == BEM_SLP ? launch_kl<BEM_HELMHOLTZ, BEM_SLP>(coupling, mixed, a, lds, s)
                           : launch_kl<BEM_HELMHOLTZ, BEM_DLP>(coupling, mixed, a, lds, s);
+}
+
+hipError_t launch_blocks_both(int kernel, const BlockArgs &a, size_t lds, hipStream_t s) {
+  if (a.nblocks == 0) return hipSuccess;
+  return kernel == BEM_LAPLACE ? launch_both<BEM_LAPLACE>(a, lds, s)
+                               : launch_both<BEM_HELMHOLTZ>(a, lds, s);
 }
 
 int learned_chunk(int q, int kernel) { return learned_xc(kernel, q); }

@@ -143,15 +143,19 @@ int get_rules(bem_ctx *ctx, const bem_op *op, const bem::DevRules **out) {
   return BEM_OK;
 }
 
+// both: the near field of both layers in one pass (out: single layer, out2:
+// double layer; op->layer is validated but not used).
 int assemble_blocks(bem_ctx *ctx, const bem_mesh *mesh, const bem_op *op,
                     const bem_blocks *blocks, void *out, int64_t out_len, void *stream,
-                    bool coupling) {
+                    bool coupling, bool both = false, void *out2 = nullptr) {
   if (!ctx) return BEM_EINVAL;
   int rc;
   if ((rc = check_mesh(ctx, mesh)) || (rc = check_op(ctx, op)) ||
       (rc = check_blocks(ctx, blocks, out, out_len)))
     return rc;
-  if (blocks->mirror_off && op->layer != BEM_SLP)
+  if (both && op->precision != BEM_PLAIN_FP64)
+    return fail(ctx, BEM_EUNSUPPORTED, "both layers in one pass: plain FP64 only");
+  if (blocks->mirror_off && !both && op->layer != BEM_SLP)
     return fail(ctx, BEM_EINVAL, "mirror_off is for single layers only");
   if (blocks->n == 0) return BEM_OK;
   if (mesh->nt == 0) return fail(ctx, BEM_EINVAL, "blocks given for an empty mesh");
@@ -179,6 +183,7 @@ int assemble_blocks(bem_ctx *ctx, const bem_mesh *mesh, const bem_op *op,
   a.out_off = blocks->out_off;
   a.mirror_off = blocks->mirror_off;
   a.out = out;
+  a.out2 = out2;
   a.out_len = out_len;
   a.rule = rules->tri;
   a.nq = rules->nq;
@@ -186,7 +191,8 @@ int assemble_blocks(bem_ctx *ctx, const bem_mesh *mesh, const bem_op *op,
   a.nq_pad = (rules->nq + xc - 1) / xc * xc;
   size_t lds;
   const bool mixed = op->precision == BEM_MIXED;
-  if (!bem::block_tile_shape(a.nq_pad, mixed, ctx->lds_budget, &a.tr, &a.tc, &lds, coupling))
+  if (!bem::block_tile_shape(a.nq_pad, mixed, ctx->lds_budget, &a.tr, &a.tc, &lds, coupling,
+                             both))
     return fail(ctx, BEM_EUNSUPPORTED, "quadrature order too high for the LDS budget");
   a.near_ratio = op->near_singular_ratio;
   for (int c = 0; c < 4; ++c) a.ss.eta[c] = rules->ss[c], a.ss.np[c] = rules->np[c];
@@ -194,7 +200,8 @@ int assemble_blocks(bem_ctx *ctx, const bem_mesh *mesh, const bem_op *op,
   a.ss.q = rules->nxi;
   a.kappa = op->kernel == BEM_HELMHOLTZ ? op->kappa : 0.0;
   a.flags = ctx->flags;
-  e = bem::launch_blocks(op->kernel, op->layer, coupling, mixed, a, lds, s);
+  e = both ? bem::launch_blocks_both(op->kernel, a, lds, s)
+           : bem::launch_blocks(op->kernel, op->layer, coupling, mixed, a, lds, s);
   if (e != hipSuccess) return hip_fail(ctx, e, "block kernel launch");
   return BEM_OK;
 }
@@ -274,6 +281,15 @@ int bem_assemble_nearfield(bem_ctx *ctx, const bem_mesh *mesh, const bem_op *op,
 int bem_assemble_coupling(bem_ctx *ctx, const bem_mesh *mesh, const bem_op *op,
                           const bem_blocks *pivots, void *out, int64_t out_len, void *stream) {
   return assemble_blocks(ctx, mesh, op, pivots, out, out_len, stream, true);
+}
+
+int bem_assemble_nearfield_both(bem_ctx *ctx, const bem_mesh *mesh, const bem_op *op,
+                                const bem_blocks *blocks, void *out_slp, void *out_dlp,
+                                int64_t out_len, void *stream) {
+  if (!ctx) return BEM_EINVAL;
+  if (out_len > 0 && (!out_dlp || out_dlp == out_slp))
+    return fail(ctx, BEM_EINVAL, "out_dlp is NULL or the same buffer as out_slp");
+  return assemble_blocks(ctx, mesh, op, blocks, out_slp, out_len, stream, false, true, out_dlp);
 }
 
 int bem_green_matrix(bem_ctx *ctx, const bem_mesh *mesh, const bem_op *op, int32_t side,

@@ -91,6 +91,7 @@ struct BlockArgs {
   const int64_t *out_off;
   const int64_t *mirror_off;  // coupling of a single layer: transposed copies (or null)
   void *out;
+  void *out2;          // both layers in one pass: the double layer's output
   int64_t out_len;
   const double *rule;  // [3][nq]
   int32_t nq, nq_pad;
@@ -244,12 +245,16 @@ hipError_t launch_geometry(const bem_mesh &m, double *geo, int64_t ldg, unsigned
                            hipStream_t s);
 hipError_t launch_blocks(int kernel, int layer, bool coupling, bool mixed, const BlockArgs &a,
                          size_t lds_bytes, hipStream_t s);
+// near field of the single and the double layer in one pass (plain FP64;
+// a.out: single layer, a.out2: double layer)
+hipError_t launch_blocks_both(int kernel, const BlockArgs &a, size_t lds_bytes, hipStream_t s);
 hipError_t launch_entries(int kernel, int layer, bool mixed, const EntryArgs &a, hipStream_t s);
 // sub-tile shape (rows, columns) and LDS bytes of the block kernel for a
 // padded rule size within an LDS budget; false if nothing fits
 bool block_tile_shape(int nq_pad, bool mixed, size_t lds_budget, int *tr, int *tc,
-                      size_t *lds_bytes, bool coupling = false);
-size_t block_lds_bytes(int nq_pad, int tr, int tc, bool mixed, bool lists = true);
+                      size_t *lds_bytes, bool coupling = false, bool both = false);
+size_t block_lds_bytes(int nq_pad, int tr, int tc, bool mixed, bool lists = true,
+                       bool both = false);
 int rule_chunk(int nq, int kernel);  // x-points per register chunk
 
 }  // namespace bem

@@ -64,6 +64,8 @@ def test_calls_reject_null_context_without_gpu():
     lib = pk.lib()
     assert lib.bem_check(None, None) == pk.BEM_EINVAL
     assert lib.bem_assemble_nearfield(None, None, None, None, None, 0, None) == pk.BEM_EINVAL
+    assert lib.bem_assemble_nearfield_both(None, None, None, None, None, None, 0,
+                                           None) == pk.BEM_EINVAL
     assert lib.bem_eval_entries(None, None, None, 0, None, None, None, None) == pk.BEM_EINVAL
     assert lib.bem_last_error(None) == b"no context"
     assert lib.bem_plan_batched(None, None, 0, None, None, None, None, None) == pk.BEM_EINVAL
