@@ -78,7 +78,9 @@ __device__ __forceinline__ Lds carve(double *base, int nqp, int TR, int TC, bool
 // column cl): sum_b wy_b sum_a wx_a k'(x_a, y_b), where k' omits the factor
 // 1/(4 pi) and, for the double layer, the factor 1/2 of the scaled normal
 // distance.  4 |x - y|^2 = |X|^2 + |Y|^2 + X . (-2Y) in block-local
-// coordinates; 1/r from v_rsq_f64 and one Newton step.
+// coordinates; 1/r from v_rsq_f64 and one Newton step.  The double layer's
+// wx <X - Y, n_j> is formed once per x-point (<Y, n_j> is constant on the
+// column triangle's plane).
 template <int KERNEL, int LAYER, int XC>
 __device__ __forceinline__ Acc<KERNEL> regular_entry(const Lds &l, int TR, int TC, int nqp, int rl,
                                                      int cl, double kq) {
@@ -94,9 +96,12 @@ __device__ __forceinline__ Acc<KERNEL> regular_entry(const Lds &l, int TR, int T
   }
   const double2 *ycol = reinterpret_cast<const double2 *>(l.ys) + 3 * cl;
   const int ystride = 3 * TC;  // double2 per point index
+  // <Y, n_j> takes one value on the column triangle's plane: that of its
+  // first point
+  const double YN = LAYER == BEM_DLP ? ycol[2].y : 0.0;
   Acc<KERNEL> acc;
   for (int ch = 0; ch < nqp; ch += XC) {
-    // WN = wx <X, n_j>, so that wx <X - Y, n_j> = fma(-wx, <Y, n_j>, WN)
+    // WN = wx <X - Y, n_j>, the same for every column point
     double X0[XC], X1[XC], X2[XC], XX[XC], WX[XC], WN[XC];
 #pragma unroll
     for (int a = 0; a < XC; ++a) {
@@ -106,11 +111,12 @@ __device__ __forceinline__ Acc<KERNEL> regular_entry(const Lds &l, int TR, int T
       X2[a] = fma(s, A2, fma(t, B2, D2));
       XX[a] = fma(X0[a], X0[a], fma(X1[a], X1[a], X2[a] * X2[a]));
       WX[a] = w * SG;
-      if constexpr (LAYER == BEM_DLP) WN[a] = WX[a] * fma(X0[a], n0, fma(X1[a], n1, X2[a] * n2));
+      if constexpr (LAYER == BEM_DLP)
+        WN[a] = WX[a] * (fma(X0[a], n0, fma(X1[a], n1, X2[a] * n2)) - YN);
     }
     // one column point: (-2Y, |Y|^2, w sqrt(g_j), <Y, n_j>) as three double2
     auto point = [&](const double2 c0, const double2 c1, const double2 c2) {
-      const double M0 = c0.x, M1 = c0.y, M2 = c1.x, YY = c1.y, WY = c2.x, YN = c2.y;
+      const double M0 = c0.x, M1 = c0.y, M2 = c1.x, YY = c1.y, WY = c2.x;
       // the XC chains are written stage by stage so that they interleave
       double sq[XC], h[XC];
 #pragma unroll
@@ -127,8 +133,7 @@ __device__ __forceinline__ Acc<KERNEL> regular_entry(const Lds &l, int TR, int T
           if constexpr (LAYER == BEM_SLP) {
             ire = fma(WX[a], z, ire);
           } else {
-            const double u = fma(-WX[a], YN, WN[a]);  // wx 2 <x - y, n_j>
-            ire = fma(u, z * z * z, ire);
+            ire = fma(WN[a], z * z * z, ire);  // wx 2 <x - y, n_j> / r^3
           }
         } else {
           const double kr = kq * sq[a] * z;  // kappa r  (kq = kappa / 4)
@@ -139,7 +144,7 @@ __device__ __forceinline__ Acc<KERNEL> regular_entry(const Lds &l, int TR, int T
             ire = fma(wz, cs, ire);
             iim = fma(wz, sn, iim);
           } else {
-            const double u = fma(-WX[a], YN, WN[a]) * z * z * z;
+            const double u = WN[a] * z * z * z;
             ire = fma(u, fma(kr, sn, cs), ire);
             iim = fma(u, fma(-kr, cs, sn), iim);
           }
@@ -173,12 +178,12 @@ __device__ __forceinline__ Acc<KERNEL> regular_entry(const Lds &l, int TR, int T
 // regular_entry.  The distance, its reciprocal root (and for Helmholtz the
 // sine and cosine) of a pair serve all three; with k3 the double layer's
 // radial factor and, per column point b,
-//   t1_b = sum_a wx_a k3_ab,   t2_b = sum_a wx_a <X_a, n_j> k3_ab,
+//   t1_b = sum_a wx_a k3_ab,   t2_b = sum_a wx_a <X_a - Y, n_j> k3_ab,
 //   SLP(i, j) = sum_b wy_b sum_a wx_a k_ab,
-//   DLP(i, j) = sum_b wy_b (t2_b - <Y_b, n_j> t1_b),
+//   DLP(i, j) = sum_b wy_b t2_b,
 //   DLP(j, i) = sum_b wy_b (<Y_b, n_i> - <X, n_i>) t1_b,
-// since <X_a, n_i> takes one value on the row triangle's plane (and <Y_b, n_j>
-// one on the column triangle's).  The point pairs of (j, i) are those of
+// since <X_a, n_i> takes one value on the row triangle's plane and <Y_b, n_j>
+// one on the column triangle's.  The point pairs of (j, i) are those of
 // (i, j) with the roles of x and y exchanged: the same triangle rule on both.
 template <int KERNEL, int XC>
 __device__ __forceinline__ void regular_entry_both(const Lds &l, int TR, int TC, int nqp, int rl,
@@ -195,6 +200,7 @@ __device__ __forceinline__ void regular_entry_both(const Lds &l, int TR, int TC,
   const double p0 = -0.5 * m0, p1 = -0.5 * m1, p2 = -0.5 * m2;
   const double2 *ycol = reinterpret_cast<const double2 *>(l.ys) + 3 * cl;
   const int ystride = 3 * TC;
+  const double YN = ycol[2].y;  // <Y, n_j>: one value on the column triangle's plane
   Acc<KERNEL> s, d, m;
   for (int ch = 0; ch < nqp; ch += XC) {
     double X0[XC], X1[XC], X2[XC], XX[XC], WX[XC], WN[XC];
@@ -206,10 +212,10 @@ __device__ __forceinline__ void regular_entry_both(const Lds &l, int TR, int TC,
       X2[a] = fma(u, A2, fma(t, B2, D2));
       XX[a] = fma(X0[a], X0[a], fma(X1[a], X1[a], X2[a] * X2[a]));
       WX[a] = w * SG;
-      WN[a] = WX[a] * fma(X0[a], n0, fma(X1[a], n1, X2[a] * n2));
+      WN[a] = WX[a] * (fma(X0[a], n0, fma(X1[a], n1, X2[a] * n2)) - YN);  // wx <X - Y, n_j>
     }
     auto point = [&](const double2 c0, const double2 c1, const double2 c2) {
-      const double M0 = c0.x, M1 = c0.y, M2 = c1.x, YY = c1.y, WY = c2.x, YN = c2.y;
+      const double M0 = c0.x, M1 = c0.y, M2 = c1.x, YY = c1.y, WY = c2.x;
       double sq[XC], h[XC];
 #pragma unroll
       for (int a = 0; a < XC; ++a)
@@ -241,11 +247,11 @@ __device__ __forceinline__ void regular_entry_both(const Lds &l, int TR, int TC,
       }
       const double wm = WY * (fma(M0, p0, fma(M1, p1, M2 * p2)) - XN);  // wy 2 <y - x, n_i>
       s.re = fma(WY, sre, s.re);
-      d.re = fma(WY, fma(-YN, t1r, t2r), d.re);
+      d.re = fma(WY, t2r, d.re);
       m.re = fma(wm, t1r, m.re);
       if constexpr (KERNEL == BEM_HELMHOLTZ) {
         s.im = fma(WY, sim, s.im);
-        d.im = fma(WY, fma(-YN, t1i, t2i), d.im);
+        d.im = fma(WY, t2i, d.im);
         m.im = fma(wm, t1i, m.im);
       }
     };
@@ -296,7 +302,8 @@ __device__ __forceinline__ Acc<KERNEL> regular_entry_f32(const Lds &l, int TR, i
   const int ystride = 2 * TC;  // float4 per point index
   float are = 0.0f, aim = 0.0f;
   for (int ch = 0; ch < nqp; ch += XC) {
-    // WN = wx <X, n_j>, so that wx <X - Y', n_j> = fma(-wx, <Y', n_j>, WN)
+    // WN = wx <X - Y', n_j> = wx (<X, n_j> - <D, n_j>): <Y_b, n_j> vanishes on
+    // the column triangle's plane
     float X0[XC], X1[XC], X2[XC], XX[XC], WX[XC], WN[XC];
 #pragma unroll
     for (int a = 0; a < XC; ++a) {
@@ -310,13 +317,12 @@ __device__ __forceinline__ Acc<KERNEL> regular_entry_f32(const Lds &l, int TR, i
       // h = 1/(2r): the SLP's k' = 1/r = 2h, the DLP's k' = 2 <x - y, n> / r^3
       // = 8 h^3 <X - Y', n> (same k' as the FP64 path)
       WX[a] = (float)(w * SG) * (LAYER == BEM_SLP ? 2.0f : 8.0f);
-      if constexpr (LAYER == BEM_DLP) WN[a] = WX[a] * fmaf(x0, n0, fmaf(x1, n1, x2 * n2));
+      if constexpr (LAYER == BEM_DLP) WN[a] = WX[a] * (fmaf(x0, n0, fmaf(x1, n1, x2 * n2)) - dn);
     }
     // one column point: (Y, w sqrt(g_j), <Y, n_j>) as two float4
     auto point = [&](const float4 c0, const float4 c1) {
       const float y0 = d0 + c0.x, y1 = d1 + c0.y, y2 = d2 + c0.z, WY = c0.w;
       const float YY = fmaf(y0, y0, fmaf(y1, y1, y2 * y2));
-      const float YN = dn + c1.x;  // <Y', n_j>
       // the XC chains are written stage by stage so that they interleave
       float sq[XC], h[XC];
 #pragma unroll
@@ -331,7 +337,7 @@ __device__ __forceinline__ Acc<KERNEL> regular_entry_f32(const Lds &l, int TR, i
           if constexpr (LAYER == BEM_SLP) {
             ire = fmaf(WX[a], h[a], ire);
           } else {
-            ire = fmaf(fmaf(-WX[a], YN, WN[a]), h[a] * h[a] * h[a], ire);
+            ire = fmaf(WN[a], h[a] * h[a] * h[a], ire);
           }
         } else {
           const float kr = hk * sq[a] * h[a];
@@ -342,7 +348,7 @@ __device__ __forceinline__ Acc<KERNEL> regular_entry_f32(const Lds &l, int TR, i
             ire = fmaf(wz, cs, ire);
             iim = fmaf(wz, sn, iim);
           } else {
-            const float u = fmaf(-WX[a], YN, WN[a]) * h[a] * h[a] * h[a];
+            const float u = WN[a] * h[a] * h[a] * h[a];
             ire = fmaf(u, fmaf(kr, sn, cs), ire);
             iim = fmaf(u, fmaf(-kr, cs, sn), iim);
           }
