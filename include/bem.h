@@ -141,8 +141,12 @@ void bem_destroy(bem_ctx *ctx);
 /* Text of the last failure on this context ("" if none). */
 const char *bem_last_error(const bem_ctx *ctx);
 /* Synchronise `stream`, then report and clear the sticky device flags raised
- * by work enqueued since the last check: BEM_OK, BEM_EINVAL or
- * BEM_ENONFINITE. */
+ * by work enqueued since the last check: BEM_OK, BEM_EINVAL, BEM_ENONFINITE,
+ * or BEM_EUNSUPPORTED when a sub-tile of a mirrored single-layer list had
+ * more singular pairs than its pair list holds (each edge-adjacent pair is
+ * listed twice there: only possible with edges shared by many triangles;
+ * that sub-tile is left unwritten -- assemble it without mirror_off, or with
+ * bem_assemble_nearfield_both, which lists each pair once). */
 int bem_check(bem_ctx *ctx, void *stream);
 
 /* Near-field assembly (Sec. 2.3-2.4: the inadmissible leaves G|_{t x s} of

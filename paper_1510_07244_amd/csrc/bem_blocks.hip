@@ -361,15 +361,24 @@ __device__ void subtile(const BlockArgs &a, const Lds &l, const BlockHdr &h, int
     if (coupling && cls) {
       atomicOr(a.flags, FLAG_EINVAL);
     } else {
-      l.list[atomicAdd(l.count, 1)] = (uint16_t)(rl | (cl << 6) | (cls << 12));
-      atomicAdd(&l.ccount[cls], 1);
-      if (LAYER != kBoth && h.moff >= 0 && cls == CLS_EDGE) {  // the mirror's entry, as (j, i)
-        l.list[atomicAdd(l.count, 1)] = (uint16_t)(rl | (cl << 6) | (cls << 12) | kSwapped);
-        atomicAdd(&l.ccount[cls], 1);
+      // an edge-adjacent pair of a mirrored block is listed twice: the
+      // mirror's entry is evaluated as (j, i)
+      const bool twice = LAYER != kBoth && h.moff >= 0 && cls == CLS_EDGE;
+      const uint16_t code = (uint16_t)(rl | (cl << 6) | (cls << 12));
+      const int n = twice ? 2 : 1;
+      const int slot = atomicAdd(l.count, n);
+      if (slot + n <= TR * TC) {  // else the sub-tile fails below
+        l.list[slot] = code;
+        if (twice) l.list[slot + 1] = code | kSwapped;
       }
+      atomicAdd(&l.ccount[cls], n);
     }
   }
   __syncthreads();
+  if (*l.count > TR * TC) {  // uniform: more listed pairs than list slots
+    if (tid == 0) atomicOr(a.flags, FLAG_LIST);
+    return;
+  }
   const Groups gr = group_listed(l);
   const int nsc = gr.total / kWave, nrc = (tr * tc + kWave - 1) / kWave;
   for (;;) {

@@ -270,6 +270,10 @@ int bem_check(bem_ctx *ctx, void *stream) {
   if (e != hipSuccess) return hip_fail(ctx, e, "reading device flags");
   if (f & bem::FLAG_EINVAL) return fail(ctx, BEM_EINVAL, "invalid index or degenerate triangle seen on the device");
   if (f & bem::FLAG_NONFINITE) return fail(ctx, BEM_ENONFINITE, "non-finite entry computed");
+  if (f & bem::FLAG_LIST)
+    return fail(ctx, BEM_EUNSUPPORTED,
+                "a sub-tile has more singular pairs than its list holds (edges shared by many "
+                "triangles in a mirrored block); assemble that block without mirror_off");
   return BEM_OK;
 }
 

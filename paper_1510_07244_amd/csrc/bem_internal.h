@@ -55,7 +55,9 @@ enum GeoField {
 };
 
 // sticky device flags
-enum : unsigned { FLAG_EINVAL = 1u, FLAG_NONFINITE = 2u };
+// FLAG_LIST: a sub-tile listed more pairs for the FP64 pass than its list
+// holds (mirrored edge-adjacent pairs of edges shared by many triangles)
+enum : unsigned { FLAG_EINVAL = 1u, FLAG_NONFINITE = 2u, FLAG_LIST = 4u };
 
 // Device copies of the quadrature tables of one (rule, q_regular, q_singular).
 struct DevRules {

@@ -10,7 +10,10 @@
   the 2048-triangle sphere's list are written; the 8192-triangle sphere is
   the benchmark's launch), and against the per-layer entry point on the
   whole list at 1e-13 of the largest entry (rounding order differs).
-* Error paths: mixed precision is refused, both outputs must differ.
+* Error paths: mixed precision is refused, both outputs must differ; a
+  mirrored per-layer list whose sub-tile has more singular pairs than its
+  list holds (a non-manifold fan of triangles around one edge) is reported
+  as BEM_EUNSUPPORTED, and the one-pass form assembles it.
 """
 import numpy as np
 import pytest
@@ -178,3 +181,45 @@ def test_both_error_paths(pk, ctx):
         ctx.assemble_nearfield_both(mesh, op, blocks, a, b[:-1])
     assert not torch.any(a != 0) and not torch.any(b != 0)  # nothing written
     ctx.check()
+
+
+def _book(n):
+    """n triangles sharing the edge (v0, v1), fanned around it: every pair is
+    edge-adjacent (a non-manifold mesh)."""
+    ang = np.linspace(0.0, 2.0 * np.pi, n, endpoint=False) + 0.1
+    v = np.zeros((n + 2, 3))
+    v[1] = (1.0, 0.0, 0.0)
+    v[2:, 0] = 0.5
+    v[2:, 1] = np.cos(ang)
+    v[2:, 2] = np.sin(ang)
+    tri = np.array([[0, 1, 2 + k] for k in range(n)], dtype=np.int32)
+    return v, tri
+
+
+def test_mirrored_list_overflow_reported_and_one_pass_form_handles_it(pk, ctx):
+    # a 64 x 64 block of edge-adjacent pairs: the per-layer single layer with
+    # a mirror would list 8192 pairs in a 4096-slot list -> BEM_EUNSUPPORTED;
+    # the one-pass form lists each pair once and matches the oracle
+    import torch
+    v, tri = _book(128)
+    mesh = pk.Mesh(torch.from_numpy(v), torch.from_numpy(tri))
+    rows = np.arange(64, dtype=np.int32)
+    cols = np.arange(64, 128, dtype=np.int32)
+    blocks = pk.Blocks(np.array([0, 64], np.int32), rows, np.array([0, 64], np.int32), cols,
+                       np.array([0], np.int64), np.array([4096], np.int64))
+    op = pk.make_op(pk.LAPLACE, pk.SLP, q_regular=3, q_singular=3)
+    out = torch.full((8192,), float("nan"), dtype=torch.float64, device="cuda")
+    ctx.assemble_nearfield(mesh, op, blocks, out)
+    with pytest.raises(pk.BemError) as e:
+        ctx.check()
+    assert e.value.code == pk.BEM_EUNSUPPORTED
+    s, d = _both(pk, ctx, mesh, op, blocks, 8192)
+    S = s[:4096].reshape(64, 64).T  # column-major (rows x cols)
+    Sm = s[4096:].reshape(64, 64).T  # transposed block (cols x rows)
+    D, Dm = d[:4096].reshape(64, 64).T, d[4096:].reshape(64, 64).T
+    r, c = rows[::9], cols[::9]
+    for layer, blk, mir in ((0, S, Sm), (1, D, Dm)):
+        ref = oracle.block(v, tri, r, c, **_kw(op, layer)).real
+        _close(blk[np.ix_(r, c - 64)], ref)
+        ref_t = oracle.block(v, tri, c, r, **_kw(op, layer)).real
+        _close(mir[np.ix_(c - 64, r)], ref_t)
