@@ -184,9 +184,8 @@ class H2Bench:
         dt = dict(dtype=torch.float32 if mixed else torch.float64, device="cuda")
         self.out = {k: torch.empty(n, **dt) for k, n in
                     (("ns", self.n_near), ("nd", self.n_near), ("cs", self.n_cs), ("cd", self.n_cd))}
-        # plain FP64: the near field of both layers in one pass over the
-        # mirrored list; the mixed form has per-layer near-field passes
-        self.phases = ["bases"] + (["ns", "nd"] if mixed else ["nb"]) + ["cs", "cd"]
+        # the near field of both layers in one pass over the mirrored list
+        self.phases = ["bases", "nb", "cs", "cd"]
         self.assemble()
         ctx.check()
         t3 = time.perf_counter()

@@ -179,8 +179,9 @@ int bem_assemble_coupling(bem_ctx *ctx, const bem_mesh *mesh, const bem_op *op,
  * op->layer = BEM_SLP and BEM_DLP, up to rounding).  Every point pair's
  * distance, reciprocal root (and for Helmholtz its sine and cosine) serve
  * both kernels.  out_slp, out_dlp: device, out_len entries each, same layout,
- * distinct buffers; op->layer (BEM_SLP or BEM_DLP) is not used; plain FP64 only
- * (BEM_EUNSUPPORTED for BEM_MIXED).  With blocks->mirror_off, block b also
+ * distinct buffers; op->layer (BEM_SLP or BEM_DLP) is not used; plain FP64 or
+ * BEM_MIXED (as bem_assemble_nearfield: regular pairs in FP32, singular and
+ * near-singular pairs in FP64, FP32 / complex64 out).  With blocks->mirror_off, block b also
  * fills its transpose at mirror_off[b] in both outputs: the single layer as
  * for bem_assemble_nearfield, the double layer of every transposed pair
  * (j, i) evaluated from the same point pairs as (i, j) (regular pairs) or by

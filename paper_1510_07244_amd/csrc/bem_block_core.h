@@ -379,5 +379,109 @@ __device__ __forceinline__ Acc<KERNEL> regular_entry_f32(const Lds &l, int TR, i
   return acc;
 }
 
+// The one-pass form of regular_entry_f32 (see regular_entry_both): both
+// layers of entry (rl, cl) and the double layer of the pair (j, i), in
+// coordinates local to the row triangle's first vertex, where <X, n_i> = 0
+// for every x-point, so that DLP(j, i) = sum_b wy_b <Y'_b, n_i> t1_b.
+// h = v_rsq_f32(4 r^2) = 1/(2r): the single layer's k' = 2h, the double
+// layer's radial factor 8 h^3 (the factors 2 and 8 are applied to the sums).
+template <int KERNEL, int XC>
+__device__ __forceinline__ void regular_entry_both_f32(const Lds &l, int TR, int TC, int nqp,
+                                                       int rl, int cl, double kappa,
+                                                       Acc<KERNEL> *gs, Acc<KERNEL> *gd,
+                                                       Acc<KERNEL> *gm) {
+  const double A0 = l.rg[3 * TR + rl], A1 = l.rg[4 * TR + rl], A2 = l.rg[5 * TR + rl];
+  const double B0 = l.rg[6 * TR + rl], B1 = l.rg[7 * TR + rl], B2 = l.rg[8 * TR + rl];
+  const double SG = l.rg[9 * TR + rl];
+  const float d0 = (float)(l.cg[cl] - l.rg[0 * TR + rl]);
+  const float d1 = (float)(l.cg[TC + cl] - l.rg[1 * TR + rl]);
+  const float d2 = (float)(l.cg[2 * TC + cl] - l.rg[2 * TR + rl]);
+  const float n0 = (float)l.cn[cl], n1 = (float)l.cn[TC + cl], n2 = (float)l.cn[2 * TC + cl];
+  const float m0 = (float)l.rn[rl], m1 = (float)l.rn[TR + rl], m2 = (float)l.rn[2 * TR + rl];
+  const float dn = fmaf(d0, n0, fmaf(d1, n1, d2 * n2));  // <D, n_j>
+  const float hk = 0.5f * (float)kappa;
+  const float4 *ycol = reinterpret_cast<const float4 *>(l.ys) + 2 * cl;
+  const int ystride = 2 * TC;
+  float sre = 0.0f, sim = 0.0f, dre = 0.0f, dim = 0.0f, mre = 0.0f, mim = 0.0f;
+  for (int ch = 0; ch < nqp; ch += XC) {
+    float X0[XC], X1[XC], X2[XC], XX[XC], WX[XC], WN[XC];
+#pragma unroll
+    for (int a = 0; a < XC; ++a) {
+      const double u = l.rule[ch + a], t = l.rule[nqp + ch + a], w = l.rule[2 * nqp + ch + a];
+      const float x0 = (float)fma(u, A0, t * B0), x1 = (float)fma(u, A1, t * B1),
+                  x2 = (float)fma(u, A2, t * B2);
+      XX[a] = fmaf(x0, x0, fmaf(x1, x1, x2 * x2));
+      X0[a] = -2.0f * x0;
+      X1[a] = -2.0f * x1;
+      X2[a] = -2.0f * x2;
+      WX[a] = (float)(w * SG);
+      WN[a] = WX[a] * (fmaf(x0, n0, fmaf(x1, n1, x2 * n2)) - dn);  // wx <X - Y', n_j>
+    }
+    auto point = [&](const float4 c0) {
+      const float y0 = d0 + c0.x, y1 = d1 + c0.y, y2 = d2 + c0.z, WY = c0.w;
+      const float YY = fmaf(y0, y0, fmaf(y1, y1, y2 * y2));
+      float sq[XC], h[XC];
+#pragma unroll
+      for (int a = 0; a < XC; ++a)
+        sq[a] = fmaf(X2[a], y2, fmaf(X1[a], y1, fmaf(X0[a], y0, XX[a] + YY)));  // 4 r^2
+#pragma unroll
+      for (int a = 0; a < XC; ++a) h[a] = __builtin_amdgcn_rsqf(sq[a]);
+      float tsr = 0.0f, tsi = 0.0f, t1r = 0.0f, t1i = 0.0f, t2r = 0.0f, t2i = 0.0f;
+#pragma unroll
+      for (int a = 0; a < XC; ++a) {
+        const float h3 = h[a] * h[a] * h[a];
+        if constexpr (KERNEL == BEM_LAPLACE) {
+          tsr = fmaf(WX[a], h[a], tsr);
+          t1r = fmaf(WX[a], h3, t1r);
+          t2r = fmaf(WN[a], h3, t2r);
+        } else {
+          const float kr = hk * sq[a] * h[a];
+          float sn, cs;
+          sincos_cw_f32(kr, &sn, &cs);
+          const float wz = WX[a] * h[a];
+          tsr = fmaf(wz, cs, tsr);
+          tsi = fmaf(wz, sn, tsi);
+          const float fr = h3 * fmaf(kr, sn, cs), fi = h3 * fmaf(-kr, cs, sn);
+          t1r = fmaf(WX[a], fr, t1r);
+          t1i = fmaf(WX[a], fi, t1i);
+          t2r = fmaf(WN[a], fr, t2r);
+          t2i = fmaf(WN[a], fi, t2i);
+        }
+      }
+      const float wm = WY * fmaf(y0, m0, fmaf(y1, m1, y2 * m2));  // wy <Y', n_i>
+      sre = fmaf(WY, tsr, sre);
+      dre = fmaf(WY, t2r, dre);
+      mre = fmaf(wm, t1r, mre);
+      if constexpr (KERNEL == BEM_HELMHOLTZ) {
+        sim = fmaf(WY, tsi, sim);
+        dim = fmaf(WY, t2i, dim);
+        mim = fmaf(wm, t1i, mim);
+      }
+    };
+    const float4 *yp = ycol;
+    float4 a0 = yp[0];
+    int kb = 0;
+    for (; kb + 2 <= nqp; kb += 2) {
+      const float4 b0 = (yp + ystride)[0];
+      __builtin_amdgcn_sched_barrier(0);
+      point(a0);
+      yp = ycol + (kb + 2 < nqp ? kb + 2 : nqp - 1) * ystride;
+      a0 = yp[0];
+      __builtin_amdgcn_sched_barrier(0);
+      point(b0);
+    }
+    if (kb < nqp) point(a0);
+  }
+  // k' factors: 2 for the single layer, 8 for the double layer
+  gs->re = 2.0 * sre;
+  gd->re = 8.0 * dre;
+  gm->re = 8.0 * mre;
+  if constexpr (KERNEL == BEM_HELMHOLTZ) {
+    gs->im = 2.0 * sim;
+    gd->im = 8.0 * dim;
+    gm->im = 8.0 * mim;
+  }
+}
+
 }  // namespace blk
 }  // namespace bem

@@ -258,21 +258,39 @@ __device__ __forceinline__ void singular_chunk(const BlockArgs &a, const Lds &l,
   }
 }
 
-// Phase E of the one-pass form (both layers; plain FP64, singular pairs
-// only): the pair (i, j) of a listed code in both layers and, if the block
-// has a mirror, the transposed pair (j, i): its double layer evaluated as
-// (j, i), its single layer copied (vertex pairs: equal up to rounding) or
-// evaluated as (j, i) (edge pairs: that rule is not symmetric).  The class
-// is uniform across the chunk.
-template <int KERNEL>
+// Phase E of the one-pass form (both layers, in FP64): the pair (i, j) of a
+// listed code in both layers and, if the block has a mirror, the transposed
+// pair (j, i): its double layer evaluated as (j, i), its single layer copied
+// (vertex and near-singular pairs: equal up to rounding) or evaluated as
+// (j, i) (edge pairs: that rule is not symmetric).  The class is uniform
+// across the chunk.
+template <int KERNEL, bool MIXED>
 __device__ __forceinline__ void singular_chunk_both(const BlockArgs &a, const Lds &l,
                                                     const BlockHdr &h, int64_t r0, int64_t c0,
                                                     const Groups &gr, int pos) {
   const int lane = threadIdx.x & (kWave - 1);
-  const int cls = pos < gr.seg[2] ? CLS_IDENTICAL : pos < gr.seg[1] ? CLS_EDGE : CLS_VERTEX;
+  const int cls = pos < gr.seg[2] ? CLS_IDENTICAL
+                  : pos < gr.seg[1] ? CLS_EDGE
+                  : pos < gr.seg[0] ? CLS_VERTEX : kNearSingular;
   const uint16_t code = l.sorted[pos + lane];
   const bool active = code != kNoPair;
   const int rl = code & 63, cl = (code >> 6) & 63;
+  const int64_t dst = h.off + (r0 + rl) + h.nr * (c0 + cl);
+  const int64_t mdst = h.moff + (c0 + cl) + h.nc * (r0 + rl);
+  if (cls == kNearSingular) {  // mixed form: a regular pair summed in FP64
+    if (!active) return;
+    const int i = l.rid[rl], j = l.cid[cl];
+    const Acc<KERNEL> vs = regular_pair_fp64<KERNEL, BEM_SLP>(a.geo, a.ldg, a.rule, a.nq, a.kappa, i, j);
+    const Acc<KERNEL> vd = regular_pair_fp64<KERNEL, BEM_DLP>(a.geo, a.ldg, a.rule, a.nq, a.kappa, i, j);
+    store_as<KERNEL, MIXED>(a.out, dst, vs, a.flags);
+    store_as<KERNEL, MIXED>(a.out2, dst, vd, a.flags);
+    if (h.moff >= 0) {
+      const Acc<KERNEL> md = regular_pair_fp64<KERNEL, BEM_DLP>(a.geo, a.ldg, a.rule, a.nq, a.kappa, j, i);
+      store_as<KERNEL, MIXED>(a.out, mdst, vs, a.flags);
+      store_as<KERNEL, MIXED>(a.out2, mdst, md, a.flags);
+    }
+    return;
+  }
   auto idle = [](PairGeo *g) {  // harmless finite geometry, result discarded
     for (int c = 0; c < 3; ++c)
       g->E1i[c] = c == 0, g->E2i[c] = c == 1, g->E1j[c] = -(c == 2), g->E2j[c] = 0, g->n[c] = 0;
@@ -286,9 +304,8 @@ __device__ __forceinline__ void singular_chunk_both(const BlockArgs &a, const Ld
   const Acc<KERNEL> vs = ss_pair_lane<KERNEL, BEM_SLP>(g, a.ss, cls, a.kappa);
   const Acc<KERNEL> vd = ss_pair_lane<KERNEL, BEM_DLP>(g, a.ss, cls, a.kappa);
   if (have) {
-    const int64_t dst = h.off + (r0 + rl) + h.nr * (c0 + cl);
-    store<KERNEL>(a.out, dst, vs, a.flags);
-    store<KERNEL>(a.out2, dst, vd, a.flags);
+    store_as<KERNEL, MIXED>(a.out, dst, vs, a.flags);
+    store_as<KERNEL, MIXED>(a.out2, dst, vd, a.flags);
   }
   if (h.moff < 0) return;  // uniform
   have = false;
@@ -299,9 +316,8 @@ __device__ __forceinline__ void singular_chunk_both(const BlockArgs &a, const Ld
   Acc<KERNEL> ms = vs;
   if (cls == CLS_EDGE) ms = ss_pair_lane<KERNEL, BEM_SLP>(g, a.ss, cls, a.kappa);
   if (have) {
-    const int64_t mdst = h.moff + (c0 + cl) + h.nc * (r0 + rl);
-    store<KERNEL>(a.out, mdst, ms, a.flags);
-    store<KERNEL>(a.out2, mdst, md, a.flags);
+    store_as<KERNEL, MIXED>(a.out, mdst, ms, a.flags);
+    store_as<KERNEL, MIXED>(a.out2, mdst, md, a.flags);
   }
 }
 
@@ -388,7 +404,7 @@ __device__ void subtile(const BlockArgs &a, const Lds &l, const BlockHdr &h, int
     if (c >= nsc + nrc) break;
     if (c < nsc) {
       if constexpr (LAYER == kBoth) {
-        singular_chunk_both<KERNEL>(a, l, h, r0, c0, gr, c * kWave);
+        singular_chunk_both<KERNEL, MIXED>(a, l, h, r0, c0, gr, c * kWave);
       } else {
         singular_chunk<KERNEL, LAYER, MIXED>(a, l, h, r0, c0, gr, c * kWave);
       }
@@ -401,19 +417,23 @@ __device__ void subtile(const BlockArgs &a, const Lds &l, const BlockHdr &h, int
     if (fp64_pair<MIXED>(l, TR, TC, rl, cl, ratio, &cls)) continue;
     if constexpr (LAYER == kBoth) {
       Acc<KERNEL> vs, vd, vm;
-      regular_entry_both<KERNEL, XC>(l, TR, TC, nqp, rl, cl, kq, &vs, &vd, &vm);
+      if constexpr (!MIXED) {
+        regular_entry_both<KERNEL, XC>(l, TR, TC, nqp, rl, cl, kq, &vs, &vd, &vm);
+      } else {
+        regular_entry_both_f32<KERNEL, XC>(l, TR, TC, nqp, rl, cl, a.kappa, &vs, &vd, &vm);
+      }
       const double fs = kInv4Pi, fd = 0.5 * kInv4Pi;
       vs.re *= fs;
       vd.re *= fd;
       vm.re *= fd;
       if constexpr (KERNEL == BEM_HELMHOLTZ) vs.im *= fs, vd.im *= fd, vm.im *= fd;
       const int64_t dst = off + (r0 + rl) + nr * (c0 + cl);
-      store<KERNEL>(a.out, dst, vs, a.flags);
-      store<KERNEL>(a.out2, dst, vd, a.flags);
+      store_as<KERNEL, MIXED>(a.out, dst, vs, a.flags);
+      store_as<KERNEL, MIXED>(a.out2, dst, vd, a.flags);
       if (h.moff >= 0) {
         const int64_t mdst = h.moff + (c0 + cl) + h.nc * (r0 + rl);
-        store<KERNEL>(a.out, mdst, vs, a.flags);
-        store<KERNEL>(a.out2, mdst, vm, a.flags);
+        store_as<KERNEL, MIXED>(a.out, mdst, vs, a.flags);
+        store_as<KERNEL, MIXED>(a.out2, mdst, vm, a.flags);
       }
       continue;
     }
@@ -665,15 +685,15 @@ hipError_t launch_pers(int xc, const PersistentArgs &p, size_t lds, hipStream_t 
   return hipGetLastError();
 }
 
-template <int KERNEL>
+template <int KERNEL, bool MIXED>
 hipError_t launch_both(const BlockArgs &a, size_t lds, hipStream_t s) {
   const dim3 grid(a.nblocks), block(kThreads);
   switch (rule_chunk(a.nq, KERNEL)) {
-    case 4: hipLaunchKernelGGL((k_blocks<KERNEL, kBoth, 4, false>), grid, block, lds, s, a, 0); break;
-    case 5: hipLaunchKernelGGL((k_blocks<KERNEL, kBoth, 5, false>), grid, block, lds, s, a, 0); break;
-    case 7: hipLaunchKernelGGL((k_blocks<KERNEL, kBoth, 7, false>), grid, block, lds, s, a, 0); break;
-    case 8: hipLaunchKernelGGL((k_blocks<KERNEL, kBoth, 8, false>), grid, block, lds, s, a, 0); break;
-    default: hipLaunchKernelGGL((k_blocks<KERNEL, kBoth, 9, false>), grid, block, lds, s, a, 0); break;
+    case 4: hipLaunchKernelGGL((k_blocks<KERNEL, kBoth, 4, MIXED>), grid, block, lds, s, a, 0); break;
+    case 5: hipLaunchKernelGGL((k_blocks<KERNEL, kBoth, 5, MIXED>), grid, block, lds, s, a, 0); break;
+    case 7: hipLaunchKernelGGL((k_blocks<KERNEL, kBoth, 7, MIXED>), grid, block, lds, s, a, 0); break;
+    case 8: hipLaunchKernelGGL((k_blocks<KERNEL, kBoth, 8, MIXED>), grid, block, lds, s, a, 0); break;
+    default: hipLaunchKernelGGL((k_blocks<KERNEL, kBoth, 9, MIXED>), grid, block, lds, s, a, 0); break;
   }
   return hipGetLastError();
 }
@@ -744,10 +764,12 @@ hipError_t launch_blocks(int kernel, int layer, bool coupling, bool mixed, const
                           : launch_kl<BEM_HELMHOLTZ, BEM_DLP>(coupling, mixed, a, lds, s);
 }
 
-hipError_t launch_blocks_both(int kernel, const BlockArgs &a, size_t lds, hipStream_t s) {
+hipError_t launch_blocks_both(int kernel, bool mixed, const BlockArgs &a, size_t lds,
+                              hipStream_t s) {
   if (a.nblocks == 0) return hipSuccess;
-  return kernel == BEM_LAPLACE ? launch_both<BEM_LAPLACE>(a, lds, s)
-                               : launch_both<BEM_HELMHOLTZ>(a, lds, s);
+  if (kernel == BEM_LAPLACE)
+    return mixed ? launch_both<BEM_LAPLACE, true>(a, lds, s) : launch_both<BEM_LAPLACE, false>(a, lds, s);
+  return mixed ? launch_both<BEM_HELMHOLTZ, true>(a, lds, s) : launch_both<BEM_HELMHOLTZ, false>(a, lds, s);
 }
 
 int learned_chunk(int q, int kernel) { return learned_xc(kernel, q); }

@@ -153,8 +153,6 @@ int assemble_blocks(bem_ctx *ctx, const bem_mesh *mesh, const bem_op *op,
   if ((rc = check_mesh(ctx, mesh)) || (rc = check_op(ctx, op)) ||
       (rc = check_blocks(ctx, blocks, out, out_len)))
     return rc;
-  if (both && op->precision != BEM_PLAIN_FP64)
-    return fail(ctx, BEM_EUNSUPPORTED, "both layers in one pass: plain FP64 only");
   if (blocks->mirror_off && !both && op->layer != BEM_SLP)
     return fail(ctx, BEM_EINVAL, "mirror_off is for single layers only");
   if (blocks->n == 0) return BEM_OK;
@@ -200,7 +198,7 @@ int assemble_blocks(bem_ctx *ctx, const bem_mesh *mesh, const bem_op *op,
   a.ss.q = rules->nxi;
   a.kappa = op->kernel == BEM_HELMHOLTZ ? op->kappa : 0.0;
   a.flags = ctx->flags;
-  e = both ? bem::launch_blocks_both(op->kernel, a, lds, s)
+  e = both ? bem::launch_blocks_both(op->kernel, mixed, a, lds, s)
            : bem::launch_blocks(op->kernel, op->layer, coupling, mixed, a, lds, s);
   if (e != hipSuccess) return hip_fail(ctx, e, "block kernel launch");
   return BEM_OK;

@@ -247,9 +247,10 @@ hipError_t launch_geometry(const bem_mesh &m, double *geo, int64_t ldg, unsigned
                            hipStream_t s);
 hipError_t launch_blocks(int kernel, int layer, bool coupling, bool mixed, const BlockArgs &a,
                          size_t lds_bytes, hipStream_t s);
-// near field of the single and the double layer in one pass (plain FP64;
-// a.out: single layer, a.out2: double layer)
-hipError_t launch_blocks_both(int kernel, const BlockArgs &a, size_t lds_bytes, hipStream_t s);
+// near field of the single and the double layer in one pass (a.out: single
+// layer, a.out2: double layer; plain FP64 or the mixed form)
+hipError_t launch_blocks_both(int kernel, bool mixed, const BlockArgs &a, size_t lds_bytes,
+                              hipStream_t s);
 hipError_t launch_entries(int kernel, int layer, bool mixed, const EntryArgs &a, hipStream_t s);
 // sub-tile shape (rows, columns) and LDS bytes of the block kernel for a
 // padded rule size within an LDS budget; false if nothing fits

@@ -10,7 +10,11 @@
   the 2048-triangle sphere's list are written; the 8192-triangle sphere is
   the benchmark's launch), and against the per-layer entry point on the
   whole list at 1e-13 of the largest entry (rounding order differs).
-* Error paths: mixed precision is refused, both outputs must differ; a
+* The mixed form (FP32 regular pairs, FP64 singular and near-singular ones)
+  of the one-pass call: every sampled block of both outputs within 1e-6
+  relative Frobenius error of the oracle, and within 1e-6 of the per-layer
+  mixed passes on every block.
+* Error paths: both outputs must differ; a
   mirrored per-layer list whose sub-tile has more singular pairs than its
   list holds (a non-manifold fan of triangles around one edge) is reported
   as BEM_EUNSUPPORTED, and the one-pass form assembles it.
@@ -172,11 +176,6 @@ def test_both_error_paths(pk, ctx):
     with pytest.raises(pk.BemError) as e:
         ctx.assemble_nearfield_both(mesh, op, blocks, a, a)
     assert e.value.code == pk.BEM_EINVAL
-    mixed = pk.make_op(pk.LAPLACE, pk.SLP, q_regular=4, q_singular=4)
-    mixed.precision = pk.MIXED
-    with pytest.raises(pk.BemError) as e:
-        ctx.assemble_nearfield_both(mesh, mixed, blocks, a.float(), b.float())
-    assert e.value.code == pk.BEM_EUNSUPPORTED
     with pytest.raises(ValueError):
         ctx.assemble_nearfield_both(mesh, op, blocks, a, b[:-1])
     assert not torch.any(a != 0) and not torch.any(b != 0)  # nothing written
@@ -223,3 +222,44 @@ def test_mirrored_list_overflow_reported_and_one_pass_form_handles_it(pk, ctx):
         _close(blk[np.ix_(r, c - 64)], ref)
         ref_t = oracle.block(v, tri, c, r, **_kw(op, layer)).real
         _close(mir[np.ix_(c - 64, r)], ref_t)
+
+
+@pytest.mark.parametrize("n,kernel,kappa", [(32, 0, 0.0), (16, 1, 4.0)])
+def test_both_mixed_form(pk, ctx, n, kernel, kappa):
+    import torch
+    from paper_1510_07244_amd.h2 import H2Setup
+    m = octahedron_sphere(n)
+    h = H2Setup(ctx, m.v, m.tri, kernel=kernel, kappa=kappa, q_regular=4, q_singular=4)
+    half, total = h.near_blocks(mirror=True)
+    full, _ = h.near_blocks()
+    ops = []
+    for layer in (pk.SLP, pk.DLP):
+        op = h.op(layer)
+        op.precision, op.near_singular_ratio = pk.MIXED, 0.5
+        ops.append(op)
+    s, d = _both(pk, ctx, h.mesh, ops[0], half, total)
+    assert s.dtype == (np.complex64 if kernel else np.float32)
+    rows = [h.ct.idx(t) for t, _ in h.near]
+    cols = [h.ct.idx(u) for _, u in h.near]
+    per_layer = []
+    for op in ops:
+        ref = torch.full((total,), float("nan"), dtype=pk.out_dtype(op), device="cuda")
+        ctx.assemble_nearfield(h.mesh, op, full, ref)
+        ctx.check()
+        per_layer.append(_split(ref.cpu().numpy(), rows, cols))
+    gs, gd = _split(s, rows, cols), _split(d, rows, cols)
+    for got, ref in ((gs, per_layer[0]), (gd, per_layer[1])):
+        for g, r in zip(got, ref):
+            assert np.all(np.isfinite(g))
+            assert np.linalg.norm(g - r) <= 1e-6 * np.linalg.norm(r)
+    up = [k for k, (t, u) in enumerate(h.near) if t < u]
+    lo = [k for k, (t, u) in enumerate(h.near) if t > u]
+    dg = [k for k, (t, u) in enumerate(h.near) if t == u]
+    pick = set()
+    for ks, seed in ((up, 13), (lo, 17), (dg, 19)):
+        pick |= set(sample_subset(np.asarray(ks), min(3, len(ks)), seed=seed).tolist())
+    for k in sorted(pick):
+        for layer, got in ((0, gs), (1, gd)):
+            ref = oracle.block(m.v, m.tri, rows[k], cols[k], **_kw(ops[0], layer))
+            ref = ref if kernel == pk.HELMHOLTZ else ref.real
+            assert np.linalg.norm(got[k] - ref) <= 1e-6 * np.linalg.norm(ref)
