@@ -17,13 +17,15 @@ chosen by the setup): Green matrices and basis contractions of both bases,
 near-field blocks of SLP and DLP (one pass for both layers over the blocks
 with t <= s), coupling blocks of SLP and DLP (the single layer's blocks of a
 pair (t, s), (s, t), t != s, evaluated once, the other written as the
-transpose).  value = Galerkin entries written (near field +
-coupling) per second; entries_evaluated_per_step counts those evaluated.  The roofline object is
+transpose).  The four phases are independent (the pivots are fixed): the
+timed step runs them on four streams; phase_ms comes from the same step on
+one stream.  value = Galerkin entries written (near field + coupling) per
+second; entries_evaluated_per_step counts those evaluated.  The roofline object is
 for the dominant kernel, the double layer's coupling launch (VALU-bound
 FP64, the step's longest), measured with HIP events on its launch stream; cpu_baseline is the FP64 CPU
 oracle on a bounded sample of the same blocks.
 
-    python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu-baseline]
+    python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu-baseline] [--one-stream]
 """
 import argparse
 import json
@@ -81,6 +83,9 @@ def parse():
     p.add_argument("--warmup", type=int, default=3)
     p.add_argument("--setup-repeats", type=int, default=3)
     p.add_argument("--no-cpu-baseline", action="store_true")
+    p.add_argument("--one-stream", action="store_true",
+                   help="time the step on one stream only (for kernel traces, where "
+                        "overlapping launches would stretch each other's durations)")
     p.add_argument("--cpu-seconds", type=float, default=12.0)
     p.add_argument("--batched-meshes", type=int, default=64)
     p.add_argument("--learned-n", type=int, default=128,
@@ -222,6 +227,36 @@ class H2Bench:
         if ev:
             ev["bases"][1].record(stream)
         self.assemble(stream, ev)
+
+    def step_concurrent(self, torch, main):
+        """The same step with its four independent phases (bases, near field,
+        single- and double-layer coupling) on four streams, each with a
+        context of its own (own geometry scratch and flags), joined on
+        `main`: launch tails and the latency-bound basis kernels overlap with
+        the other phases."""
+        if not hasattr(self, "cctx"):
+            self.cctx = [self.ctx] + [self.pk.Context(0) for _ in range(3)]
+            self.cstreams = [torch.cuda.Stream() for _ in range(4)]
+        h, o = self.h, self.out
+        c0, c1, c2, c3 = self.cctx
+        s0, s1, s2, s3 = self.cstreams
+        start = torch.cuda.Event()
+        start.record(main)
+        for st in self.cstreams:
+            st.wait_event(start)
+        c3.assemble_coupling(h.mesh, self.ops[1], self.cd, o["cd"], s3)
+        c2.assemble_coupling(h.mesh, self.ops[0], self.cs, o["cs"], s2)
+        c1.assemble_nearfield_both(h.mesh, self.ops[0], self.near_s, o["ns"], o["nd"], s1)
+        h.basis_replay(self.V, s0)
+        h.basis_replay(self.W, s0)
+        for st in self.cstreams:
+            e = torch.cuda.Event()
+            e.record(st)
+            main.wait_event(e)
+
+    def check_concurrent(self):
+        for c, st in zip(self.cctx, self.cstreams):
+            c.check(st)
 
     def entries(self):
         return 2 * self.n_near + self.n_cs + self.n_cd
@@ -442,6 +477,25 @@ def run_leg(torch, ctx, hb, stream, steps, warmup):
     return (t1 - t0) * 1e3 / steps, phase
 
 
+def run_concurrent(torch, hb, stream, steps, warmup):
+    """Time `steps` concurrent steps after `warmup` (HIP events on the
+    joining stream and wall clock)."""
+    for _ in range(warmup):
+        hb.step_concurrent(torch, stream)
+    torch.cuda.synchronize()
+    hb.check_concurrent()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    a.record(stream)
+    for _ in range(steps):
+        hb.step_concurrent(torch, stream)
+    b.record(stream)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    hb.check_concurrent()
+    return (t1 - t0) * 1e3 / steps, a.elapsed_time(b) / steps
+
+
 def per_layer_near(torch, hb, stream, reps):
     """HIP-event means of the per-layer near-field passes (mirrored single
     layer, full double layer) that the one-pass call replaces."""
@@ -510,10 +564,18 @@ def main():
         hb = H2Bench(pk, ctx, m)
         setups.append((hb.t_setup, hb.t_tree, hb.t_bases, hb.t_assembly))
     stream = torch.cuda.current_stream()
-    ms_step, phase = run_leg(torch, ctx, hb, stream, args.steps, args.warmup)
+    # per-phase timings from the sequential step; the step time from the
+    # same step with its independent phases on four streams
+    ms_seq, phase = run_leg(torch, ctx, hb, stream, args.steps, args.warmup)
     per_layer = per_layer_near(torch, hb, stream, max(5, min(args.steps, 20)))
+    if args.one_stream:
+        ms_step, ms_step_ev = ms_seq, ms_seq
+    else:
+        ms_step, ms_step_ev = run_concurrent(torch, hb, stream, args.steps, args.warmup)
     hm = H2Bench(pk, ctx, m, mixed=True)
-    ms_step_m, phase_m = run_leg(torch, ctx, hm, stream, args.steps, args.warmup)
+    ms_seq_m, phase_m = run_leg(torch, ctx, hm, stream, args.steps, args.warmup)
+    ms_step_m = ms_seq_m if args.one_stream else run_concurrent(torch, hm, stream, args.steps,
+                                                                 args.warmup)[0]
     batched = None
     if args.batched_meshes > 0:
         bb = BatchedBench(pk, ctx, args.batched_meshes)
@@ -592,6 +654,12 @@ def main():
                        "tree": float(st[best, 1]), "bases": float(st[best, 2]),
                        "assembly": float(st[best, 3]), "repeats": int(st.shape[0])},
         "phase_ms": phase,
+        "step_streams": ("one stream" if args.one_stream else
+                         "the step's four independent phases (bases, near field, SLP coupling, "
+                         "DLP coupling) on four streams, joined per step; phase_ms from the same "
+                         "step run on one stream"),
+        "ms_per_step_events": ms_step_ev,
+        "sequential": {"ms_per_step": ms_seq, "value": hb.entries() / (ms_seq * 1e-3)},
         "roofline": {
             "kernel": "k_blocks<Laplace, DLP> coupling (the step's longest launch; "
                       "+ geometry kernel in the same call)",
@@ -627,6 +695,7 @@ def main():
             "mixed": {
                 "value": hm.entries() / (ms_step_m * 1e-3), "ms_per_step": ms_step_m,
                 "speedup_vs_plain": ms_step / ms_step_m, "phase_ms": phase_m,
+                "sequential_ms_per_step": ms_seq_m,
                 "near_singular_ratio": MIXED_RATIO,
                 "dtype": "f32 regular pairs, f64 singular/near-singular, f32 out",
                 "h2_setup_s": float(hm.t_setup),
