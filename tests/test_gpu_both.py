@@ -263,3 +263,46 @@ def test_both_mixed_form(pk, ctx, n, kernel, kappa):
             ref = oracle.block(m.v, m.tri, rows[k], cols[k], **_kw(ops[0], layer))
             ref = ref if kernel == pk.HELMHOLTZ else ref.real
             assert np.linalg.norm(got[k] - ref) <= 1e-6 * np.linalg.norm(ref)
+
+
+def test_phases_on_four_streams_equal_one_stream_bitwise(pk, ctx):
+    # the step's independent phases (bases, near field of both layers, SLP
+    # and DLP coupling) on four streams, each through its own context, give
+    # the same bits as on one stream: every entry is written once by the
+    # same kernel, whatever else runs beside it
+    import torch
+    from paper_1510_07244_amd.h2 import H2Setup
+    m = octahedron_sphere(16)
+    h = H2Setup(ctx, m.v, m.tri, kernel=pk.LAPLACE, q_regular=4, q_singular=4)
+    V, W = h.bases((0, 1))
+    half, total = h.near_blocks(mirror=True)
+    cs, n_cs = h.coupling_blocks(V, V, mirror=True)
+    cd, n_cd = h.coupling_blocks(V, W)
+    slp, dlp = h.op(pk.SLP), h.op(pk.DLP)
+    f64 = dict(dtype=torch.float64, device="cuda")
+
+    def run(ctxs, streams):
+        o = [torch.full((n,), float("nan"), **f64) for n in (total, total, n_cs, n_cd)]
+        c0, c1, c2, c3 = ctxs
+        s0, s1, s2, s3 = streams
+        c3.assemble_coupling(h.mesh, dlp, cd, o[3], s3)
+        c2.assemble_coupling(h.mesh, slp, cs, o[2], s2)
+        c1.assemble_nearfield_both(h.mesh, slp, half, o[0], o[1], s1)
+        h.basis_replay(V, s0)
+        h.basis_replay(W, s0)
+        torch.cuda.synchronize()
+        for c, s in zip(ctxs, streams):
+            c.check(s)
+        return [x.cpu().numpy() for x in o] + [V.replay.V.cpu().numpy(), W.replay.V.cpu().numpy()]
+
+    main = torch.cuda.current_stream()
+    one = run([ctx] * 4, [main] * 4)
+    extra = [pk.Context(0) for _ in range(3)]
+    try:
+        four = run([ctx] + extra, [torch.cuda.Stream() for _ in range(4)])
+    finally:
+        for c in extra:
+            c.close()
+    for a, b in zip(one, four):
+        assert np.all(np.isfinite(a))
+        assert np.array_equal(a, b)
