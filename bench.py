@@ -477,6 +477,56 @@ def run_leg(torch, ctx, hb, stream, steps, warmup):
     return (t1 - t0) * 1e3 / steps, phase
 
 
+def rank_head_leg(torch, pk, ctx, m):
+    """The learned rank head: trained on the finished setups of other meshes,
+    its caps bound the pivot search of this mesh's bases (searched again
+    without the bound where a cap is reached, so the bases are unchanged)."""
+    from paper_1510_07244_amd.h2 import H2Setup
+    from paper_1510_07244_amd.selector import RankHead, cluster_features
+    from bem_inputs import cube_surface, octahedron_sphere, perturbed_sphere
+
+    def setup(mesh):
+        h = H2Setup(ctx, mesh.v, mesh.tri, kernel=pk.LAPLACE, q_regular=Q, q_singular=Q)
+        return h, h.bases((0, 1))
+
+    train = [setup(x) for x in (octahedron_sphere(16), cube_surface(16), perturbed_sphere(101),
+                                perturbed_sphere(102))]
+    head = RankHead(ctx, seed=3)
+    X, R = RankHead.samples(train)
+    t0 = time.perf_counter()
+    losses = head.fit(X, R)
+    t_train = time.perf_counter() - t0
+    h = H2Setup(ctx, m.v, m.tri, kernel=pk.LAPLACE, q_regular=Q, q_singular=Q)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    plain = h.bases((0, 1))
+    torch.cuda.synchronize()
+    t_plain = time.perf_counter() - t0
+    err = np.concatenate([np.abs(head.predict(cluster_features(h, B.side)) - B.rank) for B in plain])
+    t0 = time.perf_counter()
+    caps = [head.caps(h, 0), head.caps(h, 1)]
+    t_infer = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    capped = h.bases((0, 1), rank_caps=caps)
+    torch.cuda.synchronize()
+    t_capped = time.perf_counter() - t0
+    same = all(np.array_equal(a.rank, b.rank) for a, b in zip(plain, capped))
+    pinv = lambda Bs: int(sum(lv.cls.size * lv.max_rank ** 2 * 8 for B in Bs for lv in B.levels))
+    return {
+        "workload": "trained on the setups of a 2048-triangle sphere, a 3072-triangle cube and "
+                    "two perturbed spheres (both sides, Laplace, ACA 5e-8); applied to the "
+                    f"{m.nt}-triangle sphere's {h.ct.n} clusters x 2 sides",
+        "train_samples": int(R.size), "train_s": t_train,
+        "loss_first_epoch": float(losses[0]), "loss_last_epoch": float(losses[-1]),
+        "rank_mean": float(np.mean([B.rank.mean() for B in plain])),
+        "abs_err_mean": float(err.mean()), "abs_err_max": float(err.max()),
+        "cap_margin": 8, "levels": h.cap_stats["levels"], "fallback_levels": h.cap_stats["fallbacks"],
+        "pinv_bytes_plain": pinv(plain), "pinv_bytes_capped": pinv(capped),
+        "bases_s_plain": t_plain, "bases_s_capped": t_capped, "inference_s": t_infer,
+        "bases_equal": bool(same),
+    }
+
+
 def run_concurrent(torch, hb, stream, steps, warmup):
     """Time `steps` concurrent steps after `warmup` (HIP events on the
     joining stream and wall clock)."""
@@ -586,6 +636,7 @@ def main():
         lb = LearnedBench(pk, ctx, args.learned_n)
         learned = lb.result(torch, stream, min(args.steps, 10), 1)
         del lb
+        learned["rank_head"] = rank_head_leg(torch, pk, ctx, m)
 
     h = hb.h
     rows = [h.ct.idx(t) for t, s in h.near]

@@ -98,16 +98,24 @@ class H2Setup:
         """Construct the nested cluster basis of one side, level by level."""
         return self.bases((side,))[0]
 
-    def bases(self, sides=(0, 1)):
+    def bases(self, sides=(0, 1), rank_caps=None):
         """Construct the nested cluster bases of several sides together, level
         by level: per level one Green-matrix launch per side into one buffer,
         one copy to the host, one pivot search over the clusters of every side
         (twice the clusters per call keep the host threads busy at the top
-        levels), then one contraction launch per side."""
+        levels), then one contraction launch per side.
+
+        rank_caps (optional, one int array over the clusters per side, e.g.
+        from the learned rank head): a level's pivot search is bounded by the
+        largest cap of its clusters instead of min(rows, 2m), which sizes the
+        pivot and inverse buffers; a level where some cluster reaches that
+        bound is searched again without it, so the bases are the ones the
+        plain search gives.  self.cap_stats counts levels and fallbacks."""
         import torch
         ct, m = self.ct, self.m
         Bs = [ClusterBasis(side, ct.n) for side in sides]
         op = self.op(SLP)
+        self.cap_stats = {"levels": 0, "fallbacks": 0}
         for h in range(int(self.height.max()) + 1):
             cls = np.nonzero(self.height == h)[0]
             lvs, nrows_all = [], []
@@ -153,8 +161,21 @@ class H2Setup:
             A_h = A_all.cpu().numpy()
             Af = A_h.view(np.float64) if self.cplx else A_h
             max_rank = int(min(nrows_all.max(), 2 * m))
-            rank_all, prow, pcol, pinv = aca(Af, a_all, nrows_all, 2 * m, self.eps, max_rank,
-                                             is_complex=self.cplx)
+            if rank_caps is not None:
+                cap = max(int(np.max(rank_caps[si][cls])) for si in range(len(Bs)))
+                bound = max(1, min(max_rank, cap))
+                rank_all, prow, pcol, pinv = aca(Af, a_all, nrows_all, 2 * m, self.eps, bound,
+                                                 is_complex=self.cplx)
+                self.cap_stats["levels"] += 1
+                if bound < max_rank and int(rank_all.max()) >= bound:  # the bound may have cut
+                    self.cap_stats["fallbacks"] += 1
+                    rank_all, prow, pcol, pinv = aca(Af, a_all, nrows_all, 2 * m, self.eps,
+                                                     max_rank, is_complex=self.cplx)
+                else:
+                    max_rank = bound
+            else:
+                rank_all, prow, pcol, pinv = aca(Af, a_all, nrows_all, 2 * m, self.eps, max_rank,
+                                                 is_complex=self.cplx)
             for si, (B, lv) in enumerate(zip(Bs, lvs)):
                 sl = slice(si * cls.size, (si + 1) * cls.size)
                 nrows, rank = lv.nrows_h, rank_all[sl]

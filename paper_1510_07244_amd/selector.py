@@ -126,3 +126,64 @@ class Selector:
         out = torch.zeros(n_entries, dtype=torch.int8, device="cuda")
         self.ctx.select_orders(mesh, op, blocks, self.params, out, tol, margin, q_min, stream)
         return out
+
+
+# ------------------------------------------------------------ rank head
+RANK_SCALE = 100.0  # network output = rank / RANK_SCALE
+
+
+def cluster_features(h, side):
+    """Eight inputs per cluster of an H2 setup `h` for the rank head:
+    log2 of its triangle count, log10 of its box diagonal, the box's middle
+    and smallest extent over its largest, its height in the tree, kappa times
+    the diagonal, the side (0 rows, 1 double-layer columns), log10 of the
+    pivot-search tolerance."""
+    ct = h.ct
+    lo, hi = ct.box[:, :3], ct.box[:, 3:]
+    ext = np.sort(hi - lo, axis=1)
+    big = np.maximum(ext[:, 2], 1e-300)
+    diam = np.linalg.norm(hi - lo, axis=1)
+    n = np.maximum(ct.end - ct.begin, 1).astype(np.float64)
+    X = np.stack([np.log2(n), np.log10(np.maximum(diam, 1e-300)), ext[:, 1] / big,
+                  ext[:, 0] / big, h.height.astype(np.float64), h.kappa * diam,
+                  np.full(ct.n, float(side)), np.full(ct.n, np.log10(h.eps))], axis=1)
+    return X.astype(np.float32)
+
+
+class RankHead:
+    """Per-cluster prediction of the cross approximation's rank at the setup
+    tolerance: the selector network with one output, trained on the ranks
+    of finished setups by the library's FP32 kernels and run in FP16.  Its
+    caps bound the pivot search of H2Setup.bases (which searches again
+    without the bound wherever it is reached)."""
+
+    def __init__(self, ctx, seed=0):
+        self.net = Selector(ctx, n_out=1, seed=seed)
+
+    @staticmethod
+    def samples(items):
+        """(h, bases) pairs of finished setups -> inputs (n, 8), ranks (n,)."""
+        X, R = [], []
+        for h, Bs in items:
+            for B in Bs:
+                keep = B.rank >= 0
+                X.append(cluster_features(h, B.side)[keep])
+                R.append(B.rank[keep].astype(np.float32))
+        return np.concatenate(X), np.concatenate(R)
+
+    def fit(self, X, ranks, epochs=300, batch=256, lr=3e-3, seed=0):
+        import torch
+        Xd = torch.from_numpy(np.ascontiguousarray(X)).cuda()
+        Td = torch.from_numpy((ranks / RANK_SCALE).astype(np.float32)[:, None]).cuda()
+        self.net.set_standardisation(Xd)
+        return self.net.fit(Xd, Td, epochs=epochs, batch=batch, lr=lr, seed=seed)
+
+    def predict(self, X):
+        import torch
+        y = self.net.predict(torch.from_numpy(np.ascontiguousarray(X)).cuda(), fp16=True)
+        return y.cpu().numpy()[:, 0] * RANK_SCALE
+
+    def caps(self, h, side, margin=8):
+        """Rank caps of every cluster of `h` on one side: prediction + margin."""
+        p = self.predict(cluster_features(h, side))
+        return np.clip(np.ceil(p + margin), 1, 2 * h.m).astype(np.int64)

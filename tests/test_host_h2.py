@@ -80,3 +80,27 @@ def test_aca_nan_columns_stay_in_bounds():
     B[:, 2] = np.nan
     rank, _, pcol, _ = pk.aca(B.T.ravel().copy(), [0], [8], 6, 1e-12, 6)
     assert 0 < rank[0] <= 6 and 2 not in pcol[0, :rank[0]]
+
+
+def test_rank_head_cluster_features():
+    # the rank head's inputs from a host cluster tree (no GPU needed)
+    import types
+    import paper_1510_07244_amd as pk
+    from paper_1510_07244_amd.selector import cluster_features
+    from bem_inputs import octahedron_sphere
+    m = octahedron_sphere(8)
+    ct = pk.ClusterTree(m.v, m.tri, leaf=64)
+    height = np.zeros(ct.n, dtype=np.int32)
+    for c in range(ct.n - 1, -1, -1):
+        s = ct.sons[c]
+        if s[0] >= 0:
+            height[c] = 1 + max(height[s[0]], height[s[1]])
+    h = types.SimpleNamespace(ct=ct, height=height, kappa=0.0, eps=5e-8)
+    X = cluster_features(h, 1)
+    assert X.shape == (ct.n, 8) and X.dtype == np.float32
+    assert np.isclose(X[0, 0], np.log2(m.nt))  # the root holds every triangle
+    assert np.all((X[:, 2] <= 1) & (X[:, 3] <= X[:, 2] + 1e-7) & (X[:, 3] >= 0))
+    assert np.all(X[:, 4] == height) and np.all(X[:, 5] == 0) and np.all(X[:, 6] == 1)
+    assert np.allclose(X[:, 7], np.log10(5e-8))
+    sons = ct.sons[0]
+    assert X[sons[0], 0] < X[0, 0] and X[sons[0], 1] <= X[0, 1] + 1e-7
