@@ -306,3 +306,27 @@ def test_phases_on_four_streams_equal_one_stream_bitwise(pk, ctx):
     for a, b in zip(one, four):
         assert np.all(np.isfinite(a))
         assert np.array_equal(a, b)
+
+
+def test_both_empty_ragged_and_tri7(pk, ctx):
+    import torch
+    m = octahedron_sphere(4)
+    mesh = pk.Mesh(torch.from_numpy(m.v), torch.from_numpy(m.tri))
+    op = pk.make_op(pk.LAPLACE, pk.SLP, regular_rule=pk.RULE_TRI7, q_singular=3)
+    # blocks without entries write nothing and succeed
+    empty, total0 = pk.Blocks.from_lists([np.arange(0), np.arange(3)], [np.arange(4), np.arange(0)])
+    z = torch.zeros(0, dtype=torch.float64, device="cuda")
+    ctx.assemble_nearfield_both(mesh, op, empty, z, torch.zeros(0, dtype=torch.float64, device="cuda"))
+    ctx.check()
+    assert total0 == 0
+    # blocks with no rows or no columns between ragged ones
+    idx = np.arange(m.nt, dtype=np.int32)
+    rows = [idx[3:70], idx[:0], idx[100:101], idx[7:128]]
+    cols = [idx[50:128], idx[5:9], idx[:0], idx[0:1]]
+    blocks, total = pk.Blocks.from_lists(rows, cols)
+    s, d = _both(pk, ctx, mesh, op, blocks, total)
+    for layer, res in ((0, s), (1, d)):
+        got = _split(res, rows, cols)
+        for g, r, c in zip(got, rows, cols):
+            if r.size and c.size:
+                _close(g, oracle.block(m.v, m.tri, r, c, **_kw(op, layer)).real)
