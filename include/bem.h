@@ -113,10 +113,10 @@ typedef struct {
  * col_len).  Its entries go to out[out_off[b] + r + nrows_b * c] (column-major,
  * leading dimension nrows_b) with out_off[b] >= 0 and
  * out_off[b] + nrows_b * ncols_b <= out_len.  Blocks must not overlap in out.
- * mirror_off (single layers only, else NULL): the kernels g(x, y) = g(y, x)
- * give G_ji = G_ij, so block b also fills its transpose G[cols_b x rows_b]
- * at out[mirror_off[b] + c + ncols_b * r] (column-major); mirror_off[b] < 0:
- * no mirror.  Disjoint and vertex-adjacent pairs are written once evaluated
+ * mirror_off (single layers and bem_assemble_nearfield_both only, else
+ * NULL): the kernels g(x, y) = g(y, x) give G_ji = G_ij, so block b also
+ * fills its transpose G[cols_b x rows_b] at out[mirror_off[b] + c + ncols_b * r]
+ * (column-major); mirror_off[b] < 0: no mirror.  Disjoint and vertex-adjacent pairs are written once evaluated
  * (equal up to rounding); an edge-adjacent pair's mirror entry is evaluated
  * as the pair (j, i), the Sauter-Schwab rule for a shared edge not being
  * symmetric.  A mirror onto the block itself (a block on the diagonal) or
