@@ -83,6 +83,8 @@ def parse():
     p.add_argument("--warmup", type=int, default=3)
     p.add_argument("--setup-repeats", type=int, default=3)
     p.add_argument("--no-cpu-baseline", action="store_true")
+    p.add_argument("--no-helmholtz", action="store_true",
+                   help="skip the Helmholtz near-field leg (32768-triangle sphere)")
     p.add_argument("--one-stream", action="store_true",
                    help="time the step on one stream only (for kernel traces, where "
                         "overlapping launches would stretch each other's durations)")
@@ -477,6 +479,42 @@ def run_leg(torch, ctx, hb, stream, steps, warmup):
     return (t1 - t0) * 1e3 / steps, phase
 
 
+def helmholtz_near_leg(torch, pk, ctx, stream, reps):
+    """Near field of the Helmholtz single and double layer (kappa = 4, q = 5,
+    complex128) on the 32768-triangle sphere: the one-pass call on the
+    mirrored list against the per-layer calls (mirrored single layer, full
+    double layer).  Both layers enter the Brakhage-Werner formulation."""
+    from paper_1510_07244_amd.h2 import H2Setup
+    from bem_inputs import octahedron_sphere
+    mh = octahedron_sphere(64)
+    h = H2Setup(ctx, mh.v, mh.tri, kernel=pk.HELMHOLTZ, kappa=4.0, q_regular=5, q_singular=5)
+    half, total = h.near_blocks(mirror=True)
+    full, _ = h.near_blocks()
+    c128 = dict(dtype=torch.complex128, device="cuda")
+    s, d = torch.empty(total, **c128), torch.empty(total, **c128)
+    calls = {
+        "one_pass": lambda: ctx.assemble_nearfield_both(h.mesh, h.op(pk.SLP), half, s, d, stream),
+        "slp_mirrored": lambda: ctx.assemble_nearfield(h.mesh, h.op(pk.SLP), half, s, stream),
+        "dlp": lambda: ctx.assemble_nearfield(h.mesh, h.op(pk.DLP), full, d, stream),
+    }
+    ms = {}
+    for k, call in calls.items():
+        call()
+        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+              for _ in range(reps)]
+        for a, b in ev:
+            a.record(stream)
+            call()
+            b.record(stream)
+        torch.cuda.synchronize()
+        ms[k] = float(np.mean([a.elapsed_time(b) for a, b in ev]))
+    ctx.check(stream)
+    return {"workload": f"Helmholtz kappa 4 SLP + DLP near field, octahedron sphere {mh.nt} "
+                        f"triangles ({len(h.near)} blocks, leaf 64, eta 2), q = 5, complex128",
+            "entries_per_layer": int(total), "ms": ms,
+            "speedup_one_pass": (ms["slp_mirrored"] + ms["dlp"]) / ms["one_pass"]}
+
+
 def rank_head_leg(torch, pk, ctx, m):
     """The learned rank head: trained on the finished setups of other meshes,
     its caps bound the pivot search of this mesh's bases (searched again
@@ -626,6 +664,7 @@ def main():
     ms_seq_m, phase_m = run_leg(torch, ctx, hm, stream, args.steps, args.warmup)
     ms_step_m = ms_seq_m if args.one_stream else run_concurrent(torch, hm, stream, args.steps,
                                                                  args.warmup)[0]
+    helmholtz = None if args.no_helmholtz else helmholtz_near_leg(torch, pk, ctx, stream, 5)
     batched = None
     if args.batched_meshes > 0:
         bb = BatchedBench(pk, ctx, args.batched_meshes)
@@ -760,6 +799,8 @@ def main():
             },
         },
     }
+    if helmholtz:
+        result["forms"]["helmholtz_near_both"] = helmholtz
     if batched:
         result["forms"]["batched"] = batched
     if learned:
