@@ -61,3 +61,18 @@ def test_rank_head_predicts_and_caps_keep_the_bases(pk, ctx):
         assert all(np.array_equal(A.piv[c], B.piv[c]) for c in range(h.ct.n))
         for c in range(h.ct.n):
             assert np.array_equal(A.vhat(c), B.vhat(c))
+
+
+def test_caps_that_bind_fall_back_to_the_plain_search(pk, ctx):
+    # caps far below the ranks: every level's bound is reached, every level
+    # is searched again without it, and the bases are the plain ones
+    h, (V, W) = _setup(pk, ctx, octahedron_sphere(16))
+    caps = [np.full(h.ct.n, 5, dtype=np.int64), np.full(h.ct.n, 5, dtype=np.int64)]
+    V2, W2 = h.bases((0, 1), rank_caps=caps)
+    assert h.cap_stats["levels"] > 0
+    assert h.cap_stats["fallbacks"] == h.cap_stats["levels"]
+    for A, B in ((V, V2), (W, W2)):
+        assert np.array_equal(A.rank, B.rank)
+        for c in range(h.ct.n):
+            assert np.array_equal(A.piv[c], B.piv[c])
+            assert np.array_equal(A.vhat(c), B.vhat(c))
