@@ -1,5 +1,5 @@
 // Block assembly kernels (gfx950, wave64).  One sub-tile (up to 64 x 64
-// entries of one block G[t x s]; up to 128 x 80 for a plain coupling block)
+// entries of one block G[t x s]; up to 128 x 96 for a plain coupling block)
 // is processed by one workgroup: regular pairs one entry per lane, the rest
 // (singular pairs; near-singular pairs in the mixed form) grouped by class in
 // LDS and done one pair per lane in FP64.
