@@ -198,6 +198,14 @@ class H2Bench:
         t3 = time.perf_counter()
         self.t_tree, self.t_bases, self.t_assembly = t1 - t0, t2 - t1, t3 - t2
         self.t_setup = t3 - t0
+        # (outside the timed setup) the mirrored single layer evaluates the
+        # blocks with t <= s, plus the edge-adjacent entries of the others (as
+        # (j, i))
+        lo = [(t, s) for t, s in h.near if t > s]
+        self.near_evaluated_slp = int(sum(h.ct.idx(t).size * h.ct.idx(s).size
+                                          for t, s in h.near if t <= s))
+        self.near_evaluated_slp += int(class_counts(m.tri, [h.ct.idx(t) for t, s in lo],
+                                                    [h.ct.idx(s) for t, s in lo])[2])
 
     def near_calls(self, stream=None):
         ctx, h, o = self.ctx, self.h, self.out
@@ -265,8 +273,7 @@ class H2Bench:
 
     def entries_evaluated(self):
         # the single layer's mirrored blocks are written, not evaluated (apart
-        # from the near field's edge-adjacent entries; near_evaluated_slp is
-        # counted by the caller)
+        # from the near field's edge-adjacent entries)
         return self.near_evaluated_slp + self.n_near + self.n_cs // 2 + self.n_cd
 
 
@@ -401,7 +408,7 @@ class LearnedBench:
         learned = torch.empty(self.total, dtype=dt, device="cuda")
         orders = torch.empty(self.total, dtype=torch.int8, device="cuda")
         sel = lambda: ctx.select_orders(self.mesh, op, self.blocks, self.sel.params, orders,
-                                        self.TOL, self.MARGIN, 2, stream)
+                                        self.TOL, self.MARGIN, 2, stream, range=self.sel.range)
         runs = {
             "plain": lambda: ctx.assemble_nearfield(self.mesh, op, self.blocks, plain, stream),
             "select": sel,
@@ -603,32 +610,112 @@ def per_layer_near(torch, hb, stream, reps):
     return out
 
 
+def solve_leg(torch, pk, ctx, hb, stream, reps=20):
+    """H^2 products with the step's assembled matrices (near field, coupling
+    and nested bases; the library's grouped matrix-vector kernels) and the
+    interior Dirichlet problem of the paper's Laplace experiment for
+    f1 = x1^2 - x3^2: V alpha = (1/2 M + K) beta by conjugate gradients.
+    Roofline of the product: bytes of the matrices read once per product
+    (near-field entries, coupling entries, transfer matrices) over its time,
+    against HBM."""
+    from paper_1510_07244_amd.h2mv import H2Matrix, cg
+    h, o, m = hb.h, hb.out, hb.m
+    Hv = H2Matrix(h, hb.V, hb.V, o["ns"], o["cs"])
+    Hk = H2Matrix(h, hb.V, hb.W, o["nd"], o["cd"])
+    c = m.v[m.tri].mean(axis=1)
+    beta = torch.from_numpy(c[:, 0] ** 2 - c[:, 2] ** 2).cuda()
+    y = torch.empty_like(beta)
+    res = {}
+    for name, H in (("slp", Hv), ("dlp", Hk)):
+        H.matvec(beta, y, stream)
+        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+              for _ in range(reps)]
+        for a, b in ev:
+            a.record(stream)
+            H.matvec(beta, y, stream)
+            b.record(stream)
+        torch.cuda.synchronize()
+        ms = float(np.median([a.elapsed_time(b) for a, b in ev]))
+        nbytes = 8 * (H.near_call.A.numel() + H.coupling_call.A.numel() +
+                      sum(lv.V.numel() for lv in H.V.levels) +
+                      (sum(lv.V.numel() for lv in H.W.levels) if H.W is not H.V else 0))
+        res[name] = {"ms_per_product": ms, "matrix_bytes": nbytes,
+                     "roofline": {"bound": "hbm", "achieved": nbytes / (ms * 1e-3) / 1e9,
+                                  "peak": 8000.0, "unit": "GB/s",
+                                  "frac": nbytes / (ms * 1e-3) / 8e12},
+                     "launches": 2 + len(H.fwd) + len(H.bwd)}
+    rhs = torch.empty_like(beta)
+    Hk.matvec(beta, rhs, stream)
+    ctx.mass_apply(h.mesh, 0.5, beta, rhs, stream)
+    alpha = torch.zeros_like(beta)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    it, rel = cg(ctx, Hv.matvec, rhs, alpha, tol=1e-8, maxit=1000, stream=stream)
+    torch.cuda.synchronize()
+    t_cg = time.perf_counter() - t0
+    x = c / np.linalg.norm(c, axis=1)[:, None]
+    dn = 2 * x[:, 0] ** 2 - 2 * x[:, 2] ** 2
+    a = alpha.cpu().numpy()
+    area = 0.5 * np.linalg.norm(np.cross(m.v[m.tri[:, 1]] - m.v[m.tri[:, 0]],
+                                         m.v[m.tri[:, 2]] - m.v[m.tri[:, 0]]), axis=1)
+    err = float(np.sqrt((area * (a - dn) ** 2).sum() / (area * dn ** 2).sum()))
+    ctx.check(stream)
+    res["laplace_dirichlet_f1"] = {"cg_iterations": it, "relative_residual": rel,
+                                   "solve_s": t_cg, "neumann_l2_rel_err": err}
+    return res
+
+
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(m, hb, seconds):
+    """The FP64 oracle (built here with -O3 -march=native) on a seeded
+    sample of the step's blocks, near field and coupling, both layers: all
+    host threads for `seconds`, then one thread for a third of that."""
     import oracle
+    oracle.use_native_build()
     h = hb.h
     rng = np.random.Generator(np.random.PCG64(1))
     work = [("near", k) for k in range(len(h.near))] + [("far", k) for k in range(len(h.far))]
     order = rng.permutation(len(work))
-    n = 0
-    used = 0
-    t0 = time.perf_counter()
-    for idx in order:
-        kind, k = work[idx]
-        if kind == "near":
-            t, s = h.near[k]
-            pairs = [(h.ct.idx(t), h.ct.idx(s), 0), (h.ct.idx(t), h.ct.idx(s), 1)]
-        else:
-            t, s = h.far[k]
-            pairs = [(hb.V.piv[t], hb.V.piv[s], 0), (hb.V.piv[t], hb.W.piv[s], 1)]
-        for r, c, layer in pairs:
-            n += oracle.block(m.v, m.tri, r, c, layer=layer, q_reg=Q, q_sing=Q).size
-        used += 1
-        if time.perf_counter() - t0 > seconds:
-            break
-    dt = time.perf_counter() - t0
-    return {"value": n / dt, "unit": "entries/s", "cores": oracle.num_threads(), "kind": "oracle",
+
+    def run(limit):
+        n = used = 0
+        t0 = time.perf_counter()
+        for idx in order:
+            kind, k = work[idx]
+            if kind == "near":
+                t, s = h.near[k]
+                pairs = [(h.ct.idx(t), h.ct.idx(s), 0), (h.ct.idx(t), h.ct.idx(s), 1)]
+            else:
+                t, s = h.far[k]
+                pairs = [(hb.V.piv[t], hb.V.piv[s], 0), (hb.V.piv[t], hb.W.piv[s], 1)]
+            for r, c, layer in pairs:
+                n += oracle.block(m.v, m.tri, r, c, layer=layer, q_reg=Q, q_sing=Q).size
+            used += 1
+            if time.perf_counter() - t0 > limit:
+                break
+        return n, used, time.perf_counter() - t0
+
+    threads = oracle.num_threads()
+    n, used, dt = run(seconds)
+    oracle.set_threads(1)
+    n1, used1, dt1 = run(seconds / 3)
+    oracle.set_threads(threads)
+    return {"value": n / dt, "unit": "entries/s", "cores": threads, "kind": "oracle",
             "sample": f"{used} of {len(work)} blocks (near field and coupling, seeded order), SLP "
-                      f"and DLP each: {n} entries in {dt:.1f} s"}
+                      f"and DLP each: {n} entries in {dt:.1f} s on {threads} threads",
+            "one_thread": {"value": n1 / dt1, "sample": f"first {used1} blocks of the same "
+                                                        f"order: {n1} entries in {dt1:.1f} s"},
+            "build": "gcc -O3 -march=native -fopenmp (compiled on this host)",
+            "cpu_model": cpu_model(), "host_cpus": os.cpu_count()}
 
 
 def main():
@@ -646,12 +733,14 @@ def main():
     if args.counter_pass:
         counter_pass(torch, pk, ctx, m)
         return
-    setups = []
+    setups, bases_split = [], []
     hb = None
     for _ in range(max(1, args.setup_repeats)):
         hb = H2Bench(pk, ctx, m)
         setups.append((hb.t_setup, hb.t_tree, hb.t_bases, hb.t_assembly))
+        bases_split.append(dict(hb.h.bases_time))
     stream = torch.cuda.current_stream()
+    peak_meas = {"fp64": ctx.valu_peak(True), "fp32": ctx.valu_peak(False)}
     # per-phase timings from the sequential step; the step time from the
     # same step with its independent phases on four streams
     ms_seq, phase = run_leg(torch, ctx, hb, stream, args.steps, args.warmup)
@@ -664,6 +753,7 @@ def main():
     ms_seq_m, phase_m = run_leg(torch, ctx, hm, stream, args.steps, args.warmup)
     ms_step_m = ms_seq_m if args.one_stream else run_concurrent(torch, hm, stream, args.steps,
                                                                  args.warmup)[0]
+    solve = solve_leg(torch, pk, ctx, hb, stream)
     helmholtz = None if args.no_helmholtz else helmholtz_near_leg(torch, pk, ctx, stream, 5)
     batched = None
     if args.batched_meshes > 0:
@@ -691,7 +781,7 @@ def main():
     edges_lo = int(class_counts(m.tri, [rows[k] for k in lo], [cols[k] for k in lo])[2])
     counts_s[2] += edges_lo
     f_slp = near_flops(counts_s, 0, 0, Q, Q)
-    hb.near_evaluated_slp = int(sum(rows[k].size * cols[k].size for k in up)) + edges_lo
+    assert hb.near_evaluated_slp == int(sum(rows[k].size * cols[k].size for k in up)) + edges_lo
     # one pass over the blocks with t <= s: per regular pair the double
     # layer's work plus the single layer's accumulation (the transposed
     # pair's double layer costs per-point work only); singular pairs: both
@@ -709,7 +799,7 @@ def main():
     ranks_w = hb.W.rank[hb.W.rank > 0]
     result = {
         "metric": METRIC,
-        "value": hb.entries() / (ms_step * 1e-3),
+        "value": hb.entries_evaluated() / (ms_step * 1e-3),
         "unit": "entries/s",
         "n_gpus": 1,
         "steps": args.steps,
@@ -725,8 +815,13 @@ def main():
                         "eta 2, Sauter-Schwab q=4, Duffy/Gauss q=4, Green order 4, ACA 5e-8, "
                         "plain FP64",
             "triangles": int(m.nt), "near_blocks": int(len(h.near)), "far_blocks": int(len(h.far)),
-            "entries_per_step": int(hb.entries()),
             "entries_evaluated_per_step": int(hb.entries_evaluated()),
+            "entries_written_per_step": int(hb.entries()),
+            "written_entries_per_s": hb.entries() / (ms_step * 1e-3),
+            "value_counts": "entries evaluated by the kernels per second (the written count, "
+                            "which adds the single layer's mirrored copies, is "
+                            "written_entries_per_s); the CPU baseline counts every entry the "
+                            "oracle evaluates",
             "single_layer_symmetry": "of each pair of blocks (t, s), (s, t), t != s, of the "
                                      "single layer (near field and coupling) the block with t < s "
                                      "is evaluated, the other written as its transpose (near-field "
@@ -742,6 +837,12 @@ def main():
         },
         "h2_setup_s": {"best": float(st[best, 0]), "median": float(np.median(st[:, 0])),
                        "tree": float(st[best, 1]), "bases": float(st[best, 2]),
+                       "bases_split": bases_split[best],
+                       "bases_split_note": "device: Green matrices and the previous level's "
+                                           "pivot inverses and contractions (waited for before "
+                                           "the copy); copy: Green matrices to the host; "
+                                           "pivot_search: host cross approximation (pivots only, "
+                                           "the pivot blocks are inverted on the device)",
                        "assembly": float(st[best, 3]), "repeats": int(st.shape[0])},
         "phase_ms": phase,
         "step_streams": ("one stream" if args.one_stream else
@@ -749,7 +850,7 @@ def main():
                          "DLP coupling) on four streams, joined per step; phase_ms from the same "
                          "step run on one stream"),
         "ms_per_step_events": ms_step_ev,
-        "sequential": {"ms_per_step": ms_seq, "value": hb.entries() / (ms_seq * 1e-3)},
+        "sequential": {"ms_per_step": ms_seq, "value": hb.entries_evaluated() / (ms_seq * 1e-3)},
         "roofline": {
             "kernel": "k_blocks<Laplace, DLP> coupling (the step's longest launch; "
                       "+ geometry kernel in the same call)",
@@ -758,7 +859,11 @@ def main():
             "frac": f_cd / (phase["cd"] * 1e-3) / FP64_VALU_PEAK, "traffic": stored_traffic(),
             "traffic_unit": "bytes per launch (FETCH_SIZE + WRITE_SIZE, calibrated)",
             "ms_per_launch": phase["cd"], "flops_per_launch": f_cd,
+            "peak_measured": peak_meas["fp64"],
+            "frac_of_measured_peak": f_cd / (phase["cd"] * 1e-3) / (peak_meas["fp64"] * 1e12),
         },
+        "valu_peak_measured_tflops": dict(peak_meas, probe="bem_valu_peak: 8 independent FMA "
+                                          "chains per lane, 16 waves per CU, best of 5"),
         "roofline_near_both": {
             "kernel": "k_blocks<Laplace, SLP+DLP> near field, one pass over the blocks with "
                       "t <= s (both layers of (t, s) and (s, t))", "bound": "alu",
@@ -781,9 +886,10 @@ def main():
                 "flops_per_launch": f_slp},
         },
         "forms": {
-            "plain_fp64": {"value": hb.entries() / (ms_step * 1e-3), "ms_per_step": ms_step},
+            "plain_fp64": {"value": hb.entries_evaluated() / (ms_step * 1e-3),
+                           "ms_per_step": ms_step},
             "mixed": {
-                "value": hm.entries() / (ms_step_m * 1e-3), "ms_per_step": ms_step_m,
+                "value": hm.entries_evaluated() / (ms_step_m * 1e-3), "ms_per_step": ms_step_m,
                 "speedup_vs_plain": ms_step / ms_step_m, "phase_ms": phase_m,
                 "sequential_ms_per_step": ms_seq_m,
                 "near_singular_ratio": MIXED_RATIO,
@@ -799,6 +905,7 @@ def main():
             },
         },
     }
+    result["h2_products"] = solve
     if helmholtz:
         result["forms"]["helmholtz_near_both"] = helmholtz
     if batched:

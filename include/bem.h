@@ -260,6 +260,16 @@ typedef struct {
 int bem_plan_batched(bem_ctx *ctx, const bem_op *op, int32_t nbatch, const bem_batch *batches,
                      bem_tune *tune, const char *cache_path, void *stream, bem_plan **plan);
 
+/* Autotuning alone: the candidate launch configurations of the batch (the
+ * fields of *tune left 0, as bem_plan_batched with tune->autotune = 1) are
+ * timed by running them on `stream` (the outputs are written), the winner
+ * is stored in *tune and appended to the cache file `cache_path` (a later
+ * bem_plan_batched with autotune = 1 and the same cache then plans without
+ * timing); no plan is kept.  A cache hit returns the cached configuration
+ * without timing.  Errors as bem_plan_batched. */
+int bem_autotune(bem_ctx *ctx, const bem_op *op, int32_t nbatch, const bem_batch *batches,
+                 bem_tune *tune, const char *cache_path, void *stream);
+
 /* Enqueue one replay of the plan's graph on `stream`.  Runs of one plan
  * share its queue counter and geometry: they must not overlap in time
  * (successive runs on one stream are fine).  Device flags are raised on the
@@ -342,10 +352,15 @@ int bem_selector_samples(bem_ctx *ctx, const bem_mesh *mesh, const bem_op *op, i
  * q in [q_min, q_regular - 1] such that the FP16 network (n_out = 6,
  * params) predicts e_q' + margin <= log10(tol) at every q' in
  * [q, q_regular - 1]; q_regular when q_regular - 1 fails.  The comparison is
- * made in FP32.  op: Duffy rule, q_regular in [2, 6]. */
+ * made in FP32.  range (device float[16], may be NULL): the smallest and
+ * largest value of each of the 8 inputs over the training set ([min(8),
+ * max(8)]); a pair with an input outside it (or not finite) gets q_regular,
+ * the plain rule, whatever the network predicts.  op: Duffy rule, q_regular
+ * in [2, 6]. */
 int bem_select_orders(bem_ctx *ctx, const bem_mesh *mesh, const bem_op *op,
-                      const bem_blocks *blocks, const float *params, double tol, double margin,
-                      int32_t q_min, int8_t *orders, int64_t orders_len, void *stream);
+                      const bem_blocks *blocks, const float *params, const float *range,
+                      double tol, double margin, int32_t q_min, int8_t *orders,
+                      int64_t orders_len, void *stream);
 
 /* Near-field blocks like bem_assemble_nearfield (plain FP64, Duffy rule,
  * q_regular in [2, 6]), each regular entry with the order orders[entry]
@@ -355,6 +370,27 @@ int bem_select_orders(bem_ctx *ctx, const bem_mesh *mesh, const bem_op *op,
 int bem_assemble_nearfield_learned(bem_ctx *ctx, const bem_mesh *mesh, const bem_op *op,
                                    const bem_blocks *blocks, const int8_t *orders, void *out,
                                    int64_t out_len, void *stream);
+
+/* Save a network and its training state to a file (host I/O, synchronous:
+ * waits for `stream`): n_out, the Adam step count `step` (>= 0), the
+ * parameter vector (bem_mlp_params(n_out) floats), optionally Adam's moment
+ * vectors m and v (both or neither; NULL: not stored) and the training range
+ * of the inputs (float[16] as bem_select_orders takes it; NULL: not
+ * stored).  All arrays device memory.  Format: the 8 bytes "BEMMLP01",
+ * int32 n_out, step, contents (1: moments, 2: range), 0, then the FP32
+ * arrays in that order, little endian.  BEM_EINVAL if the file cannot be
+ * written. */
+int bem_mlp_save(bem_ctx *ctx, const char *path, int32_t n_out, const float *params,
+                 const float *m, const float *v, const float *range, int32_t step, void *stream);
+
+/* Load a file written by bem_mlp_save into device arrays (synchronous):
+ * params always, m and v (both or neither) and range when not NULL, *step
+ * when step is not NULL.  Training continued from the loaded state equals
+ * training that was never interrupted, bit for bit.  BEM_EINVAL (nothing
+ * written) for a missing or truncated file, another n_out, or contents
+ * asked for that the file does not hold. */
+int bem_mlp_load(bem_ctx *ctx, const char *path, int32_t n_out, float *params, float *m, float *v,
+                 float *range, int32_t *step, void *stream);
 
 /* ---------------------------------------------------------------------
  * Cluster bases of the Green cross approximation (Sec. 2.3-2.4).
@@ -401,6 +437,23 @@ int bem_basis_contract(bem_ctx *ctx, int32_t is_complex, int32_t nmat, const int
                        const double *pinv, const void *A, const int64_t *a_off, int32_t acols,
                        int64_t a_len, void *V, const int64_t *v_off, int64_t v_len,
                        int32_t max_rows, void *stream);
+
+/* Inverses of the pivot blocks on the device (Sec. 2.3, algebraic
+ * interpolation): for each matrix c, pinv + c * max_rank^2 receives
+ * P_c = A_c[t~_c, tau_c]^{-1} (rank[c] x rank[c], column-major, leading
+ * dimension rank[c], complex interleaved when is_complex) -- the layout
+ * bem_basis_contract reads -- with A_c the n_c x acols Green matrix at
+ * A + a_off[c] (column-major, leading dimension n_c), t~_c = piv_rows[c *
+ * max_rank .. + rank[c]) its pivot rows (local row numbers) and tau_c =
+ * piv_cols[c * max_rank ..] its pivot columns, as bem_aca returns them.
+ * Gauss-Jordan elimination with partial pivoting (largest modulus, ties to
+ * the smallest row).  max_rank <= 512.  All arrays device memory; index
+ * errors raise BEM_EINVAL, a zero or non-finite pivot BEM_ENONFINITE (device
+ * flag, see bem_check). */
+int bem_pivot_inverse(bem_ctx *ctx, int32_t is_complex, int32_t nmat, const int32_t *nrows,
+                      const int32_t *rank, int32_t max_rank, const int32_t *piv_rows,
+                      const int32_t *piv_cols, const void *A, const int64_t *a_off,
+                      int32_t acols, int64_t a_len, double *pinv, void *stream);
 
 /* ---------------------------------------------------------------------
  * Host-side H^2 structure (Sec. 2.3, the first and third construction steps;
@@ -457,10 +510,116 @@ int bem_green_points(int32_t ncl, const double *cl_box, int32_t qg, double *z, d
  * or after max_rank steps.  Outputs: rank[t]; the pivot rows (t~, local row
  * numbers) and columns (tau) in piv_rows / piv_cols [t * max_rank ..]; and
  * the inverse of the pivot block A[t~, tau] in pinv + t * max_rank^2 (leading
- * dimension rank[t]).  BEM_ENONFINITE if a pivot block is singular. */
+ * dimension rank[t]); pinv = NULL: pivots only (bem_pivot_inverse forms the
+ * inverses on the device).  BEM_ENONFINITE if a pivot block is singular. */
 int bem_aca(int32_t nmat, const int64_t *a_off, const int32_t *nrows, int32_t ncols,
             int32_t is_complex, const double *A, double eps, int32_t max_rank, int32_t *rank,
             int32_t *piv_rows, int32_t *piv_cols, double *pinv);
+
+/* ---------------------------------------------------------------------
+ * Products with the H^2 matrix and the vector operations of iterative
+ * solvers (Sec. 4 solves V alpha = (1/2 I + K) beta by conjugate gradients;
+ * the Brakhage-Werner system of the Helmholtz experiment needs a
+ * non-symmetric Krylov method).  An H^2 product y = H x (Sec. 2.3-2.4) is
+ * a sequence of grouped small products: forward transformation of the
+ * column basis (leaves W^_s^T x|_s, fathers W^_s^T over the sons'
+ * coefficients), coupling y^_t += S_ts x^_s, backward transformation of
+ * the row basis (fathers push V^_t y^_t to the sons' coefficients, leaves
+ * to y|_t) and the near field y|_t += G_ts x|_s.
+ * --------------------------------------------------------------------- */
+
+/* Grouped, gathered matrix-vector products: for every group g,
+ *     y[out_idx[k]] += (sum over blocks b of g of op(A_b) x_b)[k - out_ptr[g]],
+ *     k in [out_ptr[g], out_ptr[g+1]),
+ * the blocks of g being b in [grp_ptr[g], grp_ptr[g+1]) and
+ * x_b = x[in_idx[in_ptr[b] .. in_ptr[b+1])].  op(A) = A (trans = 0; A_b is
+ * m_g x n_b) or its plain transpose, not conjugated (trans = 1; A_b is
+ * n_b x m_g); A_b starts at A + a_off[b] (entries), column-major with the
+ * row count as leading dimension.  m_g, n_b <= 512.  Entries are double
+ * (is_complex = 0) or double[2] (is_complex = 1) for A, x and y alike.
+ * All arrays device memory; out_len, in_len, a_len, x_len and y_len are the
+ * lengths of out_idx, in_idx, A, x and y (entries).  Sums run in a fixed
+ * order (reproducible bit for bit).  Groups of one call must not share
+ * output indices, and no output index of a call may be an input index of
+ * the same call (x and y may be one buffer, read and written at disjoint
+ * places, as the levels of a nested basis are).  Index errors raise the
+ * device flag (the group or entry is skipped). */
+int bem_gemv_grouped(bem_ctx *ctx, int32_t is_complex, int32_t trans, int32_t ngroups,
+                     const int32_t *grp_ptr, const int32_t *out_ptr, const int32_t *out_idx,
+                     int64_t out_len, int32_t nblocks, const int32_t *in_ptr,
+                     const int32_t *in_idx, int64_t in_len, const int64_t *a_off, const void *A,
+                     int64_t a_len, const void *x, int64_t x_len, void *y, int64_t y_len,
+                     void *stream);
+
+/* out[0] (+ i out[1]) = sum_i c(x_i) y_i with c the complex conjugate when
+ * conj = 1 (is_complex = 1), else the identity; x, y device arrays of n
+ * entries (double or double[2]); out: device double[2].  Fixed summation
+ * order (reproducible). */
+int bem_vec_dot(bem_ctx *ctx, int32_t is_complex, int32_t conj, int64_t n, const void *x,
+                const void *y, double *out, void *stream);
+
+/* y = alpha x + beta y with alpha = ar + i ai, beta = br + i bi (real
+ * vectors use ar and br); x, y device arrays of n entries. */
+int bem_vec_axpby(bem_ctx *ctx, int32_t is_complex, int64_t n, double ar, double ai,
+                  const void *x, double br, double bi, void *y, void *stream);
+
+/* y += c M x with c = cr + i ci and M the Galerkin mass matrix of the
+ * piecewise constants, diagonal with M_ii = |tau_i| (the identity term
+ * (1/2) I of Sec. 4 in Galerkin form); x, y device arrays of mesh->nt
+ * entries (double, or double[2] when is_complex). */
+int bem_mass_apply(bem_ctx *ctx, const bem_mesh *mesh, int32_t is_complex, double cr, double ci,
+                   const void *x, void *y, void *stream);
+
+/* ---------------------------------------------------------------------
+ * Piecewise-linear (P1) bases (Sec. 2.2, eq. reference_integral: the
+ * transformed basis functions are low-order polynomials).  The nodal basis
+ * function of vertex v is 1 at v, 0 at the other vertices and linear on
+ * every triangle; its Galerkin matrix is assembled from 3 x 3 local
+ * matrices of triangle pairs.
+ * --------------------------------------------------------------------- */
+
+/* Local matrices of the triangle pairs (rows[k], cols[k]), k < n:
+ *     out[9 k + 3 a + b] = int_{tau_i} int_{tau_j} lambda_a(x) k(x, y) mu_b(y) dy dx
+ * with lambda_a, mu_b the barycentric coordinates of the a-th / b-th vertex
+ * of tau_i / tau_j in mesh order, by the rules of the piecewise-constant
+ * entries: the regular rule of op (Duffy q x q or seven points per triangle)
+ * for disjoint pairs, the Sauter-Schwab rule of order q_singular for
+ * identical, edge- and vertex-adjacent pairs (relabelled as for the
+ * piecewise-constant entries; the shape functions follow the vertices).
+ * Plain FP64 only (BEM_EUNSUPPORTED otherwise).  rows, cols: device
+ * int32[n]; out: device, 9 n entries (double or double[2]). */
+int bem_p1_pairs(bem_ctx *ctx, const bem_mesh *mesh, const bem_op *op, int64_t n,
+                 const int32_t *rows, const int32_t *cols, void *out, void *stream);
+
+/* Dense block of the P1 Galerkin matrix from local matrices: for row
+ * vertex v < nrv and column vertex w < ncv,
+ *     out[v + nrv w] = sum over p in [rs_ptr[v], rs_ptr[v+1]) and
+ *                      q in [cs_ptr[w], cs_ptr[w+1]) of
+ *                      local[9 (rs_tri[p] ntc + cs_tri[q]) + 3 rs_loc[p] + cs_loc[q]]
+ * -- the triangles around v (indices into a row triangle set of ntr, with
+ * v's position 0..2 in each) against those around w (a column set of ntc),
+ * local holding the ntr x ntc pairs' matrices (bem_p1_pairs on the pairs
+ * (row set [a], column set [b]) in the order a ntc + b).  Every entry is a
+ * sum in list order, written once (reproducible bit for bit).  All arrays
+ * device memory; rs_len, cs_len: lengths of rs_tri / rs_loc, cs_tri /
+ * cs_loc; entries double or double[2] (is_complex). */
+int bem_p1_gather(bem_ctx *ctx, int32_t is_complex, int32_t nrv, const int32_t *rs_ptr,
+                  const int32_t *rs_tri, const int32_t *rs_loc, int64_t rs_len, int32_t ncv,
+                  const int32_t *cs_ptr, const int32_t *cs_tri, const int32_t *cs_loc,
+                  int64_t cs_len, int32_t ntr, int32_t ntc, const void *local, void *out,
+                  void *stream);
+
+/* ---------------------------------------------------------------------
+ * Measurement.
+ * --------------------------------------------------------------------- */
+
+/* Vector-ALU peak of the context's GPU: a launch of independent fused
+ * multiply-add chains (FP64 when fp64 = 1, else FP32 without packed
+ * instructions, the form this library's kernels use), 16 waves per compute
+ * unit, best of five timed launches after a warm-up.  *tflops receives
+ * 2 x FMAs / time in TFLOP/s.  Synchronous (enqueues on `stream`, then
+ * waits for it). */
+int bem_valu_peak(bem_ctx *ctx, int32_t fp64, double *tflops, void *stream);
 
 #ifdef __cplusplus
 }

@@ -489,6 +489,132 @@ int oracle_entries(const double *v, int nv, const int32_t *tri, int nt,
 }
 
 /* ------------------------------------------------------------------------ */
+/* Piecewise-linear bases (Sec. 2.2, eq. reference_integral: the transformed
+ * basis functions are low-order polynomials).  For a pair of triangles the
+ * 3 x 3 local matrix
+ *     L_kl = int_{tau_i} int_{tau_j} lambda_k(x) k(x, y) mu_l(y) dy dx,
+ * with lambda_k, mu_l the nodal (barycentric) functions of the vertices of
+ * tau_i and tau_j in mesh order, by the same rules as the piecewise-constant
+ * entries: on the reference triangle Phi(s, t) = v0 + s (v1 - v0) +
+ * t (v2 - v1) the barycentric coordinates of (v0, v1, v2) are
+ * (1 - s, s - t, t); for a singular pair they are taken in the relabelled
+ * order and assigned back to the mesh-order vertices.                       */
+static void bary_of(double s, double t, double *b)
+{
+    b[0] = 1.0 - s;
+    b[1] = s - t;
+    b[2] = t;
+}
+
+/* local position in t3 of vertex id w */
+static int local_of(const int32_t *t3, int w)
+{
+    return t3[0] == w ? 0 : (t3[1] == w ? 1 : 2);
+}
+
+static void p1_duffy(const double *v, const int32_t *ti, const int32_t *tj, const oop *p,
+                     double complex L[9])
+{
+    double gx[64], gw[64];
+    oracle_gauss01(p->q_reg, gx, gw);
+    affmap mi, mj;
+    make_map(v, ti[0], ti[1], ti[2], &mi);
+    make_map(v, tj[0], tj[1], tj[2], &mj);
+    double ny[3];
+    unit_normal(v, tj, ny);
+    const int q = p->q_reg;
+    for (int e = 0; e < 9; ++e) L[e] = 0.0;
+    for (int a = 0; a < q; ++a)
+        for (int b = 0; b < q; ++b)
+            for (int c = 0; c < q; ++c)
+                for (int d = 0; d < q; ++d) {
+                    double x[3], y[3], bx[3], by[3];
+                    apply_map(&mi, gx[a], gx[a] * gx[b], x);
+                    apply_map(&mj, gx[c], gx[c] * gx[d], y);
+                    bary_of(gx[a], gx[a] * gx[b], bx);
+                    bary_of(gx[c], gx[c] * gx[d], by);
+                    double wt = gw[a] * gw[b] * gw[c] * gw[d] * gx[a] * gx[c];
+                    double complex kv = wt * kernel_eval(p->kernel, p->layer, p->kappa, x, y, ny);
+                    for (int k = 0; k < 3; ++k)
+                        for (int l = 0; l < 3; ++l) L[3 * k + l] += bx[k] * kv * by[l];
+                }
+    double sg = sqrt_gram(v, ti) * sqrt_gram(v, tj);
+    for (int e = 0; e < 9; ++e) L[e] *= sg;
+}
+
+static void p1_ss(const double *v, const int32_t *ti, const int32_t *tj, int cs, const oop *p,
+                  double complex L[9])
+{
+    double gx[64], gw[64];
+    oracle_gauss01(p->q_sing, gx, gw);
+    int li[3], lj[3];
+    relabel(ti, tj, cs, li, lj);
+    affmap mi, mj;
+    make_map(v, li[0], li[1], li[2], &mi);
+    make_map(v, lj[0], lj[1], lj[2], &mj);
+    double ny[3];
+    unit_normal(v, tj, ny); /* original orientation */
+    int pi[3], pj[3]; /* mesh-order position of relabelled vertex k */
+    for (int k = 0; k < 3; ++k) {
+        pi[k] = local_of(ti, li[k]);
+        pj[k] = local_of(tj, lj[k]);
+    }
+    const int q = p->q_sing;
+    for (int e = 0; e < 9; ++e) L[e] = 0.0;
+    for (int reg = 0; reg < oracle_ss_nregions(cs); ++reg)
+        for (int a = 0; a < q; ++a)
+            for (int b = 0; b < q; ++b)
+                for (int c = 0; c < q; ++c)
+                    for (int d = 0; d < q; ++d) {
+                        double xh[2], yh[2], jac, x[3], y[3], bx[3], by[3];
+                        ss_map(cs, reg, gx[a], gx[b], gx[c], gx[d], xh, yh, &jac);
+                        apply_map(&mi, xh[0], xh[1], x);
+                        apply_map(&mj, yh[0], yh[1], y);
+                        bary_of(xh[0], xh[1], bx);
+                        bary_of(yh[0], yh[1], by);
+                        double wt = gw[a] * gw[b] * gw[c] * gw[d] * jac;
+                        double complex kv =
+                            wt * kernel_eval(p->kernel, p->layer, p->kappa, x, y, ny);
+                        for (int k = 0; k < 3; ++k)
+                            for (int l = 0; l < 3; ++l)
+                                L[3 * pi[k] + pj[l]] += bx[k] * kv * by[l];
+                    }
+    double sg = sqrt_gram(v, ti) * sqrt_gram(v, tj);
+    for (int e = 0; e < 9; ++e) L[e] *= sg;
+}
+
+/* Local matrices of the pairs (rows[k], cols[k]): out[18 k + 2 (3 a + b)],
+ * out[.. + 1] = Re, Im of L_ab (a: vertex of the row triangle, b: of the
+ * column triangle, mesh order).  Duffy rule of order q_reg for disjoint
+ * pairs (the seven-point rule is not offered), Sauter-Schwab of order q_sing
+ * otherwise.  OpenMP over pairs.                                           */
+int oracle_p1_pairs(const double *v, int nv, const int32_t *tri, int nt, int kernel, int layer,
+                    double kappa, int q_reg, int q_sing, long n, const int32_t *rows,
+                    const int32_t *cols, double *out)
+{
+    if (kernel < 0 || kernel > 1 || layer < 0 || layer > 1) return -1;
+    if (q_reg < 1 || q_reg > 64 || q_sing < 1 || q_sing > 64) return -1;
+    for (long k = 0; k < 3L * nt; ++k)
+        if (tri[k] < 0 || tri[k] >= nv) return -1;
+    for (long k = 0; k < n; ++k)
+        if (rows[k] < 0 || rows[k] >= nt || cols[k] < 0 || cols[k] >= nt) return -1;
+    oop p = {kernel, layer, O_RULE_DUFFY, q_reg, q_sing, kappa};
+#pragma omp parallel for schedule(dynamic, 16)
+    for (long k = 0; k < n; ++k) {
+        const int32_t *ti = tri + 3 * (size_t)rows[k], *tj = tri + 3 * (size_t)cols[k];
+        int cs = oracle_shared_vertices(tri, rows[k], cols[k]);
+        double complex L[9];
+        if (cs == O_DISJOINT) p1_duffy(v, ti, tj, &p, L);
+        else p1_ss(v, ti, tj, cs, &p, L);
+        for (int e = 0; e < 9; ++e) {
+            out[18 * k + 2 * e] = creal(L[e]);
+            out[18 * k + 2 * e + 1] = cimag(L[e]);
+        }
+    }
+    return 0;
+}
+
+/* ------------------------------------------------------------------------ */
 /* Green quadrature matrices of Sec. 2.3 (eq. green_matrix).  For triangle
  * tau_i and Green quadrature point z_nu (weight w_nu, outward unit normal
  * n_nu of the box omega_t) two columns nu and m + nu:
@@ -579,6 +705,120 @@ int oracle_green_matrix(const double *v, int nv, const int32_t *tri, int nt,
     return 0;
 }
 
+/* ------------------------------------------------------------------------ */
+/* Algebraic interpolation of Sec. 2.3 (the cluster basis of the Green cross
+ * approximation): with a cluster's Green matrix A (n rows, acols columns),
+ * pivot rows t~ and pivot columns tau chosen by cross approximation (k of
+ * each), the basis is
+ *     V = A[:, tau] A[t~, tau]^{-1},
+ * so that the rows t~ of V form the identity (R_t V = I) and V interpolates
+ * every column of A that lies in the span of the pivot columns.
+ * Matrices are column-major and complex interleaved (re, im).             */
+
+/* Inverse of the k x k matrix M by Gauss-Jordan elimination with partial
+ * pivoting (largest modulus in the column).  P receives M^{-1}.  Returns 0,
+ * or -1 when a pivot is exactly zero.                                      */
+int oracle_inverse(int k, const double *M, double *P)
+{
+    if (k < 1) return -1;
+    size_t kk = (size_t)k * k;
+    double complex *a = malloc(kk * sizeof *a), *b = malloc(kk * sizeof *b);
+    if (!a || !b) { free(a); free(b); return -1; }
+    for (size_t e = 0; e < kk; ++e) {
+        a[e] = M[2 * e] + I * M[2 * e + 1];
+        b[e] = 0.0;
+    }
+    for (int e = 0; e < k; ++e) b[e + (size_t)k * e] = 1.0;
+    int rc = 0;
+    for (int c = 0; c < k && !rc; ++c) {
+        int p = c;
+        for (int r = c + 1; r < k; ++r)
+            if (cabs(a[r + (size_t)k * c]) > cabs(a[p + (size_t)k * c])) p = r;
+        if (a[p + (size_t)k * c] == 0.0) { rc = -1; break; }
+        if (p != c)
+            for (int j = 0; j < k; ++j) {
+                double complex t = a[c + (size_t)k * j];
+                a[c + (size_t)k * j] = a[p + (size_t)k * j];
+                a[p + (size_t)k * j] = t;
+                t = b[c + (size_t)k * j];
+                b[c + (size_t)k * j] = b[p + (size_t)k * j];
+                b[p + (size_t)k * j] = t;
+            }
+        double complex d = a[c + (size_t)k * c];
+        for (int j = 0; j < k; ++j) {
+            a[c + (size_t)k * j] /= d;
+            b[c + (size_t)k * j] /= d;
+        }
+        for (int r = 0; r < k; ++r) {
+            if (r == c) continue;
+            double complex f = a[r + (size_t)k * c];
+            if (f == 0.0) continue;
+            for (int j = 0; j < k; ++j) {
+                a[r + (size_t)k * j] -= f * a[c + (size_t)k * j];
+                b[r + (size_t)k * j] -= f * b[c + (size_t)k * j];
+            }
+        }
+    }
+    if (!rc)
+        for (size_t e = 0; e < kk; ++e) {
+            P[2 * e] = creal(b[e]);
+            P[2 * e + 1] = cimag(b[e]);
+        }
+    free(a);
+    free(b);
+    return rc;
+}
+
+/* V = A[:, tau] P for a given k x k matrix P (n x k result): the basis
+ * contraction, one sum per entry over the k pivot columns.                 */
+int oracle_contract(int n, int acols, const double *A, int k, const int32_t *tau,
+                    const double *P, double *V)
+{
+    if (n < 0 || k < 1) return -1;
+    for (int c = 0; c < k; ++c)
+        if (tau[c] < 0 || tau[c] >= acols) return -1;
+    for (int i = 0; i < n; ++i)
+        for (int j = 0; j < k; ++j) {
+            double complex s = 0.0;
+            for (int l = 0; l < k; ++l) {
+                size_t ia = (size_t)i + (size_t)n * tau[l];
+                size_t ip = (size_t)l + (size_t)k * j;
+                s += (A[2 * ia] + I * A[2 * ia + 1]) * (P[2 * ip] + I * P[2 * ip + 1]);
+            }
+            size_t iv = (size_t)i + (size_t)n * j;
+            V[2 * iv] = creal(s);
+            V[2 * iv + 1] = cimag(s);
+        }
+    return 0;
+}
+
+/* The interpolation basis from the pivots alone: P = A[t~, tau]^{-1} by
+ * oracle_inverse, then V = A[:, tau] P by oracle_contract.  P (k x k) may be
+ * NULL.                                                                    */
+int oracle_interp_basis(int n, int acols, const double *A, int k, const int32_t *prow,
+                        const int32_t *tau, double *V, double *P)
+{
+    if (n < 1 || k < 1 || k > n || k > acols) return -1;
+    for (int c = 0; c < k; ++c)
+        if (prow[c] < 0 || prow[c] >= n || tau[c] < 0 || tau[c] >= acols) return -1;
+    size_t kk = (size_t)k * k;
+    double *M = malloc(2 * kk * sizeof *M), *Pi = malloc(2 * kk * sizeof *Pi);
+    if (!M || !Pi) { free(M); free(Pi); return -1; }
+    for (int c = 0; c < k; ++c)
+        for (int r = 0; r < k; ++r) {
+            size_t ia = (size_t)prow[r] + (size_t)n * tau[c];
+            size_t im = (size_t)r + (size_t)k * c;
+            M[2 * im] = A[2 * ia];
+            M[2 * im + 1] = A[2 * ia + 1];
+        }
+    int rc = oracle_inverse(k, M, Pi);
+    if (!rc) rc = oracle_contract(n, acols, A, k, tau, Pi, V);
+    if (!rc && P) memcpy(P, Pi, 2 * kk * sizeof *P);
+    free(M);
+    free(Pi);
+    return rc;
+}
+
 /* Number of OpenMP threads the oracle's parallel loops use. */
 #ifdef _OPENMP
 #include <omp.h>
@@ -589,5 +829,15 @@ int oracle_num_threads(void)
     return omp_get_max_threads();
 #else
     return 1;
+#endif
+}
+
+/* Threads of the following parallel loops (n >= 1). */
+void oracle_set_threads(int n)
+{
+#ifdef _OPENMP
+    if (n >= 1) omp_set_num_threads(n);
+#else
+    (void)n;
 #endif
 }

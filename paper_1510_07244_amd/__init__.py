@@ -280,6 +280,8 @@ def _setup_bases_api():
     _lib.bem_basis_contract.argtypes = [P, ctypes.c_int32, ctypes.c_int32, P, P, ctypes.c_int32,
                                         P, P, P, P, ctypes.c_int32, ctypes.c_int64, P, P,
                                         ctypes.c_int64, ctypes.c_int32, P]
+    _lib.bem_pivot_inverse.argtypes = [P, ctypes.c_int32, ctypes.c_int32, P, P, ctypes.c_int32,
+                                       P, P, P, P, ctypes.c_int32, ctypes.c_int64, P, P]
 
 
 _setup_bases_api()
@@ -302,9 +304,10 @@ def green_points(boxes, qg):
     return z, zn, zw, delta
 
 
-def aca(A, a_off, nrows, ncols, eps, max_rank, is_complex=False):
+def aca(A, a_off, nrows, ncols, eps, max_rank, is_complex=False, inverse=True):
     """``bem_aca`` on packed host matrices (float64 array; complex as
-    interleaved pairs).  Returns rank, piv_rows, piv_cols, pinv."""
+    interleaved pairs).  Returns rank, piv_rows, piv_cols, pinv (None when
+    inverse is False: pivots only)."""
     import numpy as np
     A = np.ascontiguousarray(A)
     a_off = np.ascontiguousarray(a_off, dtype=np.int64)
@@ -313,10 +316,11 @@ def aca(A, a_off, nrows, ncols, eps, max_rank, is_complex=False):
     rank = np.zeros(nmat, dtype=np.int32)
     piv_rows = np.zeros((nmat, max_rank), dtype=np.int32)
     piv_cols = np.zeros((nmat, max_rank), dtype=np.int32)
-    pinv = np.zeros((nmat, max_rank * max_rank * (2 if is_complex else 1)), dtype=np.float64)
+    pinv = (np.zeros((nmat, max_rank * max_rank * (2 if is_complex else 1)), dtype=np.float64)
+            if inverse else None)
     rc = _lib.bem_aca(nmat, _np_ptr(a_off), _np_ptr(nrows), int(ncols), int(bool(is_complex)),
                       _np_ptr(A), float(eps), int(max_rank), _np_ptr(rank), _np_ptr(piv_rows),
-                      _np_ptr(piv_cols), _np_ptr(pinv))
+                      _np_ptr(piv_cols), _np_ptr(pinv) if inverse else ctypes.c_void_p(0))
     if rc:
         raise BemError(rc, "bem_aca failed")
     return rank, piv_rows, piv_cols, pinv
@@ -340,6 +344,107 @@ def _context_basis_contract(self, is_complex, nrows, rank, max_rank, piv_cols, p
                                      _ptr(v_off), V.numel(), int(max_rows), _stream(stream)))
 
 
+def _context_valu_peak(self, fp64=True, stream=None):
+    """bem_valu_peak: measured vector-ALU peak (TFLOP/s) of the context's GPU."""
+    _lib.bem_valu_peak.argtypes = [ctypes.c_void_p, ctypes.c_int32,
+                                   ctypes.POINTER(ctypes.c_double), ctypes.c_void_p]
+    r = ctypes.c_double()
+    self._rc(_lib.bem_valu_peak(self.h, int(bool(fp64)), ctypes.byref(r), _stream(stream)))
+    return r.value
+
+
+Context.valu_peak = _context_valu_peak
+
+
+def _setup_h2mv_api():
+    P, i32, i64, f64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double
+    _lib.bem_gemv_grouped.argtypes = [P, i32, i32, i32, P, P, P, i64, i32, P, P, i64, P, P, i64,
+                                      P, i64, P, i64, P]
+    _lib.bem_vec_dot.argtypes = [P, i32, i32, i64, P, P, P, P]
+    _lib.bem_vec_axpby.argtypes = [P, i32, i64, f64, f64, P, f64, f64, P, P]
+    _lib.bem_mass_apply.argtypes = [P, ctypes.POINTER(bem_mesh), i32, f64, f64, P, P, P]
+
+
+_setup_h2mv_api()
+
+
+def _n(t):
+    """Entries of a real or complex tensor."""
+    return t.numel()
+
+
+def _context_gemv_grouped(self, trans, grp_ptr, out_ptr, out_idx, in_ptr, in_idx, a_off, A, x, y,
+                          stream=None):
+    """bem_gemv_grouped on device tensors (complex when A is)."""
+    cplx = A.is_complex()
+    self._rc(_lib.bem_gemv_grouped(self.h, int(cplx), int(bool(trans)), grp_ptr.numel() - 1,
+                                   _ptr(grp_ptr), _ptr(out_ptr), _ptr(out_idx), out_idx.numel(),
+                                   in_ptr.numel() - 1, _ptr(in_ptr), _ptr(in_idx), in_idx.numel(),
+                                   _ptr(a_off), _ptr(A), _n(A), _ptr(x), _n(x), _ptr(y), _n(y),
+                                   _stream(stream)))
+
+
+def _context_vec_dot(self, x, y, out, conj=True, stream=None):
+    """bem_vec_dot into the device double[2] `out`."""
+    self._rc(_lib.bem_vec_dot(self.h, int(x.is_complex()), int(bool(conj)), _n(x), _ptr(x), _ptr(y),
+                              _ptr(out), _stream(stream)))
+
+
+def _context_vec_axpby(self, alpha, x, beta, y, stream=None):
+    """bem_vec_axpby: y = alpha x + beta y (alpha, beta Python numbers)."""
+    a, b = complex(alpha), complex(beta)
+    self._rc(_lib.bem_vec_axpby(self.h, int(x.is_complex()), _n(x), a.real, a.imag, _ptr(x),
+                                b.real, b.imag, _ptr(y), _stream(stream)))
+
+
+def _context_mass_apply(self, mesh, c, x, y, stream=None):
+    """bem_mass_apply: y += c M x."""
+    c = complex(c)
+    self._rc(_lib.bem_mass_apply(self.h, ctypes.byref(mesh.c), int(x.is_complex()), c.real, c.imag,
+                                 _ptr(x), _ptr(y), _stream(stream)))
+
+
+def _setup_p1_api():
+    P, i32, i64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64
+    _lib.bem_p1_pairs.argtypes = [P, ctypes.POINTER(bem_mesh), ctypes.POINTER(bem_op), i64, P, P,
+                                  P, P]
+    _lib.bem_p1_gather.argtypes = [P, i32, i32, P, P, P, i64, i32, P, P, P, i64, i32, i32, P, P,
+                                   P]
+
+
+_setup_p1_api()
+
+
+def _context_p1_pairs(self, mesh, op, rows, cols, out, stream=None):
+    """bem_p1_pairs: out (9 n entries) = local 3 x 3 matrices of the pairs."""
+    self._rc(_lib.bem_p1_pairs(self.h, ctypes.byref(mesh.c), ctypes.byref(op), rows.numel(),
+                               _ptr(rows), _ptr(cols), _ptr(out), _stream(stream)))
+
+
+def _context_p1_gather(self, rs_ptr, rs_tri, rs_loc, cs_ptr, cs_tri, cs_loc, ntr, ntc, local,
+                       out, stream=None):
+    """bem_p1_gather: dense vertex block from the pairs' local matrices."""
+    self._rc(_lib.bem_p1_gather(self.h, int(local.is_complex()), rs_ptr.numel() - 1, _ptr(rs_ptr),
+                                _ptr(rs_tri), _ptr(rs_loc), rs_tri.numel(), cs_ptr.numel() - 1,
+                                _ptr(cs_ptr), _ptr(cs_tri), _ptr(cs_loc), cs_tri.numel(),
+                                int(ntr), int(ntc), _ptr(local), _ptr(out), _stream(stream)))
+
+
+Context.p1_pairs = _context_p1_pairs
+Context.p1_gather = _context_p1_gather
+Context.gemv_grouped = _context_gemv_grouped
+Context.vec_dot = _context_vec_dot
+Context.vec_axpby = _context_vec_axpby
+Context.mass_apply = _context_mass_apply
+def _context_pivot_inverse(self, is_complex, nrows, rank, max_rank, piv_rows, piv_cols, A, a_off,
+                           acols, pinv, stream=None):
+    self._rc(_lib.bem_pivot_inverse(self.h, int(bool(is_complex)), nrows.numel(), _ptr(nrows),
+                                    _ptr(rank), int(max_rank), _ptr(piv_rows), _ptr(piv_cols),
+                                    _ptr(A), _ptr(a_off), int(acols), A.numel(), _ptr(pinv),
+                                    _stream(stream)))
+
+
+Context.pivot_inverse = _context_pivot_inverse
 Context.green_matrix = _context_green_matrix
 Context.basis_contract = _context_basis_contract
 
@@ -369,9 +474,32 @@ def _setup_plan_api():
     _lib.bem_plan_tiles.restype = ctypes.c_int64
     _lib.bem_plan_destroy.argtypes = [P]
     _lib.bem_plan_destroy.restype = None
+    _lib.bem_autotune.argtypes = [P, ctypes.POINTER(bem_op), ctypes.c_int32,
+                                  ctypes.POINTER(bem_batch), ctypes.POINTER(bem_tune),
+                                  ctypes.c_char_p, P]
 
 
 _setup_plan_api()
+
+
+def autotune(ctx, op, entries, tune=None, cache=None, stream=None):
+    """``bem_autotune``: time the launch configurations of a batch (entries
+    as for Plan), store the winner in the cache file, keep no plan.
+    Returns the chosen configuration."""
+    entries = list(entries)
+    c = (bem_batch * max(len(entries), 1))()
+    for k, (mesh, blocks, out, coupling) in enumerate(entries):
+        c[k] = bem_batch(ctypes.pointer(mesh.c), ctypes.pointer(blocks.c), int(bool(coupling)), 0,
+                         _ptr(out), out.numel())
+    t = dict(tune or {})
+    cfg = bem_tune(int(t.get("grid", 0)), int(t.get("tile_rows", 0)), int(t.get("tile_cols", 0)),
+                   int(t.get("x_chunk", 0)), 1, int(t.get("granularity", 0)),
+                   (ctypes.c_int32 * 2)(0, 0), 0.0)
+    path = os.fsencode(cache) if cache else None
+    ctx._rc(_lib.bem_autotune(ctx.h, ctypes.byref(op), len(entries), c, ctypes.byref(cfg), path,
+                              _stream(stream)))
+    return dict(grid=cfg.grid, tile_rows=cfg.tile_rows, tile_cols=cfg.tile_cols,
+                x_chunk=cfg.x_chunk, granularity=cfg.granularity, tuned_ms=cfg.tuned_ms)
 
 
 class Plan:
@@ -435,8 +563,10 @@ def _setup_learned_api():
     _lib.bem_mlp_grad.argtypes = [P, i32, P, i64, P, P, P, P, P]
     _lib.bem_mlp_adam.argtypes = [P, i64, P, P, P, P, i32, f32, f32, f32, f32, P]
     _lib.bem_selector_samples.argtypes = [P, M, O, i64, P, P, P, P, P]
-    _lib.bem_select_orders.argtypes = [P, M, O, B, P, f64, f64, i32, P, i64, P]
+    _lib.bem_select_orders.argtypes = [P, M, O, B, P, P, f64, f64, i32, P, i64, P]
     _lib.bem_assemble_nearfield_learned.argtypes = [P, M, O, B, P, P, i64, P]
+    _lib.bem_mlp_save.argtypes = [P, ctypes.c_char_p, i32, P, P, P, P, i32, P]
+    _lib.bem_mlp_load.argtypes = [P, ctypes.c_char_p, i32, P, P, P, P, ctypes.POINTER(i32), P]
 
 
 _setup_learned_api()
@@ -474,9 +604,10 @@ def _context_selector_samples(self, mesh, op, rows, cols, x, t, stream=None):
 
 
 def _context_select_orders(self, mesh, op, blocks, params, orders, tol, margin, q_min=2,
-                           stream=None):
+                           stream=None, range=None):
+    """bem_select_orders; range: device float[16] training range (or None)."""
     self._rc(_lib.bem_select_orders(self.h, ctypes.byref(mesh.c), ctypes.byref(op),
-                                    ctypes.byref(blocks.c), _ptr(params), float(tol),
+                                    ctypes.byref(blocks.c), _ptr(params), _ptr(range), float(tol),
                                     float(margin), int(q_min), _ptr(orders), orders.numel(),
                                     _stream(stream)))
 
@@ -487,6 +618,23 @@ def _context_assemble_nearfield_learned(self, mesh, op, blocks, orders, out, str
                                                  out.numel(), _stream(stream)))
 
 
+def _context_mlp_save(self, path, n_out, params, m=None, v=None, range=None, step=0,
+                      stream=None):
+    """bem_mlp_save: network (and optionally Adam moments, training range)."""
+    self._rc(_lib.bem_mlp_save(self.h, os.fsencode(path), int(n_out), _ptr(params), _ptr(m),
+                               _ptr(v), _ptr(range), int(step), _stream(stream)))
+
+
+def _context_mlp_load(self, path, n_out, params, m=None, v=None, range=None, stream=None):
+    """bem_mlp_load into device tensors; returns the stored Adam step."""
+    step = ctypes.c_int32()
+    self._rc(_lib.bem_mlp_load(self.h, os.fsencode(path), int(n_out), _ptr(params), _ptr(m),
+                               _ptr(v), _ptr(range), ctypes.byref(step), _stream(stream)))
+    return step.value
+
+
+Context.mlp_save = _context_mlp_save
+Context.mlp_load = _context_mlp_load
 Context.mlp_forward = _context_mlp_forward
 Context.mlp_grad = _context_mlp_grad
 Context.mlp_adam = _context_mlp_adam

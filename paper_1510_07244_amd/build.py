@@ -14,7 +14,8 @@ BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libbem.so")
 ARCH = os.environ.get("BEM_OFFLOAD_ARCH", "gfx950")
 
-SOURCES = ["bem_blocks.hip", "bem_kernels.hip", "bem_bases.hip", "bem_mlp.hip",
+SOURCES = ["bem_blocks.hip", "bem_kernels.hip", "bem_bases.hip", "bem_mlp.hip", "bem_peak.hip",
+           "bem_h2mv.hip", "bem_p1.hip",
            "bem_quadrature.cpp", "bem_capi.cpp", "bem_plan.cpp", "bem_learned.cpp",
            "bem_h2_tree.cpp", "bem_h2_host.cpp"]
 OPENMP = {"bem_h2_host.cpp"}

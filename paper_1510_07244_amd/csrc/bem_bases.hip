@@ -205,7 +205,151 @@ __global__ __launch_bounds__(kThreads) void k_contract(const ContractArgs a) {
   }
 }
 
+// ------------------------------------------------ pivot-block inverse
+// P_c = A_c[t~_c, tau_c]^{-1} (k_c x k_c, column-major, leading dimension
+// k_c) by in-place Gauss-Jordan elimination with partial pivoting, one
+// workgroup per matrix, in the matrix's own output slot.  The slot holds
+// X = M^T row-major (= M column-major); row operations on X then read and
+// write contiguous rows, and the inverse of X left in place row-major is
+// M^{-1} column-major.  Pivot: the largest modulus in the column (ties to
+// the smallest row); the row exchanges are undone as column exchanges in
+// reverse order at the end.  The steps are sequential (k_c of them with a
+// barrier each) and the data small: latency-bound, so the vector units and
+// L2 serve it; the matrix cores are used by the contraction that follows.
+template <bool CPLX>
+struct Z;
+template <>
+struct Z<false> {
+  double v;
+  __device__ static Z make(double r, double) { Z z; z.v = r; return z; }
+  __device__ double mag2() const { return v * v; }
+  __device__ Z operator*(const Z &o) const { return make(v * o.v, 0); }
+  __device__ Z operator-(const Z &o) const { return make(v - o.v, 0); }
+  __device__ Z div(const Z &o) const { return make(v / o.v, 0); }
+  __device__ bool finite_nonzero() const { return v != 0.0 && isfinite(v); }
+};
+template <>
+struct Z<true> {
+  double re, im;
+  __device__ static Z make(double r, double i) { Z z; z.re = r; z.im = i; return z; }
+  __device__ double mag2() const { return re * re + im * im; }
+  __device__ Z operator*(const Z &o) const { return make(re * o.re - im * o.im, re * o.im + im * o.re); }
+  __device__ Z operator-(const Z &o) const { return make(re - o.re, im - o.im); }
+  __device__ Z div(const Z &o) const {
+    // (re + i im) / (a + i b) scaled by the larger of |a|, |b| (Smith)
+    if (fabs(o.re) >= fabs(o.im)) {
+      const double t = o.im / o.re, d = o.re + o.im * t;
+      return make((re + im * t) / d, (im - re * t) / d);
+    }
+    const double t = o.re / o.im, d = o.re * t + o.im;
+    return make((re * t + im) / d, (im * t - re) / d);
+  }
+  __device__ bool finite_nonzero() const {
+    return (re != 0.0 || im != 0.0) && isfinite(re) && isfinite(im);
+  }
+};
+
+constexpr int kInvMaxRank = 512;
+
+template <bool CPLX>
+__global__ __launch_bounds__(kThreads) void k_pivot_inverse(const PivInvArgs a) {
+  using T = Z<CPLX>;
+  __shared__ T f[kInvMaxRank];
+  __shared__ int swapped[kInvMaxRank];
+  __shared__ int pvt;
+  const int c = blockIdx.x;
+  const int n = a.nrows[c], k = a.rank[c];
+  const int64_t aoff = a.a_off[c];
+  if (n < 0 || k < 0 || k > a.max_rank || k > n || aoff < 0 ||
+      aoff + (int64_t)n * a.acols > a.a_len) {
+    if (threadIdx.x == 0) atomicOr(a.flags, FLAG_EINVAL);
+    return;
+  }
+  const int tid = threadIdx.x, wave = tid / kWave, lane = tid & (kWave - 1);
+  constexpr int W = kThreads / kWave;
+  const int32_t *prow = a.piv_rows + (int64_t)c * a.max_rank;
+  const int32_t *pcol = a.piv_cols + (int64_t)c * a.max_rank;
+  const T *A = reinterpret_cast<const T *>(a.A);
+  T *X = reinterpret_cast<T *>(a.pinv) + (int64_t)c * a.max_rank * a.max_rank;
+  // X[i][j] = M[j][i] = A[prow[j], pcol[i]]
+  for (int i = wave; i < k; i += W) {
+    const int ci = pcol[i];
+    for (int j = lane; j < k; j += kWave) {
+      const int rj = prow[j];
+      if (ci < 0 || ci >= a.acols || rj < 0 || rj >= n) {
+        atomicOr(a.flags, FLAG_EINVAL);
+        X[(int64_t)i * k + j] = T::make(0, 0);
+      } else {
+        X[(int64_t)i * k + j] = A[aoff + rj + (int64_t)n * ci];
+      }
+    }
+  }
+  __syncthreads();
+  for (int s = 0; s < k; ++s) {
+    if (wave == 0) {
+      double best = -1.0;
+      int bi = s;
+      for (int r = s + lane; r < k; r += kWave) {
+        const double v = X[(int64_t)r * k + s].mag2();
+        if (v > best) best = v, bi = r;
+      }
+      for (int o = kWave / 2; o >= 1; o >>= 1) {
+        const double ob = __shfl_xor(best, o, kWave);
+        const int oi = __shfl_xor(bi, o, kWave);
+        if (ob > best || (ob == best && oi < bi)) best = ob, bi = oi;
+      }
+      if (lane == 0) pvt = bi, swapped[s] = bi;
+    }
+    __syncthreads();
+    const int p = pvt;
+    if (p != s)
+      for (int j = tid; j < k; j += kThreads) {
+        const T t = X[(int64_t)s * k + j];
+        X[(int64_t)s * k + j] = X[(int64_t)p * k + j];
+        X[(int64_t)p * k + j] = t;
+      }
+    __syncthreads();
+    const T piv = X[(int64_t)s * k + s];
+    if (tid == 0 && !piv.finite_nonzero()) atomicOr(a.flags, FLAG_NONFINITE);
+    __syncthreads();  // every thread holds piv before row s changes
+    for (int j = tid; j < k; j += kThreads) {
+      const T v = j == s ? T::make(1, 0) : X[(int64_t)s * k + j];
+      X[(int64_t)s * k + j] = v.div(piv);
+    }
+    for (int r = tid; r < k; r += kThreads) f[r] = X[(int64_t)r * k + s];
+    __syncthreads();
+    for (int r = wave; r < k; r += W) {
+      if (r == s) continue;
+      const T fr = f[r];
+      for (int j = lane; j < k; j += kWave) {
+        const T old = j == s ? T::make(0, 0) : X[(int64_t)r * k + j];
+        X[(int64_t)r * k + j] = old - fr * X[(int64_t)s * k + j];
+      }
+    }
+    __syncthreads();
+  }
+  for (int s = k - 1; s >= 0; --s) {
+    const int p = swapped[s];
+    if (p != s)
+      for (int r = tid; r < k; r += kThreads) {
+        const T t = X[(int64_t)r * k + s];
+        X[(int64_t)r * k + s] = X[(int64_t)r * k + p];
+        X[(int64_t)r * k + p] = t;
+      }
+    __syncthreads();
+  }
+}
+
 }  // namespace
+
+hipError_t launch_pivot_inverse(bool cplx, const PivInvArgs &a, hipStream_t s) {
+  if (a.nmat == 0) return hipSuccess;
+  if (a.max_rank > kInvMaxRank) return hipErrorInvalidValue;
+  const dim3 grid(a.nmat), block(kThreads);
+  if (cplx) hipLaunchKernelGGL((k_pivot_inverse<true>), grid, block, 0, s, a);
+  else hipLaunchKernelGGL((k_pivot_inverse<false>), grid, block, 0, s, a);
+  return hipGetLastError();
+}
 
 hipError_t launch_green(int kernel, int side, const GreenArgs &a, int grid_y, hipStream_t s) {
   if (a.ncl == 0) return hipSuccess;

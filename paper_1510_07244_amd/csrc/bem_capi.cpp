@@ -161,15 +161,16 @@ int assemble_blocks(bem_ctx *ctx, const bem_mesh *mesh, const bem_op *op,
   int64_t ldg;
   const bem::DevRules *rules;
   if ((rc = ensure_geo(ctx, mesh->nt, &ldg)) || (rc = get_rules(ctx, op, &rules))) return rc;
+  double *geo = ctx->geo;
   hipStream_t s = static_cast<hipStream_t>(stream);
-  hipError_t e = bem::launch_geometry(*mesh, ctx->geo, ldg, ctx->flags, s);
+  hipError_t e = bem::launch_geometry(*mesh, geo, ldg, ctx->flags, s);
   if (e != hipSuccess) return hip_fail(ctx, e, "geometry kernel launch");
   bem::BlockArgs a{};
   a.v = mesh->v;
   a.tri = mesh->tri;
   a.nv = mesh->nv;
   a.nt = mesh->nt;
-  a.geo = ctx->geo;
+  a.geo = geo;
   a.ldg = ldg;
   a.nblocks = blocks->n;
   a.row_ptr = blocks->row_ptr;
@@ -227,7 +228,10 @@ int bem_create(bem_ctx **out, int device) {
     ctx->lds_budget = std::min<size_t>((size_t)lds_max, 80 * 1024);  // keep 2 workgroups per CU
   hipError_t e = hipMalloc(&ctx->flags, 256);
   if (e == hipSuccess) e = hipMemset(ctx->flags, 0, 256);
+  if (e == hipSuccess) e = hipMalloc(&ctx->dot_part, bem::dot_scratch_doubles() * sizeof(double));
   if (e != hipSuccess) {
+    if (ctx->flags) (void)hipFree(ctx->flags);
+    if (ctx->dot_part) (void)hipFree(ctx->dot_part);
     delete ctx;
     return e == hipErrorOutOfMemory ? BEM_ENOMEM : BEM_EDEVICE;
   }
@@ -251,6 +255,7 @@ void bem_destroy(bem_ctx *ctx) {
     if (ctx->mlp_scratch) (void)hipFree(ctx->mlp_scratch);
     if (ctx->sel_scratch) (void)hipFree(ctx->sel_scratch);
     if (ctx->flags) (void)hipFree(ctx->flags);
+    if (ctx->dot_part) (void)hipFree(ctx->dot_part);
   }
   delete ctx;
 }
@@ -381,6 +386,35 @@ int bem_basis_contract(bem_ctx *ctx, int32_t is_complex, int32_t nmat, const int
   return BEM_OK;
 }
 
+int bem_pivot_inverse(bem_ctx *ctx, int32_t is_complex, int32_t nmat, const int32_t *nrows,
+                      const int32_t *rank, int32_t max_rank, const int32_t *piv_rows,
+                      const int32_t *piv_cols, const void *A, const int64_t *a_off,
+                      int32_t acols, int64_t a_len, double *pinv, void *stream) {
+  if (!ctx) return BEM_EINVAL;
+  if (nmat < 0 || max_rank < 1 || max_rank > 512 || acols < 0 || a_len < 0)
+    return fail(ctx, BEM_EINVAL, "invalid size (max_rank in [1, 512])");
+  if (nmat == 0) return BEM_OK;
+  if (!nrows || !rank || !piv_rows || !piv_cols || !a_off || !pinv || (a_len > 0 && !A))
+    return fail(ctx, BEM_EINVAL, "NULL array");
+  DeviceGuard g(ctx->device);
+  bem::PivInvArgs a{};
+  a.nmat = nmat;
+  a.nrows = nrows;
+  a.rank = rank;
+  a.piv_rows = piv_rows;
+  a.piv_cols = piv_cols;
+  a.max_rank = max_rank;
+  a.A = A;
+  a.a_off = a_off;
+  a.acols = acols;
+  a.a_len = a_len;
+  a.pinv = pinv;
+  a.flags = ctx->flags;
+  hipError_t e = bem::launch_pivot_inverse(is_complex != 0, a, static_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return hip_fail(ctx, e, "pivot inverse launch");
+  return BEM_OK;
+}
+
 int bem_eval_entries(bem_ctx *ctx, const bem_mesh *mesh, const bem_op *op, int64_t n,
                      const int32_t *rows, const int32_t *cols, void *out, void *stream) {
   if (!ctx) return BEM_EINVAL;
@@ -417,6 +451,161 @@ int bem_eval_entries(bem_ctx *ctx, const bem_mesh *mesh, const bem_op *op, int64
   a.flags = ctx->flags;
   e = bem::launch_entries(op->kernel, op->layer, op->precision == BEM_MIXED, a, s);
   if (e != hipSuccess) return hip_fail(ctx, e, "entry kernel launch");
+  return BEM_OK;
+}
+
+int bem_gemv_grouped(bem_ctx *ctx, int32_t is_complex, int32_t trans, int32_t ngroups,
+                     const int32_t *grp_ptr, const int32_t *out_ptr, const int32_t *out_idx,
+                     int64_t out_len, int32_t nblocks, const int32_t *in_ptr,
+                     const int32_t *in_idx, int64_t in_len, const int64_t *a_off, const void *A,
+                     int64_t a_len, const void *x, int64_t x_len, void *y, int64_t y_len,
+                     void *stream) {
+  if (!ctx) return BEM_EINVAL;
+  if (ngroups < 0 || nblocks < 0 || out_len < 0 || in_len < 0 || a_len < 0 || x_len < 0 ||
+      y_len < 0)
+    return fail(ctx, BEM_EINVAL, "negative size");
+  if (ngroups == 0) return BEM_OK;
+  if (!grp_ptr || !out_ptr || (out_len > 0 && !out_idx) || (nblocks > 0 && (!in_ptr || !a_off)) ||
+      (in_len > 0 && !in_idx) || (a_len > 0 && !A) || (x_len > 0 && !x) || (y_len > 0 && !y))
+    return fail(ctx, BEM_EINVAL, "NULL array");
+  DeviceGuard g(ctx->device);
+  bem::GemvArgs a{};
+  a.ngroups = ngroups;
+  a.nblocks = nblocks;
+  a.grp_ptr = grp_ptr;
+  a.out_ptr = out_ptr;
+  a.out_idx = out_idx;
+  a.out_len = out_len;
+  a.in_ptr = in_ptr;
+  a.in_idx = in_idx;
+  a.in_len = in_len;
+  a.a_off = a_off;
+  a.A = A;
+  a.a_len = a_len;
+  a.x = x;
+  a.x_len = x_len;
+  a.y = y;
+  a.y_len = y_len;
+  a.flags = ctx->flags;
+  hipError_t e = bem::launch_gemv(is_complex != 0, trans != 0, a, static_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return hip_fail(ctx, e, "gemv kernel launch");
+  return BEM_OK;
+}
+
+int bem_vec_dot(bem_ctx *ctx, int32_t is_complex, int32_t conj, int64_t n, const void *x,
+                const void *y, double *out, void *stream) {
+  if (!ctx) return BEM_EINVAL;
+  if (n < 0 || !out || (n > 0 && (!x || !y))) return fail(ctx, BEM_EINVAL, "bad size or NULL array");
+  DeviceGuard g(ctx->device);
+  hipError_t e = bem::launch_dot(is_complex != 0, conj != 0, n, static_cast<const double *>(x),
+                                 static_cast<const double *>(y), ctx->dot_part, out,
+                                 static_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return hip_fail(ctx, e, "dot kernel launch");
+  return BEM_OK;
+}
+
+int bem_vec_axpby(bem_ctx *ctx, int32_t is_complex, int64_t n, double ar, double ai,
+                  const void *x, double br, double bi, void *y, void *stream) {
+  if (!ctx) return BEM_EINVAL;
+  if (n < 0 || (n > 0 && (!x || !y))) return fail(ctx, BEM_EINVAL, "bad size or NULL array");
+  DeviceGuard g(ctx->device);
+  hipError_t e = bem::launch_axpby(is_complex != 0, n, ar, ai, static_cast<const double *>(x), br,
+                                   bi, static_cast<double *>(y), static_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return hip_fail(ctx, e, "axpby kernel launch");
+  return BEM_OK;
+}
+
+int bem_mass_apply(bem_ctx *ctx, const bem_mesh *mesh, int32_t is_complex, double cr, double ci,
+                   const void *x, void *y, void *stream) {
+  if (!ctx) return BEM_EINVAL;
+  int rc;
+  if ((rc = check_mesh(ctx, mesh))) return rc;
+  if (mesh->nt == 0) return BEM_OK;
+  if (!x || !y) return fail(ctx, BEM_EINVAL, "NULL array");
+  DeviceGuard g(ctx->device);
+  int64_t ldg;
+  if ((rc = ensure_geo(ctx, mesh->nt, &ldg))) return rc;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  hipError_t e = bem::launch_geometry(*mesh, ctx->geo, ldg, ctx->flags, s);
+  if (e == hipSuccess)
+    e = bem::launch_mass(is_complex != 0, mesh->nt, ctx->geo, ldg, cr, ci,
+                         static_cast<const double *>(x), static_cast<double *>(y), s);
+  if (e != hipSuccess) return hip_fail(ctx, e, "mass kernel launch");
+  return BEM_OK;
+}
+
+int bem_p1_pairs(bem_ctx *ctx, const bem_mesh *mesh, const bem_op *op, int64_t n,
+                 const int32_t *rows, const int32_t *cols, void *out, void *stream) {
+  if (!ctx) return BEM_EINVAL;
+  int rc;
+  if ((rc = check_mesh(ctx, mesh)) || (rc = check_op(ctx, op))) return rc;
+  if (op->precision != BEM_PLAIN_FP64)
+    return fail(ctx, BEM_EUNSUPPORTED, "piecewise-linear pairs are plain FP64");
+  if (n < 0) return fail(ctx, BEM_EINVAL, "n < 0");
+  if (n == 0) return BEM_OK;
+  if (!rows || !cols || !out) return fail(ctx, BEM_EINVAL, "rows / cols / out is NULL");
+  if (mesh->nt == 0) return fail(ctx, BEM_EINVAL, "pairs requested on an empty mesh");
+  DeviceGuard g(ctx->device);
+  int64_t ldg;
+  const bem::DevRules *rules;
+  if ((rc = ensure_geo(ctx, mesh->nt, &ldg)) || (rc = get_rules(ctx, op, &rules))) return rc;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  hipError_t e = bem::launch_geometry(*mesh, ctx->geo, ldg, ctx->flags, s);
+  if (e != hipSuccess) return hip_fail(ctx, e, "geometry kernel launch");
+  bem::P1Args a{};
+  a.v = mesh->v;
+  a.tri = mesh->tri;
+  a.nv = mesh->nv;
+  a.nt = mesh->nt;
+  a.geo = ctx->geo;
+  a.ldg = ldg;
+  a.n = n;
+  a.rows = rows;
+  a.cols = cols;
+  a.out = out;
+  a.rule = rules->tri;
+  a.nq = rules->nq;
+  for (int c = 0; c < 4; ++c) a.ss.eta[c] = rules->ss[c], a.ss.np[c] = rules->np[c];
+  a.ss.xi = rules->xi;
+  a.ss.q = rules->nxi;
+  a.kappa = op->kernel == BEM_HELMHOLTZ ? op->kappa : 0.0;
+  a.flags = ctx->flags;
+  e = bem::launch_p1_pairs(op->kernel, op->layer, a, s);
+  if (e != hipSuccess) return hip_fail(ctx, e, "P1 pair kernel launch");
+  return BEM_OK;
+}
+
+int bem_p1_gather(bem_ctx *ctx, int32_t is_complex, int32_t nrv, const int32_t *rs_ptr,
+                  const int32_t *rs_tri, const int32_t *rs_loc, int64_t rs_len, int32_t ncv,
+                  const int32_t *cs_ptr, const int32_t *cs_tri, const int32_t *cs_loc,
+                  int64_t cs_len, int32_t ntr, int32_t ntc, const void *local, void *out,
+                  void *stream) {
+  if (!ctx) return BEM_EINVAL;
+  if (nrv < 0 || ncv < 0 || ntr < 0 || ntc < 0 || rs_len < 0 || cs_len < 0)
+    return fail(ctx, BEM_EINVAL, "negative size");
+  if ((int64_t)nrv * ncv == 0) return BEM_OK;
+  if (!rs_ptr || !cs_ptr || (rs_len > 0 && (!rs_tri || !rs_loc)) ||
+      (cs_len > 0 && (!cs_tri || !cs_loc)) || !out || ((int64_t)ntr * ntc > 0 && !local))
+    return fail(ctx, BEM_EINVAL, "NULL array");
+  DeviceGuard g(ctx->device);
+  bem::P1GatherArgs a{};
+  a.nrv = nrv;
+  a.ncv = ncv;
+  a.ntr = ntr;
+  a.ntc = ntc;
+  a.rs_ptr = rs_ptr;
+  a.rs_tri = rs_tri;
+  a.rs_loc = rs_loc;
+  a.rs_len = rs_len;
+  a.cs_ptr = cs_ptr;
+  a.cs_tri = cs_tri;
+  a.cs_loc = cs_loc;
+  a.cs_len = cs_len;
+  a.local = local;
+  a.out = out;
+  a.flags = ctx->flags;
+  hipError_t e = bem::launch_p1_gather(is_complex != 0, a, static_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return hip_fail(ctx, e, "P1 gather launch");
   return BEM_OK;
 }
 

@@ -188,6 +188,7 @@ int aca_one(int n, int m, const T *A, double eps, int max_rank, int32_t *prow, i
   const int kmax = std::min(max_rank, std::min(n, m));
   const int k = aca_steps_t(n, m, R.data(), col.data(), row.data(), eps, kmax, prow, pcol);
   // inverse of the pivot block A[rows, cols]
+  if (!pinv) return k;  // pivots only (the inverse is formed on the device)
   std::vector<T> blk((size_t)k * k), inv;
   for (int c = 0; c < k; ++c)
     for (int r = 0; r < k; ++r) blk[r + (size_t)k * c] = A[prow[r] + (size_t)n * pcol[c]];
@@ -238,7 +239,7 @@ int bem_aca(int32_t nmat, const int64_t *a_off, const int32_t *nrows, int32_t nc
             int32_t is_complex, const double *A, double eps, int32_t max_rank, int32_t *rank,
             int32_t *piv_rows, int32_t *piv_cols, double *pinv) {
   if (nmat < 0 || ncols < 0 || max_rank < 1 || !(eps >= 0) ||
-      (nmat > 0 && (!a_off || !nrows || !A || !rank || !piv_rows || !piv_cols || !pinv)))
+      (nmat > 0 && (!a_off || !nrows || !A || !rank || !piv_rows || !piv_cols)))
     return BEM_EINVAL;
   for (int32_t t = 0; t < nmat; ++t)
     if (nrows[t] < 0 || a_off[t] < 0) return BEM_EINVAL;
@@ -251,11 +252,11 @@ int bem_aca(int32_t nmat, const int64_t *a_off, const int32_t *nrows, int32_t nc
       k = aca_one<cplx>(nrows[t], ncols, reinterpret_cast<const cplx *>(A) + a_off[t], eps,
                         max_rank, piv_rows + (size_t)t * max_rank,
                         piv_cols + (size_t)t * max_rank,
-                        reinterpret_cast<cplx *>(pinv) + t * kk);
+                        pinv ? reinterpret_cast<cplx *>(pinv) + t * kk : nullptr);
     } else {
       k = aca_one<double>(nrows[t], ncols, A + a_off[t], eps, max_rank,
                           piv_rows + (size_t)t * max_rank, piv_cols + (size_t)t * max_rank,
-                          pinv + t * kk);
+                          pinv ? pinv + t * kk : nullptr);
     }
     if (k < 0) {
 #pragma omp critical

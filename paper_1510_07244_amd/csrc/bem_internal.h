@@ -153,6 +153,18 @@ struct ContractArgs {
   unsigned *flags;
 };
 
+struct PivInvArgs {
+  int32_t nmat;
+  const int32_t *nrows, *rank, *piv_rows, *piv_cols;
+  int32_t max_rank;
+  const void *A;
+  const int64_t *a_off;
+  int32_t acols;
+  int64_t a_len;
+  double *pinv;
+  unsigned *flags;
+};
+
 // Arguments of the persistent batched block kernel: one BlockArgs per batch
 // entry (all with the same rule and sub-tile shape) and a queue of sub-tiles.
 struct PersistentArgs {
@@ -163,6 +175,60 @@ struct PersistentArgs {
   int32_t *counter;          // device queue head, 0 at launch
   int32_t grid;              // workgroups
 };
+
+// Grouped gathered matrix-vector products of the H^2 matrix (bem_h2mv.hip).
+struct GemvArgs {
+  int32_t ngroups, nblocks;
+  const int32_t *grp_ptr;            // [ngroups + 1] blocks of each group
+  const int32_t *out_ptr, *out_idx;  // [ngroups + 1], output indices into y
+  int64_t out_len;                   // length of out_idx
+  const int32_t *in_ptr, *in_idx;    // [nblocks + 1], input indices into x
+  int64_t in_len;                    // length of in_idx
+  const int64_t *a_off;              // [nblocks] matrix offsets (entries)
+  const void *A;
+  int64_t a_len;
+  const void *x;
+  int64_t x_len;
+  void *y;
+  int64_t y_len;
+  unsigned *flags;
+};
+hipError_t launch_gemv(bool cplx, bool trans, const GemvArgs &a, hipStream_t s);
+size_t dot_scratch_doubles();
+hipError_t launch_dot(bool cplx, bool conj, int64_t n, const double *x, const double *y,
+                      double *part, double *out, hipStream_t s);
+hipError_t launch_axpby(bool cplx, int64_t n, double ar, double ai, const double *x, double br,
+                        double bi, double *y, hipStream_t s);
+hipError_t launch_mass(bool cplx, int32_t nt, const double *geo, int64_t ldg, double cr, double ci,
+                       const double *x, double *y, hipStream_t s);
+
+// Piecewise-linear bases (bem_p1.hip).
+struct P1Args {
+  const double *v;
+  const int32_t *tri;
+  int32_t nv, nt;
+  const double *geo;
+  int64_t ldg;
+  int64_t n;
+  const int32_t *rows, *cols;
+  void *out;  // [n][9] entries
+  const double *rule;
+  int32_t nq;
+  SSArgs ss;
+  double kappa;
+  unsigned *flags;
+};
+struct P1GatherArgs {
+  int32_t nrv, ncv, ntr, ntc;
+  const int32_t *rs_ptr, *rs_tri, *rs_loc;
+  const int32_t *cs_ptr, *cs_tri, *cs_loc;
+  int64_t rs_len, cs_len;
+  const void *local;
+  void *out;
+  unsigned *flags;
+};
+hipError_t launch_p1_pairs(int kernel, int layer, const P1Args &a, hipStream_t s);
+hipError_t launch_p1_gather(bool cplx, const P1GatherArgs &a, hipStream_t s);
 
 // ----------------------------------------------------------- learned form
 constexpr int kSelQ = 6;  // selector outputs: predicted log10 error at orders 1 .. 6
@@ -198,6 +264,7 @@ struct SelectArgs {
   const double *tin_c, *tin_n;     // per-triangle inputs [3][ldt] (launch_tri_inputs)
   const float *tin_f;              // d, area, aspect [3][ldt]
   int64_t ldt;
+  const float *range;              // device [16]: training minima, maxima of the inputs (or null)
   int32_t layer, q_plain, q_min;
   float margin, log_tol;
   double kappa;
@@ -241,6 +308,7 @@ hipError_t launch_reset_counter(int32_t *counter, hipStream_t s);
 
 hipError_t launch_green(int kernel, int side, const GreenArgs &a, int grid_y, hipStream_t s);
 hipError_t launch_contract(bool cplx, const ContractArgs &a, int grid_y, hipStream_t s);
+hipError_t launch_pivot_inverse(bool cplx, const PivInvArgs &a, hipStream_t s);
 
 // launchers (bem_kernels.hip); return a hipError_t
 hipError_t launch_geometry(const bem_mesh &m, double *geo, int64_t ldg, unsigned *flags,
@@ -300,6 +368,7 @@ struct bem_ctx {
   std::string err;
   unsigned *flags = nullptr;      // device, 1 word
   double *geo = nullptr;          // device scratch
+  double *dot_part = nullptr;     // device: partial sums of bem_vec_dot
   size_t geo_cap = 0;             // doubles
   float *mlp_scratch = nullptr;   // device: per-workgroup gradient partial sums
   size_t mlp_cap = 0;             // floats

@@ -5,6 +5,8 @@
 
 #include <cmath>
 #include <cstdio>
+#include <cstring>
+#include <vector>
 
 #include "bem_internal.h"
 
@@ -174,8 +176,9 @@ int bem_selector_samples(bem_ctx *ctx, const bem_mesh *mesh, const bem_op *op, i
 }
 
 int bem_select_orders(bem_ctx *ctx, const bem_mesh *mesh, const bem_op *op,
-                      const bem_blocks *blocks, const float *params, double tol, double margin,
-                      int32_t q_min, int8_t *orders, int64_t orders_len, void *stream) {
+                      const bem_blocks *blocks, const float *params, const float *range,
+                      double tol, double margin, int32_t q_min, int8_t *orders,
+                      int64_t orders_len, void *stream) {
   if (!ctx) return BEM_EINVAL;
   int rc;
   if ((rc = block_list_args(ctx, mesh, op, blocks, orders, orders_len))) return rc;
@@ -225,6 +228,7 @@ int bem_select_orders(bem_ctx *ctx, const bem_mesh *mesh, const bem_op *op,
   a.tin_n = tin_n;
   a.tin_f = tin_f;
   a.ldt = ldt;
+  a.range = range;
   a.layer = op->layer;
   a.q_plain = op->q_regular;
   a.q_min = q_min;
@@ -294,6 +298,83 @@ int bem_assemble_nearfield_learned(bem_ctx *ctx, const bem_mesh *mesh, const bem
   a.flags = ctx->flags;
   e = launch_blocks_learned(op->kernel, op->layer, a, o, lds, s);
   if (e != hipSuccess) return hip_fail(ctx, e, "learned block kernel launch");
+  return BEM_OK;
+}
+
+// Network file: 8-byte tag, int32 n_out, step, contents (1 Adam moments, 2
+// training range), reserved, then FP32 parameters [, m, v] [, range].
+namespace {
+constexpr char kMlpTag[8] = {'B', 'E', 'M', 'M', 'L', 'P', '0', '1'};
+enum { MLP_MOMENTS = 1, MLP_RANGE = 2 };
+}  // namespace
+
+int bem_mlp_save(bem_ctx *ctx, const char *path, int32_t n_out, const float *params,
+                 const float *m, const float *v, const float *range, int32_t step, void *stream) {
+  if (!ctx) return BEM_EINVAL;
+  const int np = mlp_params(n_out);
+  if (np < 0) return fail(ctx, BEM_EINVAL, "n_out must be in [1, 16]");
+  if (!path || !params || (!m) != (!v) || step < 0)
+    return fail(ctx, BEM_EINVAL, "path / params NULL, m and v not both given, or step < 0");
+  DeviceGuard g(ctx->device);
+  hipError_t e = hipStreamSynchronize(static_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return hip_fail(ctx, e, "hipStreamSynchronize");
+  const int32_t contents = (m ? MLP_MOMENTS : 0) | (range ? MLP_RANGE : 0);
+  std::vector<float> h((size_t)np * (m ? 3 : 1) + (range ? 16 : 0));
+  e = hipMemcpy(h.data(), params, np * sizeof(float), hipMemcpyDeviceToHost);
+  if (e == hipSuccess && m) e = hipMemcpy(h.data() + np, m, np * sizeof(float), hipMemcpyDeviceToHost);
+  if (e == hipSuccess && m) e = hipMemcpy(h.data() + 2 * np, v, np * sizeof(float), hipMemcpyDeviceToHost);
+  if (e == hipSuccess && range)
+    e = hipMemcpy(h.data() + (size_t)np * (m ? 3 : 1), range, 16 * sizeof(float), hipMemcpyDeviceToHost);
+  if (e != hipSuccess) return hip_fail(ctx, e, "reading the network");
+  FILE *f = std::fopen(path, "wb");
+  if (!f) return fail(ctx, BEM_EINVAL, std::string("cannot open ") + path + " for writing");
+  const int32_t head[4] = {n_out, step, contents, 0};
+  bool ok = std::fwrite(kMlpTag, 1, 8, f) == 8 && std::fwrite(head, sizeof head, 1, f) == 1 &&
+            std::fwrite(h.data(), sizeof(float), h.size(), f) == h.size();
+  ok = (std::fclose(f) == 0) && ok;
+  if (!ok) return fail(ctx, BEM_EINVAL, std::string("writing ") + path + " failed");
+  return BEM_OK;
+}
+
+int bem_mlp_load(bem_ctx *ctx, const char *path, int32_t n_out, float *params, float *m, float *v,
+                 float *range, int32_t *step, void *stream) {
+  if (!ctx) return BEM_EINVAL;
+  const int np = mlp_params(n_out);
+  if (np < 0) return fail(ctx, BEM_EINVAL, "n_out must be in [1, 16]");
+  if (!path || !params || (!m) != (!v))
+    return fail(ctx, BEM_EINVAL, "path / params NULL, or m and v not both given");
+  FILE *f = std::fopen(path, "rb");
+  if (!f) return fail(ctx, BEM_EINVAL, std::string("cannot open ") + path);
+  char tag[8];
+  int32_t head[4];
+  bool ok = std::fread(tag, 1, 8, f) == 8 && std::memcmp(tag, kMlpTag, 8) == 0 &&
+            std::fread(head, sizeof head, 1, f) == 1;
+  const int32_t contents = ok ? head[2] : 0;
+  ok = ok && head[0] == n_out && head[1] >= 0 && (contents & ~(MLP_MOMENTS | MLP_RANGE)) == 0;
+  ok = ok && (!m || (contents & MLP_MOMENTS)) && (!range || (contents & MLP_RANGE));
+  std::vector<float> h;
+  if (ok) {
+    h.resize((size_t)np * ((contents & MLP_MOMENTS) ? 3 : 1) + ((contents & MLP_RANGE) ? 16 : 0));
+    ok = std::fread(h.data(), sizeof(float), h.size(), f) == h.size() &&
+         std::fgetc(f) == EOF;  // nothing after the declared contents
+  }
+  std::fclose(f);
+  if (!ok)
+    return fail(ctx, BEM_EINVAL, std::string(path) + ": not a network file of this n_out, "
+                                 "truncated, or without the requested moments / range");
+  DeviceGuard g(ctx->device);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  hipError_t e = hipMemcpyAsync(params, h.data(), np * sizeof(float), hipMemcpyHostToDevice, s);
+  if (e == hipSuccess && m)
+    e = hipMemcpyAsync(m, h.data() + np, np * sizeof(float), hipMemcpyHostToDevice, s);
+  if (e == hipSuccess && m)
+    e = hipMemcpyAsync(v, h.data() + 2 * (size_t)np, np * sizeof(float), hipMemcpyHostToDevice, s);
+  if (e == hipSuccess && range)
+    e = hipMemcpyAsync(range, h.data() + (size_t)np * ((contents & MLP_MOMENTS) ? 3 : 1),
+                       16 * sizeof(float), hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);  // h is released on return
+  if (e != hipSuccess) return hip_fail(ctx, e, "writing the network to the device");
+  if (step) *step = head[1];
   return BEM_OK;
 }
 

@@ -569,9 +569,11 @@ __global__ __launch_bounds__(kThreads, 2) void k_select_orders(const SelectArgs 
   __shared__ float sd[2][3][kSelTile];  // d, area, aspect
   __shared__ int sv[2][3][kSelTile], sbad;
   __shared__ h8 srot[8 * 64];  // the rotated output layer (slots kRotSlot ..)
+  __shared__ float srange[16];  // training range of the inputs: minima, maxima
   const int tid = threadIdx.x;
   Net16 N;
   load_net(reinterpret_cast<const h8 *>(a.net), &N, bias);
+  if (tid < 16) srange[tid] = a.range ? a.range[tid] : (tid < 8 ? -INFINITY : INFINITY);
   for (int k = tid; k < 8 * 64; k += kThreads) srot[k] = reinterpret_cast<const h8 *>(a.net)[kRotSlot * 64 + k];
   const int l = tid & 63, g = l >> 4, wave = tid / kWave;
   const float kappa = (float)a.kappa;
@@ -626,6 +628,7 @@ __global__ __launch_bounds__(kThreads, 2) void k_select_orders(const SelectArgs 
                                             sv[1][1][cl], sv[1][2][cl]);
         // standardised inputs of this lane's entry, packed as four half2 words
         uint32_t w[4] = {0, 0, 0, 0};
+        bool outside = false;
         if (live && cls == 0) {
           TriIn ti, tj;
           for (int m = 0; m < 3; ++m) {
@@ -636,6 +639,9 @@ __global__ __launch_bounds__(kThreads, 2) void k_select_orders(const SelectArgs 
           tj.d = sd[1][0][cl], tj.area = sd[1][1][cl], tj.aspect = sd[1][2][cl];
           float f[8];
           pair_inputs(ti, tj, a.layer, kappa, f);
+          // an input outside the training range (or not a number) keeps the
+          // plain order: the network is not trusted where it was not trained
+          for (int k = 0; k < 8; ++k) outside = outside || !(f[k] >= srange[k] && f[k] <= srange[8 + k]);
           const h8 hb = standardise(f, bias);
           for (int k = 0; k < 4; ++k) {
             const _Float16 lo = hb[2 * k], hi = hb[2 * k + 1];
@@ -681,6 +687,7 @@ __global__ __launch_bounds__(kThreads, 2) void k_select_orders(const SelectArgs 
             q = run ? t : q;
           }
         }
+        if (outside) q = a.q_plain;
         if (live) a.orders[off + (r0 + rl) + nr * (c0 + cl)] = (int8_t)(cls ? 0 : q);
       }
     }

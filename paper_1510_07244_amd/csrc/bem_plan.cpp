@@ -605,6 +605,20 @@ int bem_run_batched(bem_plan *plan, void *stream) {
 
 int64_t bem_plan_tiles(const bem_plan *plan) { return plan ? plan->ntiles : 0; }
 
+int bem_autotune(bem_ctx *ctx, const bem_op *op, int32_t nbatch, const bem_batch *batches,
+                 bem_tune *tune, const char *cache_path, void *stream) {
+  if (!ctx) return BEM_EINVAL;
+  if (!tune) return fail(ctx, BEM_EINVAL, "tune is NULL");
+  bem_tune t = *tune;
+  t.autotune = 1;
+  bem_plan *plan = nullptr;
+  const int rc = bem_plan_batched(ctx, op, nbatch, batches, &t, cache_path, stream, &plan);
+  if (rc) return rc;
+  bem_plan_destroy(plan);
+  *tune = t;
+  return BEM_OK;
+}
+
 void bem_plan_destroy(bem_plan *plan) {
   if (!plan) return;
   if (plan->ctx) plan->ctx->plans.erase(plan);

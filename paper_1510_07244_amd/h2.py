@@ -10,7 +10,7 @@ with V_t the nested row basis (side-0 Green matrices) and W_s the column
 basis: W = V for the single layer, side-1 Green matrices for the double layer.
 Nested bases store for each cluster the matrix V^_c whose rows belong to the
 triangles ``rows[c]`` (the cluster for a leaf, t^ = union of the sons' pivots
-for a father); the full basis is V_t = diag(V_t1, V_t2) V^_t.
+for a father); the full basis V_t = diag(V_t1, V_t2) V^_t is never formed.
 """
 import time
 
@@ -94,11 +94,22 @@ class H2Setup:
                        kappa=self.kappa)
 
     # ----------------------------------------------------------- bases
+    def _host_copy(self, A):
+        """A device tensor copied into a pinned host buffer kept across levels
+        (a numpy view, valid until the next call)."""
+        import torch
+        nbytes = A.numel() * A.element_size()
+        if getattr(self, "_pin", None) is None or self._pin.numel() < nbytes:
+            self._pin = torch.empty(max(nbytes, 1 << 20), dtype=torch.uint8, pin_memory=True)
+        h = self._pin[:nbytes].view(A.dtype)
+        h.copy_(A)
+        return h.numpy()
+
     def basis(self, side):
         """Construct the nested cluster basis of one side, level by level."""
         return self.bases((side,))[0]
 
-    def bases(self, sides=(0, 1), rank_caps=None):
+    def bases(self, sides=(0, 1), rank_caps=None, device_inverse=True):
         """Construct the nested cluster bases of several sides together, level
         by level: per level one Green-matrix launch per side into one buffer,
         one copy to the host, one pivot search over the clusters of every side
@@ -110,12 +121,21 @@ class H2Setup:
         largest cap of its clusters instead of min(rows, 2m), which sizes the
         pivot and inverse buffers; a level where some cluster reaches that
         bound is searched again without it, so the bases are the ones the
-        plain search gives.  self.cap_stats counts levels and fallbacks."""
+        plain search gives.  self.cap_stats counts levels and fallbacks.
+
+        device_inverse: the host search returns pivots only and the pivot
+        blocks are inverted on the device (bem_pivot_inverse), so no
+        inverse is formed on or copied from the host; otherwise bem_aca
+        forms them on the host.  self.bases_time splits the wall time into
+        device work (Green matrices, and the previous level's inverses and
+        contractions, waited for at the copy), the copy to the host and the
+        host pivot search."""
         import torch
         ct, m = self.ct, self.m
         Bs = [ClusterBasis(side, ct.n) for side in sides]
         op = self.op(SLP)
         self.cap_stats = {"levels": 0, "fallbacks": 0}
+        self.bases_time = {"device": 0.0, "copy": 0.0, "pivot_search": 0.0}
         for h in range(int(self.height.max()) + 1):
             cls = np.nonzero(self.height == h)[0]
             lvs, nrows_all = [], []
@@ -157,25 +177,34 @@ class H2Setup:
                 self.ctx.green_matrix(self.mesh, op, B.side, lv.row_ptr, lv.row_idx, lv.z, lv.zn,
                                       lv.zw, lv.delta, lv.a_off, lv.A, max_rows=lv.max_rows)
                 base += size
+            t0 = time.perf_counter()
             self.ctx.check()
-            A_h = A_all.cpu().numpy()
+            t1 = time.perf_counter()
+            A_h = self._host_copy(A_all)
             Af = A_h.view(np.float64) if self.cplx else A_h
+            t2 = time.perf_counter()
             max_rank = int(min(nrows_all.max(), 2 * m))
+            host_inv = not device_inverse
             if rank_caps is not None:
                 cap = max(int(np.max(rank_caps[si][cls])) for si in range(len(Bs)))
                 bound = max(1, min(max_rank, cap))
                 rank_all, prow, pcol, pinv = aca(Af, a_all, nrows_all, 2 * m, self.eps, bound,
-                                                 is_complex=self.cplx)
+                                                 is_complex=self.cplx, inverse=host_inv)
                 self.cap_stats["levels"] += 1
                 if bound < max_rank and int(rank_all.max()) >= bound:  # the bound may have cut
                     self.cap_stats["fallbacks"] += 1
                     rank_all, prow, pcol, pinv = aca(Af, a_all, nrows_all, 2 * m, self.eps,
-                                                     max_rank, is_complex=self.cplx)
+                                                     max_rank, is_complex=self.cplx,
+                                                     inverse=host_inv)
                 else:
                     max_rank = bound
             else:
                 rank_all, prow, pcol, pinv = aca(Af, a_all, nrows_all, 2 * m, self.eps, max_rank,
-                                                 is_complex=self.cplx)
+                                                 is_complex=self.cplx, inverse=host_inv)
+            t3 = time.perf_counter()
+            self.bases_time["device"] += t1 - t0
+            self.bases_time["copy"] += t2 - t1
+            self.bases_time["pivot_search"] += t3 - t2
             for si, (B, lv) in enumerate(zip(Bs, lvs)):
                 sl = slice(si * cls.size, (si + 1) * cls.size)
                 nrows, rank = lv.nrows_h, rank_all[sl]
@@ -187,12 +216,19 @@ class H2Setup:
                 v_off = np.zeros(cls.size, dtype=np.int64)
                 v_off[1:] = np.cumsum(nrows.astype(np.int64) * rank)[:-1]
                 lv.v_off_h = v_off
-                lv.rank_h, lv.pcol_h, lv.pinv_h = rank, pcol[sl], pinv[sl]
+                lv.rank_h, lv.pcol_h, lv.prow_h = rank, pcol[sl], prow[sl]
                 lv.nrows = _dev(nrows, torch.int32)
                 lv.rank = _dev(rank, torch.int32)
                 lv.piv_cols = _dev(pcol[sl], torch.int32)
-                lv.pinv = _dev(pinv[sl], torch.float64)
                 lv.max_rank = max_rank
+                if device_inverse:
+                    lv.piv_rows = _dev(prow[sl], torch.int32)
+                    lv.pinv = torch.empty((cls.size, max_rank * max_rank * (2 if self.cplx else 1)),
+                                          dtype=torch.float64, device="cuda")
+                    self.ctx.pivot_inverse(self.cplx, lv.nrows, lv.rank, max_rank, lv.piv_rows,
+                                           lv.piv_cols, lv.A, lv.a_off, 2 * m, lv.pinv)
+                else:
+                    lv.pinv = _dev(pinv[sl], torch.float64)
                 lv.v_off = _dev(v_off, torch.int64)
                 lv.V = torch.empty(int((nrows.astype(np.int64) * rank).sum()), dtype=self.adtype,
                                    device="cuda")
@@ -200,7 +236,9 @@ class H2Setup:
                                         lv.pinv, lv.A, lv.a_off, 2 * m, lv.V, lv.v_off,
                                         max_rows=lv.max_rows)
                 B.levels.append(lv)
+        t0 = time.perf_counter()
         self.ctx.check()
+        self.bases_time["device"] += time.perf_counter() - t0
         for B in Bs:
             B.replay = None  # built by the first basis_replay
         return Bs
@@ -225,14 +263,17 @@ class H2Setup:
         K = max(lv.max_rank for lv in Ls)
         f = 2 if self.cplx else 1
         pcol = np.zeros((cls.size, K), dtype=np.int32)
-        pinv = np.zeros((cls.size, K * K * f), dtype=np.float64)
+        pinv_d = torch.zeros((cls.size, K * K * f), dtype=torch.float64, device="cuda")
         i = 0
         for lv in Ls:
-            for p in range(lv.cls.size):
+            n_l = lv.cls.size
+            for p in range(n_l):
                 k = int(lv.rank_h[p])
-                pcol[i, :k] = lv.pcol_h[p, :k]
-                pinv[i, :k * k * f] = lv.pinv_h[p, :k * k * f]
-                i += 1
+                pcol[i + p, :k] = lv.pcol_h[p, :k]
+            # each inverse occupies the first k^2 entries of its slot
+            w = lv.max_rank * lv.max_rank * f
+            pinv_d[i:i + n_l, :w].copy_(lv.pinv.view(n_l, -1)[:, :w])
+            i += n_l
         rp.ncl = int(cls.size)
         rp.row_ptr = _dev(ptr, torch.int32)
         rp.row_idx = _dev(np.concatenate([lv.row_idx_h for lv in Ls]), torch.int32)
@@ -240,7 +281,7 @@ class H2Setup:
         rp.zw, rp.delta = _dev(self.zw[cls], torch.float64), _dev(self.delta[cls], torch.float64)
         rp.a_off, rp.v_off = _dev(a_off, torch.int64), _dev(v_off, torch.int64)
         rp.nrows, rp.rank = _dev(nrows, torch.int32), _dev(rank, torch.int32)
-        rp.piv_cols, rp.pinv, rp.max_rank = _dev(pcol, torch.int32), _dev(pinv, torch.float64), K
+        rp.piv_cols, rp.pinv, rp.max_rank = _dev(pcol, torch.int32), pinv_d, K
         rp.max_rows = int(nrows.max())
         rp.A = torch.empty(int((nrows * m2).sum()), dtype=self.adtype, device="cuda")
         rp.V = torch.empty(int((nrows * rank).sum()), dtype=self.adtype, device="cuda")
@@ -265,17 +306,6 @@ class H2Setup:
         self.ctx.basis_contract(self.cplx, rp.nrows, rp.rank, rp.max_rank, rp.piv_cols, rp.pinv,
                                 rp.A, rp.a_off, 2 * self.m, rp.V, rp.v_off, max_rows=rp.max_rows,
                                 stream=stream)
-
-    def full_basis(self, B, c):
-        """V_t (rows ordered like the cluster's triangles) as a host array."""
-        s = self.ct.sons[c]
-        if s[0] < 0:
-            return B.vhat(c)
-        V1, V2 = self.full_basis(B, s[0]), self.full_basis(B, s[1])
-        D = np.zeros((V1.shape[0] + V2.shape[0], V1.shape[1] + V2.shape[1]), dtype=V1.dtype)
-        D[:V1.shape[0], :V1.shape[1]] = V1
-        D[V1.shape[0]:, V1.shape[1]:] = V2
-        return D @ B.vhat(c)
 
     # ----------------------------------------------------------- blocks
     def near_blocks(self, mirror=False):

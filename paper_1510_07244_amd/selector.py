@@ -76,14 +76,18 @@ class Selector:
             p[o:o + n_o * n_i] = rng.uniform(-lim, lim, size=n_o * n_i)
             o += n_o * n_i + n_o  # weights, then zero biases
         self.params = torch.from_numpy(p).cuda()
+        self.range = None  # set with the standardisation
 
     def set_standardisation(self, X):
-        """mu, sigma of the inputs (sigma floored at 1e-3 for constant ones)."""
+        """mu, sigma of the inputs (sigma floored at 1e-3 for constant ones),
+        and the training range (per-input minimum and maximum) outside which
+        the order selection keeps the plain rule."""
         import torch
         mu = X.mean(dim=0)
         sd = X.std(dim=0).clamp_min(1e-3)
         self.params[0:8] = mu
         self.params[8:16] = sd
+        self.range = torch.cat([X.min(dim=0).values, X.max(dim=0).values]).contiguous()
         torch.cuda.synchronize()
 
     def fit(self, X, T, epochs=20, batch=4096, lr=2e-3, seed=0, stream=None):
@@ -112,7 +116,27 @@ class Selector:
                 step += 1
                 self.ctx.mlp_adam(P, grad, m, v, step, rate, stream=stream)
         per_epoch = losses.view(epochs, -1).mean(dim=1)
+        self.adam = (m, v, step)
         return per_epoch.cpu().numpy()
+
+    def save(self, path):
+        """bem_mlp_save: parameters, training range and (after fit) Adam's
+        moments and step count."""
+        m, v, step = getattr(self, "adam", (None, None, 0))
+        self.ctx.mlp_save(path, self.n_out, self.params, m, v, range=self.range, step=step)
+
+    def load(self, path, moments=False):
+        """bem_mlp_load into this selector (the training range is required;
+        moments=True also restores Adam's state)."""
+        import torch
+        self.range = torch.empty(16, dtype=torch.float32, device="cuda")
+        m = v = None
+        if moments:
+            m, v = torch.empty_like(self.params), torch.empty_like(self.params)
+        step = self.ctx.mlp_load(path, self.n_out, self.params, m, v, range=self.range)
+        if moments:
+            self.adam = (m, v, step)
+        return step
 
     def predict(self, X, fp16=True):
         import torch
@@ -120,11 +144,14 @@ class Selector:
         self.ctx.mlp_forward(self.n_out, self.params, X, y, fp16=fp16)
         return y
 
-    def orders(self, mesh, op, blocks, n_entries, tol, margin, q_min=2, stream=None):
-        """int8 order map of the entries of near-field blocks."""
+    def orders(self, mesh, op, blocks, n_entries, tol, margin, q_min=2, stream=None,
+               guard=True):
+        """int8 order map of the entries of near-field blocks (guard: pairs
+        outside the training range keep the plain order)."""
         import torch
         out = torch.zeros(n_entries, dtype=torch.int8, device="cuda")
-        self.ctx.select_orders(mesh, op, blocks, self.params, out, tol, margin, q_min, stream)
+        self.ctx.select_orders(mesh, op, blocks, self.params, out, tol, margin, q_min, stream,
+                               range=self.range if guard else None)
         return out
 
 

@@ -180,6 +180,31 @@ def test_autotune_and_cache(pk, ctx, batch, tmp_path):
     torch.cuda.synchronize()
 
 
+def test_autotune_entry_point_fills_the_cache(pk, ctx, batch, tmp_path):
+    # bem_autotune times the candidates and keeps no plan; a plan made with
+    # the same cache afterwards takes the tuned configuration without timing
+    import torch
+    op = pk.make_op(pk.LAPLACE, pk.SLP, q_regular=4, q_singular=4)
+    outs = [torch.zeros(e["total"], dtype=torch.float64, device="cuda") for e in batch]
+    cache = str(tmp_path / "tune.jsonl")
+    cfg = pk.autotune(ctx, op, [(e["mesh"], e["blocks"], o, e["coupling"])
+                                for e, o in zip(batch, outs)], cache=cache)
+    assert cfg["tuned_ms"] > 0 and cfg["grid"] > 0
+    assert len(open(cache).readlines()) == 1
+    plan, outs2 = _plan(pk, ctx, op, batch, autotune=True, cache=cache)
+    c2 = plan.config
+    assert c2["tuned_ms"] == 0.0
+    assert [c2[k] for k in ("grid", "tile_rows", "tile_cols", "x_chunk", "granularity")] == \
+        [cfg[k] for k in ("grid", "tile_rows", "tile_cols", "x_chunk", "granularity")]
+    plan.run()
+    ctx.check()
+    for e, o in zip(batch, outs2):
+        ref = _per_call(pk, ctx, op, e).cpu().numpy()
+        got = o.cpu().numpy()
+        assert np.abs(got - ref).max() <= 1e-13 * np.abs(ref).max()
+    plan.close()
+
+
 @pytest.mark.parametrize("granularity", [1, 2])
 def test_fixed_configuration_and_small_tiles(pk, ctx, batch, granularity):
     # a ragged sub-tile shape and a small grid still give the per-call bits,

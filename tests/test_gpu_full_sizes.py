@@ -15,6 +15,7 @@ import numpy as np
 import pytest
 
 import oracle
+from h2util import full_basis
 from bem_inputs import cube_surface, octahedron_sphere, sample_subset
 from oracle import htree
 
@@ -115,7 +116,7 @@ def test_helmholtz_h2_coupling_sphere32768(pk, ctx):
         t, s = h.far[k]
         kt, ks = V.piv[t].size, W.piv[s].size
         S = out[int(offs[k]):int(offs[k]) + kt * ks].cpu().numpy().reshape(ks, kt).T
-        approx = h.full_basis(V, t) @ S @ h.full_basis(W, s).T
+        approx = full_basis(h, V, t) @ S @ full_basis(h, W, s).T
         ref = oracle.block(m.v, m.tri, h.ct.idx(t), h.ct.idx(s), kernel=pk.HELMHOLTZ, kappa=8.0,
                            layer=pk.DLP, q_reg=5, q_sing=5)
         assert np.linalg.norm(approx - ref) <= 1e-6 * np.linalg.norm(ref)

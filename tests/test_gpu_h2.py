@@ -15,6 +15,7 @@ import numpy as np
 import pytest
 
 import oracle
+from h2util import full_basis
 from bem_inputs import octahedron_sphere, sample_subset
 from oracle import htree
 
@@ -126,7 +127,7 @@ def _h2_errors(pk, ctx, m, kernel, kappa, layer, nblocks, seed):
         t, s = h.far[k]
         kt, ks = V.piv[t].size, W.piv[s].size
         S = S_all[offs[k]:offs[k] + kt * ks].reshape(ks, kt).T
-        approx = h.full_basis(V, t) @ S @ h.full_basis(W, s).T
+        approx = full_basis(h, V, t) @ S @ full_basis(h, W, s).T
         ref = oracle.block(m.v, m.tri, h.ct.idx(t), h.ct.idx(s), kernel=kernel, kappa=kappa,
                            layer=layer, q_reg=4, q_sing=4)
         ref = ref if kernel else ref.real
@@ -140,7 +141,7 @@ def test_h2_sphere8192_laplace_accuracy(pk, ctx, layer):
     assert errs.max() <= 1e-6, errs.max()
     # the bases interpolate: R_t V_t = I on the pivots of a leaf
     leaf = next(c for c in range(h.ct.n) if h.ct.sons[c, 0] < 0)
-    Vt = h.full_basis(V, leaf)
+    Vt = full_basis(h, V, leaf)
     pos = [list(h.ct.idx(leaf)).index(p) for p in V.piv[leaf]]
     assert np.allclose(Vt[pos], np.eye(len(pos)), atol=1e-8)
 

@@ -16,6 +16,7 @@ import numpy as np
 import pytest
 
 from bem_inputs import octahedron_sphere
+from h2util import FullBases
 
 pytestmark = pytest.mark.gpu
 
@@ -56,6 +57,7 @@ def _far_rowsum(h, res, row_basis, col_basis):
     # y_t += V_t S_ts (W_s^T 1_s), with the full (expanded) nested bases
     y = np.zeros(h.tri.shape[0])
     vfull, wsum = {}, {}
+    Vf, Wf = FullBases(h, row_basis), FullBases(h, col_basis)
     o = 0
     for t, s in h.far:
         t, s = int(t), int(s)
@@ -63,9 +65,9 @@ def _far_rowsum(h, res, row_basis, col_basis):
         S = res[o:o + kt * ks].reshape(ks, kt).T
         o += kt * ks
         if t not in vfull:
-            vfull[t] = h.full_basis(row_basis, t)
+            vfull[t] = Vf(t)
         if s not in wsum:
-            wsum[s] = h.full_basis(col_basis, s).sum(axis=0)
+            wsum[s] = Wf(s).sum(axis=0)
         np.add.at(y, h.ct.idx(t), vfull[t] @ (S @ wsum[s]))
     return y
 

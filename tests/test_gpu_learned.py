@@ -273,3 +273,60 @@ def test_trained_selector_gain(pk, ctx):
             err = np.linalg.norm(got - ref) / np.linalg.norm(ref)
             assert err <= 1e-6, (layer, err)
     assert saved_points >= 0.2 * plain_points, (saved_points, plain_points)
+    # outside the training range (these Laplace samples all have kappa D = 0)
+    # the plain order is kept for every pair, whatever the network predicts
+    oph = pk.make_op(pk.HELMHOLTZ, pk.SLP, q_regular=4, q_singular=4, kappa=30.0)
+    guarded = sel.orders(mesh, oph, blocks, total, tol=1e-7, margin=0.5).cpu().numpy()
+    free = sel.orders(mesh, oph, blocks, total, tol=1e-7, margin=0.5, guard=False).cpu().numpy()
+    reg = guarded > 0
+    assert np.array_equal(reg, free > 0)
+    assert np.all(guarded[reg] == 4)
+    # on the mesh the network was trained on, the guard changes only the
+    # few pairs beyond the sampled extremes, and only by raising orders
+    opl = pk.make_op(pk.LAPLACE, pk.DLP, q_regular=4, q_singular=4)
+    a = sel.orders(mesh, opl, blocks, total, tol=1e-7, margin=0.5).cpu().numpy()
+    b = sel.orders(mesh, opl, blocks, total, tol=1e-7, margin=0.5, guard=False).cpu().numpy()
+    assert (a == b).mean() >= 0.99 and np.all(a >= b) and np.any(a[a > 0] < 4)
+
+
+def test_mlp_save_load_resumes_training_bitwise(pk, ctx, tmp_path):
+    """Training resumed from a saved file (parameters, Adam moments, step)
+    equals training that was never interrupted, bit for bit; a file without
+    moments refuses a request for them."""
+    import torch
+    rng = np.random.Generator(np.random.PCG64(17))
+    n_out, n = 6, 1000
+    X = torch.from_numpy(rng.standard_normal((n, 8)).astype(np.float32)).cuda()
+    T = torch.from_numpy(rng.standard_normal((n, n_out)).astype(np.float32)).cuda()
+    np_ = pk.mlp_params(n_out)
+    P0 = torch.from_numpy((0.1 * rng.standard_normal(np_)).astype(np.float32)).cuda()
+    P0[8:16] = 1.0
+    rg = torch.from_numpy(np.concatenate([-np.ones(8), np.ones(8)]).astype(np.float32)).cuda()
+
+    def steps(P, m, v, first, count):
+        g = torch.zeros_like(P)
+        for k in range(first, first + count):
+            ctx.mlp_grad(n_out, P, X, T, g)
+            ctx.mlp_adam(P, g, m, v, k, 1e-3)
+
+    P, m, v = P0.clone(), torch.zeros_like(P0), torch.zeros_like(P0)
+    steps(P, m, v, 1, 5)
+    path = str(tmp_path / "net.bin")
+    ctx.mlp_save(path, n_out, P, m, v, range=rg, step=5)
+    steps(P, m, v, 6, 5)  # uninterrupted
+    P2, m2, v2 = (torch.full_like(P0, float("nan")) for _ in range(3))
+    rg2 = torch.full_like(rg, float("nan"))
+    step = ctx.mlp_load(path, n_out, P2, m2, v2, range=rg2)
+    assert step == 5 and torch.equal(rg2, rg)
+    steps(P2, m2, v2, step + 1, 5)  # resumed
+    torch.cuda.synchronize()
+    for a, b in ((P, P2), (m, m2), (v, v2)):
+        assert np.array_equal(a.cpu().numpy().view(np.uint32), b.cpu().numpy().view(np.uint32))
+    bare = str(tmp_path / "bare.bin")
+    ctx.mlp_save(bare, n_out, P)
+    with pytest.raises(pk.BemError) as e:
+        ctx.mlp_load(bare, n_out, P2, m2, v2)
+    assert e.value.code == pk.BEM_EINVAL
+    with pytest.raises(pk.BemError) as e:
+        ctx.mlp_load(path, 1, P2)  # another n_out
+    assert e.value.code == pk.BEM_EINVAL
