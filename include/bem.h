@@ -73,6 +73,7 @@ extern "C" {
 #define BEM_RULE_TRI7 1  /* seven-point degree-5 rule per triangle */
 
 #define BEM_MAX_ORDER 12 /* largest q_regular / q_singular */
+#define BEM_NOALLOC_MAX_TRI 32768 /* largest mesh of bem_assemble_nearfield_noalloc */
 
 typedef struct bem_ctx bem_ctx;
 
@@ -158,6 +159,25 @@ int bem_check(bem_ctx *ctx, void *stream);
 int bem_assemble_nearfield(bem_ctx *ctx, const bem_mesh *mesh, const bem_op *op,
                            const bem_blocks *blocks, void *out, int64_t out_len,
                            void *stream);
+
+/* Near-field assembly that allocates nothing, for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid allocation).  Arguments, result (bit for bit) and
+ * errors as bem_assemble_nearfield; the per-triangle geometry goes to a
+ * fixed device array of the library (BEM_NOALLOC_MAX_TRI triangles, about
+ * 5 MB, one per GPU, held until the process ends) instead of context
+ * scratch, and no device or host memory is allocated by the call.
+ * mesh->nt > BEM_NOALLOC_MAX_TRI: BEM_EINVAL.  The quadrature tables of the
+ * operator's rule and orders must already exist on the context, built by an
+ * earlier call of any entry point with the same regular rule, q_regular and
+ * q_singular: otherwise BEM_EINVAL, nothing enqueued.  The array keeps the
+ * last call's geometry; each call rewrites what it reads before reading it.
+ * Every call on one GPU shares that GPU's array: calls that overlap in time
+ * on one GPU (from any context or stream) race and must be serialised by
+ * the caller. */
+int bem_assemble_nearfield_noalloc(bem_ctx *ctx, const bem_mesh *mesh, const bem_op *op,
+                                   const bem_blocks *blocks, void *out, int64_t out_len,
+                                   void *stream);
 
 /* Coupling assembly (Sec. 2.3-2.4: G|_{t~ x s~} of admissible blocks on the
  * pivot sets chosen by cross approximation).  Blocks are given like

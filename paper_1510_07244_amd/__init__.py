@@ -17,6 +17,7 @@ SLP, DLP = 0, 1
 PLAIN_FP64, MIXED = 0, 1
 RULE_DUFFY, RULE_TRI7 = 0, 1
 MAX_ORDER = 12
+NOALLOC_MAX_TRI = 32768  # largest mesh of bem_assemble_nearfield_noalloc
 
 _ERRNAMES = {BEM_EINVAL: "EINVAL", BEM_ENOMEM: "ENOMEM", BEM_EDEVICE: "EDEVICE",
              BEM_EUNSUPPORTED: "EUNSUPPORTED", BEM_ENONFINITE: "ENONFINITE"}
@@ -60,7 +61,8 @@ def _load():
     L.bem_last_error.argtypes = [P]
     L.bem_last_error.restype = ctypes.c_char_p
     L.bem_check.argtypes = [P, P]
-    for name in ("bem_assemble_nearfield", "bem_assemble_coupling"):
+    for name in ("bem_assemble_nearfield", "bem_assemble_coupling",
+                 "bem_assemble_nearfield_noalloc"):
         getattr(L, name).argtypes = [P, ctypes.POINTER(bem_mesh), ctypes.POINTER(bem_op),
                                      ctypes.POINTER(bem_blocks), P, ctypes.c_int64, P]
     L.bem_assemble_nearfield_both.argtypes = [P, ctypes.POINTER(bem_mesh), ctypes.POINTER(bem_op),
@@ -180,6 +182,14 @@ class Context:
         self._rc(_lib.bem_assemble_nearfield(self.h, ctypes.byref(mesh.c), ctypes.byref(op),
                                              ctypes.byref(blocks.c), _ptr(out), out.numel(),
                                              _stream(stream)))
+
+    def assemble_nearfield_noalloc(self, mesh, op, blocks, out, stream=None):
+        """bem_assemble_nearfield_noalloc: as assemble_nearfield, allocating
+        nothing (geometry in the library's fixed per-GPU array; the orders'
+        quadrature tables must exist on the context already)."""
+        self._rc(_lib.bem_assemble_nearfield_noalloc(self.h, ctypes.byref(mesh.c),
+                                                     ctypes.byref(op), ctypes.byref(blocks.c),
+                                                     _ptr(out), out.numel(), _stream(stream)))
 
     def assemble_nearfield_both(self, mesh, op, blocks, out_slp, out_dlp, stream=None):
         """bem_assemble_nearfield_both: single layer to out_slp, double layer

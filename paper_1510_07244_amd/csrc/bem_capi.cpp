@@ -145,9 +145,12 @@ int get_rules(bem_ctx *ctx, const bem_op *op, const bem::DevRules **out) {
 
 // both: the near field of both layers in one pass (out: single layer, out2:
 // double layer; op->layer is validated but not used).
+// noalloc: geometry in the library's fixed array, quadrature tables only if
+// the context already holds them (no allocation of any kind).
 int assemble_blocks(bem_ctx *ctx, const bem_mesh *mesh, const bem_op *op,
                     const bem_blocks *blocks, void *out, int64_t out_len, void *stream,
-                    bool coupling, bool both = false, void *out2 = nullptr) {
+                    bool coupling, bool both = false, void *out2 = nullptr,
+                    bool noalloc = false) {
   if (!ctx) return BEM_EINVAL;
   int rc;
   if ((rc = check_mesh(ctx, mesh)) || (rc = check_op(ctx, op)) ||
@@ -160,8 +163,24 @@ int assemble_blocks(bem_ctx *ctx, const bem_mesh *mesh, const bem_op *op,
   DeviceGuard g(ctx->device);
   int64_t ldg;
   const bem::DevRules *rules;
-  if ((rc = ensure_geo(ctx, mesh->nt, &ldg)) || (rc = get_rules(ctx, op, &rules))) return rc;
   double *geo = ctx->geo;
+  if (noalloc) {
+    if (mesh->nt > BEM_NOALLOC_MAX_TRI)
+      return fail(ctx, BEM_EINVAL, "mesh larger than BEM_NOALLOC_MAX_TRI triangles");
+    if (!ctx->noalloc_geo) return fail(ctx, BEM_EDEVICE, "no fixed geometry array on this device");
+    const int qr = op->regular_rule == BEM_RULE_TRI7 ? 0 : op->q_regular;
+    const auto it = ctx->rules.find(std::make_tuple(op->regular_rule, qr, op->q_singular));
+    if (it == ctx->rules.end())
+      return fail(ctx, BEM_EINVAL,
+                  "quadrature tables of these orders are not built on this context (make one "
+                  "call of another entry point with the same rule and orders first)");
+    rules = &it->second;
+    geo = ctx->noalloc_geo;
+    ldg = ((int64_t)mesh->nt + 63) / 64 * 64;
+  } else {
+    if ((rc = ensure_geo(ctx, mesh->nt, &ldg)) || (rc = get_rules(ctx, op, &rules))) return rc;
+    geo = ctx->geo;
+  }
   hipStream_t s = static_cast<hipStream_t>(stream);
   hipError_t e = bem::launch_geometry(*mesh, geo, ldg, ctx->flags, s);
   if (e != hipSuccess) return hip_fail(ctx, e, "geometry kernel launch");
@@ -228,6 +247,8 @@ int bem_create(bem_ctx **out, int device) {
     ctx->lds_budget = std::min<size_t>((size_t)lds_max, 80 * 1024);  // keep 2 workgroups per CU
   hipError_t e = hipMalloc(&ctx->flags, 256);
   if (e == hipSuccess) e = hipMemset(ctx->flags, 0, 256);
+  // the fixed array of the allocation-free entry point (address per device)
+  if (e == hipSuccess) e = bem::noalloc_scratch(device, &ctx->noalloc_geo);
   if (e == hipSuccess) e = hipMalloc(&ctx->dot_part, bem::dot_scratch_doubles() * sizeof(double));
   if (e != hipSuccess) {
     if (ctx->flags) (void)hipFree(ctx->flags);
@@ -283,6 +304,13 @@ int bem_check(bem_ctx *ctx, void *stream) {
 int bem_assemble_nearfield(bem_ctx *ctx, const bem_mesh *mesh, const bem_op *op,
                            const bem_blocks *blocks, void *out, int64_t out_len, void *stream) {
   return assemble_blocks(ctx, mesh, op, blocks, out, out_len, stream, false);
+}
+
+int bem_assemble_nearfield_noalloc(bem_ctx *ctx, const bem_mesh *mesh, const bem_op *op,
+                                   const bem_blocks *blocks, void *out, int64_t out_len,
+                                   void *stream) {
+  return assemble_blocks(ctx, mesh, op, blocks, out, out_len, stream, false, false, nullptr,
+                         true);
 }
 
 int bem_assemble_coupling(bem_ctx *ctx, const bem_mesh *mesh, const bem_op *op,

@@ -311,6 +311,9 @@ hipError_t launch_contract(bool cplx, const ContractArgs &a, int grid_y, hipStre
 hipError_t launch_pivot_inverse(bool cplx, const PivInvArgs &a, hipStream_t s);
 
 // launchers (bem_kernels.hip); return a hipError_t
+// device address of the fixed geometry scratch of the allocation-free entry
+// point on `device` (which must be current)
+hipError_t noalloc_scratch(int device, double **ptr);
 hipError_t launch_geometry(const bem_mesh &m, double *geo, int64_t ldg, unsigned *flags,
                            hipStream_t s);
 hipError_t launch_blocks(int kernel, int layer, bool coupling, bool mixed, const BlockArgs &a,
@@ -368,6 +371,7 @@ struct bem_ctx {
   std::string err;
   unsigned *flags = nullptr;      // device, 1 word
   double *geo = nullptr;          // device scratch
+  double *noalloc_geo = nullptr;  // fixed geometry array of the allocation-free entry point
   double *dot_part = nullptr;     // device: partial sums of bem_vec_dot
   size_t geo_cap = 0;             // doubles
   float *mlp_scratch = nullptr;   // device: per-workgroup gradient partial sums

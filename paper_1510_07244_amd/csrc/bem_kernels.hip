@@ -2,6 +2,8 @@
 // evaluation of arbitrary entry lists.  The block kernel is in bem_blocks.hip.
 #include <hip/hip_runtime.h>
 
+#include <mutex>
+
 #include "bem_device.h"
 
 namespace bem {
@@ -99,7 +101,31 @@ void launch_entries_kl(bool mixed, const EntryArgs &a, dim3 grid, dim3 block, hi
   else hipLaunchKernelGGL((k_entries<KERNEL, LAYER, false>), grid, block, 0, s, a);
 }
 
+// Fixed triangle-geometry scratch of the allocation-free near-field entry
+// point: GEO_NF fields of up to BEM_NOALLOC_MAX_TRI triangles (leading
+// dimension BEM_NOALLOC_MAX_TRI), one copy per GPU, held until the process
+// ends.  Host code never passes this name to a kernel: it is a host-side
+// stand-in; the device address comes from hipGetSymbolAddress.
+static __device__ __align__(256) double scratch[GEO_NF * (size_t)BEM_NOALLOC_MAX_TRI];
+
 }  // namespace
+
+hipError_t noalloc_scratch(int device, double **ptr) {
+  // the array's address on each device, looked up once with that device
+  // current (the caller makes it current) and kept
+  static std::mutex mu;
+  static double *addr[64] = {};
+  if (device < 0 || device >= 64) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(mu);
+  if (!addr[device]) {
+    void *p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    addr[device] = static_cast<double *>(p);
+  }
+  *ptr = addr[device];
+  return hipSuccess;
+}
 
 hipError_t launch_geometry(const bem_mesh &m, double *geo, int64_t ldg, unsigned *flags,
                            hipStream_t s) {
