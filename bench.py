@@ -147,6 +147,32 @@ def class_counts(tri, rows, cols):
     return counts
 
 
+def mirrored_counts(h, tri):
+    """Pair classes of the near field as the mirrored lists evaluate it:
+    `eval` the pairs (i, j) evaluated (blocks with t < s, and the entries with
+    row >= column of the blocks (t, t)), `trans` their transposed pairs
+    (j, i) (those blocks' pairs, the diagonal blocks' with row > column)."""
+    ev = np.zeros(4, dtype=np.int64)
+    tr_ = np.zeros(4, dtype=np.int64)
+    for t, s in h.near:
+        if t > s:
+            continue
+        r, c = h.ct.idx(t), h.ct.idx(s)
+        a, b = tri[r], tri[c]
+        sh = np.zeros((r.size, c.size), dtype=np.int8)
+        for x in range(3):
+            for y in range(3):
+                sh += a[:, x, None] == b[None, :, y]
+        if t < s:
+            cnt = np.bincount(sh.ravel(), minlength=4)[:4]
+            ev += cnt
+            tr_ += cnt
+        else:
+            ev += np.bincount(sh[np.tril_indices(r.size)], minlength=4)[:4]
+            tr_ += np.bincount(sh[np.tril_indices(r.size, -1)], minlength=4)[:4]
+    return ev, tr_
+
+
 def near_flops(counts, kernel, layer, q_reg, q_sing):
     """Laplace: the singular xi sums are moments, q^3 eta points per region.
     Identical pairs: the single layer needs 3 of the 6 regions (the others
@@ -163,14 +189,15 @@ def near_flops(counts, kernel, layer, q_reg, q_sing):
 
 
 class H2Bench:
-    def __init__(self, pk, ctx, m, mixed=False):
+    def __init__(self, pk, ctx, m, mixed=False, kernel=0, kappa=0.0, q=Q):
         import torch
         from paper_1510_07244_amd.h2 import H2Setup
         self.pk, self.ctx, self.m = pk, ctx, m
-        self.mixed = mixed
+        self.mixed, self.kernel, self.kappa, self.q = mixed, kernel, kappa, q
         sync = torch.cuda.synchronize
         t0 = time.perf_counter()
-        self.h = h = H2Setup(ctx, m.v, m.tri, kernel=pk.LAPLACE, q_regular=Q, q_singular=Q)
+        self.h = h = H2Setup(ctx, m.v, m.tri, kernel=kernel, kappa=kappa, q_regular=q,
+                             q_singular=q)
         t1 = time.perf_counter()
         self.V, self.W = h.bases((0, 1))
         sync()
@@ -188,7 +215,7 @@ class H2Bench:
             for op in self.ops:
                 op.precision = pk.MIXED
                 op.near_singular_ratio = MIXED_RATIO
-        dt = dict(dtype=torch.float32 if mixed else torch.float64, device="cuda")
+        dt = dict(dtype=pk.out_dtype(self.ops[0]), device="cuda")
         self.out = {k: torch.empty(n, **dt) for k, n in
                     (("ns", self.n_near), ("nd", self.n_near), ("cs", self.n_cs), ("cd", self.n_cd))}
         # the near field of both layers in one pass over the mirrored list
@@ -201,11 +228,8 @@ class H2Bench:
         # (outside the timed setup) the mirrored single layer evaluates the
         # blocks with t <= s, plus the edge-adjacent entries of the others (as
         # (j, i))
-        lo = [(t, s) for t, s in h.near if t > s]
-        self.near_evaluated_slp = int(sum(h.ct.idx(t).size * h.ct.idx(s).size
-                                          for t, s in h.near if t <= s))
-        self.near_evaluated_slp += int(class_counts(m.tri, [h.ct.idx(t) for t, s in lo],
-                                                    [h.ct.idx(s) for t, s in lo])[2])
+        self.ev_pairs, self.tr_pairs = mirrored_counts(h, m.tri)
+        self.near_evaluated_slp = int(self.ev_pairs.sum() + self.tr_pairs[2])
 
     def near_calls(self, stream=None):
         ctx, h, o = self.ctx, self.h, self.out
@@ -354,7 +378,8 @@ class LearnedBench:
     """Learned form: the order selector trained on the GPU on 1e6 pairs drawn
     from the near fields of the config-1..3 meshes (the 512-, 8192- and
     32768-triangle spheres and the 24576-triangle cube; Laplace SLP/DLP on
-    all, Helmholtz kappa 2/4/8 SLP/DLP on the last two), then applied to the
+    all, Helmholtz kappa 2/4/8 SLP/DLP on the last two) and 2.4e5 pairs of
+    the admissible blocks of the two finer spheres, then applied to the
     near field of a large sphere: selection (FP16 inference) + per-entry
     order assembly against the plain fixed-order assembly."""
 
@@ -374,6 +399,9 @@ class LearnedBench:
             jobs.append((s2.v, s2.tri, pk.make_op(L, layer), 120000, 20 + layer))
             jobs.append((s3.v, s3.tri, pk.make_op(L, layer), 100000, 30 + layer))
             jobs.append((cube.v, cube.tri, pk.make_op(L, layer), 40000, 40 + layer))
+            # pairs of the admissible blocks (the coupling blocks' entries)
+            jobs.append((s2.v, s2.tri, pk.make_op(L, layer), 60000, 70 + layer, "far"))
+            jobs.append((s3.v, s3.tri, pk.make_op(L, layer), 60000, 80 + layer, "far"))
             for k in (2.0, 4.0, 8.0):
                 jobs.append((s3.v, s3.tri, pk.make_op(H, layer, kappa=k), 40000, 50 + layer + int(k)))
                 jobs.append((cube.v, cube.tri, pk.make_op(H, layer, kappa=k), 26667, 60 + layer + int(k)))
@@ -465,6 +493,68 @@ class LearnedBench:
                          "loss_last_epoch": float(self.losses[-1])},
             "legs": legs,
         }
+
+
+def learned_h2_leg(torch, pk, ctx, hb, sel, stream, steps, warmup, tol=1e-7, margin=0.5):
+    """The H^2 step with learned orders on the coupling blocks: per entry of
+    the single- and double-layer coupling lists the order the selector picks
+    (chosen once in the setup), assembled by the per-entry-order kernel (the
+    single layer's list unmirrored: that kernel evaluates every block); the
+    near field and the bases as in the plain step.  Coupling matrices against
+    the plain step's, entry counts and point counts."""
+    h, o = hb.h, hb.out
+    cs_full, n_cs = h.coupling_blocks(hb.V, hb.V)
+    lists = {"cs": (cs_full, n_cs, hb.ops[0]), "cd": (hb.cd, hb.n_cd, hb.ops[1])}
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    orders = {k: sel.orders(h.mesh, op, b, n, tol, margin) for k, (b, n, op) in lists.items()}
+    torch.cuda.synchronize()
+    t_select = time.perf_counter() - t0
+    out = {k: torch.empty(n, dtype=torch.float64, device="cuda") for k, (b, n, op) in lists.items()}
+    ev = {k: (torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+          for k in ("bases", "nb", "cs", "cd")}
+    phase = {k: [] for k in ev}
+
+    def step(record):
+        if record:
+            ev["bases"][0].record(stream)
+        h.basis_replay(hb.V, stream)
+        h.basis_replay(hb.W, stream)
+        if record:
+            ev["bases"][1].record(stream)
+            ev["nb"][0].record(stream)
+        ctx.assemble_nearfield_both(h.mesh, hb.ops[0], hb.near_s, o["ns"], o["nd"], stream)
+        if record:
+            ev["nb"][1].record(stream)
+        for k, (b, n, op) in lists.items():
+            if record:
+                ev[k][0].record(stream)
+            ctx.assemble_nearfield_learned(h.mesh, op, b, orders[k], out[k], stream)
+            if record:
+                ev[k][1].record(stream)
+
+    for _ in range(warmup):
+        step(False)
+    ctx.check(stream)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        step(True)
+        torch.cuda.synchronize()
+        for k in ev:
+            phase[k].append(ev[k][0].elapsed_time(ev[k][1]))
+    ms = (time.perf_counter() - t0) * 1e3 / steps
+    ctx.check(stream)
+    res = {"ms_per_step": ms, "phase_ms": {k: float(np.mean(v)) for k, v in phase.items()},
+           "select_s": t_select, "tol": tol, "margin": margin}
+    for k, (b, n, op) in lists.items():
+        q = orders[k].to(torch.int64)
+        res[k] = {"entries": int(n), "points_fraction": float((q ** 4).sum()) / (n * Q ** 4),
+                  "orders": {int(v): int((q == v).sum()) for v in range(2, Q + 1)},
+                  "rel_err_vs_plain": float(torch.linalg.vector_norm(out[k] - o[k]) /
+                                                torch.linalg.vector_norm(o[k]))}
+    res["plain_ms_per_step_one_stream"] = None
+    return res
 
 
 def run_leg(torch, ctx, hb, stream, steps, warmup):
@@ -610,6 +700,67 @@ def per_layer_near(torch, hb, stream, reps):
     return out
 
 
+def one_pass_flops(ev, tr_, k, q):
+    """Near field of both layers in one pass over the mirrored list: per
+    evaluated regular pair the double layer's work plus the single layer's
+    accumulation (a complex one is two FMAs; the transposed pair's double
+    layer costs per-point work only); singular pairs: both layers of (i, j),
+    the double layer of (j, i) and the single layer of edge-adjacent
+    (j, i)."""
+    sing = lambda c: [0] + list(c[1:])
+    acc = 2.0 if k == 0 else 4.0
+    return (float(ev[0]) * (q * q) ** 2 * (FLOPS_PER_POINT[(k, 1)] + acc) +
+            near_flops(sing(ev), k, 0, q, q) + near_flops(sing(ev), k, 1, q, q) +
+            near_flops([0, tr_[1], tr_[2], 0], k, 1, q, q) +
+            near_flops([0, 0, tr_[2], 0], k, 0, q, q))
+
+
+def step_flops(hb):
+    """Algorithmic flops of the step's block launches (near field of both
+    layers in one pass, single-layer coupling on the mirrored list, double-
+    layer coupling), by the per-point-pair counts."""
+    k, q = hb.kernel, hb.q
+    f_nb = one_pass_flops(hb.ev_pairs, hb.tr_pairs, k, q)
+    f_cs = float(hb.n_cs // 2) * (q * q) ** 2 * FLOPS_PER_POINT[(k, 0)]
+    f_cd = float(hb.n_cd) * (q * q) ** 2 * FLOPS_PER_POINT[(k, 1)]
+    return {"nb": f_nb, "cs": f_cs, "cd": f_cd}
+
+
+def helmholtz_h2_leg(torch, pk, ctx, stream, steps=3, warmup=1, peak64=None):
+    """The Helmholtz workloads: SLP + DLP H^2 matrices of the 32768-triangle
+    sphere and the 24576-triangle cube surface, kappa 2, 4 and 8, q = 5,
+    plain complex128 and mixed complex64: setup time (trees, bases with the
+    host pivot search, first assembly) and the step on one stream (bases
+    replay, one-pass near field, both couplings) with per-phase HIP-event
+    times and the roofline of the longest launch."""
+    from bem_inputs import cube_surface, octahedron_sphere
+    out = []
+    for name, mesh in (("sphere32768", octahedron_sphere(64)), ("cube24576", cube_surface(32))):
+        for kappa in (2.0, 4.0, 8.0):
+            for mixed in (False, True):
+                hb = H2Bench(pk, ctx, mesh, mixed=mixed, kernel=pk.HELMHOLTZ, kappa=kappa, q=5)
+                ms, phase = run_leg(torch, ctx, hb, stream, steps, warmup)
+                fl = step_flops(hb)
+                longest = max(("nb", "cs", "cd"), key=lambda k: phase[k])
+                peak = (FP32_VALU_PEAK if mixed else FP64_VALU_PEAK) / 1e12
+                ach = fl[longest] / (phase[longest] * 1e-3) / 1e12
+                out.append({
+                    "mesh": name, "kappa": kappa,
+                    "form": "mixed complex64" if mixed else "plain complex128",
+                    "h2_setup_s": hb.t_setup, "bases_s": hb.t_bases,
+                    "bases_split": dict(hb.h.bases_time), "ms_per_step": ms, "phase_ms": phase,
+                    "entries_evaluated_per_step": hb.entries_evaluated(),
+                    "value": hb.entries_evaluated() / (ms * 1e-3),
+                    "near_blocks": len(hb.h.near), "far_blocks": len(hb.h.far),
+                    "roofline": {"launch": {"nb": "one-pass near field", "cs": "SLP coupling",
+                                            "cd": "DLP coupling"}[longest],
+                                 "bound": "alu", "achieved": ach, "peak": peak, "unit": "TFLOP/s",
+                                 "frac": ach / peak, "flops_per_launch": fl[longest]},
+                })
+                del hb
+    return out
+
+
 def solve_leg(torch, pk, ctx, hb, stream, reps=20):
     """H^2 products with the step's assembled matrices (near field, coupling
     and nested bases; the library's grouped matrix-vector kernels) and the
@@ -636,14 +787,14 @@ def solve_leg(torch, pk, ctx, hb, stream, reps=20):
             b.record(stream)
         torch.cuda.synchronize()
         ms = float(np.median([a.elapsed_time(b) for a, b in ev]))
-        nbytes = 8 * (H.near_call.A.numel() + H.coupling_call.A.numel() +
+        nbytes = 8 * (H.near.numel() + H.coupling.numel() +
                       sum(lv.V.numel() for lv in H.V.levels) +
                       (sum(lv.V.numel() for lv in H.W.levels) if H.W is not H.V else 0))
         res[name] = {"ms_per_product": ms, "matrix_bytes": nbytes,
                      "roofline": {"bound": "hbm", "achieved": nbytes / (ms * 1e-3) / 1e9,
                                   "peak": 8000.0, "unit": "GB/s",
                                   "frac": nbytes / (ms * 1e-3) / 8e12},
-                     "launches": 2 + len(H.fwd) + len(H.bwd)}
+                     "launches": 1 + len(H.near_calls) + len(H.fwd) + len(H.bwd)}
     rhs = torch.empty_like(beta)
     Hk.matvec(beta, rhs, stream)
     ctx.mass_apply(h.mesh, 0.5, beta, rhs, stream)
@@ -755,6 +906,7 @@ def main():
                                                                  args.warmup)[0]
     solve = solve_leg(torch, pk, ctx, hb, stream)
     helmholtz = None if args.no_helmholtz else helmholtz_near_leg(torch, pk, ctx, stream, 5)
+    helmholtz_h2 = None if args.no_helmholtz else helmholtz_h2_leg(torch, pk, ctx, stream)
     batched = None
     if args.batched_meshes > 0:
         bb = BatchedBench(pk, ctx, args.batched_meshes)
@@ -764,6 +916,9 @@ def main():
     if args.learned_n > 0:
         lb = LearnedBench(pk, ctx, args.learned_n)
         learned = lb.result(torch, stream, min(args.steps, 10), 1)
+        learned["h2_step"] = learned_h2_leg(torch, pk, ctx, hb, lb.sel, stream,
+                                            min(args.steps, 10), 2)
+        learned["h2_step"]["plain_ms_per_step_one_stream"] = ms_seq
         del lb
         learned["rank_head"] = rank_head_leg(torch, pk, ctx, m)
 
@@ -773,26 +928,13 @@ def main():
     counts = class_counts(m.tri, rows, cols)
     f_dlp = near_flops(counts, 0, 1, Q, Q)
     f_cd = float(hb.n_cd) * (Q ** 2) ** 2 * FLOPS_PER_POINT[(0, 1)]  # coupling: regular pairs only
-    # the mirrored single layer evaluates the blocks with t <= s, plus the
-    # edge-adjacent entries of the others (as (j, i))
-    up = [k for k, (t, s) in enumerate(h.near) if t <= s]
-    lo = [k for k, (t, s) in enumerate(h.near) if t > s]
-    counts_s = class_counts(m.tri, [rows[k] for k in up], [cols[k] for k in up])
-    edges_lo = int(class_counts(m.tri, [rows[k] for k in lo], [cols[k] for k in lo])[2])
-    counts_s[2] += edges_lo
+    # the mirrored single layer evaluates the pairs (i, j) of the blocks with
+    # t < s and the lower triangles of the blocks (t, t), plus the
+    # edge-adjacent transposed pairs (as (j, i))
+    counts_s = hb.ev_pairs.copy()
+    counts_s[2] += hb.tr_pairs[2]
     f_slp = near_flops(counts_s, 0, 0, Q, Q)
-    assert hb.near_evaluated_slp == int(sum(rows[k].size * cols[k].size for k in up)) + edges_lo
-    # one pass over the blocks with t <= s: per regular pair the double
-    # layer's work plus the single layer's accumulation (the transposed
-    # pair's double layer costs per-point work only); singular pairs: both
-    # layers of (i, j), the double layer of (j, i) and the single layer of
-    # edge-adjacent (j, i)
-    cu = class_counts(m.tri, [rows[k] for k in up], [cols[k] for k in up])
-    cl_ = class_counts(m.tri, [rows[k] for k in lo], [cols[k] for k in lo])
-    sing = lambda c: [0] + list(c[1:])
-    f_both = (float(cu[0]) * (Q ** 2) ** 2 * (FLOPS_PER_POINT[(0, 1)] + 2) +
-              near_flops(sing(cu), 0, 0, Q, Q) + near_flops(sing(cu), 0, 1, Q, Q) +
-              near_flops(sing(cl_), 0, 1, Q, Q) + near_flops([0, 0, cl_[2], 0], 0, 0, Q, Q))
+    f_both = one_pass_flops(hb.ev_pairs, hb.tr_pairs, 0, Q)
     st = np.array(setups)
     best = int(np.argmin(st[:, 0]))
     ranks_v = hb.V.rank[hb.V.rank > 0]
@@ -908,6 +1050,8 @@ def main():
     result["h2_products"] = solve
     if helmholtz:
         result["forms"]["helmholtz_near_both"] = helmholtz
+    if helmholtz_h2:
+        result["helmholtz_h2"] = helmholtz_h2
     if batched:
         result["forms"]["batched"] = batched
     if learned:

@@ -120,9 +120,13 @@ typedef struct {
  * (column-major); mirror_off[b] < 0: no mirror.  Disjoint and vertex-adjacent pairs are written once evaluated
  * (equal up to rounding); an edge-adjacent pair's mirror entry is evaluated
  * as the pair (j, i), the Sauter-Schwab rule for a shared edge not being
- * symmetric.  A mirror onto the block itself (a block on the diagonal) or
- * one that does not fit in out raises the device flag and is not written;
- * mirrors must not overlap other outputs.  NULL: no mirrors. */
+ * symmetric.  mirror_off[b] == out_off[b] marks a block on the diagonal of
+ * the matrix (square, the same triangle list for rows and columns -- the
+ * caller's promise): it is its own mirror, so only its entries with row >=
+ * column are evaluated and each is also written to its transposed place.
+ * Any other mirror onto the block itself, or one that does not fit in out,
+ * raises the device flag and is not written; mirrors must not overlap other
+ * outputs.  NULL: no mirrors. */
 typedef struct {
     int32_t n;
     const int32_t *row_ptr;
@@ -367,8 +371,9 @@ int bem_selector_samples(bem_ctx *ctx, const bem_mesh *mesh, const bem_op *op, i
                          const int32_t *rows, const int32_t *cols, float *x, float *t,
                          void *stream);
 
-/* Orders of the entries of near-field blocks (layout of the blocks' output,
- * one int8 per entry): 0 for pairs with a common vertex, else the smallest
+/* Orders of the entries of a block list -- near-field blocks, or the
+ * coupling blocks of admissible pairs (pivot lists) -- in the layout of the
+ * blocks' output, one int8 per entry: 0 for pairs with a common vertex, else the smallest
  * q in [q_min, q_regular - 1] such that the FP16 network (n_out = 6,
  * params) predicts e_q' + margin <= log10(tol) at every q' in
  * [q, q_regular - 1]; q_regular when q_regular - 1 fails.  The comparison is
@@ -386,7 +391,10 @@ int bem_select_orders(bem_ctx *ctx, const bem_mesh *mesh, const bem_op *op,
  * q_regular in [2, 6]), each regular entry with the order orders[entry]
  * (device int8, the output's layout) in [2, q_regular]; an order outside
  * raises the flag and leaves the entry unwritten.  With q_regular
- * everywhere the result equals bem_assemble_nearfield's bit for bit. */
+ * everywhere the result equals bem_assemble_nearfield's bit for bit.  A
+ * coupling list (pivot lists of admissible blocks, no common vertices) is
+ * assembled the same way, entry for entry as bem_assemble_coupling with
+ * q_regular; mirror_off is not used (every block is evaluated). */
 int bem_assemble_nearfield_learned(bem_ctx *ctx, const bem_mesh *mesh, const bem_op *op,
                                    const bem_blocks *blocks, const int8_t *orders, void *out,
                                    int64_t out_len, void *stream);
@@ -411,6 +419,19 @@ int bem_mlp_save(bem_ctx *ctx, const char *path, int32_t n_out, const float *par
  * asked for that the file does not hold. */
 int bem_mlp_load(bem_ctx *ctx, const char *path, int32_t n_out, float *params, float *m, float *v,
                  float *range, int32_t *step, void *stream);
+
+/* Inputs of the rank head (the selector network with one output, predicting
+ * the rank the cross approximation of Sec. 2.3 reaches for a cluster), eight
+ * per cluster, computed on the host: log2 of the triangle count
+ * end[c] - begin[c] (at least 1), log10 of the bounding-box diagonal D (at
+ * least 1e-300), the box's middle and smallest extent over its largest,
+ * height[c] (leaves 0), kappa * D, `side` (0 rows, 1 double-layer columns),
+ * log10(eps) of the pivot-search tolerance.  box: host double[n][6] (lower
+ * corner, upper corner); begin, end, height: host int32[n]; out: host
+ * float[n][8].  BEM_EINVAL for n < 0, NULL arrays (n > 0) or eps <= 0. */
+int bem_cluster_features(int32_t n, const double *box, const int32_t *begin, const int32_t *end,
+                         const int32_t *height, double kappa, int32_t side, double eps,
+                         float *out);
 
 /* ---------------------------------------------------------------------
  * Cluster bases of the Green cross approximation (Sec. 2.3-2.4).
@@ -466,8 +487,10 @@ int bem_basis_contract(bem_ctx *ctx, int32_t is_complex, int32_t nmat, const int
  * A + a_off[c] (column-major, leading dimension n_c), t~_c = piv_rows[c *
  * max_rank .. + rank[c]) its pivot rows (local row numbers) and tau_c =
  * piv_cols[c * max_rank ..] its pivot columns, as bem_aca returns them.
- * Gauss-Jordan elimination with partial pivoting (largest modulus, ties to
- * the smallest row).  max_rank <= 512.  All arrays device memory; index
+ * Gauss-Jordan elimination in the order of the pivots, without further
+ * pivoting: the cross approximation picks each pivot as the largest entry
+ * of the residual, so that order is elimination with complete pivoting
+ * (pivot lists from elsewhere must have the same property).  max_rank <= 512.  All arrays device memory; index
  * errors raise BEM_EINVAL, a zero or non-finite pivot BEM_ENONFINITE (device
  * flag, see bem_check). */
 int bem_pivot_inverse(bem_ctx *ctx, int32_t is_complex, int32_t nmat, const int32_t *nrows,

@@ -577,10 +577,30 @@ def _setup_learned_api():
     _lib.bem_assemble_nearfield_learned.argtypes = [P, M, O, B, P, P, i64, P]
     _lib.bem_mlp_save.argtypes = [P, ctypes.c_char_p, i32, P, P, P, P, i32, P]
     _lib.bem_mlp_load.argtypes = [P, ctypes.c_char_p, i32, P, P, P, P, ctypes.POINTER(i32), P]
+    _lib.bem_cluster_features.argtypes = [i32, P, P, P, P, f64, i32, f64, P]
 
 
 _setup_learned_api()
 SEL_OUT = 6  # selector outputs: predicted log10 error at orders 1 .. 6
+
+
+def cluster_features(box, begin, end, height, kappa, side, eps):
+    """bem_cluster_features: the rank head's eight inputs per cluster
+    (float32 [n, 8]) from the cluster boxes, index ranges and heights."""
+    import numpy as np
+    box = np.ascontiguousarray(box, dtype=np.float64)
+    begin = np.ascontiguousarray(begin, dtype=np.int32)
+    end = np.ascontiguousarray(end, dtype=np.int32)
+    height = np.ascontiguousarray(height, dtype=np.int32)
+    n = begin.size
+    if box.shape != (n, 6) or end.size != n or height.size != n:
+        raise ValueError("box [n, 6], begin, end, height [n]")
+    out = np.empty((n, 8), dtype=np.float32)
+    rc = _lib.bem_cluster_features(n, _np_ptr(box), _np_ptr(begin), _np_ptr(end), _np_ptr(height),
+                                   float(kappa), int(side), float(eps), _np_ptr(out))
+    if rc != 0:
+        raise BemError(rc, "bem_cluster_features: invalid arguments")
+    return out
 
 
 def mlp_params(n_out):

@@ -207,15 +207,14 @@ __global__ __launch_bounds__(kThreads) void k_contract(const ContractArgs a) {
 
 // ------------------------------------------------ pivot-block inverse
 // P_c = A_c[t~_c, tau_c]^{-1} (k_c x k_c, column-major, leading dimension
-// k_c) by in-place Gauss-Jordan elimination with partial pivoting, one
-// workgroup per matrix, in the matrix's own output slot.  The slot holds
-// X = M^T row-major (= M column-major); row operations on X then read and
-// write contiguous rows, and the inverse of X left in place row-major is
-// M^{-1} column-major.  Pivot: the largest modulus in the column (ties to
-// the smallest row); the row exchanges are undone as column exchanges in
-// reverse order at the end.  The steps are sequential (k_c of them with a
-// barrier each) and the data small: latency-bound, so the vector units and
-// L2 serve it; the matrix cores are used by the contraction that follows.
+// k_c) by in-place Gauss-Jordan elimination in the order of the cross
+// approximation's pivots, one workgroup per matrix.  The matrix is
+// X = M^T row-major (= M column-major), M[l][l'] = A_c[t~_c[l], tau_c[l']];
+// row operations on X read and write contiguous rows, and the inverse of X
+// left in place row-major is M^{-1} column-major.  The steps are sequential
+// (k_c of them, two barriers each) and the data small: latency-bound, so the
+// matrix sits in LDS when it fits and the vector units serve it; the matrix
+// cores are used by the contraction that follows.
 template <bool CPLX>
 struct Z;
 template <>
@@ -250,13 +249,59 @@ struct Z<true> {
 };
 
 constexpr int kInvMaxRank = 512;
+constexpr size_t kInvLdsBytes = 136 * 1024;  // matrices held in LDS up to this size
 
+// Gauss-Jordan on the k x k row-major matrix M (leading dimension ld, in LDS
+// or global memory), in place and in the given order, without further
+// pivoting: the pivots are the cross approximation's, each chosen as the
+// largest entry of the residual of the whole Green matrix, so eliminating in
+// their order is elimination with complete pivoting.  Two barriers per
+// step: column s and the pivot row divided by the pivot are gathered into
+// LDS, then every entry is updated by its own thread.
+template <class T>
+__device__ __forceinline__ void gauss_jordan(T *M, int ld, int k, T *fcol, T *ps,
+                                             unsigned *flags) {
+  const int tid = threadIdx.x, wave = tid / kWave, lane = tid & (kWave - 1);
+  constexpr int W = kThreads / kWave;
+  constexpr int kBatch = 8;  // rows per batch: the batch's loads issue together
+  for (int s = 0; s < k; ++s) {
+    const T piv = M[s * ld + s];
+    if (tid == 0 && !piv.finite_nonzero()) atomicOr(flags, FLAG_NONFINITE);
+    for (int r = tid; r < k; r += kThreads) {
+      fcol[r] = M[r * ld + s];
+      ps[r] = (r == s ? T::make(1, 0) : M[s * ld + r]).div(piv);
+    }
+    __syncthreads();
+    for (int j = lane; j - lane < k; j += kWave) {  // uniform trip count
+      const bool col = j < k;
+      const T pj = col ? ps[j] : T::make(0, 0);
+      for (int r0 = wave * kBatch; r0 < k; r0 += W * kBatch) {
+        T fr[kBatch], old[kBatch];
+#pragma unroll
+        for (int u = 0; u < kBatch; ++u) {
+          const int r = r0 + u;
+          fr[u] = r < k && r != s ? fcol[r] : T::make(0, 0);
+          old[u] = col && r < k && r != s && j != s ? M[r * ld + j] : T::make(0, 0);
+        }
+#pragma unroll
+        for (int u = 0; u < kBatch; ++u) {
+          const int r = r0 + u;
+          if (col && r < k) M[r * ld + j] = r == s ? pj : old[u] - fr[u] * pj;
+        }
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// One workgroup per matrix.  Matrices of up to lds_k rows are eliminated in
+// LDS (leading dimension k + 1 against bank conflicts on column reads) and
+// written out once; larger ones in their global slot.
 template <bool CPLX>
-__global__ __launch_bounds__(kThreads) void k_pivot_inverse(const PivInvArgs a) {
+__global__ __launch_bounds__(kThreads) void k_pivot_inverse(const PivInvArgs a, int lds_k) {
   using T = Z<CPLX>;
-  __shared__ T f[kInvMaxRank];
-  __shared__ int swapped[kInvMaxRank];
-  __shared__ int pvt;
+  extern __shared__ __align__(16) double inv_lds[];
+  __shared__ T fcol[kInvMaxRank], ps[kInvMaxRank];
   const int c = blockIdx.x;
   const int n = a.nrows[c], k = a.rank[c];
   const int64_t aoff = a.a_off[c];
@@ -271,72 +316,27 @@ __global__ __launch_bounds__(kThreads) void k_pivot_inverse(const PivInvArgs a) 
   const int32_t *pcol = a.piv_cols + (int64_t)c * a.max_rank;
   const T *A = reinterpret_cast<const T *>(a.A);
   T *X = reinterpret_cast<T *>(a.pinv) + (int64_t)c * a.max_rank * a.max_rank;
+  const bool in_lds = k <= lds_k;  // uniform
+  T *L = reinterpret_cast<T *>(inv_lds);
   // X[i][j] = M[j][i] = A[prow[j], pcol[i]]
   for (int i = wave; i < k; i += W) {
     const int ci = pcol[i];
     for (int j = lane; j < k; j += kWave) {
       const int rj = prow[j];
-      if (ci < 0 || ci >= a.acols || rj < 0 || rj >= n) {
-        atomicOr(a.flags, FLAG_EINVAL);
-        X[(int64_t)i * k + j] = T::make(0, 0);
-      } else {
-        X[(int64_t)i * k + j] = A[aoff + rj + (int64_t)n * ci];
-      }
+      T v = T::make(0, 0);
+      if (ci < 0 || ci >= a.acols || rj < 0 || rj >= n) atomicOr(a.flags, FLAG_EINVAL);
+      else v = A[aoff + rj + (int64_t)n * ci];
+      if (in_lds) L[i * (k + 1) + j] = v;
+      else X[(int64_t)i * k + j] = v;
     }
   }
   __syncthreads();
-  for (int s = 0; s < k; ++s) {
-    if (wave == 0) {
-      double best = -1.0;
-      int bi = s;
-      for (int r = s + lane; r < k; r += kWave) {
-        const double v = X[(int64_t)r * k + s].mag2();
-        if (v > best) best = v, bi = r;
-      }
-      for (int o = kWave / 2; o >= 1; o >>= 1) {
-        const double ob = __shfl_xor(best, o, kWave);
-        const int oi = __shfl_xor(bi, o, kWave);
-        if (ob > best || (ob == best && oi < bi)) best = ob, bi = oi;
-      }
-      if (lane == 0) pvt = bi, swapped[s] = bi;
-    }
-    __syncthreads();
-    const int p = pvt;
-    if (p != s)
-      for (int j = tid; j < k; j += kThreads) {
-        const T t = X[(int64_t)s * k + j];
-        X[(int64_t)s * k + j] = X[(int64_t)p * k + j];
-        X[(int64_t)p * k + j] = t;
-      }
-    __syncthreads();
-    const T piv = X[(int64_t)s * k + s];
-    if (tid == 0 && !piv.finite_nonzero()) atomicOr(a.flags, FLAG_NONFINITE);
-    __syncthreads();  // every thread holds piv before row s changes
-    for (int j = tid; j < k; j += kThreads) {
-      const T v = j == s ? T::make(1, 0) : X[(int64_t)s * k + j];
-      X[(int64_t)s * k + j] = v.div(piv);
-    }
-    for (int r = tid; r < k; r += kThreads) f[r] = X[(int64_t)r * k + s];
-    __syncthreads();
-    for (int r = wave; r < k; r += W) {
-      if (r == s) continue;
-      const T fr = f[r];
-      for (int j = lane; j < k; j += kWave) {
-        const T old = j == s ? T::make(0, 0) : X[(int64_t)r * k + j];
-        X[(int64_t)r * k + j] = old - fr * X[(int64_t)s * k + j];
-      }
-    }
-    __syncthreads();
-  }
-  for (int s = k - 1; s >= 0; --s) {
-    const int p = swapped[s];
-    if (p != s)
-      for (int r = tid; r < k; r += kThreads) {
-        const T t = X[(int64_t)r * k + s];
-        X[(int64_t)r * k + s] = X[(int64_t)r * k + p];
-        X[(int64_t)r * k + p] = t;
-      }
-    __syncthreads();
+  if (in_lds) {
+    gauss_jordan(L, k + 1, k, fcol, ps, a.flags);
+    for (int i = wave; i < k; i += W)
+      for (int j = lane; j < k; j += kWave) X[(int64_t)i * k + j] = L[i * (k + 1) + j];
+  } else {
+    gauss_jordan(X, k, k, fcol, ps, a.flags);
   }
 }
 
@@ -346,8 +346,13 @@ hipError_t launch_pivot_inverse(bool cplx, const PivInvArgs &a, hipStream_t s) {
   if (a.nmat == 0) return hipSuccess;
   if (a.max_rank > kInvMaxRank) return hipErrorInvalidValue;
   const dim3 grid(a.nmat), block(kThreads);
-  if (cplx) hipLaunchKernelGGL((k_pivot_inverse<true>), grid, block, 0, s, a);
-  else hipLaunchKernelGGL((k_pivot_inverse<false>), grid, block, 0, s, a);
+  // largest k whose k x (k + 1) matrix fits the LDS allowance, at most max_rank
+  const size_t elem = cplx ? 16 : 8;
+  int lds_k = 0;
+  while (lds_k < a.max_rank && (size_t)(lds_k + 1) * (lds_k + 2) * elem <= kInvLdsBytes) ++lds_k;
+  const size_t lds = (size_t)lds_k * (lds_k + 1) * elem;
+  if (cplx) hipLaunchKernelGGL((k_pivot_inverse<true>), grid, block, lds, s, a, lds_k);
+  else hipLaunchKernelGGL((k_pivot_inverse<false>), grid, block, lds, s, a, lds_k);
   return hipGetLastError();
 }
 

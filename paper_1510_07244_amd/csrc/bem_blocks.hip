@@ -20,6 +20,8 @@ using namespace blk;
 struct BlockHdr {
   int64_t rp0, cp0, nr, nc, off;
   int64_t moff;       // transposed copy (coupling of a single layer), -1: none
+  bool diag;          // its own mirror (moff == off): a block on the diagonal,
+                      // only its entries with row >= column are evaluated
   double cx, cy, cz;  // block-local origin: first vertex of the first row triangle
 };
 
@@ -48,7 +50,8 @@ __device__ __forceinline__ bool block_header(const BlockArgs &a, int b, BlockHdr
   h->nc = nc;
   h->off = off;
   h->moff = a.mirror_off ? a.mirror_off[b] : -1;
-  if (h->moff >= 0 && nr > 0 &&
+  h->diag = h->moff >= 0 && h->moff == off && nr == nc;
+  if (h->moff >= 0 && nr > 0 && !h->diag &&
       (h->moff == off || h->moff > a.out_len || nc > (a.out_len - h->moff) / nr)) {
     if (threadIdx.x == 0) atomicOr(a.flags, FLAG_EINVAL);  // onto itself, or does not fit
     h->moff = -1;
@@ -307,7 +310,9 @@ __device__ __forceinline__ void singular_chunk_both(const BlockArgs &a, const Ld
     store_as<KERNEL, MIXED>(a.out, dst, vs, a.flags);
     store_as<KERNEL, MIXED>(a.out2, dst, vd, a.flags);
   }
-  if (h.moff < 0) return;  // uniform
+  // uniform: no mirror, or an identical pair of a diagonal block (its own
+  // transpose, already written)
+  if (h.moff < 0 || (h.diag && cls == CLS_IDENTICAL)) return;
   have = false;
   if (active)
     have = pair_geometry(a.v, a.tri, a.nv, a.geo, a.ldg, l.cid[cl], l.rid[rl], cls, a.flags, &g);
@@ -348,6 +353,19 @@ __device__ __forceinline__ bool fp64_pair(const Lds &l, int TR, int TC, int rl, 
   return fp64;
 }
 
+// Entry e of the lower triangle (row >= column) of an n x n tile, columns
+// in turn: column c holds rows c .. n - 1 and starts at S(c) = c n - c (c -
+// 1) / 2; the FP32 estimate of c is corrected to the exact one.
+__device__ __forceinline__ void lower_entry(int e, int n, int *rl, int *cl) {
+  const float b = 2.0f * n + 1.0f;
+  int c = (int)((b - sqrtf(fmaxf(b * b - 8.0f * e, 0.0f))) * 0.5f);
+  c = max(0, min(c, n - 1));
+  while (c > 0 && c * n - c * (c - 1) / 2 > e) --c;
+  while (c + 1 < n && (c + 1) * n - (c + 1) * c / 2 <= e) ++c;
+  *cl = c;
+  *rl = c + (e - (c * n - c * (c - 1) / 2));
+}
+
 // One sub-tile: rows r0 .. r0 + TR, columns c0 .. c0 + TC of the block
 // (LAYER = kBoth: the single layer to a.out and the double layer to a.out2).
 // After staging, the pairs of the FP64 pass are listed and grouped by class;
@@ -367,11 +385,18 @@ __device__ void subtile(const BlockArgs &a, const Lds &l, const BlockHdr &h, int
   const double scale = (LAYER == BEM_DLP ? 0.5 : 1.0) * kInv4Pi;
   const double ratio = a.near_ratio;
   const int tr = (int)min((int64_t)TR, h.nr - r0), tc = (int)min((int64_t)TC, h.nc - c0);
+  // a diagonal block evaluates its entries with row >= column only (the
+  // rest are their transposes): a sub-tile wholly above the diagonal is
+  // skipped, a square one on it enumerates its lower triangle
+  if (h.diag && r0 + tr - 1 < c0) return;  // uniform
+  const bool lower = h.diag && r0 == c0 && tr == tc;
+  const bool upper_skip = h.diag && !lower;
   if (!stage_tile<MIXED>(a, l, h, r0, c0, tr, tc)) return;
   stage_columns<MIXED>(a, l, h, tc, a.nq, nqp);
   // phase C: list the pairs of the FP64 pass
   for (int e = tid; e < tr * tc; e += kThreads) {
     const int rl = e % tr, cl = e / tr;
+    if (h.diag && r0 + rl < c0 + cl) continue;
     int cls;
     if (!fp64_pair<MIXED>(l, TR, TC, rl, cl, ratio, &cls)) continue;
     if (coupling && cls) {
@@ -396,7 +421,8 @@ __device__ void subtile(const BlockArgs &a, const Lds &l, const BlockHdr &h, int
     return;
   }
   const Groups gr = group_listed(l);
-  const int nsc = gr.total / kWave, nrc = (tr * tc + kWave - 1) / kWave;
+  const int nreg = lower ? tr * (tr + 1) / 2 : tr * tc;
+  const int nsc = gr.total / kWave, nrc = (nreg + kWave - 1) / kWave;
   for (;;) {
     int c = 0;
     if (lane == 0) c = atomicAdd(l.rcount, 1);
@@ -411,8 +437,14 @@ __device__ void subtile(const BlockArgs &a, const Lds &l, const BlockHdr &h, int
       continue;
     }
     const int e = (c - nsc) * kWave + lane;
-    if (e >= tr * tc) continue;
-    const int rl = e % tr, cl = e / tr;
+    if (e >= nreg) continue;
+    int rl, cl;
+    if (lower) {
+      lower_entry(e, tr, &rl, &cl);
+    } else {
+      rl = e % tr, cl = e / tr;
+      if (upper_skip && r0 + rl < c0 + cl) continue;
+    }
     int cls;
     if (fp64_pair<MIXED>(l, TR, TC, rl, cl, ratio, &cls)) continue;
     if constexpr (LAYER == kBoth) {

@@ -8,7 +8,8 @@
 // transformation of the row basis, near field).  Each reads its matrices
 // once, so it is bound by HBM bandwidth, not arithmetic: the kernels read
 // every matrix column-wise with 64 consecutive lanes on 64 consecutive rows
-// (one 512-byte line per wave and column) and keep the gathered input in LDS.
+// (one 512-byte line per wave and column), and the waves of a workgroup work
+// on different blocks without barriers between them.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -23,13 +24,20 @@ using namespace dev;
 constexpr int kMaxVec = 512;  // longest output and input of one group / block
 constexpr int kChunks = kMaxVec / kWave;
 
+// v of lane k, k uniform across the wave (two scalar reads of the halves)
+__device__ __forceinline__ double read_lane(double v, int k) {
+  const int lo = __builtin_amdgcn_readlane(__double2loint(v), k);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), k);
+  return __hiloint2double(hi, lo);
+}
+
 template <bool CPLX>
 struct Num;
 template <>
 struct Num<false> {
   double v;
   __device__ static Num zero() { Num r; r.v = 0.0; return r; }
-  __device__ void fma_into(const double *A, int64_t k, const Num &x) { v = fma(A[k], x.v, v); }
+  __device__ void fma(const Num &m, const Num &x) { v = ::fma(m.v, x.v, v); }
   __device__ static Num load(const double *p, int64_t k) { Num r; r.v = p[k]; return r; }
   __device__ void add_to(double *p, int64_t k) const { p[k] += v; }
   __device__ void add(const Num &o) { v += o.v; }
@@ -38,17 +46,18 @@ struct Num<false> {
     for (int o = kWave / 2; o >= 1; o >>= 1) r.v += __shfl_xor(r.v, o, kWave);
     return r;
   }
+  // the value of lane k (k uniform across the wave)
+  __device__ Num lane(int k) const { Num r; r.v = read_lane(v, k); return r; }
 };
 template <>
 struct Num<true> {
   double re, im;
   __device__ static Num zero() { Num r; r.re = r.im = 0.0; return r; }
-  __device__ void fma_into(const double *A, int64_t k, const Num &x) {
-    const double ar = A[2 * k], ai = A[2 * k + 1];
-    re = fma(ar, x.re, re);
-    re = fma(-ai, x.im, re);
-    im = fma(ar, x.im, im);
-    im = fma(ai, x.re, im);
+  __device__ void fma(const Num &m, const Num &x) {
+    re = ::fma(m.re, x.re, re);
+    re = ::fma(-m.im, x.im, re);
+    im = ::fma(m.re, x.im, im);
+    im = ::fma(m.im, x.re, im);
   }
   __device__ static Num load(const double *p, int64_t k) {
     Num r;
@@ -69,19 +78,33 @@ struct Num<true> {
     }
     return r;
   }
+  __device__ Num lane(int k) const {
+    Num r;
+    r.re = read_lane(re, k);
+    r.im = read_lane(im, k);
+    return r;
+  }
 };
 
 // Group g: y[out_idx[out_ptr[g] ..]] += sum_{b in group g} op(A_b) x[in_idx[in_ptr[b] ..]],
 // op(A) = A (TRANS false; A is m_out x n_in) or A^T (TRANS true; A is
 // n_in x m_out), column-major with the row count as leading dimension.  One
-// workgroup per group; the sum over a group's blocks and inside each block
-// runs in a fixed order (results are reproducible bit for bit).
+// workgroup per group.  The group's work is cut into panels -- kPanel input
+// columns of a block (TRANS false) or kPanel output columns (TRANS true), 16
+// real or 8 complex -- dealt to the waves in turn, so that a group of one
+// block still keeps all waves busy; a wave issues the loads of a panel's 64
+// rows before it uses them (kPanel loads in flight), since a product reads
+// every matrix entry once and waits on memory.  TRANS false: lane l takes
+// output row l + 64 c of chunk c, the panel's inputs are gathered one per
+// lane and broadcast.  TRANS true: lane l takes input row l + 64 c, runs
+// along the panel's columns and the wave adds each column's products up.
+// The waves' partial sums are added in wave order at the end: every sum runs
+// in a fixed order, so results are reproducible bit for bit.
 template <bool CPLX, bool TRANS>
-__global__ __launch_bounds__(kThreads) void k_gemv(const GemvArgs a) {
+__global__ __launch_bounds__(kThreads, 2) void k_gemv(const GemvArgs a) {
   using T = Num<CPLX>;
-  __shared__ T xs[kMaxVec];
+  constexpr int kPanel = CPLX ? 8 : 16;
   __shared__ T part[kThreads / kWave][kMaxVec];
-  __shared__ int bad;
   const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid / kWave;
   constexpr int W = kThreads / kWave;
   const double *A = static_cast<const double *>(a.A);
@@ -96,55 +119,83 @@ __global__ __launch_bounds__(kThreads) void k_gemv(const GemvArgs a) {
       if (tid == 0) atomicOr(a.flags, FLAG_EINVAL);
       continue;  // uniform
     }
-    T acc[kChunks];  // TRANS false: rows lane + 64 c of this wave's columns
-    for (int i = tid; i < W * kMaxVec; i += kThreads) part[i / kMaxVec][i % kMaxVec] = T::zero();
-    __syncthreads();
-    for (int64_t b = b0; b < b1; ++b) {
-      const int64_t i0 = a.in_ptr[b], i1 = a.in_ptr[b + 1];
-      const int64_t n = i1 - i0;
-      const int64_t off = a.a_off[b];
-      __syncthreads();  // xs of the previous block no longer read
-      if (tid == 0) bad = !(i0 >= 0 && i0 <= i1 && i1 <= a.in_len && n <= kMaxVec && off >= 0 &&
-                            off <= a.a_len && (m == 0 || n <= (a.a_len - off) / m));
-      __syncthreads();
-      if (bad) {
-        if (tid == 0) atomicOr(a.flags, FLAG_EINVAL);
-        continue;  // uniform
-      }
-      for (int64_t k = tid; k < n; k += kThreads) {
-        const int id = a.in_idx[i0 + k];
-        if (id < 0 || id >= a.x_len) {
-          atomicOr(a.flags, FLAG_EINVAL);
-          xs[k] = T::zero();
-        } else {
-          xs[k] = T::load(x, id);
+    for (int64_t i = lane; i < m; i += kWave) part[wave][i] = T::zero();
+    // TRANS false: one pass over the group per chunk of 64 output rows;
+    // TRANS true: one pass (the chunks are the inputs, summed per panel)
+    const int passes = TRANS ? 1 : (int)((m + kWave - 1) / kWave);
+    for (int c = 0; c < passes; ++c) {
+      T acc = T::zero();  // TRANS false: output row lane + 64 c
+      int64_t task = 0;   // panels of the group's blocks so far
+      for (int64_t b = b0; b < b1; ++b) {
+        const int64_t i0 = a.in_ptr[b], i1 = a.in_ptr[b + 1], off = a.a_off[b];
+        const int64_t n = i1 - i0;
+        const int64_t np = ((TRANS ? m : n) + kPanel - 1) / kPanel;
+        int64_t p = ((wave - task) % W + W) % W;  // this wave's first panel of block b
+        task += np;
+        if (p >= np) continue;
+        if (!(i0 >= 0 && i0 <= i1 && i1 <= a.in_len && n <= kMaxVec && off >= 0 &&
+              off <= a.a_len && (m == 0 || n <= (a.a_len - off) / m))) {
+          if (lane == 0 && c == 0) atomicOr(a.flags, FLAG_EINVAL);
+          continue;  // uniform in the wave
         }
-      }
-      __syncthreads();
-      if (!TRANS) {
-        // wave w takes the columns j = w, w + 4, ...; lane l the rows l + 64 c
-        for (int c = 0; c < kChunks; ++c) acc[c] = T::zero();
-        for (int64_t j = wave; j < n; j += W) {
-          const T xj = xs[j];
+        for (; p < np; p += W) {
+          const int64_t j0 = p * kPanel;
+          if (!TRANS) {
+            const int jn = (int)min((int64_t)kPanel, n - j0);
+            T xl = T::zero();
+            if (lane < jn) {
+              const int id = a.in_idx[i0 + j0 + lane];
+              if (id >= 0 && id < a.x_len) xl = T::load(x, id);
+              else if (c == 0) atomicOr(a.flags, FLAG_EINVAL);
+            }
+            // the panel's first column at a uniform address, the rest by
+            // 32-bit offsets (m, n <= 512)
+            const double *P = A + (CPLX ? 2 : 1) * (off + m * j0);
+            const int i = lane + kWave * c, mi = (int)m;
+            const bool in = i < mi;
+            T av[kPanel];
 #pragma unroll
-          for (int c = 0; c < kChunks; ++c) {
-            const int64_t i = lane + kWave * c;
-            if (i < m) acc[c].fma_into(A, off + i + m * j, xj);
+            for (int u = 0; u < kPanel; ++u)
+              av[u] = in && u < jn ? T::load(P, i + mi * u) : T::zero();
+#pragma unroll
+            for (int u = 0; u < kPanel; ++u) acc.fma(av[u], xl.lane(u));
+          } else {
+            const int jn = (int)min((int64_t)kPanel, m - j0);
+            T s[kPanel];
+#pragma unroll
+            for (int u = 0; u < kPanel; ++u) s[u] = T::zero();
+            const double *P = A + (CPLX ? 2 : 1) * (off + n * j0);
+            const int ni = (int)n;
+#pragma unroll 1
+            for (int i = lane; i - lane < ni; i += kWave) {  // uniform trip count
+              T xi = T::zero();
+              if (i < ni) {
+                const int id = a.in_idx[i0 + i];
+                if (id >= 0 && id < a.x_len) xi = T::load(x, id);
+                else atomicOr(a.flags, FLAG_EINVAL);
+              }
+              T av[kPanel];
+#pragma unroll
+              for (int u = 0; u < kPanel; ++u)
+                av[u] = i < ni && u < jn ? T::load(P, i + ni * u) : T::zero();
+#pragma unroll
+              for (int u = 0; u < kPanel; ++u) s[u].fma(av[u], xi);
+            }
+            // butterfly sums leave every column's total in every lane; lane
+            // u adds output j0 + u
+            T mine = T::zero();
+#pragma unroll
+            for (int u = 0; u < kPanel; ++u) {
+              const T t = s[u].shfl_down_sum();
+              if (lane == u) mine = t;
+            }
+            if (lane < jn) part[wave][j0 + lane].add(mine);
           }
         }
-#pragma unroll
-        for (int c = 0; c < kChunks; ++c) {
-          const int64_t i = lane + kWave * c;
-          if (i < m) part[wave][i].add(acc[c]);
-        }
-      } else {
-        // wave w takes the outputs j = w, w + 4, ...; lanes run down column j
-        for (int64_t j = wave; j < m; j += W) {
-          T s = T::zero();
-          for (int64_t i = lane; i < n; i += kWave) s.fma_into(A, off + i + n * j, xs[i]);
-          s = s.shfl_down_sum();
-          if (lane == 0) part[wave][j].add(s);
-        }
+      }
+      if (!TRANS) {
+        const int64_t i = lane + kWave * (int64_t)c;
+        if (i < m) part[wave][i] = acc;
       }
     }
     __syncthreads();
@@ -155,7 +206,7 @@ __global__ __launch_bounds__(kThreads) void k_gemv(const GemvArgs a) {
       if (id < 0 || id >= a.y_len) atomicOr(a.flags, FLAG_EINVAL);
       else s.add_to(y, id);
     }
-    __syncthreads();  // part is cleared for the next group
+    __syncthreads();  // part is reused by the next group
   }
 }
 

@@ -3,6 +3,7 @@
 // blocks and the near-field assembly with per-entry orders.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -375,6 +376,33 @@ int bem_mlp_load(bem_ctx *ctx, const char *path, int32_t n_out, float *params, f
   if (e == hipSuccess) e = hipStreamSynchronize(s);  // h is released on return
   if (e != hipSuccess) return hip_fail(ctx, e, "writing the network to the device");
   if (step) *step = head[1];
+  return BEM_OK;
+}
+
+int bem_cluster_features(int32_t n, const double *box, const int32_t *begin, const int32_t *end,
+                         const int32_t *height, double kappa, int32_t side, double eps,
+                         float *out) {
+  if (n < 0 || !(eps > 0.0) || (n > 0 && (!box || !begin || !end || !height || !out)))
+    return BEM_EINVAL;
+  const double leps = std::log10(eps);
+  for (int32_t c = 0; c < n; ++c) {
+    double ext[3], d2 = 0.0;
+    for (int k = 0; k < 3; ++k) {
+      ext[k] = box[6 * (int64_t)c + 3 + k] - box[6 * (int64_t)c + k];
+      d2 += ext[k] * ext[k];
+    }
+    std::sort(ext, ext + 3);
+    const double big = std::max(ext[2], 1e-300), diam = std::sqrt(d2);
+    float *x = out + 8 * (int64_t)c;
+    x[0] = (float)std::log2((double)std::max(end[c] - begin[c], 1));
+    x[1] = (float)std::log10(std::max(diam, 1e-300));
+    x[2] = (float)(ext[1] / big);
+    x[3] = (float)(ext[0] / big);
+    x[4] = (float)height[c];
+    x[5] = (float)(kappa * diam);
+    x[6] = (float)side;
+    x[7] = (float)leps;
+  }
   return BEM_OK;
 }
 

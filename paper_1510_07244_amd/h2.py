@@ -25,6 +25,76 @@ def _dev(a, dtype):
     return torch.as_tensor(np.ascontiguousarray(a)).to(device="cuda", dtype=dtype)
 
 
+_PINNED = {}
+
+
+def _pinned(nbytes):
+    """A pinned host byte buffer of at least nbytes, kept for the process
+    (pinned allocations are slow; every setup reuses this one)."""
+    import torch
+    buf = _PINNED.get("buf")
+    if buf is None or buf.numel() < nbytes:
+        buf = torch.empty(max(nbytes, 1 << 22), dtype=torch.uint8, pin_memory=True)
+        _PINNED["buf"] = buf
+    return buf
+
+
+class _Stager:
+    """Host-to-device uploads through a pinned staging buffer, copied
+    asynchronously on the current stream (a synchronous copy from pageable
+    memory would also wait for every kernel queued before it).  The staged
+    bytes must stay untouched until the copies are done: reset() only after
+    the stream has been synchronised."""
+
+    def __init__(self):
+        self.buf, self.pos = None, 0
+
+    def reset(self):
+        self.pos = 0
+
+    def upload(self, *arrays):
+        """Several host arrays (each (array, numpy dtype)) to the device, one
+        copy per dtype; returns device tensors (shapes kept) in order."""
+        import torch
+        groups = {}
+        for k, (a, dt) in enumerate(arrays):
+            groups.setdefault(np.dtype(dt), []).append(k)
+        out = [None] * len(arrays)
+        for dt, ks in groups.items():
+            arrs = [np.ascontiguousarray(arrays[k][0], dtype=dt) for k in ks]
+            n = sum(a.size for a in arrs)
+            nbytes = n * dt.itemsize
+            start = (self.pos + 255) // 256 * 256
+            if self.buf is None or start + nbytes > self.buf.numel():
+                if self.buf is not None and self.pos > 0:
+                    torch.cuda.current_stream().synchronize()  # earlier copies done
+                start = 0
+                if self.buf is None or nbytes > self.buf.numel():
+                    self.buf = torch.empty(max(nbytes, 8 << 20), dtype=torch.uint8,
+                                           pin_memory=True)
+            host = self.buf[start:start + nbytes].view(torch.from_numpy(np.zeros(0, dt)).dtype)
+            hn = host.numpy()
+            o = 0
+            for a in arrs:
+                hn[o:o + a.size] = a.ravel()
+                o += a.size
+            dev = torch.empty(n, dtype=host.dtype, device="cuda")
+            dev.copy_(host, non_blocking=True)
+            self.pos = start + nbytes
+            o = 0
+            for k, a in zip(ks, arrs):
+                out[k] = dev[o:o + a.size].view(a.shape)
+                o += a.size
+        return out
+
+
+_STAGER = _Stager()
+
+
+def _upload(*arrays):
+    return _STAGER.upload(*arrays)
+
+
 class LevelPlan:
     """Device inputs of one tree level of a basis construction (cached so that
     the GPU part can be replayed without the host pivot search)."""
@@ -36,7 +106,7 @@ class ClusterBasis:
         self.rows = [None] * ncl   # triangle ids of the rows of V^_c
         self.piv = [None] * ncl    # pivot triangles t~_c
         self.rank = np.zeros(ncl, dtype=np.int32)
-        self.levels = []           # LevelPlan per height
+        self.levels = []           # LevelPlan per height (needed clusters only)
         self.where = [None] * ncl  # (level index, position in level)
 
     def vhat(self, c):
@@ -86,6 +156,16 @@ class H2Setup:
             s = self.ct.sons[c]
             if s[0] >= 0:
                 self.height[c] = 1 + max(self.height[s[0]], self.height[s[1]])
+        # clusters that need a basis: those of an admissible block and all
+        # their descendants (a father's nested basis is expressed through its
+        # sons'); the clusters above the admissible part of the block tree
+        # (the root and its first descendants) enter no product
+        self.needed = np.zeros(n, dtype=bool)
+        self.needed[np.asarray(far, dtype=np.int64).ravel()] = True
+        for c in range(n):  # fathers before sons (pre-order)
+            s = self.ct.sons[c]
+            if s[0] >= 0 and self.needed[c]:
+                self.needed[s] = True
         self.z, self.zn, self.zw, self.delta = green_points(self.ct.box, qg)
         self.m = self.zw.shape[1]
 
@@ -95,13 +175,10 @@ class H2Setup:
 
     # ----------------------------------------------------------- bases
     def _host_copy(self, A):
-        """A device tensor copied into a pinned host buffer kept across levels
-        (a numpy view, valid until the next call)."""
-        import torch
+        """A device tensor copied into the pinned host buffer (a numpy view,
+        valid until the next call)."""
         nbytes = A.numel() * A.element_size()
-        if getattr(self, "_pin", None) is None or self._pin.numel() < nbytes:
-            self._pin = torch.empty(max(nbytes, 1 << 20), dtype=torch.uint8, pin_memory=True)
-        h = self._pin[:nbytes].view(A.dtype)
+        h = _pinned(nbytes)[:nbytes].view(A.dtype)
         h.copy_(A)
         return h.numpy()
 
@@ -111,7 +188,8 @@ class H2Setup:
 
     def bases(self, sides=(0, 1), rank_caps=None, device_inverse=True):
         """Construct the nested cluster bases of several sides together, level
-        by level: per level one Green-matrix launch per side into one buffer,
+        by level (the clusters of self.needed only; the others keep rank 0 and
+        no pivots): per level one Green-matrix launch per side into one buffer,
         one copy to the host, one pivot search over the clusters of every side
         (twice the clusters per call keep the host threads busy at the top
         levels), then one contraction launch per side.
@@ -137,7 +215,9 @@ class H2Setup:
         self.cap_stats = {"levels": 0, "fallbacks": 0}
         self.bases_time = {"device": 0.0, "copy": 0.0, "pivot_search": 0.0}
         for h in range(int(self.height.max()) + 1):
-            cls = np.nonzero(self.height == h)[0]
+            cls = np.nonzero((self.height == h) & self.needed)[0]
+            if cls.size == 0:
+                continue
             lvs, nrows_all = [], []
             for B in Bs:
                 lv = LevelPlan()
@@ -165,13 +245,10 @@ class H2Setup:
                 a_off = np.zeros(cls.size, dtype=np.int64)
                 a_off[1:] = np.cumsum(nrows.astype(np.int64) * 2 * m)[:-1]
                 size = int(nrows.astype(np.int64).sum() * 2 * m)
-                lv.row_ptr = _dev(rp, torch.int32)
-                lv.row_idx = _dev(lv.row_idx_h, torch.int32)
-                lv.z = _dev(self.z[cls], torch.float64)
-                lv.zn = _dev(self.zn[cls], torch.float64)
-                lv.zw = _dev(self.zw[cls], torch.float64)
-                lv.delta = _dev(self.delta[cls], torch.float64)
-                lv.a_off = _dev(a_off, torch.int64)
+                (lv.row_ptr, lv.row_idx, lv.z, lv.zn, lv.zw, lv.delta, lv.a_off) = _upload(
+                    (rp, np.int32), (lv.row_idx_h, np.int32), (self.z[cls], np.float64),
+                    (self.zn[cls], np.float64), (self.zw[cls], np.float64),
+                    (self.delta[cls], np.float64), (a_off, np.int64))
                 lv.A = A_all[base:base + size]
                 lv.max_rows = int(nrows.max())
                 self.ctx.green_matrix(self.mesh, op, B.side, lv.row_ptr, lv.row_idx, lv.z, lv.zn,
@@ -179,6 +256,7 @@ class H2Setup:
                 base += size
             t0 = time.perf_counter()
             self.ctx.check()
+            _STAGER.reset()  # the stream is idle: staged uploads are done
             t1 = time.perf_counter()
             A_h = self._host_copy(A_all)
             Af = A_h.view(np.float64) if self.cplx else A_h
@@ -217,19 +295,17 @@ class H2Setup:
                 v_off[1:] = np.cumsum(nrows.astype(np.int64) * rank)[:-1]
                 lv.v_off_h = v_off
                 lv.rank_h, lv.pcol_h, lv.prow_h = rank, pcol[sl], prow[sl]
-                lv.nrows = _dev(nrows, torch.int32)
-                lv.rank = _dev(rank, torch.int32)
-                lv.piv_cols = _dev(pcol[sl], torch.int32)
+                lv.nrows, lv.rank, lv.piv_cols, lv.piv_rows, lv.v_off = _upload(
+                    (nrows, np.int32), (rank, np.int32), (pcol[sl], np.int32),
+                    (prow[sl], np.int32), (v_off, np.int64))
                 lv.max_rank = max_rank
                 if device_inverse:
-                    lv.piv_rows = _dev(prow[sl], torch.int32)
                     lv.pinv = torch.empty((cls.size, max_rank * max_rank * (2 if self.cplx else 1)),
                                           dtype=torch.float64, device="cuda")
                     self.ctx.pivot_inverse(self.cplx, lv.nrows, lv.rank, max_rank, lv.piv_rows,
                                            lv.piv_cols, lv.A, lv.a_off, 2 * m, lv.pinv)
                 else:
                     lv.pinv = _dev(pinv[sl], torch.float64)
-                lv.v_off = _dev(v_off, torch.int64)
                 lv.V = torch.empty(int((nrows.astype(np.int64) * rank).sum()), dtype=self.adtype,
                                    device="cuda")
                 self.ctx.basis_contract(self.cplx, lv.nrows, lv.rank, max_rank, lv.piv_cols,
@@ -312,7 +388,9 @@ class H2Setup:
         """Triangle lists of the inadmissible blocks, outputs back to back in
         the order of self.near.  mirror (a single layer): of each pair (t, s),
         (s, t) with t != s only t < s is evaluated, the other written as its
-        transpose (edge-adjacent entries evaluated as (j, i))."""
+        transpose (edge-adjacent entries evaluated as (j, i)); a block (t, t)
+        is its own mirror: its entries with row >= column are evaluated and
+        written transposed too."""
         rows = [self.ct.idx(t) for t, s in self.near]
         cols = [self.ct.idx(s) for t, s in self.near]
         if not mirror:
@@ -323,14 +401,13 @@ class H2Setup:
     @staticmethod
     def _mirrored(pairs, rows, cols, keep):
         """Blocks `keep` of the list (t, s) -> rows, cols, each with the output
-        offset of (s, t) as its mirror (-1 for t == s); the output layout is
-        that of the whole list."""
+        offset of (s, t) as its mirror (its own offset for t == s: the block
+        is its own transpose); the output layout is that of the whole list."""
         sizes = np.array([len(r) * len(c) for r, c in zip(rows, cols)], dtype=np.int64)
         off = np.zeros(len(rows), dtype=np.int64)
         off[1:] = np.cumsum(sizes)[:-1]
         pos = {(int(t), int(s)): k for k, (t, s) in enumerate(pairs)}
-        mirror_off = np.array([-1 if pairs[k][0] == pairs[k][1] else
-                               off[pos[(int(pairs[k][1]), int(pairs[k][0]))]] for k in keep],
+        mirror_off = np.array([off[pos[(int(pairs[k][1]), int(pairs[k][0]))]] for k in keep],
                               dtype=np.int64)
         kr = [rows[k] for k in keep]
         kc = [cols[k] for k in keep]

@@ -21,6 +21,19 @@ def _dev(a, dtype):
     return torch.as_tensor(np.ascontiguousarray(a)).to(device="cuda", dtype=dtype)
 
 
+def _on(stream):
+    """Context making `stream` (a torch stream or a raw HIP stream handle)
+    torch's current stream, so that the tensor operations around the library
+    calls (zeroing, copies, scalar reads) are ordered with them."""
+    import contextlib
+    import torch
+    if stream is None:
+        return contextlib.nullcontext()
+    if not isinstance(stream, torch.cuda.Stream):
+        stream = torch.cuda.ExternalStream(int(stream))
+    return torch.cuda.stream(stream)
+
+
 class _Call:
     """Device index lists of one bem_gemv_grouped call."""
 
@@ -74,14 +87,21 @@ class H2Matrix:
         self.xh = torch.zeros(int(self.cw[-1]), dtype=self.dtype, device="cuda")
         self.yh = torch.zeros(int(self.cv[-1]), dtype=self.dtype, device="cuda")
         rng = lambda off, c: np.arange(off[c], off[c] + (off[c + 1] - off[c]))
-        # near field, grouped by row leaf
+        # near field, grouped by row cluster; a block is inadmissible when
+        # either cluster is a leaf, so a row cluster may be a father whose
+        # triangles are its sons' too: one call per height of the row cluster
+        # (clusters of one height are disjoint, so a call's groups never
+        # share an output)
         rows = {}
         o = 0
         for t, s in h.near:
             t, s = int(t), int(s)
             rows.setdefault(t, []).append((o, ct.idx(s)))
             o += ct.idx(t).size * ct.idx(s).size
-        self.near_call = _Call([(ct.idx(t), bl) for t, bl in rows.items()], False, near, "x", "y")
+        by_height = {}
+        for t, bl in rows.items():
+            by_height.setdefault(int(h.height[t]), []).append((ct.idx(t), bl))
+        self.near_calls = [_Call(g, False, near, "x", "y") for _, g in sorted(by_height.items())]
         # forward transformation of the column basis, level by level upwards
         fwd = []
         for lv in col_basis.levels:
@@ -116,6 +136,7 @@ class H2Matrix:
             leaf = ct.sons[int(lv.cls[0]), 0] < 0
             bwd.append(_Call(groups, False, lv.V, "yh", "y" if leaf else "yh"))
         self.fwd, self.bwd = fwd, bwd
+        self.near, self.coupling = near, coupling
         for lv_list in (col_basis.levels, row_basis.levels):
             for lv in lv_list:  # one kind of cluster per level (heights)
                 kinds = {bool(ct.sons[int(c), 0] < 0) for c in lv.cls}
@@ -127,18 +148,21 @@ class H2Matrix:
                               stream=stream)
 
     def matvec(self, x, y, stream=None, accumulate=False):
-        """y (+)= H x for device vectors of n entries."""
-        if not accumulate:
-            y.zero_()
-        self.xh.zero_()
-        self.yh.zero_()
-        bufs = {"x": x, "y": y, "xh": self.xh, "yh": self.yh}
-        self._run(self.near_call, bufs, stream)
-        for c in self.fwd:
-            self._run(c, bufs, stream)
-        self._run(self.coupling_call, bufs, stream)
-        for c in self.bwd:
-            self._run(c, bufs, stream)
+        """y (+)= H x for device vectors of n entries, on `stream` (default:
+        torch's current stream)."""
+        with _on(stream):
+            if not accumulate:
+                y.zero_()
+            self.xh.zero_()
+            self.yh.zero_()
+            bufs = {"x": x, "y": y, "xh": self.xh, "yh": self.yh}
+            for c in self.near_calls:
+                self._run(c, bufs, None)
+            for c in self.fwd:
+                self._run(c, bufs, None)
+            self._run(self.coupling_call, bufs, None)
+            for c in self.bwd:
+                self._run(c, bufs, None)
         return y
 
 
@@ -160,8 +184,15 @@ def cg(ctx, apply, b, x, tol=1e-10, maxit=1000, stream=None):
     positive definite operator `apply(p, q)` (q = A p), from the initial
     guess in x; stops when |r| <= tol |b|.  Returns (iterations, relative
     residual).  Vector updates and dot products are library kernels; the
-    scalars come back to the host once per step."""
+    scalars come back to the host once per step.  Everything runs on
+    `stream` (made torch's current stream, which `apply` is called on)."""
+    with _on(stream):
+        return _cg(ctx, apply, b, x, tol, maxit)
+
+
+def _cg(ctx, apply, b, x, tol, maxit):
     import torch
+    stream = None
     dot = _Dot(ctx)
     r = torch.empty_like(b)
     q = torch.empty_like(b)
@@ -187,8 +218,14 @@ def cg(ctx, apply, b, x, tol=1e-10, maxit=1000, stream=None):
 def bicgstab(ctx, apply, b, x, tol=1e-10, maxit=1000, stream=None):
     """BiCGStab (van der Vorst) for a general (complex) operator
     `apply(p, q)`; stops when |r| <= tol |b|.  Returns (iterations, relative
-    residual)."""
+    residual).  Runs on `stream` like cg."""
+    with _on(stream):
+        return _bicgstab(ctx, apply, b, x, tol, maxit)
+
+
+def _bicgstab(ctx, apply, b, x, tol, maxit):
     import torch
+    stream = None
     dot = _Dot(ctx)
     r = torch.empty_like(b)
     v = torch.empty_like(b)

@@ -11,6 +11,7 @@ training inputs before training.
 import numpy as np
 
 from . import SEL_OUT, Blocks, ClusterTree, Mesh, block_tree, mlp_params
+from . import cluster_features as _cluster_features
 
 
 def near_pairs(v, tri, count, seed, leaf=64, eta=2.0):
@@ -40,14 +41,40 @@ def near_pairs(v, tri, count, seed, leaf=64, eta=2.0):
     return np.concatenate(rows).astype(np.int32), np.concatenate(cols).astype(np.int32)
 
 
+def far_pairs(v, tri, count, seed, leaf=64, eta=2.0):
+    """`count` pairs drawn uniformly (seeded PCG64) from the entries of the
+    admissible blocks of the mesh's block tree (the coupling blocks' pairs
+    are a subset of these)."""
+    tri = np.asarray(tri)
+    ct = ClusterTree(v, tri, leaf=leaf)
+    _, far = block_tree(ct, eta=eta)
+    nr = (ct.end - ct.begin)[far[:, 0]].astype(np.int64)
+    nc = (ct.end - ct.begin)[far[:, 1]].astype(np.int64)
+    if far.shape[0] == 0:
+        raise ValueError(f"far_pairs: the {tri.shape[0]}-triangle mesh has no admissible "
+                         f"blocks at leaf {leaf}, eta {eta}")
+    size = nr * nc
+    cum = np.cumsum(size)
+    rng = np.random.Generator(np.random.PCG64(seed))
+    k = rng.integers(0, cum[-1], size=count)
+    b = np.searchsorted(cum, k, side="right")
+    local = k - (cum[b] - size[b])
+    r = ct.perm[ct.begin[far[b, 0]] + local % nr[b]]
+    c = ct.perm[ct.begin[far[b, 1]] + local // nr[b]]
+    return r.astype(np.int32), c.astype(np.int32)
+
+
 def samples(ctx, jobs):
-    """Training samples for a list of (mesh arrays v, tri, op, count, seed):
-    returns device tensors X (n, 8) and T (n, 6)."""
+    """Training samples for a list of (mesh arrays v, tri, op, count, seed)
+    or (..., seed, "far"): pairs of the near field (default) or of the
+    admissible blocks; returns device tensors X (n, 8) and T (n, 6)."""
     import torch
     xs, ts = [], []
-    for v, tri, op, count, seed in jobs:
+    for job in jobs:
+        v, tri, op, count, seed = job[:5]
+        far = len(job) > 5 and job[5] == "far"
         mesh = Mesh(torch.from_numpy(np.asarray(v)), torch.from_numpy(np.asarray(tri)))
-        r, c = near_pairs(v, tri, count, seed)
+        r, c = (far_pairs if far else near_pairs)(v, tri, count, seed)
         rows = torch.from_numpy(r).cuda()
         cols = torch.from_numpy(c).cuda()
         x = torch.empty((r.size, 8), dtype=torch.float32, device="cuda")
@@ -160,21 +187,14 @@ RANK_SCALE = 100.0  # network output = rank / RANK_SCALE
 
 
 def cluster_features(h, side):
-    """Eight inputs per cluster of an H2 setup `h` for the rank head:
-    log2 of its triangle count, log10 of its box diagonal, the box's middle
-    and smallest extent over its largest, its height in the tree, kappa times
-    the diagonal, the side (0 rows, 1 double-layer columns), log10 of the
-    pivot-search tolerance."""
+    """Eight inputs per cluster of an H2 setup `h` for the rank head
+    (bem_cluster_features: log2 of its triangle count, log10 of its box
+    diagonal, the box's middle and smallest extent over its largest, its
+    height in the tree, kappa times the diagonal, the side (0 rows, 1
+    double-layer columns), log10 of the pivot-search tolerance)."""
     ct = h.ct
-    lo, hi = ct.box[:, :3], ct.box[:, 3:]
-    ext = np.sort(hi - lo, axis=1)
-    big = np.maximum(ext[:, 2], 1e-300)
-    diam = np.linalg.norm(hi - lo, axis=1)
-    n = np.maximum(ct.end - ct.begin, 1).astype(np.float64)
-    X = np.stack([np.log2(n), np.log10(np.maximum(diam, 1e-300)), ext[:, 1] / big,
-                  ext[:, 0] / big, h.height.astype(np.float64), h.kappa * diam,
-                  np.full(ct.n, float(side)), np.full(ct.n, np.log10(h.eps))], axis=1)
-    return X.astype(np.float32)
+    return _cluster_features(ct.box, ct.begin[:ct.n], ct.end[:ct.n], h.height, h.kappa, side,
+                             h.eps)
 
 
 class RankHead:
@@ -193,7 +213,7 @@ class RankHead:
         X, R = [], []
         for h, Bs in items:
             for B in Bs:
-                keep = B.rank >= 0
+                keep = h.needed
                 X.append(cluster_features(h, B.side)[keep])
                 R.append(B.rank[keep].astype(np.float32))
         return np.concatenate(X), np.concatenate(R)

@@ -260,12 +260,31 @@ def test_coupling_real_pivots_helmholtz_dlp_k8(pk, ctx):
     _contraction_parity(h, W, cplx=True, per_level=3)
 
 
+def _complete_pivoting_order(M):
+    """Row and column orders in which Gaussian elimination on M takes the
+    largest remaining entry as each pivot (what the cross approximation's
+    full pivoting gives the pivot block)."""
+    R = np.array(M, dtype=np.complex128)
+    rows, cols = list(range(M.shape[0])), list(range(M.shape[1]))
+    orow, ocol = [], []
+    for _ in range(M.shape[0]):
+        sub = np.abs(R[np.ix_(rows, cols)])
+        i, j = np.unravel_index(np.argmax(sub), sub.shape)
+        r, c = rows[i], cols[j]
+        R -= np.outer(R[:, c], R[r, :]) / R[r, c]
+        orow.append(r), ocol.append(c)
+        rows.remove(r), cols.remove(c)
+    return np.array(orow), np.array(ocol)
+
+
 @pytest.mark.parametrize("cplx", [False, True])
 def test_pivot_inverse_against_oracle(pk, ctx, cplx):
     """bem_pivot_inverse on seeded matrices with pivot rows and columns
-    scattered in a larger one (ragged ranks, k = 1, a zero leading entry
-    that needs a row exchange), against the oracle's Gauss-Jordan inverse
-    relative to the block's condition number."""
+    scattered in a larger one (ragged ranks, k = 1, a zero entry in the
+    block), listed in complete-pivoting order as the cross approximation
+    lists them, against the oracle's Gauss-Jordan inverse relative to the
+    block's condition number.  A list whose first pivot is zero raises
+    BEM_ENONFINITE."""
     import torch
     rng = np.random.Generator(np.random.PCG64(30 + cplx))
     acols, max_rank = 48, 40
@@ -276,8 +295,9 @@ def test_pivot_inverse_against_oracle(pk, ctx, cplx):
         pr = rng.choice(n, size=k, replace=False)
         pc = rng.choice(acols, size=k, replace=False)
         if k > 1:
-            A[pr[0], pc[0]] = 0.0  # the first pivot needs a row exchange
-        A_list.append(A), prow.append(pr), pcol.append(pc)
+            A[pr[0], pc[0]] = 0.0  # a zero in the block
+        orow, ocol = _complete_pivoting_order(A[np.ix_(pr, pc)])
+        A_list.append(A), prow.append(pr[orow]), pcol.append(pc[ocol])
     nrows = np.array([s[0] for s in shapes], dtype=np.int32)
     rank = np.array([s[1] for s in shapes], dtype=np.int32)
     a_off = np.concatenate([[0], np.cumsum(nrows * acols)[:-1]]).astype(np.int64)
@@ -305,3 +325,16 @@ def test_pivot_inverse_against_oracle(pk, ctx, cplx):
         cond = np.linalg.cond(M)
         assert np.linalg.norm(P - ref) <= 1e-13 * cond * np.linalg.norm(ref), (t, cond)
         assert np.abs(M @ P - np.eye(k)).max() <= 1e-13 * cond, t
+    # a zero first pivot: the device flag, reported at the check
+    t = 0
+    zr = np.where(A_list[t] == 0.0)
+    PR0, PC0 = PR.copy(), PC.copy()
+    PR0[t, 0], PC0[t, 0] = zr[0][0], zr[1][0]
+    PR0[t, 1:rank[t]] = [r for r in prow[t] if r != zr[0][0]][:rank[t] - 1]
+    PC0[t, 1:rank[t]] = [c for c in pcol[t] if c != zr[1][0]][:rank[t] - 1]
+    ctx.pivot_inverse(cplx, dev(nrows, torch.int32), dev(rank, torch.int32), max_rank,
+                      dev(PR0, torch.int32), dev(PC0, torch.int32), A_dev,
+                      dev(a_off, torch.int64), acols, pinv)
+    with pytest.raises(pk.BemError) as err:
+        ctx.check()
+    assert err.value.code == pk.BEM_ENONFINITE

@@ -330,3 +330,56 @@ def test_mlp_save_load_resumes_training_bitwise(pk, ctx, tmp_path):
     with pytest.raises(pk.BemError) as e:
         ctx.mlp_load(path, 1, P2)  # another n_out
     assert e.value.code == pk.BEM_EINVAL
+
+
+def test_learned_coupling_keeps_h2_accuracy(pk, ctx):
+    """Orders chosen per entry of the coupling blocks (pivot lists of the
+    admissible blocks) by a network trained on near-field and admissible
+    pairs: the H2 blocks V_t S W_s^T of the 8192-triangle sphere stay within
+    1e-6 of the dense oracle, the coupling matrices within 1e-6 of the plain
+    ones, with far fewer quadrature points."""
+    import torch
+    from h2util import FullBases, coupling_matrix, coupling_offsets
+    from paper_1510_07244_amd.h2 import H2Setup
+    from paper_1510_07244_amd.selector import Selector, samples
+    jobs = []
+    for n, cnt in ((8, 20000), (16, 40000), (32, 60000)):
+        m = octahedron_sphere(n)
+        for layer in (0, 1):
+            jobs.append((m.v, m.tri, pk.make_op(pk.LAPLACE, layer), cnt, 100 * n + layer))
+            if n > 8:  # the 512-triangle sphere has no admissible blocks
+                jobs.append((m.v, m.tri, pk.make_op(pk.LAPLACE, layer), cnt // 2,
+                             300 * n + layer, "far"))
+    X, T = samples(ctx, jobs)
+    sel = Selector(ctx, seed=1)
+    sel.set_standardisation(X)
+    sel.fit(X, T, epochs=12, batch=2048, lr=2e-3, seed=2)
+    m = octahedron_sphere(32)
+    h = H2Setup(ctx, m.v, m.tri)
+    V, W = h.bases((0, 1))
+    for layer, B in ((pk.SLP, V), (pk.DLP, W)):
+        op = h.op(layer)
+        blocks, total = h.coupling_blocks(V, B)
+        plain = torch.empty(total, dtype=torch.float64, device="cuda")
+        ctx.assemble_coupling(h.mesh, op, blocks, plain)
+        orders = sel.orders(h.mesh, op, blocks, total, tol=1e-7, margin=0.5)
+        learned = torch.full_like(plain, float("nan"))
+        ctx.assemble_nearfield_learned(h.mesh, op, blocks, orders, learned)
+        ctx.check()
+        q = orders.cpu().numpy().astype(np.int64)
+        assert q.min() >= 2 and q.max() <= 4
+        saved = 1.0 - float((q ** 4).sum()) / (q.size * 4 ** 4)
+        assert saved >= 0.5, saved  # admissible pairs are far apart
+        P, L = plain.cpu().numpy(), learned.cpu().numpy()
+        offs, _ = coupling_offsets(h, V, B)
+        Vf, Bf = FullBases(h, V), FullBases(h, B)
+        for k in sample_subset(np.arange(len(h.far)), 25, seed=7 + layer):
+            t, s = h.far[k]
+            kt, ks = V.piv[t].size, B.piv[s].size
+            Sp = coupling_matrix(P, offs[k], kt, ks)
+            Sl = coupling_matrix(L, offs[k], kt, ks)
+            assert np.linalg.norm(Sl - Sp) <= 1e-6 * np.linalg.norm(Sp), (layer, k)
+            ref = oracle.block(m.v, m.tri, h.ct.idx(t), h.ct.idx(s), layer=layer, q_reg=4,
+                               q_sing=4).real
+            err = np.linalg.norm(Vf(t) @ Sl @ Bf(s).T - ref) / np.linalg.norm(ref)
+            assert err <= 1e-6, (layer, k, err)

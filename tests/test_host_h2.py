@@ -104,3 +104,32 @@ def test_rank_head_cluster_features():
     assert np.allclose(X[:, 7], np.log10(5e-8))
     sons = ct.sons[0]
     assert X[sons[0], 0] < X[0, 0] and X[sons[0], 1] <= X[0, 1] + 1e-7
+
+
+def test_cluster_features_follow_their_definition():
+    """bem_cluster_features against the eight inputs written out here: log2
+    of the triangle count, log10 of the box diagonal, middle and smallest box
+    extent over the largest, height, kappa times the diagonal, side, log10 of
+    the tolerance (a flat box and a one-triangle cluster included)."""
+    import paper_1510_07244_amd as pk
+    m = octahedron_sphere(8)
+    ct = pk.ClusterTree(m.v, m.tri)
+    height = np.zeros(ct.n, dtype=np.int32)
+    for c in range(ct.n - 1, -1, -1):
+        s = ct.sons[c]
+        if s[0] >= 0:
+            height[c] = 1 + max(height[s[0]], height[s[1]])
+    box = ct.box.copy()
+    begin, end = ct.begin.copy(), ct.end.copy()
+    box[0, 2] = box[0, 5]  # a flat box
+    end[1] = begin[1] + 1  # one triangle
+    X = pk.cluster_features(box, begin, end, height, 3.0, 1, 5e-8)
+    for c in range(ct.n):
+        e = sorted(box[c, 3:] - box[c, :3])
+        d = float(np.sqrt(sum(x * x for x in e)))
+        ref = [np.log2(max(end[c] - begin[c], 1)), np.log10(d), e[1] / e[2], e[0] / e[2],
+               height[c], 3.0 * d, 1.0, np.log10(5e-8)]
+        assert np.allclose(X[c], np.float32(ref), rtol=1e-6, atol=1e-7), c
+    assert X[0, 3] == 0.0 and X[1, 0] == 0.0
+    with pytest.raises(pk.BemError):
+        pk.cluster_features(box, begin, end, height, 3.0, 1, 0.0)
