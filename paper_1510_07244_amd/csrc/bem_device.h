@@ -25,9 +25,13 @@ __device__ __forceinline__ double rsqrt_newton(double a) {
 
 // sin and cos of x: Cody-Waite reduction x = k pi/2 + r, |r| <= pi/4, with
 // pi/2 split into three parts (the first two with 33 significant bits so that
-// k * part is exact for |k| < 2^20), then the Taylor polynomials of sin and
-// cos on [-pi/4, pi/4] truncated after x^17 / x^18 (remainders below 1e-19),
-// and the quadrant of k.
+// k * part is exact for |k| < 2^20), then sin r = r + r^3 P(r^2) and
+// cos r = 1 - r^2 / 2 + r^4 Q(r^2) with P, Q of degree 5 whose coefficients
+// minimise the error relative to sin r and cos r on [-pi/4, pi/4] (Remez
+// exchange on the Taylor tail, computed by sincos_minimax.py beside this
+// file: below 1.1e-17 and 1.2e-18 with the coefficients rounded to double,
+// against 8 and 9 coefficients for Taylor polynomials of that accuracy), and
+// the quadrant of k.
 constexpr double kTwoOverPi = 0.63661977236758134308;
 constexpr double kPio2a = 1.5707963267341256;     // 0x1.921fb544p+0
 constexpr double kPio2b = 6.077100506303966e-11;  // 0x1.0b4611a6p-34
@@ -39,24 +43,20 @@ __device__ __forceinline__ void sincos_cw(double x, double *s, double *c) {
   r = fma(-k, kPio2b, r);
   r = fma(-k, kPio2c, r);
   const double r2 = r * r;
-  double ps = 1.0 / 355687428096000.0;       //  1/17!
-  ps = fma(ps, r2, -1.0 / 1307674368000.0);  // -1/15!
-  ps = fma(ps, r2, 1.0 / 6227020800.0);      //  1/13!
-  ps = fma(ps, r2, -1.0 / 39916800.0);       // -1/11!
-  ps = fma(ps, r2, 1.0 / 362880.0);          //  1/9!
-  ps = fma(ps, r2, -1.0 / 5040.0);           // -1/7!
-  ps = fma(ps, r2, 1.0 / 120.0);             //  1/5!
-  ps = fma(ps, r2, -1.0 / 6.0);              // -1/3!
+  double ps = 0x1.5d8fd1fcbc639p-33;  // P, highest degree first
+  ps = fma(ps, r2, -0x1.ae5e5a9290a58p-26);
+  ps = fma(ps, r2, 0x1.71de3567d4885p-19);
+  ps = fma(ps, r2, -0x1.a01a019bfdf03p-13);
+  ps = fma(ps, r2, 0x1.111111110f7d0p-7);
+  ps = fma(ps, r2, -0x1.5555555555548p-3);
   const double sr = fma(r * r2, ps, r);
-  double pc = -1.0 / 6402373705728000.0;     // -1/18!
-  pc = fma(pc, r2, 1.0 / 20922789888000.0);  //  1/16!
-  pc = fma(pc, r2, -1.0 / 87178291200.0);    // -1/14!
-  pc = fma(pc, r2, 1.0 / 479001600.0);       //  1/12!
-  pc = fma(pc, r2, -1.0 / 3628800.0);        // -1/10!
-  pc = fma(pc, r2, 1.0 / 40320.0);           //  1/8!
-  pc = fma(pc, r2, -1.0 / 720.0);            // -1/6!
-  pc = fma(pc, r2, 1.0 / 24.0);              //  1/4!
-  pc = fma(pc, r2, -0.5);                    // -1/2!
+  double pc = -0x1.8fa49a08c34a9p-37;  // Q, highest degree first
+  pc = fma(pc, r2, 0x1.1ee9d7b4e4aa0p-29);
+  pc = fma(pc, r2, -0x1.27e4f7eac4bd6p-22);
+  pc = fma(pc, r2, 0x1.a01a019c844f5p-16);
+  pc = fma(pc, r2, -0x1.6c16c16c14f91p-10);
+  pc = fma(pc, r2, 0x1.555555555554bp-5);
+  pc = fma(pc, r2, -0.5);
   const double cr = fma(r2, pc, 1.0);
   const int q = static_cast<int>(k) & 3;
   const double a = (q & 1) ? cr : sr;
@@ -67,23 +67,22 @@ __device__ __forceinline__ void sincos_cw(double x, double *s, double *c) {
 
 // FP32 sine and cosine for the mixed-precision path: the same Cody-Waite
 // reduction with pi/2 truncated to 12 + 12 + 24 significant bits (k * part
-// exact for |k| < 2^12), Taylor polynomials to x^9 / x^10 (remainders below
-// 2e-9 on [-pi/4, pi/4]).
+// exact for |k| < 2^12), minimax P and Q of degree 2 from the same
+// construction (relative errors below 8.4e-9 and 1.8e-10 with the
+// coefficients rounded to float).
 __device__ __forceinline__ void sincos_cw_f32(float x, float *s, float *c) {
   const float k = __builtin_rintf(x * 0.63661977f);
   float r = fmaf(-k, 1.5703125f, x);              // 0x1.92p+0
   r = fmaf(-k, 4.837512969970703125e-4f, r);      // 0x1.fb4p-12
   r = fmaf(-k, 7.549789415861596e-8f, r);         // 0x1.4442dp-24
   const float r2 = r * r;
-  float ps = 1.0f / 362880.0f;
-  ps = fmaf(ps, r2, -1.0f / 5040.0f);
-  ps = fmaf(ps, r2, 1.0f / 120.0f);
-  ps = fmaf(ps, r2, -1.0f / 6.0f);
+  float ps = -0x1.9943e0p-13f;
+  ps = fmaf(ps, r2, 0x1.11073ap-7f);
+  ps = fmaf(ps, r2, -0x1.555546p-3f);
   const float sr = fmaf(r * r2, ps, r);
-  float pc = -1.0f / 3628800.0f;
-  pc = fmaf(pc, r2, 1.0f / 40320.0f);
-  pc = fmaf(pc, r2, -1.0f / 720.0f);
-  pc = fmaf(pc, r2, 1.0f / 24.0f);
+  float pc = 0x1.99eb9cp-16f;
+  pc = fmaf(pc, r2, -0x1.6c0c34p-10f);
+  pc = fmaf(pc, r2, 0x1.55554ap-5f);
   pc = fmaf(pc, r2, -0.5f);
   const float cr = fmaf(r2, pc, 1.0f);
   const int q = static_cast<int>(k) & 3;
