@@ -14,6 +14,14 @@ bench run printed (roofline.ms_per_launch in its JSON line).
 counters: per-dispatch counter values of the listed launches (kernel name
 and grid size), and the FLOP count the VALU instruction counters give:
 64 lanes x (2 FMA + ADD + MUL + TRANS) per wave instruction, per precision.
+
+traffic: the block-kernel launches of `bench.py --counter-pass` (near field
+of each layer, the double layer's coupling, the one-pass near field) from
+its counter passes -- HBM bytes from FETCH_SIZE and WRITE_SIZE, each scaled
+by its reading of the pass's closing 512 MiB copy, counted FLOPs, issue
+counters -- beside the algorithmic bytes and flops and the durations of the
+same launches in a kernel trace of the bench; ends with the values bench.py
+reads for roofline.traffic and the hash of the sources they stay valid for.
 """
 import argparse
 import collections
@@ -119,6 +127,109 @@ def cmd_counters(a):
     print("\n".join(out))
 
 
+def _counter_rows(path):
+    """(kernel, workgroups) -> list of {counter: value} per dispatch, in
+    dispatch order."""
+    per = collections.OrderedDict()
+    for r in csv.DictReader(open(path)):
+        key = (int(r["Dispatch_Id"]), _kname(r["Kernel_Name"]), _grid_wg(r))
+        per.setdefault(key, {})[r["Counter_Name"]] = float(r["Counter_Value"])
+    out = collections.OrderedDict()
+    for (_, name, wg), v in sorted(per.items()):
+        out.setdefault((name, wg), []).append(v)
+    return out
+
+
+def cmd_traffic(a):
+    import hashlib
+    import os
+    runs = [_counter_rows(p) for p in a.csv]
+    trace = read_trace(a.trace) if a.trace else {}
+    js = bench_json(a.bench_log) if a.bench_log else None
+    # the launches, identified by kernel and workgroups (k-th occurrence)
+    launches = [("SLP near field (2400 blocks)", "k_blocks<0, 0, 8, false>", 2400, 0,
+                 a.near_entries * 8, None),
+                ("DLP near field (2400 blocks)", "k_blocks<0, 1, 8, false>", 2400, 0,
+                 a.near_entries * 8, "near_per_layer.roofline_dlp"),
+                ("DLP coupling (3760 blocks)", "k_blocks<0, 1, 8, false>", 3760, 0,
+                 a.coupling_entries * 8, "roofline"),
+                ("SLP+DLP near field, one pass (1292 blocks)", "k_blocks<0, 2, 8, false>", 1292, 0,
+                 2 * a.near_entries * 8, "roofline_near_both")]
+
+    def value(name, wg, k, counter):
+        for run in runs:
+            v = run.get((name, wg))
+            if v and k < len(v) and counter in v[k]:
+                return v[k][counter]
+        return None
+
+    # calibration: the largest copy of the pass (512 MiB read and written)
+    copies = [v for run in runs for (n, wg), vs in run.items() if n == "__amd_rocclr_copyBuffer"
+              for v in vs]
+    cf = max((c["FETCH_SIZE"] for c in copies if "FETCH_SIZE" in c), default=None)
+    cw = max((c["WRITE_SIZE"] for c in copies if "WRITE_SIZE" in c), default=None)
+    kib = a.copy_bytes / 1024
+    fs, ws = kib / cf, kib / cw
+    out = [f"# {a.title}", "", "Commands (repository root, MI355X, one GPU; one counter pass per run):",
+           "", "    export TMPDIR=/tmp"] + [f"    {c}" for c in a.cmd] + ["",
+           "Made by `bench_profile.py traffic` from the runs' counter-collection CSVs (and the",
+           "kernel trace and JSON line of a bench run for durations and algorithmic flops).", "",
+           f"Calibration: the pass's closing copy of {a.copy_bytes} bytes reads FETCH_SIZE = "
+           f"{cf:.0f} KiB and WRITE_SIZE = {cw:.0f} KiB, so FETCH_SIZE is scaled by {fs:.4f} and "
+           f"WRITE_SIZE by {ws:.4f}.", "",
+           "| Launch | FETCH_SIZE KiB | WRITE_SIZE KiB | HBM bytes (scaled) | algorithmic bytes "
+           "(output) | write / output | SQ_INSTS_VALU | SQ_INSTS_LDS | FP64 FLOP counted | "
+           "FP32 FLOP counted | algorithmic FLOP | counted / algorithmic | trace ms (last 5) | "
+           "counted TFLOP/s |",
+           "|---|---|---|---|---|---|---|---|---|---|---|---|---|---|"]
+    stored = None
+    for label, name, wg, k, out_bytes, key in launches:
+        f, w = value(name, wg, k, "FETCH_SIZE"), value(name, wg, k, "WRITE_SIZE")
+        hbm = 1024 * (f * fs + w * ws) if f is not None and w is not None else None
+
+        def flop(p):
+            parts = [value(name, wg, k, f"SQ_INSTS_VALU_{x}_{p}") for x in ("FMA", "ADD", "MUL",
+                                                                        "TRANS")]
+            if any(x is None for x in parts):
+                return None
+            return 64 * (2 * parts[0] + parts[1] + parts[2] + parts[3])
+        f64, f32 = flop("F64"), flop("F32")
+        model = None
+        if js and key:
+            node = js
+            for part in key.split("."):
+                node = node.get(part) if isinstance(node, dict) else None
+            model = node.get("flops_per_launch") if isinstance(node, dict) else None
+        d = trace.get((name, wg))
+        ms = sum(d[-5:]) / len(d[-5:]) / 1e6 if d else None
+        fmt = lambda x, spec: "-" if x is None else format(x, spec)
+        out.append(f"| {label} | {fmt(f, '.0f')} | {fmt(w, '.0f')} | {fmt(hbm, '.4g')} | "
+                   f"{out_bytes:.4g} | {fmt(None if w is None else 1024 * w * ws / out_bytes, '.2f')} | "
+                   f"{fmt(value(name, wg, k, 'SQ_INSTS_VALU'), '.4g')} | "
+                   f"{fmt(value(name, wg, k, 'SQ_INSTS_LDS'), '.4g')} | {fmt(f64, '.4g')} | "
+                   f"{fmt(f32, '.4g')} | {fmt(model, '.4g')} | "
+                   f"{fmt(None if model is None or f64 is None else (f64 + (f32 or 0)) / model, '.3f')} | "
+                   f"{fmt(ms, '.4f')} | {fmt(None if ms is None or f64 is None else f64 / ms / 1e9, '.2f')} |")
+        if key == "roofline":
+            stored = (f, w)
+    out += ["", f"Algorithmic output: near field {a.near_entries:,} FP64 entries = "
+                f"{a.near_entries * 8 / 1e6:.1f} MB per launch and layer; DLP coupling "
+                f"{a.coupling_entries:,} entries = {a.coupling_entries * 8 / 1e6:.1f} MB.",
+            "Counted FLOP = 64 lanes x (2 FMA + ADD + MUL + TRANS) per wave instruction; the",
+            "algorithmic FLOP are bench.py's model (the roofline numerator): counted over model",
+            "is the instruction overhead of the reciprocal square root, its Newton step and the",
+            "quadrature bookkeeping.", ""]
+    h = hashlib.sha256()
+    for src in a.sources:
+        h.update(open(os.path.join(a.root, src), "rb").read())
+    out += ["Values read by bench.py (roofline.traffic of the DLP coupling launch, bytes",
+            "per launch; valid while the sources below hash to this value):", "",
+            f"    source_sha256: {h.hexdigest()}", f"    sources: {' '.join(a.sources)}",
+            f"    fetch_kib_per_launch: {stored[0]:.0f}", f"    write_kib_per_launch: {stored[1]:.0f}",
+            f"    fetch_scale: {fs:.6f}", f"    write_scale: {ws:.6f}"]
+    print("\n".join(out))
+
+
 def main():
     p = argparse.ArgumentParser()
     sub = p.add_subparsers(dest="what", required=True)
@@ -138,8 +249,19 @@ def main():
     c.add_argument("--cmd", required=True)
     c.add_argument("--title", required=True)
     c.add_argument("--min-grid", type=int, default=0)
+    r = sub.add_parser("traffic")
+    r.add_argument("--csv", nargs="+", required=True, help="counter-collection CSVs")
+    r.add_argument("--cmd", nargs="+", required=True)
+    r.add_argument("--title", required=True)
+    r.add_argument("--trace")
+    r.add_argument("--bench-log")
+    r.add_argument("--near-entries", type=int, required=True)
+    r.add_argument("--coupling-entries", type=int, required=True)
+    r.add_argument("--copy-bytes", type=int, default=512 * 1024 * 1024)
+    r.add_argument("--sources", nargs="+", required=True)
+    r.add_argument("--root", default=".")
     a = p.parse_args()
-    cmd_trace(a) if a.what == "trace" else cmd_counters(a)
+    {"trace": cmd_trace, "counters": cmd_counters, "traffic": cmd_traffic}[a.what](a)
 
 
 if __name__ == "__main__":

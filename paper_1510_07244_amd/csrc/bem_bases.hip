@@ -226,6 +226,12 @@ struct Z<false> {
   __device__ Z operator-(const Z &o) const { return make(v - o.v, 0); }
   __device__ Z div(const Z &o) const { return make(v / o.v, 0); }
   __device__ bool finite_nonzero() const { return v != 0.0 && isfinite(v); }
+  // the value of lane l (l uniform across the wave)
+  __device__ Z lane_value(int l) const {
+    const int lo = __builtin_amdgcn_readlane(__double2loint(v), l);
+    const int hi = __builtin_amdgcn_readlane(__double2hiint(v), l);
+    return make(__hiloint2double(hi, lo), 0);
+  }
 };
 template <>
 struct Z<true> {
@@ -245,6 +251,13 @@ struct Z<true> {
   }
   __device__ bool finite_nonzero() const {
     return (re != 0.0 || im != 0.0) && isfinite(re) && isfinite(im);
+  }
+  __device__ Z lane_value(int l) const {
+    const int rl = __builtin_amdgcn_readlane(__double2loint(re), l);
+    const int rh = __builtin_amdgcn_readlane(__double2hiint(re), l);
+    const int il = __builtin_amdgcn_readlane(__double2loint(im), l);
+    const int ih = __builtin_amdgcn_readlane(__double2hiint(im), l);
+    return make(__hiloint2double(rh, rl), __hiloint2double(ih, il));
   }
 };
 
@@ -298,12 +311,14 @@ __device__ __forceinline__ void gauss_jordan(T *M, int ld, int k, T *fcol, T *ps
 // LDS (leading dimension k + 1 against bank conflicts on column reads) and
 // written out once; larger ones in their global slot.
 template <bool CPLX>
-__global__ __launch_bounds__(kThreads) void k_pivot_inverse(const PivInvArgs a, int lds_k) {
+__global__ __launch_bounds__(kThreads) void k_pivot_inverse(const PivInvArgs a, int lds_k,
+                                                             int reg_k) {
   using T = Z<CPLX>;
   extern __shared__ __align__(16) double inv_lds[];
   __shared__ T fcol[kInvMaxRank], ps[kInvMaxRank];
   const int c = blockIdx.x;
   const int n = a.nrows[c], k = a.rank[c];
+  if (k <= reg_k) return;  // uniform: done by the register-resident kernel
   const int64_t aoff = a.a_off[c];
   if (n < 0 || k < 0 || k > a.max_rank || k > n || aoff < 0 ||
       aoff + (int64_t)n * a.acols > a.a_len) {
@@ -340,6 +355,126 @@ __global__ __launch_bounds__(kThreads) void k_pivot_inverse(const PivInvArgs a, 
   }
 }
 
+// Register-resident form for the common ranks: 16 waves (1024 threads); wave
+// w holds rows w, w + 16, ... (RPW of them) and lane l columns l, l + 64, ...
+// (CPL), so a matrix of up to 16 RPW = 64 CPL rows lives in registers for the
+// whole elimination and LDS only carries, per step, column s and the pivot
+// row.  Same steps and arithmetic as gauss_jordan; matrices of other sizes
+// are left to k_pivot_inverse (the launcher runs both, each skipping the
+// other's).
+constexpr int kRegThreads = 1024;
+constexpr int kRegWaves = kRegThreads / kWave;
+
+template <bool CPLX, int RPW, int CPL>
+__global__ __launch_bounds__(kRegThreads) void k_pivot_inverse_reg(const PivInvArgs a) {
+  using T = Z<CPLX>;
+  constexpr int KMAX = kRegWaves * RPW;
+  static_assert(KMAX == kWave * CPL, "square register tile");
+  __shared__ T fcol[KMAX], ps[KMAX];
+  const int c = blockIdx.x;
+  const int n = a.nrows[c], k = a.rank[c];
+  if (k > KMAX) return;  // uniform: the LDS / global kernel takes it
+  const int64_t aoff = a.a_off[c];
+  if (n < 0 || k < 0 || k > a.max_rank || k > n || aoff < 0 ||
+      aoff + (int64_t)n * a.acols > a.a_len) {
+    if (threadIdx.x == 0) atomicOr(a.flags, FLAG_EINVAL);
+    return;
+  }
+  const int tid = threadIdx.x, wave = tid / kWave, lane = tid & (kWave - 1);
+  const int32_t *prow = a.piv_rows + (int64_t)c * a.max_rank;
+  const int32_t *pcol = a.piv_cols + (int64_t)c * a.max_rank;
+  const T *A = reinterpret_cast<const T *>(a.A);
+  T *X = reinterpret_cast<T *>(a.pinv) + (int64_t)c * a.max_rank * a.max_rank;
+  // X[r][j] = M[j][r] = A[prow[j], pcol[r]], r = wave + 16 i, j = lane + 64 q
+  T x[RPW][CPL];
+  int rj[CPL];
+#pragma unroll
+  for (int q = 0; q < CPL; ++q) {
+    const int j = lane + kWave * q;
+    rj[q] = j < k ? prow[j] : 0;
+    if (j < k && (rj[q] < 0 || rj[q] >= n)) atomicOr(a.flags, FLAG_EINVAL), rj[q] = 0;
+  }
+#pragma unroll
+  for (int i = 0; i < RPW; ++i) {
+    const int r = wave + kRegWaves * i;
+    int ci = r < k ? pcol[r] : 0;
+    if (r < k && (ci < 0 || ci >= a.acols)) {
+      if (lane == 0) atomicOr(a.flags, FLAG_EINVAL);
+      ci = 0;
+    }
+#pragma unroll
+    for (int q = 0; q < CPL; ++q) {
+      const int j = lane + kWave * q;
+      x[i][q] = r < k && j < k ? A[aoff + rj[q] + (int64_t)n * ci] : T::make(0, 0);
+    }
+  }
+  for (int s = 0; s < k; ++s) {
+    const int si = s / kRegWaves, sw = s % kRegWaves, sq = s / kWave, sl = s % kWave;
+    // the pivot, from the lane that holds it, to the whole pivot row's wave
+    T piv = T::make(0, 0);
+    if (wave == sw) {
+      T mine = T::make(0, 0);
+#pragma unroll
+      for (int i = 0; i < RPW; ++i)
+#pragma unroll
+        for (int q = 0; q < CPL; ++q)
+          if (i == si && q == sq) mine = x[i][q];
+      piv = mine.lane_value(sl);
+      if (lane == 0 && !piv.finite_nonzero()) atomicOr(a.flags, FLAG_NONFINITE);
+      // the pivot row divided by the pivot (its own entry: 1 / pivot)
+#pragma unroll
+      for (int q = 0; q < CPL; ++q) {
+        const int j = lane + kWave * q;
+        T v = T::make(0, 0);
+#pragma unroll
+        for (int i = 0; i < RPW; ++i)
+          if (i == si) v = x[i][q];
+        if (j < k) ps[j] = (j == s ? T::make(1, 0) : v).div(piv);
+      }
+    }
+    // column s of every row, from the lanes that hold it
+    if (lane == sl) {
+#pragma unroll
+      for (int i = 0; i < RPW; ++i) {
+        const int r = wave + kRegWaves * i;
+        T v = T::make(0, 0);
+#pragma unroll
+        for (int q = 0; q < CPL; ++q)
+          if (q == sq) v = x[i][q];
+        if (r < k) fcol[r] = v;
+      }
+    }
+    __syncthreads();
+    T pj[CPL];
+#pragma unroll
+    for (int q = 0; q < CPL; ++q) {
+      const int j = lane + kWave * q;
+      pj[q] = j < k ? ps[j] : T::make(0, 0);
+    }
+#pragma unroll
+    for (int i = 0; i < RPW; ++i) {
+      const int r = wave + kRegWaves * i;
+      const T fr = r < k ? fcol[r] : T::make(0, 0);
+#pragma unroll
+      for (int q = 0; q < CPL; ++q) {
+        const int j = lane + kWave * q;
+        if (r == s) x[i][q] = pj[q];
+        else x[i][q] = (j == s ? T::make(0, 0) : x[i][q]) - fr * pj[q];
+      }
+    }
+    __syncthreads();  // fcol and ps are rewritten by the next step
+  }
+#pragma unroll
+  for (int i = 0; i < RPW; ++i) {
+    const int r = wave + kRegWaves * i;
+#pragma unroll
+    for (int q = 0; q < CPL; ++q) {
+      const int j = lane + kWave * q;
+      if (r < k && j < k) X[(int64_t)r * k + j] = x[i][q];
+    }
+  }
+}
+
 }  // namespace
 
 hipError_t launch_pivot_inverse(bool cplx, const PivInvArgs &a, hipStream_t s) {
@@ -351,8 +486,16 @@ hipError_t launch_pivot_inverse(bool cplx, const PivInvArgs &a, hipStream_t s) {
   int lds_k = 0;
   while (lds_k < a.max_rank && (size_t)(lds_k + 1) * (lds_k + 2) * elem <= kInvLdsBytes) ++lds_k;
   const size_t lds = (size_t)lds_k * (lds_k + 1) * elem;
-  if (cplx) hipLaunchKernelGGL((k_pivot_inverse<true>), grid, block, lds, s, a, lds_k);
-  else hipLaunchKernelGGL((k_pivot_inverse<false>), grid, block, lds, s, a, lds_k);
+  // ranks up to reg_k in registers (real 192 = 16 x 12 rows by 64 x 3
+  // columns, complex 128 = 16 x 8 by 64 x 2), the rest in LDS or global memory
+  const int reg_k = cplx ? kRegWaves * 8 : kRegWaves * 12;
+  const dim3 rblock(kRegThreads);
+  if (cplx) hipLaunchKernelGGL((k_pivot_inverse_reg<true, 8, 2>), grid, rblock, 0, s, a);
+  else hipLaunchKernelGGL((k_pivot_inverse_reg<false, 12, 3>), grid, rblock, 0, s, a);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess || a.max_rank <= reg_k) return e;
+  if (cplx) hipLaunchKernelGGL((k_pivot_inverse<true>), grid, block, lds, s, a, lds_k, reg_k);
+  else hipLaunchKernelGGL((k_pivot_inverse<false>), grid, block, lds, s, a, lds_k, reg_k);
   return hipGetLastError();
 }
 

@@ -109,6 +109,17 @@ class ClusterBasis:
         self.levels = []           # LevelPlan per height (needed clusters only)
         self.where = [None] * ncl  # (level index, position in level)
 
+    def flat_pivots(self):
+        """(flat, start, size): cluster c's pivot triangles are
+        flat[start[c] : start[c] + size[c]] (empty for clusters without a
+        basis)."""
+        size = np.array([0 if p is None else p.size for p in self.piv], dtype=np.int64)
+        start = np.zeros(size.size, dtype=np.int64)
+        np.cumsum(size[:-1], out=start[1:])
+        flat = np.concatenate([p for p in self.piv if p is not None and p.size]
+                              or [np.zeros(0, np.int64)]).astype(np.int64)
+        return flat, start, size
+
     def vhat(self, c):
         """V^_c as a host numpy array (n_c x k_c)."""
         li, p = self.where[c]
@@ -117,6 +128,47 @@ class ClusterBasis:
         o = lv.v_off_h[p]
         flat = lv.V.cpu().numpy()
         return flat[o:o + n * k].reshape(k, n).T
+
+
+def _block_lists(pairs, rows, cols, mirror, keep_diag):
+    """Blocks of the cluster pairs (t, s): rows / cols = (flat, start, size)
+    give a cluster c's triangles flat[start[c] : start[c] + size[c]].
+    Outputs back to back in list order (column-major blocks).  mirror: only
+    the blocks with t < s (and t == s if keep_diag) are listed, each with the
+    output offset of (s, t) as its mirror -- its own for t == s, the block
+    being its own transpose.  Returns (Blocks, total entries)."""
+    pairs = np.asarray(pairs, dtype=np.int64).reshape(-1, 2)
+    t, s_ = pairs[:, 0], pairs[:, 1]
+    nr, nc = rows[2][t], cols[2][s_]
+    sizes = nr * nc
+    off = np.zeros(pairs.shape[0], dtype=np.int64)
+    if sizes.size:
+        np.cumsum(sizes[:-1], out=off[1:])
+    keep = np.arange(pairs.shape[0])
+    mirror_off = None
+    if mirror:
+        keep = np.nonzero(t <= s_ if keep_diag else t < s_)[0]
+        if not keep_diag and 2 * keep.size != pairs.shape[0]:
+            raise ValueError("the admissible blocks are not symmetric")
+        ncl = int(pairs.max()) + 1 if pairs.size else 1
+        key = t * ncl + s_
+        order = np.argsort(key, kind="stable")
+        want = s_[keep] * ncl + t[keep]
+        at = np.searchsorted(key[order], want)
+        if np.any(at >= key.size) or np.any(key[order][np.minimum(at, key.size - 1)] != want):
+            raise ValueError("a block (t, s) without its transpose (s, t)")
+        mirror_off = off[order[at]]
+
+    def gather(flat, start, size, ids):
+        n = size[ids]
+        ptr = np.zeros(ids.size + 1, dtype=np.int64)
+        np.cumsum(n, out=ptr[1:])
+        idx = np.arange(ptr[-1], dtype=np.int64) + np.repeat(start[ids] - ptr[:-1], n)
+        return ptr.astype(np.int32), flat[idx].astype(np.int32)
+
+    rp, ri = gather(*rows, t[keep])
+    cp, ci = gather(*cols, s_[keep])
+    return Blocks(rp, ri, cp, ci, off[keep], mirror_off), int(sizes.sum())
 
 
 class H2Setup:
@@ -391,45 +443,18 @@ class H2Setup:
         transpose (edge-adjacent entries evaluated as (j, i)); a block (t, t)
         is its own mirror: its entries with row >= column are evaluated and
         written transposed too."""
-        rows = [self.ct.idx(t) for t, s in self.near]
-        cols = [self.ct.idx(s) for t, s in self.near]
-        if not mirror:
-            return Blocks.from_lists(rows, cols)
-        keep = [k for k, (t, s) in enumerate(self.near) if t <= s]
-        return self._mirrored(self.near, rows, cols, keep)
-
-    @staticmethod
-    def _mirrored(pairs, rows, cols, keep):
-        """Blocks `keep` of the list (t, s) -> rows, cols, each with the output
-        offset of (s, t) as its mirror (its own offset for t == s: the block
-        is its own transpose); the output layout is that of the whole list."""
-        sizes = np.array([len(r) * len(c) for r, c in zip(rows, cols)], dtype=np.int64)
-        off = np.zeros(len(rows), dtype=np.int64)
-        off[1:] = np.cumsum(sizes)[:-1]
-        pos = {(int(t), int(s)): k for k, (t, s) in enumerate(pairs)}
-        mirror_off = np.array([off[pos[(int(pairs[k][1]), int(pairs[k][0]))]] for k in keep],
-                              dtype=np.int64)
-        kr = [rows[k] for k in keep]
-        kc = [cols[k] for k in keep]
-        rp = np.zeros(len(keep) + 1, dtype=np.int32)
-        cp = np.zeros(len(keep) + 1, dtype=np.int32)
-        rp[1:] = np.cumsum([len(r) for r in kr])
-        cp[1:] = np.cumsum([len(c) for c in kc])
-        cat = lambda xs: np.concatenate(xs).astype(np.int32) if xs else np.zeros(0, np.int32)
-        return Blocks(rp, cat(kr), cp, cat(kc), off[keep], mirror_off), int(sizes.sum())
+        ct = self.ct
+        size = (ct.end - ct.begin).astype(np.int64)
+        start = ct.begin.astype(np.int64)
+        return _block_lists(self.near, (ct.perm, start, size), (ct.perm, start, size), mirror,
+                            keep_diag=True)
 
     def coupling_blocks(self, row_basis, col_basis, mirror=False):
         """Pivot lists of the admissible blocks, outputs back to back in the
         order of self.far.  mirror (a single layer with one basis for rows and
         columns): of each pair (t, s), (s, t) only the block with t < s is
         evaluated and the other is written as its transpose."""
-        rows = [row_basis.piv[t] for t, s in self.far]
-        cols = [col_basis.piv[s] for t, s in self.far]
-        if not mirror:
-            return Blocks.from_lists(rows, cols)
-        if row_basis is not col_basis:
+        if mirror and row_basis is not col_basis:
             raise ValueError("mirrored coupling blocks need one basis for rows and columns")
-        keep = [k for k, (t, s) in enumerate(self.far) if t < s]
-        if 2 * len(keep) != len(self.far):
-            raise ValueError("the admissible blocks are not symmetric")
-        return self._mirrored(self.far, rows, cols, keep)
+        return _block_lists(self.far, row_basis.flat_pivots(), col_basis.flat_pivots(), mirror,
+                            keep_diag=False)

@@ -133,3 +133,56 @@ def test_cluster_features_follow_their_definition():
     assert X[0, 3] == 0.0 and X[1, 0] == 0.0
     with pytest.raises(pk.BemError):
         pk.cluster_features(box, begin, end, height, 3.0, 1, 0.0)
+
+
+def test_block_lists_match_the_per_block_construction(monkeypatch):
+    """h2._block_lists (index arithmetic over the whole list) against the
+    lists built block by block: near field plain and mirrored (diagonal
+    blocks their own mirror), coupling-like pivot lists plain and mirrored."""
+    import paper_1510_07244_amd as pk
+    from paper_1510_07244_amd import h2
+
+    class Rec:
+        def __init__(self, rp, ri, cp, ci, off, mirror=None):
+            self.rp, self.ri, self.cp, self.ci = rp, ri, cp, ci
+            self.off, self.mirror = off, mirror
+
+    monkeypatch.setattr(h2, "Blocks", Rec)
+    m = octahedron_sphere(16)
+    ct = pk.ClusterTree(m.v, m.tri)
+    near, far = pk.block_tree(ct, eta=2.0)
+    size = (ct.end - ct.begin).astype(np.int64)
+    start = ct.begin.astype(np.int64)
+    rng = np.random.default_rng(7)
+    piv = [np.sort(rng.choice(ct.idx(c), size=min(size[c], rng.integers(1, 9)), replace=False))
+           for c in range(ct.n)]
+    psize = np.array([p.size for p in piv], dtype=np.int64)
+    pstart = np.concatenate([[0], np.cumsum(psize)[:-1]])
+    pflat = np.concatenate(piv)
+
+    def reference(pairs, lists, mirror, keep_diag):
+        rows = [lists(t) for t, s in pairs]
+        cols = [lists(s) for t, s in pairs]
+        sizes = [len(r) * len(c) for r, c in zip(rows, cols)]
+        off = np.concatenate([[0], np.cumsum(sizes)[:-1]])
+        keep = [k for k, (t, s) in enumerate(pairs) if (t <= s if keep_diag else t < s)] \
+            if mirror else list(range(len(pairs)))
+        pos = {(int(t), int(s)): k for k, (t, s) in enumerate(pairs)}
+        mo = [off[pos[(int(pairs[k][1]), int(pairs[k][0]))]] for k in keep] if mirror else None
+        return ([r for k in keep for r in rows[k]], [len(rows[k]) for k in keep],
+                [c for k in keep for c in cols[k]], [len(cols[k]) for k in keep],
+                off[keep], mo, sum(sizes))
+
+    for pairs, spec, lists, keep_diag in (
+            (near, (ct.perm, start, size), ct.idx, True),
+            (far, (pflat, pstart, psize), lambda c: piv[c], False)):
+        for mirror in (False, True):
+            b, total = h2._block_lists(pairs, spec, spec, mirror, keep_diag)
+            ri, nr, ci, nc, off, mo, tot = reference(pairs, lists, mirror, keep_diag)
+            assert total == tot
+            assert np.array_equal(b.ri, ri) and np.array_equal(np.diff(b.rp), nr)
+            assert np.array_equal(b.ci, ci) and np.array_equal(np.diff(b.cp), nc)
+            assert np.array_equal(b.off, off)
+            assert (b.mirror is None) == (mo is None)
+            if mo is not None:
+                assert np.array_equal(b.mirror, mo)
