@@ -31,6 +31,7 @@ import argparse
 import json
 import os
 import sys
+import tempfile
 import time
 
 import numpy as np
@@ -330,10 +331,20 @@ class BatchedBench:
         entries = []
         for (h, near, n_near, cs, n_cs), (on, oc) in zip(self.items, self.out):
             entries += [(h.mesh, near, on, 0), (h.mesh, cs, oc, 1)]
+        cache = os.path.join(tempfile.gettempdir(), f"bem_tune_{os.getpid()}.txt")
         t1 = time.perf_counter()
-        self.plan = pk.Plan(ctx, self.op, entries, autotune=True)
+        first = pk.Plan(ctx, self.op, entries, autotune=True, cache=cache)
         torch.cuda.synchronize()
         self.t_plan = time.perf_counter() - t1
+        self.tuned = first.config
+        first.close()
+        # the same plan again with the tuning cached (a later run on this
+        # device and operator): lists, queue and graph only
+        t1 = time.perf_counter()
+        self.plan = pk.Plan(ctx, self.op, entries, autotune=True, cache=cache)
+        torch.cuda.synchronize()
+        self.t_plan_cached = time.perf_counter() - t1
+        os.remove(cache)
         self.n_entries = sum(n_near + n_cs for h, near, n_near, cs, n_cs in self.items)
         self.triangles = sum(m.nt for m in self.meshes)
 
@@ -369,8 +380,12 @@ class BatchedBench:
             "workload": f"Laplace SLP near field + coupling blocks of {len(sizes)} perturbed "
                         f"spheres ({min(sizes)}..{max(sizes)} triangles, {self.triangles} total), "
                         "each with its own H2 setup (leaf 64, eta 2, ACA 5e-8), plain FP64",
-            "tiles": self.plan.tiles, "tune": self.plan.config,
-            "plan_s": self.t_plan, "bases_s": self.t_bases,
+            "tiles": self.plan.tiles, "tune": self.tuned,
+            "plan_s": self.t_plan, "plan_cached_tuning_s": self.t_plan_cached,
+            "plan_note": "plan_s includes the autotuner's timed candidates; "
+                         "plan_cached_tuning_s is the same plan with the tuning read from its "
+                         "cache file",
+            "bases_s": self.t_bases,
         }
 
 
@@ -384,6 +399,7 @@ class LearnedBench:
     order assembly against the plain fixed-order assembly."""
 
     TOL, MARGIN = 1e-7, 0.5
+    GROUP = 4  # rows of a column per network evaluation
 
     def __init__(self, pk, ctx, n):
         import torch
@@ -435,16 +451,18 @@ class LearnedBench:
         plain = torch.empty(self.total, dtype=dt, device="cuda")
         learned = torch.empty(self.total, dtype=dt, device="cuda")
         orders = torch.empty(self.total, dtype=torch.int8, device="cuda")
-        sel = lambda: ctx.select_orders(self.mesh, op, self.blocks, self.sel.params, orders,
-                                        self.TOL, self.MARGIN, 2, stream, range=self.sel.range)
+        sel = lambda g: ctx.select_orders(self.mesh, op, self.blocks, self.sel.params, orders,
+                                          self.TOL, self.MARGIN, 2, stream, range=self.sel.range,
+                                          group=g)
         runs = {
             "plain": lambda: ctx.assemble_nearfield(self.mesh, op, self.blocks, plain, stream),
-            "select": sel,
+            "select_per_entry": lambda: sel(1),
+            "select": lambda: sel(self.GROUP),
             "learned": lambda: ctx.assemble_nearfield_learned(self.mesh, op, self.blocks, orders,
                                                               learned, stream),
         }
         ms = {}
-        for name in ("plain", "select", "learned"):
+        for name in ("plain", "select_per_entry", "select", "learned"):
             for _ in range(warmup):
                 runs[name]()
             ctx.check(stream)
@@ -469,6 +487,7 @@ class LearnedBench:
         tot = float(torch.linalg.vector_norm(learned - plain) / torch.linalg.vector_norm(plain))
         del plain, learned, orders
         return {"plain_ms": ms["plain"], "select_ms": ms["select"], "learned_ms": ms["learned"],
+                "select_per_entry_ms": ms["select_per_entry"],
                 "speedup_vs_plain": ms["plain"] / (ms["select"] + ms["learned"]),
                 "assembly_speedup_excl_select": ms["plain"] / ms["learned"],
                 "points_fraction": pts_learned / pts_plain, "orders": counts,
@@ -481,13 +500,17 @@ class LearnedBench:
         for name, op in (("laplace_slp", pk.make_op(pk.LAPLACE, pk.SLP, q_regular=4, q_singular=4)),
                          ("laplace_dlp", pk.make_op(pk.LAPLACE, pk.DLP, q_regular=4, q_singular=4)),
                          ("helmholtz8_slp", pk.make_op(pk.HELMHOLTZ, pk.SLP, q_regular=5,
+                                                       q_singular=5, kappa=8.0)),
+                         ("helmholtz8_dlp", pk.make_op(pk.HELMHOLTZ, pk.DLP, q_regular=5,
                                                        q_singular=5, kappa=8.0))):
             legs[name] = self.leg(torch, op, stream, steps, warmup)
         return {
             "workload": f"near field of the octahedron sphere with {self.m.nt} triangles "
                         f"({self.nblocks} blocks, leaf 64, eta 2): plain fixed order (q=4 Laplace, "
                         "q=5 Helmholtz kappa 8) vs learned per-entry orders "
-                        f"(tol {self.TOL}, margin {self.MARGIN}); FP64",
+                        f"(tol {self.TOL}, margin {self.MARGIN}; one network evaluation per "
+                        f"run of {self.GROUP} rows of a column, select_per_entry_ms: one per "
+                        "entry); FP64",
             "training": {"pairs": self.n_train, "samples_s": self.t_samples,
                          "train_s": self.t_train, "loss_first_epoch": float(self.losses[0]),
                          "loss_last_epoch": float(self.losses[-1])},
@@ -637,7 +660,9 @@ def rank_head_leg(torch, pk, ctx, m):
     plain = h.bases((0, 1))
     torch.cuda.synchronize()
     t_plain = time.perf_counter() - t0
-    err = np.concatenate([np.abs(head.predict(cluster_features(h, B.side)) - B.rank) for B in plain])
+    need = h.needed  # clusters with a basis (the others enter no product)
+    err = np.concatenate([np.abs(head.predict(cluster_features(h, B.side)) - B.rank)[need]
+                          for B in plain])
     t0 = time.perf_counter()
     caps = [head.caps(h, 0), head.caps(h, 1)]
     t_infer = time.perf_counter() - t0
@@ -650,10 +675,11 @@ def rank_head_leg(torch, pk, ctx, m):
     return {
         "workload": "trained on the setups of a 2048-triangle sphere, a 3072-triangle cube and "
                     "two perturbed spheres (both sides, Laplace, ACA 5e-8); applied to the "
-                    f"{m.nt}-triangle sphere's {h.ct.n} clusters x 2 sides",
+                    f"{m.nt}-triangle sphere's {int(h.needed.sum())} clusters with a basis "
+                    "x 2 sides",
         "train_samples": int(R.size), "train_s": t_train,
         "loss_first_epoch": float(losses[0]), "loss_last_epoch": float(losses[-1]),
-        "rank_mean": float(np.mean([B.rank.mean() for B in plain])),
+        "rank_mean": float(np.mean([B.rank[need].mean() for B in plain])),
         "abs_err_mean": float(err.mean()), "abs_err_max": float(err.max()),
         "cap_margin": 8, "levels": h.cap_stats["levels"], "fallback_levels": h.cap_stats["fallbacks"],
         "pinv_bytes_plain": pinv(plain), "pinv_bytes_capped": pinv(capped),
@@ -1056,6 +1082,13 @@ def main():
         result["forms"]["batched"] = batched
     if learned:
         result["forms"]["learned"] = learned
+    # H2 setup time of the 8192-sphere matrix by form (tree, bases, first
+    # assembly; the learned form adds the order selection of its coupling
+    # lists, the network being trained once offline)
+    by_form = {"plain_fp64": float(st[best, 0]), "mixed": float(hm.t_setup)}
+    if learned:
+        by_form["learned_coupling"] = float(st[best, 0]) + learned["h2_step"]["select_s"]
+    result["h2_setup_s_by_form"] = by_form
     if not args.no_cpu_baseline:
         result["cpu_baseline"] = cpu_baseline(m, hb, args.cpu_seconds)
     ctx.close()

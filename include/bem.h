@@ -381,11 +381,18 @@ int bem_selector_samples(bem_ctx *ctx, const bem_mesh *mesh, const bem_op *op, i
  * largest value of each of the 8 inputs over the training set ([min(8),
  * max(8)]); a pair with an input outside it (or not finite) gets q_regular,
  * the plain rule, whatever the network predicts.  op: Duffy rule, q_regular
- * in [2, 6]. */
+ * in [2, 6].  group (1 .. 8): the rows of a block column are taken in runs
+ * of `group` (the last run of a sub-tile of 64 rows may be shorter) that
+ * share one network evaluation -- on the inputs of the run's pair with the
+ * smallest centroid distance over the larger triangle diameter, with the
+ * largest row-triangle aspect ratio of the run -- and so one order (pairs
+ * with a common vertex still get 0); group = 1 decides entry by entry.  The
+ * network runs once per run, so larger groups cost less to select and may
+ * pick higher orders for the run's farther pairs. */
 int bem_select_orders(bem_ctx *ctx, const bem_mesh *mesh, const bem_op *op,
                       const bem_blocks *blocks, const float *params, const float *range,
-                      double tol, double margin, int32_t q_min, int8_t *orders,
-                      int64_t orders_len, void *stream);
+                      double tol, double margin, int32_t q_min, int32_t group,
+                      int8_t *orders, int64_t orders_len, void *stream);
 
 /* Near-field blocks like bem_assemble_nearfield (plain FP64, Duffy rule,
  * q_regular in [2, 6]), each regular entry with the order orders[entry]

@@ -573,7 +573,7 @@ def _setup_learned_api():
     _lib.bem_mlp_grad.argtypes = [P, i32, P, i64, P, P, P, P, P]
     _lib.bem_mlp_adam.argtypes = [P, i64, P, P, P, P, i32, f32, f32, f32, f32, P]
     _lib.bem_selector_samples.argtypes = [P, M, O, i64, P, P, P, P, P]
-    _lib.bem_select_orders.argtypes = [P, M, O, B, P, P, f64, f64, i32, P, i64, P]
+    _lib.bem_select_orders.argtypes = [P, M, O, B, P, P, f64, f64, i32, i32, P, i64, P]
     _lib.bem_assemble_nearfield_learned.argtypes = [P, M, O, B, P, P, i64, P]
     _lib.bem_mlp_save.argtypes = [P, ctypes.c_char_p, i32, P, P, P, P, i32, P]
     _lib.bem_mlp_load.argtypes = [P, ctypes.c_char_p, i32, P, P, P, P, ctypes.POINTER(i32), P]
@@ -634,12 +634,13 @@ def _context_selector_samples(self, mesh, op, rows, cols, x, t, stream=None):
 
 
 def _context_select_orders(self, mesh, op, blocks, params, orders, tol, margin, q_min=2,
-                           stream=None, range=None):
-    """bem_select_orders; range: device float[16] training range (or None)."""
+                           stream=None, range=None, group=1):
+    """bem_select_orders; range: device float[16] training range (or None);
+    group: rows of a column sharing one decision (1: entry by entry)."""
     self._rc(_lib.bem_select_orders(self.h, ctypes.byref(mesh.c), ctypes.byref(op),
                                     ctypes.byref(blocks.c), _ptr(params), _ptr(range), float(tol),
-                                    float(margin), int(q_min), _ptr(orders), orders.numel(),
-                                    _stream(stream)))
+                                    float(margin), int(q_min), int(group), _ptr(orders),
+                                    orders.numel(), _stream(stream)))
 
 
 def _context_assemble_nearfield_learned(self, mesh, op, blocks, orders, out, stream=None):

@@ -266,6 +266,7 @@ struct SelectArgs {
   int64_t ldt;
   const float *range;              // device [16]: training minima, maxima of the inputs (or null)
   int32_t layer, q_plain, q_min;
+  int32_t group;                   // rows of a column that share one decision (1 .. 8)
   float margin, log_tol;
   double kappa;
   unsigned *flags;

@@ -178,8 +178,8 @@ int bem_selector_samples(bem_ctx *ctx, const bem_mesh *mesh, const bem_op *op, i
 
 int bem_select_orders(bem_ctx *ctx, const bem_mesh *mesh, const bem_op *op,
                       const bem_blocks *blocks, const float *params, const float *range,
-                      double tol, double margin, int32_t q_min, int8_t *orders,
-                      int64_t orders_len, void *stream) {
+                      double tol, double margin, int32_t q_min, int32_t group,
+                      int8_t *orders, int64_t orders_len, void *stream) {
   if (!ctx) return BEM_EINVAL;
   int rc;
   if ((rc = block_list_args(ctx, mesh, op, blocks, orders, orders_len))) return rc;
@@ -189,6 +189,7 @@ int bem_select_orders(bem_ctx *ctx, const bem_mesh *mesh, const bem_op *op,
       q_min > op->q_regular)
     return fail(ctx, BEM_EINVAL, "tol > 0, finite margin, q_min in [2, q_regular]");
   if (!params) return fail(ctx, BEM_EINVAL, "params is NULL");
+  if (group < 1 || group > 8) return fail(ctx, BEM_EINVAL, "group in [1, 8]");
   if (blocks->n == 0) return BEM_OK;
   DeviceGuard g(ctx->device);
   int64_t ldg;
@@ -233,6 +234,7 @@ int bem_select_orders(bem_ctx *ctx, const bem_mesh *mesh, const bem_op *op,
   a.layer = op->layer;
   a.q_plain = op->q_regular;
   a.q_min = q_min;
+  a.group = group;
   a.margin = (float)margin;
   a.log_tol = (float)std::log10(tol);
   a.kappa = op->kernel == BEM_HELMHOLTZ ? op->kappa : 0.0;

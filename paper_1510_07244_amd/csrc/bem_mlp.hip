@@ -558,9 +558,9 @@ __global__ __launch_bounds__(kThreads) void k_selector_samples(const SampleArgs 
 // error plus the margin is at most log10(tol) at it and at every order above
 // it below q_plain; q_plain when q_plain - 1 fails.  One workgroup per block,
 // 64 x 64 sub-tiles; the sub-tile's triangles' inputs are staged in LDS, each
-// lane forms the inputs of one entry, and each wave runs the network on its
-// 64 entries in four groups of 16 (inputs moved to lanes 0..15 by lane
-// shuffles).
+// lane forms the inputs of one group of a.group rows of a column (one entry
+// for a.group = 1), and each wave runs the network on its 64 groups in four
+// sets of 16 (inputs moved to lanes 0..15 by lane shuffles).
 constexpr int kSelTile = 64;
 
 __global__ __launch_bounds__(kThreads, 2) void k_select_orders(const SelectArgs a) {
@@ -615,27 +615,51 @@ __global__ __launch_bounds__(kThreads, 2) void k_select_orders(const SelectArgs 
         if (tid == 0) atomicOr(a.flags, FLAG_EINVAL);
         continue;  // uniform
       }
-      const int ne = tr * tc;
-      // e / tr by a float reciprocal: e < 4096 and tr <= 64 keep (e + 1/2) / tr
-      // at least 1 / 128 away from an integer, far above the rounding error
-      const float itr = 1.0f / (float)tr;
+      // a lane takes a group of G rows of one column (G = a.group, 1 .. 8):
+      // the network runs once for the group, on the inputs of its pair with
+      // the smallest distance over diameter (the one its error grows with
+      // most) and the largest row aspect of the group
+      const int G = a.group, ngr = (tr + G - 1) / G;
+      const int ne = ngr * tc;
+      // e / ngr by a float reciprocal: e < 4096 and ngr <= 64 keep
+      // (e + 1/2) / ngr at least 1 / 128 away from an integer, far above the
+      // rounding error
+      const float itr = 1.0f / (float)ngr;
       for (int e0 = wave * 64; e0 < ne; e0 += kThreads) {  // no barrier inside: trip counts differ
         const int e = e0 + l;
         const bool live = e < ne;
         const int cq = (int)(((float)e + 0.5f) * itr);
-        const int rl = live ? e - cq * tr : 0, cl = live ? cq : 0;
-        const int cls = shared_vertex_count(sv[0][0][rl], sv[0][1][rl], sv[0][2][rl], sv[1][0][cl],
-                                            sv[1][1][cl], sv[1][2][cl]);
-        // standardised inputs of this lane's entry, packed as four half2 words
+        const int rg = live ? (e - cq * ngr) * G : 0, cl = live ? cq : 0;
+        const int rn = live ? min(G, tr - rg) : 0;  // rows of this group
+        unsigned cls_bits = 0;  // 2 bits per row: the pair class
+        int rep = -1;
+        float best = 0.0f, aspect = 0.0f;
+        for (int u = 0; u < rn; ++u) {
+          const int rl = rg + u;
+          const int cls = shared_vertex_count(sv[0][0][rl], sv[0][1][rl], sv[0][2][rl],
+                                              sv[1][0][cl], sv[1][1][cl], sv[1][2][cl]);
+          cls_bits |= (unsigned)cls << (2 * u);
+          if (cls) continue;
+          double r2 = 0.0;
+          for (int m = 0; m < 3; ++m) {
+            const double d = sc[0][m][rl] - sc[1][m][cl];
+            r2 = fma(d, d, r2);
+          }
+          const float D = nonneg_max(sd[0][0][rl], sd[1][0][cl]);
+          const float ratio = (float)r2 * __builtin_amdgcn_rcpf(D * D);
+          if (rep < 0 || ratio < best) best = ratio, rep = rl;
+          aspect = nonneg_max(aspect, sd[0][2][rl]);
+        }
+        // standardised inputs of this lane's group, packed as four half2 words
         uint32_t w[4] = {0, 0, 0, 0};
         bool outside = false;
-        if (live && cls == 0) {
+        if (rep >= 0) {
           TriIn ti, tj;
           for (int m = 0; m < 3; ++m) {
-            ti.c[m] = sc[0][m][rl], ti.n[m] = sn[0][m][rl];
+            ti.c[m] = sc[0][m][rep], ti.n[m] = sn[0][m][rep];
             tj.c[m] = sc[1][m][cl], tj.n[m] = sn[1][m][cl];
           }
-          ti.d = sd[0][0][rl], ti.area = sd[0][1][rl], ti.aspect = sd[0][2][rl];
+          ti.d = sd[0][0][rep], ti.area = sd[0][1][rep], ti.aspect = aspect;
           tj.d = sd[1][0][cl], tj.area = sd[1][1][cl], tj.aspect = sd[1][2][cl];
           float f[8];
           pair_inputs(ti, tj, a.layer, kappa, f);
@@ -653,10 +677,10 @@ __global__ __launch_bounds__(kThreads, 2) void k_select_orders(const SelectArgs 
         // 16 G + l % 16; only lanes 0..15 meet nonzero first-layer weights
         // (the other lanes' k-slots multiply zeros, exactly)
         h8 bop[4];
-        for (int G = 0; G < 4; ++G) {
+        for (int Gn = 0; Gn < 4; ++Gn) {
           uint32_t v[4];
-          for (int k = 0; k < 4; ++k) v[k] = (uint32_t)__shfl((int)w[k], G * 16 + (l & 15), kWave);
-          bop[G] = __builtin_bit_cast(h8, v);
+          for (int k = 0; k < 4; ++k) v[k] = (uint32_t)__shfl((int)w[k], Gn * 16 + (l & 15), kWave);
+          bop[Gn] = __builtin_bit_cast(h8, v);
         }
         f4 out[4];
         net<true, 2, 0>(N, srot, bias, bop, out);
@@ -688,7 +712,10 @@ __global__ __launch_bounds__(kThreads, 2) void k_select_orders(const SelectArgs 
           }
         }
         if (outside) q = a.q_plain;
-        if (live) a.orders[off + (r0 + rl) + nr * (c0 + cl)] = (int8_t)(cls ? 0 : q);
+        for (int u = 0; u < rn; ++u) {
+          const int cls = (cls_bits >> (2 * u)) & 3;
+          a.orders[off + (r0 + rg + u) + nr * (c0 + cl)] = (int8_t)(cls ? 0 : q);
+        }
       }
     }
   }

@@ -172,13 +172,14 @@ class Selector:
         return y
 
     def orders(self, mesh, op, blocks, n_entries, tol, margin, q_min=2, stream=None,
-               guard=True):
-        """int8 order map of the entries of near-field blocks (guard: pairs
-        outside the training range keep the plain order)."""
+               guard=True, group=1):
+        """int8 order map of the entries of a block list (guard: pairs
+        outside the training range keep the plain order; group: rows of a
+        column that share one decision)."""
         import torch
         out = torch.zeros(n_entries, dtype=torch.int8, device="cuda")
         self.ctx.select_orders(mesh, op, blocks, self.params, out, tol, margin, q_min, stream,
-                               range=self.range if guard else None)
+                               range=self.range if guard else None, group=group)
         return out
 
 

@@ -252,27 +252,39 @@ def test_trained_selector_gain(pk, ctx):
     m = octahedron_sphere(32)
     mesh = pk.Mesh(torch.from_numpy(m.v), torch.from_numpy(m.tri))
     rows, cols, blocks, total = _near(pk, m, 12, 5)
-    saved_points, plain_points = 0, 0
+    saved_points = {1: 0, 4: 0}
+    plain_points = 0
     for layer in (0, 1):
         op = pk.make_op(pk.LAPLACE, layer, q_regular=4, q_singular=4)
-        orders = sel.orders(mesh, op, blocks, total, tol=1e-7, margin=0.5)
-        out = torch.full((total,), float("nan"), dtype=torch.float64, device="cuda")
-        ctx.assemble_nearfield_learned(mesh, op, blocks, orders, out)
-        ctx.check()
-        q = orders.cpu().numpy().astype(np.int64)
-        reg = q > 0
-        plain_points += int(reg.sum()) * 4 ** 4
-        saved_points += int((4 ** 4 - q[reg] ** 4).sum())
-        res = out.cpu().numpy()
-        off = 0
-        for r, c in zip(rows, cols):
-            n = len(r) * len(c)
-            got = res[off:off + n].reshape(len(c), len(r)).T
-            off += n
-            ref = oracle.block(m.v, m.tri, r, c, layer=layer, q_reg=4, q_sing=4).real
-            err = np.linalg.norm(got - ref) / np.linalg.norm(ref)
-            assert err <= 1e-6, (layer, err)
-    assert saved_points >= 0.2 * plain_points, (saved_points, plain_points)
+        refs = [oracle.block(m.v, m.tri, r, c, layer=layer, q_reg=4, q_sing=4).real
+                for r, c in zip(rows, cols)]
+        for group in (1, 4):  # entry by entry, and runs of four rows
+            orders = sel.orders(mesh, op, blocks, total, tol=1e-7, margin=0.5, group=group)
+            out = torch.full((total,), float("nan"), dtype=torch.float64, device="cuda")
+            ctx.assemble_nearfield_learned(mesh, op, blocks, orders, out)
+            ctx.check()
+            q = orders.cpu().numpy().astype(np.int64)
+            reg = q > 0
+            if group == 1:
+                plain_points += int(reg.sum()) * 4 ** 4
+            saved_points[group] += int((4 ** 4 - q[reg] ** 4).sum())
+            res = out.cpu().numpy()
+            off = 0
+            for (r, c), ref in zip(zip(rows, cols), refs):
+                n = len(r) * len(c)
+                got = res[off:off + n].reshape(len(c), len(r)).T
+                qb = q[off:off + n].reshape(len(c), len(r)).T
+                off += n
+                err = np.linalg.norm(got - ref) / np.linalg.norm(ref)
+                assert err <= 1e-6, (layer, group, err)
+                # a run of `group` rows (sub-tiles of 64 rows) of a column
+                # shares one order among its pairs without a common vertex
+                for r0 in range(0, len(r), group):
+                    run = qb[r0:min(r0 + group, (r0 // 64 + 1) * 64)]
+                    for col in run.T:
+                        assert len(set(col[col > 0].tolist())) <= 1
+    assert saved_points[1] >= 0.2 * plain_points, (saved_points, plain_points)
+    assert saved_points[4] >= 0.1 * plain_points, (saved_points, plain_points)
     # outside the training range (these Laplace samples all have kappa D = 0)
     # the plain order is kept for every pair, whatever the network predicts
     oph = pk.make_op(pk.HELMHOLTZ, pk.SLP, q_regular=4, q_singular=4, kappa=30.0)
