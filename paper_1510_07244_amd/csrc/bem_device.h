@@ -23,73 +23,80 @@ __device__ __forceinline__ double rsqrt_newton(double a) {
   return fma(0.5 * y, e, y);
 }
 
-// sin and cos of x: Cody-Waite reduction x = k pi/2 + r, |r| <= pi/4, with
-// pi/2 split into three parts (the first two with 33 significant bits so that
+// sin and cos of x: Cody-Waite reduction x = k pi + r, |r| <= pi/2, with pi
+// split into three parts (the first two with 33 significant bits so that
 // k * part is exact for |k| < 2^20), then sin r = r + r^3 P(r^2) and
-// cos r = 1 - r^2 / 2 + r^4 Q(r^2) with P, Q of degree 5 whose coefficients
-// minimise the error relative to sin r and cos r on [-pi/4, pi/4] (Remez
-// exchange on the Taylor tail, computed by sincos_minimax.py beside this
-// file: below 1.1e-17 and 1.2e-18 with the coefficients rounded to double,
-// against 8 and 9 coefficients for Taylor polynomials of that accuracy), and
-// the quadrant of k.
-constexpr double kTwoOverPi = 0.63661977236758134308;
-constexpr double kPio2a = 1.5707963267341256;     // 0x1.921fb544p+0
-constexpr double kPio2b = 6.077100506303966e-11;  // 0x1.0b4611a6p-34
-constexpr double kPio2c = 2.0222662487959506e-21; // 0x1.3198a2e037073p-69
+// cos r = 1 - r^2 / 2 + r^4 Q(r^2), P of degree 7 minimising the error
+// relative to sin r and Q of degree 6 minimising the absolute error of cos r
+// on [-pi/2, pi/2] (Remez exchange on the Taylor tail, computed by
+// sincos_minimax.py beside this file: below 5.4e-18 relative and 1.4e-17
+// absolute with the coefficients rounded to double); odd k negates both,
+// by the sign bit.  Reducing by pi rather than pi/2 costs two more
+// polynomial terms and saves the quadrant's exchange of sine and cosine.
+constexpr double kOneOverPi = 0.31830988618379067154;
+constexpr double kPia = 3.1415926534682512;      // 0x1.921fb544p+1
+constexpr double kPib = 1.2154201012607932e-10;  // 0x1.0b4611a6p-33
+constexpr double kPic = 4.044532497591901e-21;   // 0x1.3198a2e037073p-68
 
-__device__ __forceinline__ void sincos_cw(double x, double *s, double *c) {
-  const double k = __builtin_rint(x * kTwoOverPi);
-  double r = fma(-k, kPio2a, x);
-  r = fma(-k, kPio2b, r);
-  r = fma(-k, kPio2c, r);
-  const double r2 = r * r;
-  double ps = 0x1.5d8fd1fcbc639p-33;  // P, highest degree first
-  ps = fma(ps, r2, -0x1.ae5e5a9290a58p-26);
-  ps = fma(ps, r2, 0x1.71de3567d4885p-19);
-  ps = fma(ps, r2, -0x1.a01a019bfdf03p-13);
-  ps = fma(ps, r2, 0x1.111111110f7d0p-7);
-  ps = fma(ps, r2, -0x1.5555555555548p-3);
-  const double sr = fma(r * r2, ps, r);
-  double pc = -0x1.8fa49a08c34a9p-37;  // Q, highest degree first
-  pc = fma(pc, r2, 0x1.1ee9d7b4e4aa0p-29);
-  pc = fma(pc, r2, -0x1.27e4f7eac4bd6p-22);
-  pc = fma(pc, r2, 0x1.a01a019c844f5p-16);
-  pc = fma(pc, r2, -0x1.6c16c16c14f91p-10);
-  pc = fma(pc, r2, 0x1.555555555554bp-5);
-  pc = fma(pc, r2, -0.5);
-  const double cr = fma(r2, pc, 1.0);
-  const int q = static_cast<int>(k) & 3;
-  const double a = (q & 1) ? cr : sr;
-  const double b = (q & 1) ? sr : cr;
-  *s = (q & 2) ? -a : a;
-  *c = ((q + 1) & 2) ? -b : b;
+// x with its sign flipped when bit 31 of sgn is set
+__device__ __forceinline__ double flip_sign(double x, int sgn) {
+  return __hiloint2double(__double2hiint(x) ^ sgn, __double2loint(x));
 }
 
-// FP32 sine and cosine for the mixed-precision path: the same Cody-Waite
-// reduction with pi/2 truncated to 12 + 12 + 24 significant bits (k * part
-// exact for |k| < 2^12), minimax P and Q of degree 2 from the same
-// construction (relative errors below 8.4e-9 and 1.8e-10 with the
-// coefficients rounded to float).
+__device__ __forceinline__ void sincos_cw(double x, double *s, double *c) {
+  const double k = __builtin_rint(x * kOneOverPi);
+  double r = fma(-k, kPia, x);
+  r = fma(-k, kPib, r);
+  r = fma(-k, kPic, r);
+  const double r2 = r * r;
+  double ps = 0x1.8829a2ffb2991p-49;  // P, highest degree first
+  ps = fma(ps, r2, -0x1.ae431d98dda7bp-41);
+  ps = fma(ps, r2, 0x1.6123cb29045c6p-33);
+  ps = fma(ps, r2, -0x1.ae6454cb574e2p-26);
+  ps = fma(ps, r2, 0x1.71de3a5287c76p-19);
+  ps = fma(ps, r2, -0x1.a01a01a0148bcp-13);
+  ps = fma(ps, r2, 0x1.11111111110c1p-7);
+  ps = fma(ps, r2, -0x1.5555555555555p-3);
+  const double sr = fma(r * r2, ps, r);
+  double pc = 0x1.9fc8d3c9114a6p-45;  // Q, highest degree first
+  pc = fma(pc, r2, -0x1.93573fa1f69b4p-37);
+  pc = fma(pc, r2, 0x1.1eecfaec8e87dp-29);
+  pc = fma(pc, r2, -0x1.27e4f9f33e2edp-22);
+  pc = fma(pc, r2, 0x1.a01a019ba7403p-16);
+  pc = fma(pc, r2, -0x1.6c16c16c10218p-10);
+  pc = fma(pc, r2, 0x1.55555555554ddp-5);
+  pc = fma(pc, r2, -0.5);
+  const double cr = fma(r2, pc, 1.0);
+  const int sgn = static_cast<int>((static_cast<unsigned>(static_cast<int>(k)) & 1u) << 31);
+  *s = flip_sign(sr, sgn);
+  *c = flip_sign(cr, sgn);
+}
+
+// FP32 sine and cosine for the mixed-precision path: the same reduction by
+// pi, truncated to 12 + 12 + 24 significant bits (k * part exact for
+// |k| < 2^12), minimax P and Q of degree 3 from the same construction (errors
+// below 9.7e-9 relative and 5.8e-9 absolute with the coefficients rounded to
+// float).
 __device__ __forceinline__ void sincos_cw_f32(float x, float *s, float *c) {
-  const float k = __builtin_rintf(x * 0.63661977f);
-  float r = fmaf(-k, 1.5703125f, x);              // 0x1.92p+0
-  r = fmaf(-k, 4.837512969970703125e-4f, r);      // 0x1.fb4p-12
-  r = fmaf(-k, 7.549789415861596e-8f, r);         // 0x1.4442dp-24
+  const float k = __builtin_rintf(x * 0.31830988f);
+  float r = fmaf(-k, 3.140625f, x);               // 0x1.92p+1
+  r = fmaf(-k, 9.67502593994140625e-4f, r);       // 0x1.fb4p-11
+  r = fmaf(-k, 1.5099579e-7f, r);                 // 0x1.4442dp-23
   const float r2 = r * r;
-  float ps = -0x1.9943e0p-13f;
-  ps = fmaf(ps, r2, 0x1.11073ap-7f);
-  ps = fmaf(ps, r2, -0x1.555546p-3f);
+  float ps = 0x1.5dbdf0p-19f;
+  ps = fmaf(ps, r2, -0x1.9f6ffep-13f);
+  ps = fmaf(ps, r2, 0x1.110ed4p-7f);
+  ps = fmaf(ps, r2, -0x1.55554cp-3f);
   const float sr = fmaf(r * r2, ps, r);
-  float pc = 0x1.99eb9cp-16f;
-  pc = fmaf(pc, r2, -0x1.6c0c34p-10f);
-  pc = fmaf(pc, r2, 0x1.55554ap-5f);
+  float pc = -0x1.194102p-22f;
+  pc = fmaf(pc, r2, 0x1.9f8f5ap-16f);
+  pc = fmaf(pc, r2, -0x1.6c149cp-10f);
+  pc = fmaf(pc, r2, 0x1.555550p-5f);
   pc = fmaf(pc, r2, -0.5f);
   const float cr = fmaf(r2, pc, 1.0f);
-  const int q = static_cast<int>(k) & 3;
-  const float a = (q & 1) ? cr : sr;
-  const float b = (q & 1) ? sr : cr;
-  *s = (q & 2) ? -a : a;
-  *c = ((q + 1) & 2) ? -b : b;
+  const int sgn = static_cast<int>((static_cast<unsigned>(static_cast<int>(k)) & 1u) << 31);
+  *s = __int_as_float(__float_as_int(sr) ^ sgn);
+  *c = __int_as_float(__float_as_int(cr) ^ sgn);
 }
 
 template <int KERNEL>

@@ -1,26 +1,29 @@
 """Coefficients of the sine and cosine polynomials of bem_device.h.
 
-After the Cody-Waite reduction to r in [-pi/4, pi/4], t = r^2 in [0, T],
-T = (pi/4)^2:
+After the Cody-Waite reduction x = k pi + r to r in [-pi/2, pi/2],
+t = r^2 in [0, T], T = (pi/2)^2:
 
     sin r ~ r + r^3 P(t),   cos r ~ 1 - t/2 + t^2 Q(t)
 
-with P, Q of degree 5 (FP64) or 2 (FP32), chosen to minimise the largest
-error relative to sin r and cos r on the reduction interval (minimax in the
-weights t^(3/2) / sin(sqrt t) and t^2 / cos(sqrt t)).  Method: the Remez
-exchange algorithm (E. Ya. Remez, 1934) in x86 long double, applied to the
-part of the Taylor series beyond the polynomial's degree -- the polynomial is
-the Taylor polynomial plus a minimax correction, so the levelled linear
-systems solve for quantities of the size of the error, not of the
-coefficients -- on t in [1e-3 T, T] (below, the weights make every error
-negligible).  Run as a script to print the coefficients as hexadecimal
-floats; tests/test_host_sincos.py checks the header's against this
-construction's error bounds.
+(sin x and cos x are then those of r, both negated for odd k).  P is
+chosen to minimise the largest error relative to sin r (weight
+t^(3/2) / sin(sqrt t)), Q the largest absolute error of cos r (weight t^2:
+cos r vanishes at the interval's ends, where only absolute accuracy makes
+sense -- it is what the kernel e^{i kappa r} needs).  FP64: P of degree 7,
+Q of degree 6; FP32: degree 3 each.  Method: the Remez exchange algorithm
+(E. Ya. Remez, 1934) in x86 long double, applied to the part of the Taylor
+series beyond the polynomial's degree -- the polynomial is the Taylor
+polynomial plus a minimax correction, so the levelled linear systems solve
+for quantities of the size of the error, not of the coefficients -- on t in
+[1e-3 T, T] (below, the weights make every error negligible).  Run as a
+script to print the coefficients as hexadecimal floats;
+tests/test_host_sincos.py checks the header's against this construction's
+error bounds.
 """
 import numpy as np
 
 L = np.longdouble
-T = L(np.pi / 4) ** 2
+T = L(np.pi / 2) ** 2
 
 
 def _fact(n):
@@ -59,8 +62,9 @@ def sin_w(t):
 
 
 def cos_w(t):
+    """Absolute error of cos r."""
     t = np.asarray(t, dtype=L)
-    return t * t / (1 - t / 2 + t * t * cos_f(t))
+    return t * t
 
 
 def _solve(A, b):
@@ -130,8 +134,9 @@ def coefficients(kind, deg):
 
 
 def max_rel_error(kind, coefs, npts=200001):
-    """Largest error relative to sin r / cos r over t in [0, T] of the
-    polynomial with the given (rounded) coefficients, in long double."""
+    """Largest error over t in [0, T] of the polynomial with the given
+    (rounded) coefficients, in long double: relative to sin r for the sine,
+    absolute for the cosine."""
     t = np.linspace(0.0, float(T), npts).astype(L)
     P = np.zeros_like(t)
     for c in coefs[::-1]:
@@ -142,8 +147,8 @@ def max_rel_error(kind, coefs, npts=200001):
 
 
 if __name__ == "__main__":
-    for kind, deg, typ in (("sin", 5, np.float64), ("cos", 5, np.float64),
-                           ("sin", 2, np.float32), ("cos", 2, np.float32)):
+    for kind, deg, typ in (("sin", 7, np.float64), ("cos", 6, np.float64),
+                           ("sin", 3, np.float32), ("cos", 3, np.float32)):
         c, E = coefficients(kind, deg)
         r = [typ(x) for x in c]
         print(kind, typ.__name__, "levelled", E, "rounded", max_rel_error(kind, r))
