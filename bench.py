@@ -94,9 +94,10 @@ def parse():
     p.add_argument("--learned-n", type=int, default=128,
                    help="octahedron subdivision of the learned-form sphere (nt = 8 n^2)")
     p.add_argument("--counter-pass", action="store_true",
-                   help="for hardware-counter runs: one near-field launch of the Laplace SLP "
-                        "and one of the DLP on the 8192-triangle sphere, then a 512 MiB device "
-                        "copy that calibrates FETCH_SIZE / WRITE_SIZE; prints no JSON")
+                   help="for hardware-counter runs: the block launches of the 8192-triangle "
+                        "sphere's Laplace step (and the Helmholtz kappa 4 coupling launches), "
+                        "then a 512 MiB device copy that calibrates FETCH_SIZE / WRITE_SIZE; "
+                        "prints no JSON")
     return p.parse_args()
 
 
@@ -126,13 +127,27 @@ def counter_pass(torch, pk, ctx, m):
     o1 = torch.empty(tot, dtype=torch.float64, device="cuda")
     o2 = torch.empty_like(o1)
     ctx.assemble_nearfield_both(h.mesh, h.op(pk.SLP), half, o1, o2)
+    # the single layer's mirrored coupling launch (the step's), then the
+    # Helmholtz coupling launches of config 3's kernel on this mesh
+    cs, n_cs = h.coupling_blocks(V, V, mirror=True)
+    ctx.assemble_coupling(h.mesh, h.op(pk.SLP), cs, torch.empty(n_cs, dtype=torch.float64,
+                                                                 device="cuda"))
+    hh = H2Setup(ctx, m.v, m.tri, kernel=pk.HELMHOLTZ, kappa=4.0, q_regular=5, q_singular=5)
+    Vh, Wh = hh.bases((0, 1))
+    cdh, n_cdh = hh.coupling_blocks(Vh, Wh)
+    csh, n_csh = hh.coupling_blocks(Vh, Vh, mirror=True)
+    ctx.assemble_coupling(hh.mesh, hh.op(pk.DLP), cdh,
+                          torch.empty(n_cdh, dtype=torch.complex128, device="cuda"))
+    ctx.assemble_coupling(hh.mesh, hh.op(pk.SLP), csh,
+                          torch.empty(n_csh, dtype=torch.complex128, device="cuda"))
     ctx.check()
     a = torch.ones(1 << 26, dtype=torch.float64, device="cuda")  # 512 MiB
     b = torch.empty_like(a)
     b.copy_(a)
     torch.cuda.synchronize()
     print(f"near-field entries per launch {total}, DLP coupling entries {n_cd}, "
-          f"copy bytes {a.numel() * 8}", flush=True)
+          f"SLP coupling entries {n_cs // 2} evaluated, Helmholtz DLP / SLP coupling entries "
+          f"{n_cdh} / {n_csh // 2}, copy bytes {a.numel() * 8}", flush=True)
 
 
 def class_counts(tri, rows, cols):
@@ -787,6 +802,60 @@ def helmholtz_h2_leg(torch, pk, ctx, stream, steps=3, warmup=1, peak64=None):
     return out
 
 
+def batched_config2_leg(torch, pk, ctx, hb, stream, steps=10):
+    """The batched form on the config-2 matrix: one persistent plan per layer
+    (single layer: the mirrored near-field and coupling lists; double layer:
+    the full near-field list and the coupling list), autotuned, replayed
+    after the bases; setup = the plain setup plus both plans (with their
+    tuning cached, as on a second run), outputs against the plain step's."""
+    h, o = hb.h, hb.out
+    out = {k: torch.empty_like(v) for k, v in o.items()}
+    lists = [(hb.ops[0], [(h.mesh, hb.near_s, out["ns"], 0), (h.mesh, hb.cs, out["cs"], 1)]),
+             (hb.ops[1], [(h.mesh, hb.near, out["nd"], 0), (h.mesh, hb.cd, out["cd"], 1)])]
+    cache = os.path.join(tempfile.gettempdir(), f"bem_tune_c2_{os.getpid()}.txt")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    plans = [pk.Plan(ctx, op, ent, autotune=True, cache=cache, stream=stream) for op, ent in lists]
+    torch.cuda.synchronize()
+    t_tune = time.perf_counter() - t0
+    tuned = [p.config for p in plans]
+    for p in plans:
+        p.close()
+    t0 = time.perf_counter()
+    plans = [pk.Plan(ctx, op, ent, autotune=True, cache=cache, stream=stream) for op, ent in lists]
+    torch.cuda.synchronize()
+    t_cached = time.perf_counter() - t0
+    os.remove(cache)
+
+    def step():
+        h.basis_replay(hb.V, stream)
+        h.basis_replay(hb.W, stream)
+        for p in plans:
+            p.run(stream)
+    step()
+    ctx.check(stream)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(steps):
+        step()
+    e1.record(stream)
+    e1.synchronize()
+    ctx.check(stream)
+    ms = e0.elapsed_time(e1) / steps
+    hb.step(stream)  # the plain step's outputs, for the comparison
+    torch.cuda.synchronize()
+    diff = {k: float(torch.linalg.vector_norm(out[k] - o[k]) / torch.linalg.vector_norm(o[k]))
+            for k in out}
+    for p in plans:
+        p.close()
+    return {"ms_per_step": ms, "plan_tuning_s": t_tune, "plan_cached_tuning_s": t_cached,
+            "h2_setup_s": float(hb.t_setup) + t_cached, "tune": tuned,
+            "rel_diff_vs_plain_step": diff,
+            "note": "two persistent graph replays (one per layer) after the bases; the plain "
+                    "step's single-layer near field is the one-pass launch, so the outputs "
+                    "agree up to rounding"}
+
+
 def solve_leg(torch, pk, ctx, hb, stream, reps=20):
     """H^2 products with the step's assembled matrices (near field, coupling
     and nested bases; the library's grouped matrix-vector kernels) and the
@@ -931,6 +1000,8 @@ def main():
     ms_step_m = ms_seq_m if args.one_stream else run_concurrent(torch, hm, stream, args.steps,
                                                                  args.warmup)[0]
     solve = solve_leg(torch, pk, ctx, hb, stream)
+    batched_c2 = None if args.batched_meshes <= 0 else batched_config2_leg(torch, pk, ctx, hb,
+                                                                           stream)
     helmholtz = None if args.no_helmholtz else helmholtz_near_leg(torch, pk, ctx, stream, 5)
     helmholtz_h2 = None if args.no_helmholtz else helmholtz_h2_leg(torch, pk, ctx, stream)
     batched = None
@@ -954,6 +1025,7 @@ def main():
     counts = class_counts(m.tri, rows, cols)
     f_dlp = near_flops(counts, 0, 1, Q, Q)
     f_cd = float(hb.n_cd) * (Q ** 2) ** 2 * FLOPS_PER_POINT[(0, 1)]  # coupling: regular pairs only
+    f_cs_lap = float(hb.n_cs // 2) * (Q ** 2) ** 2 * FLOPS_PER_POINT[(0, 0)]  # evaluated half
     # the mirrored single layer evaluates the pairs (i, j) of the blocks with
     # t < s and the lower triangles of the blocks (t, t), plus the
     # edge-adjacent transposed pairs (as (j, i))
@@ -1032,6 +1104,13 @@ def main():
         },
         "valu_peak_measured_tflops": dict(peak_meas, probe="bem_valu_peak: 8 independent FMA "
                                           "chains per lane, 16 waves per CU, best of 5"),
+        "roofline_slp_coupling": {
+            "kernel": "k_blocks<Laplace, SLP> coupling, mirrored (blocks with t < s, each also "
+                      "written transposed)", "bound": "alu",
+            "achieved": f_cs_lap / (phase["cs"] * 1e-3) / 1e12, "peak": FP64_VALU_PEAK / 1e12,
+            "unit": "TFLOP/s", "frac": f_cs_lap / (phase["cs"] * 1e-3) / FP64_VALU_PEAK,
+            "ms_per_launch": phase["cs"], "flops_per_launch": f_cs_lap,
+        },
         "roofline_near_both": {
             "kernel": "k_blocks<Laplace, SLP+DLP> near field, one pass over the blocks with "
                       "t <= s (both layers of (t, s) and (s, t))", "bound": "alu",
@@ -1069,6 +1148,14 @@ def main():
                     "peak": FP32_VALU_PEAK / 1e12, "unit": "TFLOP/s",
                     "frac": f_cd / (phase_m["cd"] * 1e-3) / FP32_VALU_PEAK,
                     "ms_per_launch": phase_m["cd"], "flops_per_launch": f_cd,
+                    "peak_without_packed_fp32": FP64_VALU_PEAK / 1e12,
+                    "frac_without_packed_fp32": f_cd / (phase_m["cd"] * 1e-3) / FP64_VALU_PEAK,
+                    "peak_measured": peak_meas["fp32"],
+                    "frac_of_measured_peak": f_cd / (phase_m["cd"] * 1e-3) /
+                                             (peak_meas["fp32"] * 1e12),
+                    "note": "the build does not use packed FP32 instructions, whose pairs of "
+                            "operations make the 157.3 TFLOP/s figure; without them the FP32 "
+                            "vector rate is that of FP64, 78.6",
                 },
             },
         },
@@ -1080,12 +1167,16 @@ def main():
         result["helmholtz_h2"] = helmholtz_h2
     if batched:
         result["forms"]["batched"] = batched
+    if batched_c2:
+        result["forms"]["batched_config2"] = batched_c2
     if learned:
         result["forms"]["learned"] = learned
     # H2 setup time of the 8192-sphere matrix by form (tree, bases, first
     # assembly; the learned form adds the order selection of its coupling
     # lists, the network being trained once offline)
     by_form = {"plain_fp64": float(st[best, 0]), "mixed": float(hm.t_setup)}
+    if batched_c2:
+        by_form["batched"] = float(st[best, 0]) + batched_c2["plan_cached_tuning_s"]
     if learned:
         by_form["learned_coupling"] = float(st[best, 0]) + learned["h2_step"]["select_s"]
     result["h2_setup_s_by_form"] = by_form

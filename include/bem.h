@@ -277,7 +277,9 @@ typedef struct {
  * planning requires a new plan.  Meshes given by identical descriptors share
  * one geometry buffer.  The plan owns its device memory (geometry, queue,
  * counter) and a HIP graph; autotuning launches the kernel (writing the
- * outputs) on `stream`.  `cache_path` (may be NULL) names a text file of
+ * outputs) on `stream`: every candidate once, then the fastest quarter (at
+ * least two) three more times, the best launch of each deciding
+ * (successive halving).  `cache_path` (may be NULL) names a text file of
  * tuned configurations, one JSON object per line, keyed by device and
  * workload; a hit skips the timing and a new result is appended.
  * Host-visible errors (ranges, offsets, ids) fail with BEM_EINVAL here. */

@@ -532,31 +532,53 @@ int bem_plan_batched(bem_ctx *ctx, const bem_op *op, int32_t nbatch, const bem_b
       best = {cached.grid, cached.tile_rows, cached.tile_cols, cached.x_chunk, cached.granularity == 1};
   }
   if (!hit && want.autotune && cands.size() > 1) {
+    // successive halving: every candidate timed once (after one warm-up
+    // launch of the first), then the fastest quarter (at least two) three
+    // times more; the best of a candidate's launches decides
     hipEvent_t t0, t1;
     if (hipEventCreate(&t0) != hipSuccess || hipEventCreate(&t1) != hipSuccess)
       return bail(fail(ctx, BEM_EDEVICE, "hipEventCreate"));
-    double bms = 1e300;
-    for (const Candidate &c : cands) {
+    auto timed = [&](const Candidate &c, int reps, bool warm, float *best_of) -> int {
       PersistentArgs pa{};
-      if ((rc = stage(c, &pa))) return bail(rc);
-      hipError_t e = enqueue(pa, c.xc, s);  // warm-up
-      float ms = 0.f, tot = 0.f, mn = 1e30f;
-      for (int r = 0; r < 3 && e == hipSuccess; ++r) {
+      int r0 = stage(c, &pa);
+      if (r0) return r0;
+      hipError_t e = warm ? enqueue(pa, c.xc, s) : hipSuccess;
+      float ms = 0.f, mn = 1e30f;
+      for (int r = 0; r < reps && e == hipSuccess; ++r) {
         e = hipEventRecord(t0, s);
         if (e == hipSuccess) e = enqueue(pa, c.xc, s);
         if (e == hipSuccess) e = hipEventRecord(t1, s);
         if (e == hipSuccess) e = hipEventSynchronize(t1);
         if (e == hipSuccess) e = hipEventElapsedTime(&ms, t0, t1);
-        tot += ms;
         mn = std::min(mn, ms);
       }
-      if (e != hipSuccess) {
+      if (e != hipSuccess) return hip_fail(ctx, e, "autotune launch");
+      *best_of = mn;
+      return BEM_OK;
+    };
+    std::vector<std::pair<float, size_t>> round1;
+    for (size_t k = 0; k < cands.size(); ++k) {
+      float ms = 0.f;
+      if ((rc = timed(cands[k], 1, k == 0, &ms))) {
         (void)hipEventDestroy(t0);
         (void)hipEventDestroy(t1);
-        return bail(hip_fail(ctx, e, "autotune launch"));
+        return bail(rc);
       }
-      (void)tot;
-      if (mn < bms) bms = mn, best = c;
+      round1.push_back({ms, k});
+    }
+    std::sort(round1.begin(), round1.end());
+    const size_t keep = std::max<size_t>(2, (cands.size() + 3) / 4);
+    double bms = 1e300;
+    for (size_t i = 0; i < std::min(keep, round1.size()); ++i) {
+      const Candidate &c = cands[round1[i].second];
+      float ms = 0.f;
+      if ((rc = timed(c, 3, false, &ms))) {
+        (void)hipEventDestroy(t0);
+        (void)hipEventDestroy(t1);
+        return bail(rc);
+      }
+      ms = std::min(ms, round1[i].first);
+      if (ms < bms) bms = ms, best = c;
     }
     (void)hipEventDestroy(t0);
     (void)hipEventDestroy(t1);
