@@ -362,6 +362,15 @@ class BatchedBench:
         os.remove(cache)
         self.n_entries = sum(n_near + n_cs for h, near, n_near, cs, n_cs in self.items)
         self.triangles = sum(m.nt for m in self.meshes)
+        # model flops of what one replay evaluates: per mesh the mirrored
+        # near field (blocks with t <= s, edge-adjacent transposed pairs
+        # evaluated as (j, i)) and half of the mirrored coupling entries
+        self.flops = 0.0
+        for (h, near, n_near, cs, n_cs), m in zip(self.items, self.meshes):
+            ev, tr_ = mirrored_counts(h, m.tri)
+            ev = ev.copy()
+            ev[2] += tr_[2]
+            self.flops += near_flops(ev, 0, 0, Q, Q) + float(n_cs // 2) * Q ** 4 * FLOPS_PER_POINT[(0, 0)]
 
     def per_call(self, stream):
         for (h, near, n_near, cs, n_cs), (on, oc) in zip(self.items, self.out):
@@ -395,6 +404,12 @@ class BatchedBench:
             "workload": f"Laplace SLP near field + coupling blocks of {len(sizes)} perturbed "
                         f"spheres ({min(sizes)}..{max(sizes)} triangles, {self.triangles} total), "
                         "each with its own H2 setup (leaf 64, eta 2, ACA 5e-8), plain FP64",
+            "roofline": {"bound": "alu", "achieved": self.flops / (ms_b * 1e-3) / 1e12,
+                         "peak": FP64_VALU_PEAK / 1e12, "unit": "TFLOP/s",
+                         "frac": self.flops / (ms_b * 1e-3) / FP64_VALU_PEAK,
+                         "flops_per_launch": self.flops, "ms_per_launch": ms_b,
+                         "kernel": "k_persistent<Laplace, SLP> (one replay: near field and "
+                                   "coupling of the 64 meshes)"},
             "tiles": self.plan.tiles, "tune": self.tuned,
             "plan_s": self.t_plan, "plan_cached_tuning_s": self.t_plan_cached,
             "plan_note": "plan_s includes the autotuner's timed candidates; "
@@ -459,6 +474,8 @@ class LearnedBench:
         offs = np.concatenate([[0], np.cumsum(sizes)[:-1]])
         rng = np.random.Generator(np.random.PCG64(5))
         self.check = [(int(offs[k]), int(sizes[k])) for k in rng.choice(len(near), 256, replace=False)]
+        # pair classes of the whole near field (for the rooflines)
+        self.counts = class_counts(m.tri, [ct.idx(t) for t, s in near], [ct.idx(s) for t, s in near])
 
     def leg(self, torch, op, stream, steps, warmup):
         ctx, pk = self.ctx, self.pk
@@ -501,7 +518,20 @@ class LearnedBench:
             errs.append(float(torch.linalg.vector_norm(a - b) / torch.linalg.vector_norm(b)))
         tot = float(torch.linalg.vector_norm(learned - plain) / torch.linalg.vector_norm(plain))
         del plain, learned, orders
+        # rooflines of the two assemblies: the model flops of the plain rule,
+        # and of the learned orders (regular pairs at their own order, the
+        # singular pairs by the same Sauter-Schwab rules)
+        F = FLOPS_PER_POINT[(op.kernel, op.layer)]
+        f_plain = near_flops(self.counts, op.kernel, op.layer, qp, op.q_singular)
+        f_learned = f_plain - float(self.counts[0]) * qp ** 4 * F + \
+            sum(float(n) * k ** 4 * F for k, n in counts.items())
+        peak = FP64_VALU_PEAK
+        roof = lambda f, t: {"bound": "alu", "achieved": f / (t * 1e-3) / 1e12,
+                             "peak": peak / 1e12, "unit": "TFLOP/s", "frac": f / (t * 1e-3) / peak,
+                             "flops_per_launch": f, "ms_per_launch": t}
         return {"plain_ms": ms["plain"], "select_ms": ms["select"], "learned_ms": ms["learned"],
+                "roofline_plain": roof(f_plain, ms["plain"]),
+                "roofline_learned": roof(f_learned, ms["learned"]),
                 "select_per_entry_ms": ms["select_per_entry"],
                 "speedup_vs_plain": ms["plain"] / (ms["select"] + ms["learned"]),
                 "assembly_speedup_excl_select": ms["plain"] / ms["learned"],
