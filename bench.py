@@ -55,10 +55,11 @@ MIXED_RATIO = 0.5  # mixed form: pairs with box gap < 0.5 max diameter stay FP64
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_k_blocks_sphere8192.md")
 
 
-def stored_traffic():
-    """HBM bytes per DLP coupling launch from the committed counter passes
-    (FETCH_SIZE and WRITE_SIZE, each scaled by its reading of a copy of known
-    size), or None if the block kernel's sources changed since."""
+def stored_counters():
+    """(HBM bytes, counted FP64 flops) per DLP coupling launch from the
+    committed counter passes (FETCH_SIZE and WRITE_SIZE, each scaled by its
+    reading of a copy of known size; the SQ_INSTS_VALU_*_F64 counters), or
+    (None, None) if the block kernel's sources changed since."""
     import hashlib
     try:
         kv = {}
@@ -70,11 +71,18 @@ def stored_traffic():
         for src in kv["sources"].split():
             h.update(open(os.path.join(ROOT, src), "rb").read())
         if h.hexdigest() != kv["source_sha256"]:
-            return None
-        return 1024.0 * (float(kv["fetch_kib_per_launch"]) * float(kv["fetch_scale"]) +
-                         float(kv["write_kib_per_launch"]) * float(kv["write_scale"]))
+            return None, None
+        traffic = 1024.0 * (float(kv["fetch_kib_per_launch"]) * float(kv["fetch_scale"]) +
+                            float(kv["write_kib_per_launch"]) * float(kv["write_scale"]))
+        flops = float(kv["fp64_flop_counted_per_launch"]) if "fp64_flop_counted_per_launch" in kv \
+            else None
+        return traffic, flops
     except (OSError, KeyError, ValueError):
-        return None
+        return None, None
+
+
+def stored_traffic():
+    return stored_counters()[0]
 
 
 def parse():
@@ -91,6 +99,8 @@ def parse():
                         "overlapping launches would stretch each other's durations)")
     p.add_argument("--cpu-seconds", type=float, default=12.0)
     p.add_argument("--batched-meshes", type=int, default=64)
+    p.add_argument("--learned-group", type=int, default=4,
+                   help="rows of a column per network evaluation in the learned legs")
     p.add_argument("--learned-n", type=int, default=128,
                    help="octahedron subdivision of the learned-form sphere (nt = 8 n^2)")
     p.add_argument("--counter-pass", action="store_true",
@@ -1042,6 +1052,7 @@ def main():
     learned = None
     if args.learned_n > 0:
         lb = LearnedBench(pk, ctx, args.learned_n)
+        lb.GROUP = args.learned_group
         learned = lb.result(torch, stream, min(args.steps, 10), 1)
         learned["h2_step"] = learned_h2_leg(torch, pk, ctx, hb, lb.sel, stream,
                                             min(args.steps, 10), 2)
@@ -1055,6 +1066,7 @@ def main():
     counts = class_counts(m.tri, rows, cols)
     f_dlp = near_flops(counts, 0, 1, Q, Q)
     f_cd = float(hb.n_cd) * (Q ** 2) ** 2 * FLOPS_PER_POINT[(0, 1)]  # coupling: regular pairs only
+    counted_cd = stored_counters()[1]
     f_cs_lap = float(hb.n_cs // 2) * (Q ** 2) ** 2 * FLOPS_PER_POINT[(0, 0)]  # evaluated half
     # the mirrored single layer evaluates the pairs (i, j) of the blocks with
     # t < s and the lower triangles of the blocks (t, t), plus the
@@ -1131,6 +1143,14 @@ def main():
             "ms_per_launch": phase["cd"], "flops_per_launch": f_cd,
             "peak_measured": peak_meas["fp64"],
             "frac_of_measured_peak": f_cd / (phase["cd"] * 1e-3) / (peak_meas["fp64"] * 1e12),
+            "flops_model": "strict: 19 flops per point pair (the reciprocal root as one)",
+            "counted_flops_per_launch": counted_cd,
+            "counted_frac_of_measured_peak": (None if counted_cd is None else
+                                              counted_cd / (phase["cd"] * 1e-3) /
+                                              (peak_meas["fp64"] * 1e12)),
+            "counted_note": "FP64 FLOP of the launch from the SQ_INSTS_VALU_*_F64 counters of "
+                            "the committed counter pass (64 x (2 FMA + ADD + MUL + TRANS)), null "
+                            "once the kernel's sources change",
         },
         "valu_peak_measured_tflops": dict(peak_meas, probe="bem_valu_peak: 8 independent FMA "
                                           "chains per lane, 16 waves per CU, best of 5"),

@@ -129,11 +129,15 @@ def cmd_counters(a):
 
 def _counter_rows(path):
     """(kernel, workgroups) -> list of {counter: value} per dispatch, in
-    dispatch order."""
+    dispatch order (with the dispatch's duration under the counters, ns, as
+    'duration_ns')."""
     per = collections.OrderedDict()
     for r in csv.DictReader(open(path)):
         key = (int(r["Dispatch_Id"]), _kname(r["Kernel_Name"]), _grid_wg(r))
-        per.setdefault(key, {})[r["Counter_Name"]] = float(r["Counter_Value"])
+        d = per.setdefault(key, {})
+        d[r["Counter_Name"]] = float(r["Counter_Value"])
+        if r.get("Start_Timestamp") and r.get("End_Timestamp"):
+            d["duration_ns"] = float(int(r["End_Timestamp"]) - int(r["Start_Timestamp"]))
     out = collections.OrderedDict()
     for (_, name, wg), v in sorted(per.items()):
         out.setdefault((name, wg), []).append(v)
@@ -154,7 +158,13 @@ def cmd_traffic(a):
                 ("DLP coupling (3760 blocks)", "k_blocks<0, 1, 8, false>", 3760, 0,
                  a.coupling_entries * 8, "roofline"),
                 ("SLP+DLP near field, one pass (1292 blocks)", "k_blocks<0, 2, 8, false>", 1292, 0,
-                 2 * a.near_entries * 8, "roofline_near_both")]
+                 2 * a.near_entries * 8, "roofline_near_both"),
+                ("SLP coupling, mirrored (1880 blocks)", "k_blocks<0, 0, 8, false>", 1880, 0,
+                 2 * a.slp_coupling_entries * 8, "roofline_slp_coupling"),
+                ("Helmholtz kappa 4 DLP coupling, q 5 (3760 blocks)", "k_blocks<1, 1, 5, false>",
+                 3760, 0, a.helmholtz_dlp_entries * 16, None),
+                ("Helmholtz kappa 4 SLP coupling, q 5, mirrored (1880 blocks)",
+                 "k_blocks<1, 0, 5, false>", 1880, 0, 2 * a.helmholtz_slp_entries * 16, None)]
 
     def value(name, wg, k, counter):
         for run in runs:
@@ -179,7 +189,8 @@ def cmd_traffic(a):
            f"WRITE_SIZE by {ws:.4f}.", "",
            "| Launch | FETCH_SIZE KiB | WRITE_SIZE KiB | HBM bytes (scaled) | algorithmic bytes "
            "(output) | write / output | SQ_INSTS_VALU | SQ_INSTS_LDS | FP64 FLOP counted | "
-           "FP32 FLOP counted | algorithmic FLOP | counted / algorithmic | trace ms (last 5) | "
+           "FP32 FLOP counted | algorithmic FLOP | counted / algorithmic | ms (trace, last 5; "
+           "else the FLOP pass) | "
            "counted TFLOP/s |",
            "|---|---|---|---|---|---|---|---|---|---|---|---|---|---|"]
     stored = None
@@ -202,6 +213,11 @@ def cmd_traffic(a):
             model = node.get("flops_per_launch") if isinstance(node, dict) else None
         d = trace.get((name, wg))
         ms = sum(d[-5:]) / len(d[-5:]) / 1e6 if d else None
+        if ms is None:  # not in the trace: the FLOP pass's own duration
+            for run in runs:
+                v = run.get((name, wg))
+                if v and k < len(v) and "SQ_INSTS_VALU_FMA_F64" in v[k] and "duration_ns" in v[k]:
+                    ms = v[k]["duration_ns"] / 1e6
         fmt = lambda x, spec: "-" if x is None else format(x, spec)
         out.append(f"| {label} | {fmt(f, '.0f')} | {fmt(w, '.0f')} | {fmt(hbm, '.4g')} | "
                    f"{out_bytes:.4g} | {fmt(None if w is None else 1024 * w * ws / out_bytes, '.2f')} | "
@@ -211,7 +227,7 @@ def cmd_traffic(a):
                    f"{fmt(None if model is None or f64 is None else (f64 + (f32 or 0)) / model, '.3f')} | "
                    f"{fmt(ms, '.4f')} | {fmt(None if ms is None or f64 is None else f64 / ms / 1e9, '.2f')} |")
         if key == "roofline":
-            stored = (f, w)
+            stored = (f, w, f64)
     out += ["", f"Algorithmic output: near field {a.near_entries:,} FP64 entries = "
                 f"{a.near_entries * 8 / 1e6:.1f} MB per launch and layer; DLP coupling "
                 f"{a.coupling_entries:,} entries = {a.coupling_entries * 8 / 1e6:.1f} MB.",
@@ -226,7 +242,8 @@ def cmd_traffic(a):
             "per launch; valid while the sources below hash to this value):", "",
             f"    source_sha256: {h.hexdigest()}", f"    sources: {' '.join(a.sources)}",
             f"    fetch_kib_per_launch: {stored[0]:.0f}", f"    write_kib_per_launch: {stored[1]:.0f}",
-            f"    fetch_scale: {fs:.6f}", f"    write_scale: {ws:.6f}"]
+            f"    fetch_scale: {fs:.6f}", f"    write_scale: {ws:.6f}",
+            f"    fp64_flop_counted_per_launch: {stored[2]:.6g}"]
     print("\n".join(out))
 
 
@@ -257,6 +274,11 @@ def main():
     r.add_argument("--bench-log")
     r.add_argument("--near-entries", type=int, required=True)
     r.add_argument("--coupling-entries", type=int, required=True)
+    r.add_argument("--slp-coupling-entries", type=int, default=0,
+                   help="evaluated entries of the mirrored single-layer coupling launch")
+    r.add_argument("--helmholtz-dlp-entries", type=int, default=0)
+    r.add_argument("--helmholtz-slp-entries", type=int, default=0,
+                   help="evaluated entries of the mirrored Helmholtz single-layer coupling")
     r.add_argument("--copy-bytes", type=int, default=512 * 1024 * 1024)
     r.add_argument("--sources", nargs="+", required=True)
     r.add_argument("--root", default=".")

@@ -213,8 +213,8 @@ __global__ __launch_bounds__(kThreads) void k_contract(const ContractArgs a) {
 // row operations on X read and write contiguous rows, and the inverse of X
 // left in place row-major is M^{-1} column-major.  The steps are sequential
 // (k_c of them, two barriers each) and the data small: latency-bound, so the
-// matrix sits in LDS when it fits and the vector units serve it; the matrix
-// cores are used by the contraction that follows.
+// matrix stays in registers for the common ranks and the vector units serve
+// it; the matrix cores are used by the contraction that follows.
 template <bool CPLX>
 struct Z;
 template <>
@@ -262,10 +262,9 @@ struct Z<true> {
 };
 
 constexpr int kInvMaxRank = 512;
-constexpr size_t kInvLdsBytes = 136 * 1024;  // matrices held in LDS up to this size
 
-// Gauss-Jordan on the k x k row-major matrix M (leading dimension ld, in LDS
-// or global memory), in place and in the given order, without further
+// Gauss-Jordan on the k x k row-major matrix M (leading dimension ld, in
+// global memory), in place and in the given order, without further
 // pivoting: the pivots are the cross approximation's, each chosen as the
 // largest entry of the residual of the whole Green matrix, so eliminating in
 // their order is elimination with complete pivoting.  Two barriers per
@@ -307,14 +306,12 @@ __device__ __forceinline__ void gauss_jordan(T *M, int ld, int k, T *fcol, T *ps
   }
 }
 
-// One workgroup per matrix.  Matrices of up to lds_k rows are eliminated in
-// LDS (leading dimension k + 1 against bank conflicts on column reads) and
-// written out once; larger ones in their global slot.
+// One workgroup per matrix, in the matrix's global output slot: the ranks
+// beyond the register-resident kernel's (real > 192, complex > 128), which
+// an LDS copy could not hold either (160 KB).
 template <bool CPLX>
-__global__ __launch_bounds__(kThreads) void k_pivot_inverse(const PivInvArgs a, int lds_k,
-                                                             int reg_k) {
+__global__ __launch_bounds__(kThreads) void k_pivot_inverse(const PivInvArgs a, int reg_k) {
   using T = Z<CPLX>;
-  extern __shared__ __align__(16) double inv_lds[];
   __shared__ T fcol[kInvMaxRank], ps[kInvMaxRank];
   const int c = blockIdx.x;
   const int n = a.nrows[c], k = a.rank[c];
@@ -331,8 +328,6 @@ __global__ __launch_bounds__(kThreads) void k_pivot_inverse(const PivInvArgs a, 
   const int32_t *pcol = a.piv_cols + (int64_t)c * a.max_rank;
   const T *A = reinterpret_cast<const T *>(a.A);
   T *X = reinterpret_cast<T *>(a.pinv) + (int64_t)c * a.max_rank * a.max_rank;
-  const bool in_lds = k <= lds_k;  // uniform
-  T *L = reinterpret_cast<T *>(inv_lds);
   // X[i][j] = M[j][i] = A[prow[j], pcol[i]]
   for (int i = wave; i < k; i += W) {
     const int ci = pcol[i];
@@ -341,18 +336,11 @@ __global__ __launch_bounds__(kThreads) void k_pivot_inverse(const PivInvArgs a, 
       T v = T::make(0, 0);
       if (ci < 0 || ci >= a.acols || rj < 0 || rj >= n) atomicOr(a.flags, FLAG_EINVAL);
       else v = A[aoff + rj + (int64_t)n * ci];
-      if (in_lds) L[i * (k + 1) + j] = v;
-      else X[(int64_t)i * k + j] = v;
+      X[(int64_t)i * k + j] = v;
     }
   }
   __syncthreads();
-  if (in_lds) {
-    gauss_jordan(L, k + 1, k, fcol, ps, a.flags);
-    for (int i = wave; i < k; i += W)
-      for (int j = lane; j < k; j += kWave) X[(int64_t)i * k + j] = L[i * (k + 1) + j];
-  } else {
-    gauss_jordan(X, k, k, fcol, ps, a.flags);
-  }
+  gauss_jordan(X, k, k, fcol, ps, a.flags);
 }
 
 // Register-resident form for the common ranks: 16 waves (1024 threads); wave
@@ -481,21 +469,16 @@ hipError_t launch_pivot_inverse(bool cplx, const PivInvArgs &a, hipStream_t s) {
   if (a.nmat == 0) return hipSuccess;
   if (a.max_rank > kInvMaxRank) return hipErrorInvalidValue;
   const dim3 grid(a.nmat), block(kThreads);
-  // largest k whose k x (k + 1) matrix fits the LDS allowance, at most max_rank
-  const size_t elem = cplx ? 16 : 8;
-  int lds_k = 0;
-  while (lds_k < a.max_rank && (size_t)(lds_k + 1) * (lds_k + 2) * elem <= kInvLdsBytes) ++lds_k;
-  const size_t lds = (size_t)lds_k * (lds_k + 1) * elem;
   // ranks up to reg_k in registers (real 192 = 16 x 12 rows by 64 x 3
-  // columns, complex 128 = 16 x 8 by 64 x 2), the rest in LDS or global memory
+  // columns, complex 128 = 16 x 8 by 64 x 2), the rest in global memory
   const int reg_k = cplx ? kRegWaves * 8 : kRegWaves * 12;
   const dim3 rblock(kRegThreads);
   if (cplx) hipLaunchKernelGGL((k_pivot_inverse_reg<true, 8, 2>), grid, rblock, 0, s, a);
   else hipLaunchKernelGGL((k_pivot_inverse_reg<false, 12, 3>), grid, rblock, 0, s, a);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess || a.max_rank <= reg_k) return e;
-  if (cplx) hipLaunchKernelGGL((k_pivot_inverse<true>), grid, block, lds, s, a, lds_k, reg_k);
-  else hipLaunchKernelGGL((k_pivot_inverse<false>), grid, block, lds, s, a, lds_k, reg_k);
+  if (cplx) hipLaunchKernelGGL((k_pivot_inverse<true>), grid, block, 0, s, a, reg_k);
+  else hipLaunchKernelGGL((k_pivot_inverse<false>), grid, block, 0, s, a, reg_k);
   return hipGetLastError();
 }
 

@@ -89,24 +89,26 @@ struct Num<true> {
 // Group g: y[out_idx[out_ptr[g] ..]] += sum_{b in group g} op(A_b) x[in_idx[in_ptr[b] ..]],
 // op(A) = A (TRANS false; A is m_out x n_in) or A^T (TRANS true; A is
 // n_in x m_out), column-major with the row count as leading dimension.  One
-// workgroup per group.  The group's work is cut into panels -- kPanel input
-// columns of a block (TRANS false) or kPanel output columns (TRANS true), 16
-// real or 8 complex -- dealt to the waves in turn, so that a group of one
-// block still keeps all waves busy; a wave issues the loads of a panel's 64
-// rows before it uses them (kPanel loads in flight), since a product reads
-// every matrix entry once and waits on memory.  TRANS false: lane l takes
-// output row l + 64 c of chunk c, the panel's inputs are gathered one per
-// lane and broadcast.  TRANS true: lane l takes input row l + 64 c, runs
-// along the panel's columns and the wave adds each column's products up.
-// The waves' partial sums are added in wave order at the end: every sum runs
-// in a fixed order, so results are reproducible bit for bit.
+// workgroup of eight waves per group.  The group's work is cut into panels
+// -- kPanel input columns of a block (TRANS false) or kPanel output columns
+// (TRANS true), 16 real or 8 complex -- dealt to the waves in turn, so that a
+// group of one small block still keeps every wave busy; a wave issues the
+// loads of a panel's 64 rows before it uses them (kPanel loads in flight),
+// since a product reads every matrix entry once and waits on memory.  TRANS
+// false: lane l takes output row l + 64 c of chunk c, the panel's inputs are
+// gathered one per lane and broadcast.  TRANS true: lane l takes input row
+// l + 64 c, runs along the panel's columns and the wave adds each column's
+// products up.  The waves' partial sums are added in wave order at the end:
+// every sum runs in a fixed order, so results are reproducible bit for bit.
+constexpr int kGemvThreads = 512;  // eight waves per group: more loads in flight
+
 template <bool CPLX, bool TRANS>
-__global__ __launch_bounds__(kThreads, 2) void k_gemv(const GemvArgs a) {
+__global__ __launch_bounds__(kGemvThreads, 1) void k_gemv(const GemvArgs a) {
   using T = Num<CPLX>;
   constexpr int kPanel = CPLX ? 8 : 16;
-  __shared__ T part[kThreads / kWave][kMaxVec];
+  __shared__ T part[kGemvThreads / kWave][kMaxVec];
   const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid / kWave;
-  constexpr int W = kThreads / kWave;
+  constexpr int W = kGemvThreads / kWave;
   const double *A = static_cast<const double *>(a.A);
   const double *x = static_cast<const double *>(a.x);
   double *y = static_cast<double *>(a.y);
@@ -199,7 +201,7 @@ __global__ __launch_bounds__(kThreads, 2) void k_gemv(const GemvArgs a) {
       }
     }
     __syncthreads();
-    for (int64_t k = tid; k < m; k += kThreads) {
+    for (int64_t k = tid; k < m; k += kGemvThreads) {
       T s = part[0][k];
       for (int w = 1; w < W; ++w) s.add(part[w][k]);
       const int id = a.out_idx[o0 + k];
@@ -306,7 +308,7 @@ __global__ __launch_bounds__(kThreads) void k_mass(int32_t nt, const double *geo
 
 hipError_t launch_gemv(bool cplx, bool trans, const GemvArgs &a, hipStream_t s) {
   if (a.ngroups == 0) return hipSuccess;
-  const dim3 grid((unsigned)std::min<int64_t>(a.ngroups, 4096)), block(kThreads);
+  const dim3 grid((unsigned)std::min<int64_t>(a.ngroups, 4096)), block(kGemvThreads);
   if (cplx) {
     if (trans) hipLaunchKernelGGL((k_gemv<true, true>), grid, block, 0, s, a);
     else hipLaunchKernelGGL((k_gemv<true, false>), grid, block, 0, s, a);

@@ -280,15 +280,20 @@ def _complete_pivoting_order(M):
 @pytest.mark.parametrize("cplx", [False, True])
 def test_pivot_inverse_against_oracle(pk, ctx, cplx):
     """bem_pivot_inverse on seeded matrices with pivot rows and columns
-    scattered in a larger one (ragged ranks, k = 1, a zero entry in the
+    scattered in a larger one (ragged ranks, k = 1, the largest rank of the
+    register-resident kernel and one beyond it, a zero entry in the
     block), listed in complete-pivoting order as the cross approximation
     lists them, against the oracle's Gauss-Jordan inverse relative to the
     block's condition number.  A list whose first pivot is zero raises
     BEM_ENONFINITE."""
     import torch
     rng = np.random.Generator(np.random.PCG64(30 + cplx))
-    acols, max_rank = 48, 40
-    shapes = [(40, 40), (57, 33), (9, 1), (64, 17), (30, 8)]
+    # ranks up to 192 (real) / 128 (complex) take the register-resident
+    # kernel, larger ones the one in global memory
+    big = 200 if not cplx else 150
+    acols, max_rank = 256, big
+    shapes = [(40, 40), (57, 33), (9, 1), (64, 17), (30, 8), (big + 20, big),
+              (192 if not cplx else 128, 192 if not cplx else 128)]
     A_list, prow, pcol = [], [], []
     for n, k in shapes:
         A = rng.standard_normal((n, acols)) + (1j * rng.standard_normal((n, acols)) if cplx else 0)
