@@ -843,35 +843,45 @@ def helmholtz_h2_leg(torch, pk, ctx, stream, steps=3, warmup=1, peak64=None):
 
 
 def batched_config2_leg(torch, pk, ctx, hb, stream, steps=10):
-    """The batched form on the config-2 matrix: one persistent plan per layer
-    (single layer: the mirrored near-field and coupling lists; double layer:
-    the full near-field list and the coupling list), autotuned, replayed
-    after the bases; setup = the plain setup plus both plans (with their
-    tuning cached, as on a second run), outputs against the plain step's."""
+    """The batched form on the config-2 matrix: one persistent plan holding
+    the whole matrix step (the mirrored near field with both layers in one
+    pass, the mirrored single-layer coupling and the double-layer coupling,
+    each list with its own layer and sub-tile shape in one cost-sorted
+    queue), autotuned, replayed after the bases; setup = the plain setup plus
+    the plan (with its tuning cached, as on a second run), outputs against
+    the plain step's."""
     h, o = hb.h, hb.out
     out = {k: torch.empty_like(v) for k, v in o.items()}
-    lists = [(hb.ops[0], [(h.mesh, hb.near_s, out["ns"], 0), (h.mesh, hb.cs, out["cs"], 1)]),
-             (hb.ops[1], [(h.mesh, hb.near, out["nd"], 0), (h.mesh, hb.cd, out["cd"], 1)])]
+    entries = [(h.mesh, hb.near_s, out["ns"], 0, pk.BATCH_BOTH, out["nd"]),
+               (h.mesh, hb.cs, out["cs"], 1, pk.BATCH_SLP),
+               (h.mesh, hb.cd, out["cd"], 1, pk.BATCH_DLP)]
     cache = os.path.join(tempfile.gettempdir(), f"bem_tune_c2_{os.getpid()}.txt")
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    plans = [pk.Plan(ctx, op, ent, autotune=True, cache=cache, stream=stream) for op, ent in lists]
+    plans = [pk.Plan(ctx, hb.ops[0], entries, autotune=True, cache=cache, stream=stream)]
     torch.cuda.synchronize()
     t_tune = time.perf_counter() - t0
     tuned = [p.config for p in plans]
     for p in plans:
         p.close()
     t0 = time.perf_counter()
-    plans = [pk.Plan(ctx, op, ent, autotune=True, cache=cache, stream=stream) for op, ent in lists]
+    plans = [pk.Plan(ctx, hb.ops[0], entries, autotune=True, cache=cache, stream=stream)]
     torch.cuda.synchronize()
     t_cached = time.perf_counter() - t0
     os.remove(cache)
 
+    # the coupling lists need the pivots only, not the basis matrices: the
+    # bases run on a second stream beside the plan (the plan has its own
+    # geometry buffer), as the plain step's bases beside its near field
+    side = torch.cuda.Stream()
+
     def step():
-        h.basis_replay(hb.V, stream)
-        h.basis_replay(hb.W, stream)
+        side.wait_stream(stream)
+        h.basis_replay(hb.V, side)
+        h.basis_replay(hb.W, side)
         for p in plans:
             p.run(stream)
+        stream.wait_stream(side)
     step()
     ctx.check(stream)
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -891,9 +901,9 @@ def batched_config2_leg(torch, pk, ctx, hb, stream, steps=10):
     return {"ms_per_step": ms, "plan_tuning_s": t_tune, "plan_cached_tuning_s": t_cached,
             "h2_setup_s": float(hb.t_setup) + t_cached, "tune": tuned,
             "rel_diff_vs_plain_step": diff,
-            "note": "two persistent graph replays (one per layer) after the bases; the plain "
-                    "step's single-layer near field is the one-pass launch, so the outputs "
-                    "agree up to rounding"}
+            "note": "one persistent graph replay (near field of both layers in one pass, "
+                    "single- and double-layer coupling, one queue) beside the bases on a "
+                    "second stream"}
 
 
 def solve_leg(torch, pk, ctx, hb, stream, reps=20):

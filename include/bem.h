@@ -227,10 +227,11 @@ int bem_eval_entries(bem_ctx *ctx, const bem_mesh *mesh, const bem_op *op, int64
  * Sec. 3 assembles a matrix by splitting its blocks into work lists of a
  * bounded size that worker threads dequeue and run on the GPU (Algorithms
  * add_block / assemble_gpu and schedule_tasks).  Here the lists of many
- * block lists, possibly of many meshes, become one device queue of
- * work items (whole blocks, or sub-tiles of at most 64 x 64 entries),
- * sorted by decreasing estimated cost; a fixed grid of workgroups pops items
- * from it until it is empty.  The queue, per-mesh geometry and launch are built once by
+ * block lists, possibly of many meshes and of either layer, become one
+ * device queue of work items (whole blocks, or sub-tiles: at most 64 x 64
+ * entries, 128 x 96 in plain coupling lists), sorted by decreasing
+ * estimated cost; a fixed grid of workgroups pops items from it until it is
+ * empty.  The queue, per-mesh geometry and launch are built once by
  * bem_plan_batched and captured in a HIP graph (a counter-reset kernel,
  * the geometry kernels and the persistent kernel); bem_run_batched replays
  * it.  Entries are bitwise equal to those of bem_assemble_nearfield /
@@ -239,15 +240,26 @@ int bem_eval_entries(bem_ctx *ctx, const bem_mesh *mesh, const bem_op *op, int64
 
 typedef struct bem_plan bem_plan;
 
-/* One batch entry: a block list of one mesh and its output. */
+/* bem_batch.layers: the operator a batch entry assembles. */
+#define BEM_BATCH_OP_LAYER 0 /* op->layer into out */
+#define BEM_BATCH_SLP 1      /* the single layer into out */
+#define BEM_BATCH_DLP 2      /* the double layer into out */
+#define BEM_BATCH_BOTH 3     /* near-field lists only: both layers in one pass,
+                                as bem_assemble_nearfield_both (single layer
+                                into out, double layer into out2) */
+
+/* One batch entry: a block list of one mesh and its output(s).  mirror_off
+ * is allowed for the single layer and for BEM_BATCH_BOTH. */
 typedef struct {
   const bem_mesh *mesh;     /* host struct; its arrays are device memory */
   const bem_blocks *blocks; /* host struct; its arrays are device memory */
   int32_t coupling;         /* 0: near-field blocks, 1: coupling blocks (no
                                common vertices allowed, as bem_assemble_coupling) */
-  int32_t reserved;         /* must be 0 */
+  int32_t layers;           /* BEM_BATCH_OP_LAYER .. BEM_BATCH_BOTH */
   void *out;                /* device, out_len entries of the output type */
   int64_t out_len;
+  void *out2;               /* BEM_BATCH_BOTH: device, out_len entries, not
+                               out; else NULL */
 } bem_batch;
 
 /* Launch configuration of the persistent kernel.  In: a field left 0 is
@@ -255,8 +267,12 @@ typedef struct {
  * default); out: the configuration used. */
 typedef struct {
   int32_t grid;      /* workgroups (default 2 per compute unit) */
-  int32_t tile_rows; /* sub-tile rows, 1..64 (default: the per-block kernel's) */
-  int32_t tile_cols; /* sub-tile columns, 1..64 */
+  int32_t tile_rows; /* sub-tile rows, 1..64, of the lists whose sub-tiles
+                        carry pair lists (near-field lists; every list in the
+                        mixed form); plain coupling lists take
+                        bem_assemble_coupling's sub-tile (default: the
+                        per-block kernel's) */
+  int32_t tile_cols; /* sub-tile columns, 1..64, of the same lists */
   int32_t x_chunk;   /* regular-rule points per register chunk: 4, 5, 7, 8 or 9
                         (default: the per-block kernel's) */
   int32_t autotune;  /* 1: time the candidates of every field left 0 */
@@ -269,7 +285,8 @@ typedef struct {
                         (0 when nothing was timed) */
 } bem_tune;
 
-/* Plan the batched assembly of `nbatch` entries with one operator.
+/* Plan the batched assembly of `nbatch` entries with one operator (kernel,
+ * precision, rules; the layer per entry, see bem_batch.layers).
  * The plan keeps the device pointers of every mesh, block list and output
  * and reads their CONTENTS at every run, except the block lists' row_ptr,
  * col_ptr, out_off, row_idx and col_idx and the meshes' tri, which are read

@@ -14,6 +14,8 @@ LIB_PATH = os.path.join(HERE, "libbem.so")
 BEM_OK, BEM_EINVAL, BEM_ENOMEM, BEM_EDEVICE, BEM_EUNSUPPORTED, BEM_ENONFINITE = 0, -1, -2, -3, -4, -5
 LAPLACE, HELMHOLTZ = 0, 1
 SLP, DLP = 0, 1
+# bem_batch.layers
+BATCH_OP_LAYER, BATCH_SLP, BATCH_DLP, BATCH_BOTH = 0, 1, 2, 3
 PLAIN_FP64, MIXED = 0, 1
 RULE_DUFFY, RULE_TRI7 = 0, 1
 MAX_ORDER = 12
@@ -462,8 +464,18 @@ Context.basis_contract = _context_basis_contract
 # ------------------------------------------------------------ batched plans
 class bem_batch(ctypes.Structure):
     _fields_ = [("mesh", ctypes.POINTER(bem_mesh)), ("blocks", ctypes.POINTER(bem_blocks)),
-                ("coupling", ctypes.c_int32), ("reserved", ctypes.c_int32),
-                ("out", ctypes.c_void_p), ("out_len", ctypes.c_int64)]
+                ("coupling", ctypes.c_int32), ("layers", ctypes.c_int32),
+                ("out", ctypes.c_void_p), ("out_len", ctypes.c_int64),
+                ("out2", ctypes.c_void_p)]
+
+
+def _batch(entry):
+    """bem_batch of a plan entry (mesh, blocks, out, coupling[, layers[, out2]])."""
+    mesh, blocks, out, coupling = entry[:4]
+    layers = int(entry[4]) if len(entry) > 4 else BATCH_OP_LAYER
+    out2 = entry[5] if len(entry) > 5 else None
+    return bem_batch(ctypes.pointer(mesh.c), ctypes.pointer(blocks.c), int(bool(coupling)), layers,
+                     _ptr(out), out.numel(), _ptr(out2))
 
 
 class bem_tune(ctypes.Structure):
@@ -498,9 +510,8 @@ def autotune(ctx, op, entries, tune=None, cache=None, stream=None):
     Returns the chosen configuration."""
     entries = list(entries)
     c = (bem_batch * max(len(entries), 1))()
-    for k, (mesh, blocks, out, coupling) in enumerate(entries):
-        c[k] = bem_batch(ctypes.pointer(mesh.c), ctypes.pointer(blocks.c), int(bool(coupling)), 0,
-                         _ptr(out), out.numel())
+    for k, e in enumerate(entries):
+        c[k] = _batch(e)
     t = dict(tune or {})
     cfg = bem_tune(int(t.get("grid", 0)), int(t.get("tile_rows", 0)), int(t.get("tile_cols", 0)),
                    int(t.get("x_chunk", 0)), 1, int(t.get("granularity", 0)),
@@ -514,8 +525,12 @@ def autotune(ctx, op, entries, tune=None, cache=None, stream=None):
 
 class Plan:
     """``bem_plan_batched``: one persistent, graph-captured assembly of many
-    block lists.  ``entries`` is a list of (mesh, blocks, out, coupling);
-    the plan keeps references to them (the device pointers are captured).
+    block lists.  ``entries`` is a list of (mesh, blocks, out, coupling)
+    or (mesh, blocks, out, coupling, layers[, out2]) with layers one of
+    BATCH_OP_LAYER (the operator's), BATCH_SLP, BATCH_DLP, BATCH_BOTH (near
+    field, both layers in one pass: single layer to out, double layer to
+    out2); the plan keeps references to them (the device pointers are
+    captured).
     ``tune`` fixes fields of the launch configuration (grid, tile_rows,
     tile_cols, x_chunk); ``autotune`` times candidates for the others;
     ``cache`` names the tuning cache file."""
@@ -524,9 +539,8 @@ class Plan:
         self.ctx, self.op, self.entries = ctx, op, list(entries)
         n = len(self.entries)
         self._c = (bem_batch * max(n, 1))()
-        for k, (mesh, blocks, out, coupling) in enumerate(self.entries):
-            self._c[k] = bem_batch(ctypes.pointer(mesh.c), ctypes.pointer(blocks.c),
-                                   int(bool(coupling)), 0, _ptr(out), out.numel())
+        for k, e in enumerate(self.entries):
+            self._c[k] = _batch(e)
         t = dict(tune or {})
         self.tune = bem_tune(int(t.get("grid", 0)), int(t.get("tile_rows", 0)),
                              int(t.get("tile_cols", 0)), int(t.get("x_chunk", 0)),

@@ -17,6 +17,17 @@ namespace {
 
 using namespace blk;
 
+// The thread's index, read through an empty asm statement: values derived
+// from it (lane, strides of the staging loops, LDS offsets) are then formed
+// where they are used instead of being hoisted to the kernel's entry and
+// held, or spilled, across the sub-tile loops (the block kernels drop 30 to
+// 50 registers and their scratch spills this way).
+__device__ __forceinline__ int thread_id() {
+  int t = __builtin_amdgcn_workitem_id_x();
+  asm volatile("" : "+v"(t));
+  return t;
+}
+
 struct BlockHdr {
   int64_t rp0, cp0, nr, nc, off;
   int64_t moff;       // transposed copy (coupling of a single layer), -1: none
@@ -41,7 +52,7 @@ __device__ __forceinline__ bool block_header(const BlockArgs &a, int b, BlockHdr
     ok = i0 >= 0 && i0 < a.nt;
   }
   if (!ok) {
-    if (threadIdx.x == 0) atomicOr(a.flags, FLAG_EINVAL);
+    if (thread_id() == 0) atomicOr(a.flags, FLAG_EINVAL);
     return false;
   }
   h->rp0 = rp0;
@@ -53,7 +64,7 @@ __device__ __forceinline__ bool block_header(const BlockArgs &a, int b, BlockHdr
   h->diag = h->moff >= 0 && h->moff == off && nr == nc;
   if (h->moff >= 0 && nr > 0 && !h->diag &&
       (h->moff == off || h->moff > a.out_len || nc > (a.out_len - h->moff) / nr)) {
-    if (threadIdx.x == 0) atomicOr(a.flags, FLAG_EINVAL);  // onto itself, or does not fit
+    if (thread_id() == 0) atomicOr(a.flags, FLAG_EINVAL);  // onto itself, or does not fit
     h->moff = -1;
   }
   if (nr > 0 && nc > 0) {
@@ -67,7 +78,7 @@ __device__ __forceinline__ bool block_header(const BlockArgs &a, int b, BlockHdr
 // The quadrature rule into LDS (padded with zero weights to nqp points).
 __device__ __forceinline__ void load_rule(const BlockArgs &a, const Lds &l) {
   const int nqp = a.nq_pad, nq = a.nq;
-  for (int k = threadIdx.x; k < nqp; k += kThreads) {
+  for (int k = thread_id(); k < nqp; k += kThreads) {
     const bool real = k < nq;
     l.rule[k] = real ? a.rule[k] : 0.0;
     l.rule[nqp + k] = real ? a.rule[nq + k] : 0.0;
@@ -83,7 +94,7 @@ __device__ __forceinline__ void load_rule(const BlockArgs &a, const Lds &l) {
 template <bool MIXED>
 __device__ bool stage_tile(const BlockArgs &a, const Lds &l, const BlockHdr &h, int64_t r0,
                            int64_t c0, int tr, int tc) {
-  const int tid = threadIdx.x, TR = a.tr, TC = a.tc;
+  const int tid = thread_id(), TR = a.tr, TC = a.tc;
   const int64_t L = a.ldg;
   const double cx = h.cx, cy = h.cy, cz = h.cz;
   __syncthreads();
@@ -143,7 +154,7 @@ __device__ void stage_columns(const BlockArgs &a, const Lds &l, const BlockHdr &
   const int TC = a.tc;
   const int64_t L = a.ldg;
   const double cx = h.cx, cy = h.cy, cz = h.cz;
-  for (int k = threadIdx.x; k < tc * nqp; k += kThreads) {
+  for (int k = thread_id(); k < tc * nqp; k += kThreads) {
     const int cl = k % tc, q = k / tc;
     const int id = l.cid[cl];
     const bool real = q < nq;
@@ -194,7 +205,7 @@ struct Groups {
 };
 
 __device__ __forceinline__ Groups group_listed(const Lds &l) {
-  const int tid = threadIdx.x;
+  const int tid = thread_id();
   const int ns = *l.count;
   Groups g;
   const int n3 = (l.ccount[3] + 63) & ~63, n2 = (l.ccount[2] + 63) & ~63,
@@ -222,7 +233,7 @@ template <int KERNEL, int LAYER, bool MIXED>
 __device__ __forceinline__ void singular_chunk(const BlockArgs &a, const Lds &l,
                                                const BlockHdr &h, int64_t r0, int64_t c0,
                                                const Groups &gr, int pos) {
-  const int lane = threadIdx.x & (kWave - 1);
+  const int lane = thread_id() & (kWave - 1);
   const int cls = pos < gr.seg[2] ? CLS_IDENTICAL
                   : pos < gr.seg[1] ? CLS_EDGE
                   : pos < gr.seg[0] ? CLS_VERTEX : kNearSingular;
@@ -271,7 +282,7 @@ template <int KERNEL, bool MIXED>
 __device__ __forceinline__ void singular_chunk_both(const BlockArgs &a, const Lds &l,
                                                     const BlockHdr &h, int64_t r0, int64_t c0,
                                                     const Groups &gr, int pos) {
-  const int lane = threadIdx.x & (kWave - 1);
+  const int lane = thread_id() & (kWave - 1);
   const int cls = pos < gr.seg[2] ? CLS_IDENTICAL
                   : pos < gr.seg[1] ? CLS_EDGE
                   : pos < gr.seg[0] ? CLS_VERTEX : kNearSingular;
@@ -378,7 +389,7 @@ __device__ __forceinline__ void lower_entry(int e, int n, int *rl, int *cl) {
 template <int KERNEL, int LAYER, int XC, bool MIXED>
 __device__ void subtile(const BlockArgs &a, const Lds &l, const BlockHdr &h, int64_t r0,
                         int64_t c0, int coupling) {
-  const int tid = threadIdx.x, lane = tid & (kWave - 1);
+  const int tid = thread_id(), lane = tid & (kWave - 1);
   const int nqp = a.nq_pad, TR = a.tr, TC = a.tc;
   const int64_t nr = h.nr, off = h.off;
   const double kq = 0.25 * a.kappa;
@@ -510,7 +521,7 @@ __device__ __forceinline__ Acc<KERNEL> regular_entry_q(int q, const Lds &l, int 
 template <int KERNEL, int LAYER>
 __device__ void subtile_learned(const BlockArgs &a, const OrderRules &o, const Lds &l,
                                 const BlockHdr &h, int64_t r0, int64_t c0) {
-  const int tid = threadIdx.x, lane = tid & (kWave - 1);
+  const int tid = thread_id(), lane = tid & (kWave - 1);
   const int TR = a.tr, TC = a.tc;
   const int64_t nr = h.nr, off = h.off;
   const double kq = 0.25 * a.kappa;
@@ -622,8 +633,9 @@ __global__ __launch_bounds__(kThreads, 2) void k_blocks(const BlockArgs a, const
 
 // Persistent form: every workgroup pops work items (batch, block, r0, c0) --
 // one sub-tile, or the whole block when r0 = c0 = -1 -- from a queue sorted by
-// decreasing cost until it is empty; every batch shares the operator (rule,
-// sub-tile shape) and has its own mesh, blocks and output.
+// decreasing cost until it is empty; every batch shares the operator's kernel,
+// precision and rules and has its own mesh, blocks, layer (single, double or
+// both in one pass), sub-tile shape and output.
 // Copy of a read-only struct at a wave-uniform address by scalar loads.
 template <class T>
 __device__ __forceinline__ T uniform_copy(const T *p) {
@@ -637,9 +649,45 @@ __device__ __forceinline__ T uniform_copy(const T *p) {
   return v;
 }
 
+// One work item of batch entry d.x in the layer LAYER: the argument and
+// header checks, the LDS layout of the entry's sub-tile shape (the rule,
+// shared by every entry, loaded again where that layout moves it; no wave
+// reads the LDS between the queue's barriers and the first barrier of the
+// sub-tile's staging), then the sub-tile or the whole block.  Each layer has
+// its own copy, so that nothing but the queue state is live across the
+// choice of layer.
 template <int KERNEL, int LAYER, int XC, bool MIXED>
+__device__ __forceinline__ void persistent_item(const BlockArgs *batches, int4 d, int cp,
+                                                double *lds_raw, int *carved) {
+  const BlockArgs a = uniform_copy(batches + d.x);
+  if (d.y < 0 || d.y >= a.nblocks) {
+    if (thread_id() == 0) atomicOr(a.flags, FLAG_EINVAL);
+    return;
+  }
+  BlockHdr h;
+  if (!block_header(a, d.y, &h) || h.nr == 0 || h.nc == 0) return;
+  const bool whole = d.z == -1 && d.w == -1;
+  if (!whole && (d.z >= h.nr || d.w >= h.nc || d.z < 0 || d.w < 0)) {
+    if (thread_id() == 0) atomicOr(a.flags, FLAG_EINVAL);
+    return;
+  }
+  const Lds l = carve<MIXED>(lds_raw, a.nq_pad, a.tr, a.tc, LAYER == kBoth);
+  const int shape = a.tr | (a.tc << 10);
+  if (shape != *carved) {
+    load_rule(a, l);
+    *carved = shape;
+  }
+  if (whole) {  // the whole block, sub-tile by sub-tile
+    for (int64_t r0 = 0; r0 < h.nr; r0 += a.tr)
+      for (int64_t c0 = 0; c0 < h.nc; c0 += a.tc) subtile<KERNEL, LAYER, XC, MIXED>(a, l, h, r0, c0, cp);
+  } else {
+    subtile<KERNEL, LAYER, XC, MIXED>(a, l, h, d.z, d.w, cp);
+  }
+}
+
+template <int KERNEL, int XC, bool MIXED>
 __global__ __launch_bounds__(kThreads, 2) void k_persistent(const BlockArgs *batches,
-                                                            const int32_t *coupling,
+                                                            const int32_t *mode,
                                                             const int4 *tiles, int32_t ntiles,
                                                             int32_t nbatch, int32_t *counter) {
   extern __shared__ __align__(16) double lds_raw[];  // 16-byte aligned: ds_read_b128 of points
@@ -648,38 +696,25 @@ __global__ __launch_bounds__(kThreads, 2) void k_persistent(const BlockArgs *bat
   // (scalar) loads keep every argument, pointer and loop bound in scalar
   // registers as in the per-block kernel
   typedef const int32_t __attribute__((address_space(4))) *cint_t;
-  const BlockArgs a0 = uniform_copy(batches);
-  const Lds l = carve<MIXED>(lds_raw, a0.nq_pad, a0.tr, a0.tc);
-  load_rule(a0, l);
+  int carved = -1;  // sub-tile shape whose LDS layout holds the rule, -1: none yet
   for (;;) {
     __syncthreads();  // everyone has read s_tile and left the previous tile
-    if (threadIdx.x == 0) s_tile = atomicAdd(counter, 1);
+    if (thread_id() == 0) s_tile = atomicAdd(counter, 1);
     __syncthreads();
     const int t = __builtin_amdgcn_readfirstlane(s_tile);
     if (t >= ntiles) break;  // the counter only grows: every workgroup exits
     const int4 d = uniform_copy(tiles + t);
-    if (d.x < 0 || d.x >= nbatch) {
-      if (threadIdx.x == 0) atomicOr(a0.flags, FLAG_EINVAL);
-      continue;
+    const int md = d.x >= 0 && d.x < nbatch ? ((cint_t)mode)[d.x] : -1;
+    const int cp = md & 1, layer = md >> 1;
+    if (layer == BEM_SLP) {
+      persistent_item<KERNEL, BEM_SLP, XC, MIXED>(batches, d, cp, lds_raw, &carved);
+    } else if (layer == BEM_DLP) {
+      persistent_item<KERNEL, BEM_DLP, XC, MIXED>(batches, d, cp, lds_raw, &carved);
+    } else if (layer == kBoth) {
+      persistent_item<KERNEL, kBoth, XC, MIXED>(batches, d, cp, lds_raw, &carved);
+    } else if (thread_id() == 0) {  // batch index or mode out of range
+      atomicOr(batches->flags, FLAG_EINVAL);
     }
-    const BlockArgs a = uniform_copy(batches + d.x);
-    const int cp = ((cint_t)coupling)[d.x];
-    if (d.y < 0 || d.y >= a.nblocks) {
-      if (threadIdx.x == 0) atomicOr(a.flags, FLAG_EINVAL);
-      continue;
-    }
-    BlockHdr h;
-    if (!block_header(a, d.y, &h) || h.nr == 0 || h.nc == 0) continue;
-    if (d.z == -1 && d.w == -1) {  // the whole block, sub-tile by sub-tile
-      for (int64_t r0 = 0; r0 < h.nr; r0 += a.tr)
-        for (int64_t c0 = 0; c0 < h.nc; c0 += a.tc) subtile<KERNEL, LAYER, XC, MIXED>(a, l, h, r0, c0, cp);
-      continue;
-    }
-    if (d.z >= h.nr || d.w >= h.nc || d.z < 0 || d.w < 0) {
-      if (threadIdx.x == 0) atomicOr(a.flags, FLAG_EINVAL);
-      continue;
-    }
-    subtile<KERNEL, LAYER, XC, MIXED>(a, l, h, d.z, d.w, cp);
   }
 }
 
@@ -699,13 +734,13 @@ hipError_t launch_klm(bool coupling, const BlockArgs &a, size_t lds, hipStream_t
   return hipGetLastError();
 }
 
-template <int KERNEL, int LAYER, bool MIXED>
+template <int KERNEL, bool MIXED>
 hipError_t launch_pers(int xc, const PersistentArgs &p, size_t lds, hipStream_t s) {
   const dim3 grid(p.grid), block(kThreads);
   switch (xc) {
-#define BEM_PERS(X)                                                                            \
-  hipLaunchKernelGGL((k_persistent<KERNEL, LAYER, X, MIXED>), grid, block, lds, s, p.batches, \
-                     p.coupling, p.tiles, p.ntiles, p.nbatch, p.counter)
+#define BEM_PERS(X)                                                                     \
+  hipLaunchKernelGGL((k_persistent<KERNEL, X, MIXED>), grid, block, lds, s, p.batches, \
+                     p.mode, p.tiles, p.ntiles, p.nbatch, p.counter)
     case 4: BEM_PERS(4); break;
     case 5: BEM_PERS(5); break;
     case 7: BEM_PERS(7); break;
@@ -825,21 +860,14 @@ hipError_t launch_reset_counter(int32_t *counter, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t launch_persistent(int kernel, int layer, bool mixed, int xc, const PersistentArgs &p,
-                             size_t lds, hipStream_t s) {
+hipError_t launch_persistent(int kernel, bool mixed, int xc, const PersistentArgs &p, size_t lds,
+                             hipStream_t s) {
   if (p.ntiles == 0 || p.grid == 0) return hipSuccess;
-  if (kernel == BEM_LAPLACE) {
-    if (layer == BEM_SLP)
-      return mixed ? launch_pers<BEM_LAPLACE, BEM_SLP, true>(xc, p, lds, s)
-                   : launch_pers<BEM_LAPLACE, BEM_SLP, false>(xc, p, lds, s);
-    return mixed ? launch_pers<BEM_LAPLACE, BEM_DLP, true>(xc, p, lds, s)
-                 : launch_pers<BEM_LAPLACE, BEM_DLP, false>(xc, p, lds, s);
-  }
-  if (layer == BEM_SLP)
-    return mixed ? launch_pers<BEM_HELMHOLTZ, BEM_SLP, true>(xc, p, lds, s)
-                 : launch_pers<BEM_HELMHOLTZ, BEM_SLP, false>(xc, p, lds, s);
-  return mixed ? launch_pers<BEM_HELMHOLTZ, BEM_DLP, true>(xc, p, lds, s)
-               : launch_pers<BEM_HELMHOLTZ, BEM_DLP, false>(xc, p, lds, s);
+  if (kernel == BEM_LAPLACE)
+    return mixed ? launch_pers<BEM_LAPLACE, true>(xc, p, lds, s)
+                 : launch_pers<BEM_LAPLACE, false>(xc, p, lds, s);
+  return mixed ? launch_pers<BEM_HELMHOLTZ, true>(xc, p, lds, s)
+               : launch_pers<BEM_HELMHOLTZ, false>(xc, p, lds, s);
 }
 
 }  // namespace bem

@@ -169,7 +169,8 @@ struct PivInvArgs {
 // entry (all with the same rule and sub-tile shape) and a queue of sub-tiles.
 struct PersistentArgs {
   const BlockArgs *batches;  // device [nbatch]
-  const int32_t *coupling;   // device [nbatch]: 1 = coupling block list
+  const int32_t *mode;       // device [nbatch]: bit 0 coupling block list,
+                             // bits 1-2 layer (BEM_SLP, BEM_DLP, kBoth = 2)
   const int4 *tiles;         // device [ntiles]: batch, block, first row, first column
   int32_t ntiles, nbatch;
   int32_t *counter;          // device queue head, 0 at launch
@@ -302,8 +303,9 @@ hipError_t launch_blocks_learned(int kernel, int layer, const BlockArgs &a, cons
                                  size_t lds_bytes, hipStream_t s);
 
 // xc: x-points per register chunk (4, 5, 7, 8 or 9; nq_pad of every batch
-// entry is nq rounded up to a multiple of it)
-hipError_t launch_persistent(int kernel, int layer, bool mixed, int xc, const PersistentArgs &p,
+// entry is nq rounded up to a multiple of it); the layer of each entry is in
+// PersistentArgs::mode, its sub-tile shape in its BlockArgs
+hipError_t launch_persistent(int kernel, bool mixed, int xc, const PersistentArgs &p,
                              size_t lds_bytes, hipStream_t s);
 hipError_t launch_reset_counter(int32_t *counter, hipStream_t s);
 

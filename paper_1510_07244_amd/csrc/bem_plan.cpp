@@ -30,7 +30,7 @@ using namespace bem;
 struct bem_plan {
   bem_ctx *ctx = nullptr;  // null once the context is destroyed
   int device = 0;
-  int kernel = 0, layer = 0;
+  int kernel = 0;
   bool mixed = false;
   int32_t nq = 0;
   size_t lds = 0;
@@ -40,7 +40,7 @@ struct bem_plan {
   // device memory owned by the plan
   double *geo = nullptr;
   BlockArgs *dbatch = nullptr;
-  int32_t *dcoupling = nullptr;
+  int32_t *dmode = nullptr;  // per batch: coupling flag | layer << 1
   int4 *dtiles = nullptr;
   int32_t *counter = nullptr;
   // distinct meshes and their geometry slices
@@ -56,12 +56,15 @@ namespace {
 struct HostBatch {
   int mesh = 0;  // index into bem_plan::meshes
   int coupling = 0;
+  int layer = 0;  // BEM_SLP, BEM_DLP or kLayerBoth
   bem_blocks blocks{};
-  void *out = nullptr;
+  void *out = nullptr, *out2 = nullptr;
   int64_t out_len = 0;
   std::vector<int32_t> row_ptr, col_ptr, row_idx, col_idx;
   std::vector<int64_t> out_off;
 };
+
+constexpr int kLayerBoth = 2;  // both layers in one pass (the kernels' layer value)
 
 template <class T>
 hipError_t d2h(std::vector<T> *dst, const T *src, int64_t n) {
@@ -70,20 +73,33 @@ hipError_t d2h(std::vector<T> *dst, const T *src, int64_t n) {
   return hipMemcpy(dst->data(), src, (size_t)n * sizeof(T), hipMemcpyDeviceToHost);
 }
 
-// Estimated cost of one sub-tile in regular point-pair units: regular
-// entries use nqp^2 point pairs; a pair with k common vertices has 2, 5 or 6
-// regions of q_s^3 eta points (k = 1, 2, 3), each about twice a regular
-// point pair's work and summed one pair per lane: 8 k q_s^3 (measured on the
-// near field of the 8192-triangle sphere, the singular pass takes about 1/6
-// of the launch for 1/40 of its flops).
+// Estimated cost of one sub-tile in regular point-pair units of the single
+// layer: regular entries use nqp^2 point pairs; a pair with k common
+// vertices has 2, 5 or 6 regions of q_s^3 eta points (k = 1, 2, 3), each
+// about twice a regular point pair's work and summed one pair per lane:
+// 8 k q_s^3 (measured on the near field of the 8192-triangle sphere, the
+// singular pass takes about 1/6 of the launch for 1/40 of its flops).  The
+// other layers scale the regular part by their issue slots per point pair
+// over the single layer's (Laplace 12 : 14 : 16 for single, double, both in
+// one pass; Helmholtz, with the sine and cosine, about 36 : 41 : 46) and the
+// singular part by the Sauter-Schwab evaluations per pair (1, 1, 2.5: both
+// layers of (i, j), the double layer of (j, i)).
 struct CostModel {
   int nqp = 0, qs = 0;
+  double reg_w = 1.0, sing_w = 1.0;
   std::vector<int32_t> vcount;  // per vertex: rows of the tile touching it
 };
 
+void layer_weights(int kernel, int layer, double *reg_w, double *sing_w) {
+  static const double lap[3] = {1.0, 14.0 / 12.0, 16.0 / 12.0};
+  static const double hel[3] = {1.0, 41.0 / 36.0, 46.0 / 36.0};
+  *reg_w = (kernel == BEM_LAPLACE ? lap : hel)[layer];
+  *sing_w = layer == kLayerBoth ? 2.5 : 1.0;
+}
+
 double tile_cost(CostModel &cm, const HostBatch &hb, const std::vector<int32_t> &tri,
                  int64_t rp0, int64_t cp0, int64_t r0, int64_t c0, int tr, int tc) {
-  const double reg = (double)tr * tc * cm.nqp * cm.nqp;
+  const double reg = cm.reg_w * (double)tr * tc * cm.nqp * cm.nqp;
   if (hb.coupling) return reg;
   for (int k = 0; k < tr; ++k)
     for (int m = 0; m < 3; ++m) ++cm.vcount[tri[3 * (size_t)hb.row_idx[rp0 + r0 + k] + m]];
@@ -92,23 +108,27 @@ double tile_cost(CostModel &cm, const HostBatch &hb, const std::vector<int32_t> 
     for (int m = 0; m < 3; ++m) shared += cm.vcount[tri[3 * (size_t)hb.col_idx[cp0 + c0 + k] + m]];
   for (int k = 0; k < tr; ++k)
     for (int m = 0; m < 3; ++m) cm.vcount[tri[3 * (size_t)hb.row_idx[rp0 + r0 + k] + m]] = 0;
-  return reg + 8.0 * (double)shared * cm.qs * cm.qs * cm.qs;
+  return reg + cm.sing_w * 8.0 * (double)shared * cm.qs * cm.qs * cm.qs;
 }
 
 // Work items (batch, block, first row, first column) -- every sub-tile, or
 // with whole = true every block as (batch, block, -1, -1) with the sum of its
 // sub-tiles' costs -- sorted by decreasing cost; ties keep the natural order.
+// shapes[e]: sub-tile rows and columns of batch entry e.
 std::vector<int4> build_tiles(const std::vector<HostBatch> &hbs,
                               const std::vector<std::vector<int32_t>> &tris,
-                              const std::vector<bem_mesh> &meshes, int tr, int tc, int nqp,
+                              const std::vector<bem_mesh> &meshes,
+                              const std::vector<std::pair<int, int>> &shapes, int kernel, int nqp,
                               int qs, bool whole) {
   std::vector<int4> tiles;
   std::vector<double> cost;
   for (size_t e = 0; e < hbs.size(); ++e) {
     const HostBatch &hb = hbs[e];
+    const int tr = shapes[e].first, tc = shapes[e].second;
     CostModel cm;
     cm.nqp = nqp;
     cm.qs = qs;
+    layer_weights(kernel, hb.layer, &cm.reg_w, &cm.sing_w);
     if (!hb.coupling) cm.vcount.assign((size_t)meshes[hb.mesh].nv, 0);
     for (int32_t b = 0; b < hb.blocks.n; ++b) {
       const int64_t rp0 = hb.row_ptr[b], cp0 = hb.col_ptr[b];
@@ -220,7 +240,7 @@ void release(bem_plan *p) {
   if (p->exec) (void)hipGraphExecDestroy(p->exec);
   if (p->graph) (void)hipGraphDestroy(p->graph);
   if (p->cap) (void)hipStreamDestroy(p->cap);
-  for (void *m : {(void *)p->geo, (void *)p->dbatch, (void *)p->dcoupling, (void *)p->dtiles,
+  for (void *m : {(void *)p->geo, (void *)p->dbatch, (void *)p->dmode, (void *)p->dtiles,
                   (void *)p->counter})
     if (m) (void)hipFree(m);
   p->exec = nullptr;
@@ -228,14 +248,15 @@ void release(bem_plan *p) {
   p->cap = nullptr;
   p->geo = nullptr;
   p->dbatch = nullptr;
-  p->dcoupling = nullptr;
+  p->dmode = nullptr;
   p->dtiles = nullptr;
   p->counter = nullptr;
 }
 
 struct Candidate {
   int grid, tr, tc, xc;
-  bool whole;  // queue whole blocks instead of sub-tiles
+  bool whole;    // queue whole blocks instead of sub-tiles
+  int ctr, ctc;  // sub-tile of the plain coupling lists (0: none in the batch)
 };
 
 }  // namespace
@@ -273,7 +294,6 @@ int bem_plan_batched(bem_ctx *ctx, const bem_op *op, int32_t nbatch, const bem_b
   p->ctx = ctx;
   p->device = ctx->device;
   p->kernel = op->kernel;
-  p->layer = op->layer;
   p->mixed = op->precision == BEM_MIXED;
   p->nbatch = nbatch;
   auto bail = [&](int code) {
@@ -293,15 +313,29 @@ int bem_plan_batched(bem_ctx *ctx, const bem_op *op, int32_t nbatch, const bem_b
       HostBatch &hb = hbs[k];
       if ((rc = check_mesh(ctx, bt.mesh)) || (rc = check_blocks(ctx, bt.blocks, bt.out, bt.out_len)))
         return bail(rc);
-      if ((bt.coupling != 0 && bt.coupling != 1) || bt.reserved)
-        return bail(fail(ctx, BEM_EINVAL, "bem_batch.coupling must be 0/1, reserved 0"));
-      if (bt.blocks->mirror_off && op->layer != BEM_SLP)
-        return bail(fail(ctx, BEM_EINVAL, "mirror_off is for single layers only"));
+      if ((bt.coupling != 0 && bt.coupling != 1) || bt.layers < BEM_BATCH_OP_LAYER ||
+          bt.layers > BEM_BATCH_BOTH)
+        return bail(fail(ctx, BEM_EINVAL, "bem_batch.coupling must be 0/1, layers 0..3"));
+      hb.layer = bt.layers == BEM_BATCH_OP_LAYER ? op->layer
+                 : bt.layers == BEM_BATCH_SLP    ? BEM_SLP
+                 : bt.layers == BEM_BATCH_DLP    ? BEM_DLP
+                                                 : kLayerBoth;
+      if (hb.layer == kLayerBoth) {
+        if (bt.coupling)
+          return bail(fail(ctx, BEM_EINVAL, "BEM_BATCH_BOTH is for near-field lists only"));
+        if (bt.out_len > 0 && (!bt.out2 || bt.out2 == bt.out))
+          return bail(fail(ctx, BEM_EINVAL, "BEM_BATCH_BOTH: out2 is NULL or the same buffer as out"));
+      } else if (bt.out2) {
+        return bail(fail(ctx, BEM_EINVAL, "bem_batch.out2 is for BEM_BATCH_BOTH only"));
+      }
+      if (bt.blocks->mirror_off && hb.layer == BEM_DLP)
+        return bail(fail(ctx, BEM_EINVAL, "mirror_off is for single layers and BEM_BATCH_BOTH"));
       if (bt.blocks->n > 0 && bt.mesh->nt == 0)
         return bail(fail(ctx, BEM_EINVAL, "blocks given for an empty mesh"));
       hb.coupling = bt.coupling;
       hb.blocks = *bt.blocks;
       hb.out = bt.out;
+      hb.out2 = bt.out2;
       hb.out_len = bt.out_len;
       // meshes with identical descriptors share a geometry slice
       int mi = -1;
@@ -345,18 +379,18 @@ int bem_plan_batched(bem_ctx *ctx, const bem_op *op, int32_t nbatch, const bem_b
     if (total > 0 && (e = hipMalloc(&p->geo, (size_t)total * sizeof(double))) != hipSuccess)
       return bail(hip_fail(ctx, e, "hipMalloc(plan geometry)"));
     if ((e = hipMalloc(&p->counter, 256)) != hipSuccess ||
-        (e = hipMalloc(&p->dcoupling, sizeof(int32_t) * std::max(nbatch, 1))) != hipSuccess ||
+        (e = hipMalloc(&p->dmode, sizeof(int32_t) * std::max(nbatch, 1))) != hipSuccess ||
         (e = hipMalloc(&p->dbatch, sizeof(BlockArgs) * std::max(nbatch, 1))) != hipSuccess)
       return bail(hip_fail(ctx, e, "hipMalloc(plan)"));
     for (size_t q = 0; q < p->meshes.size(); ++q)
       if ((e = launch_geometry(p->meshes[q], p->geo + p->geo_off[q], p->geo_ld[q], ctx->flags, s)) !=
           hipSuccess)
         return bail(hip_fail(ctx, e, "geometry kernel launch"));
-    std::vector<int32_t> hcoup((size_t)std::max(nbatch, 1), 0);
-    for (int32_t k = 0; k < nbatch; ++k) hcoup[k] = hbs[k].coupling;
-    if ((e = hipMemcpy(p->dcoupling, hcoup.data(), hcoup.size() * sizeof(int32_t),
+    std::vector<int32_t> hmode((size_t)std::max(nbatch, 1), 0);
+    for (int32_t k = 0; k < nbatch; ++k) hmode[k] = hbs[k].coupling | hbs[k].layer << 1;
+    if ((e = hipMemcpy(p->dmode, hmode.data(), hmode.size() * sizeof(int32_t),
                        hipMemcpyHostToDevice)) != hipSuccess)
-      return bail(hip_fail(ctx, e, "hipMemcpy(coupling flags)"));
+      return bail(hip_fail(ctx, e, "hipMemcpy(batch modes)"));
   } catch (const std::bad_alloc &) {
     return bail(fail(ctx, BEM_ENOMEM, "host allocation failed"));
   }
@@ -376,6 +410,46 @@ int bem_plan_batched(bem_ctx *ctx, const bem_op *op, int32_t nbatch, const bem_b
       for (int x : {8, 9, 7, 5, 4})
         if (x != def_xc && p->nq % x == 0) xcs.push_back(x);
   }
+  // sub-tiles: the lists with pair lists (near field; all in the mixed form)
+  // take the candidate's shape, plain coupling lists the coupling kernel's
+  bool any_lists = false, any_plain_coupling = false;
+  for (const HostBatch &hb : hbs) {
+    if (hb.coupling && !p->mixed) any_plain_coupling = true;
+    else any_lists = true;
+  }
+  auto has_lists = [&](const HostBatch &hb) { return !hb.coupling || p->mixed; };
+  auto make_cand = [&](int grid, int tr, int tc, int xc, bool whole) {
+    Candidate c{grid, tr, tc, xc, whole, 0, 0};
+    if (any_plain_coupling) {
+      const int nqp = (p->nq + xc - 1) / xc * xc;
+      size_t lds;
+      if (!block_tile_shape(nqp, false, ctx->lds_budget, &c.ctr, &c.ctc, &lds, true, false))
+        c.ctr = c.ctc = 0;
+    }
+    return c;
+  };
+  auto shapes_of = [&](const Candidate &c) {
+    std::vector<std::pair<int, int>> sh(hbs.size());
+    for (size_t k = 0; k < hbs.size(); ++k)
+      sh[k] = has_lists(hbs[k]) ? std::make_pair(c.tr, c.tc) : std::make_pair(c.ctr, c.ctc);
+    return sh;
+  };
+  // LDS of the launch: the largest layout of its batch entries (0: no entry)
+  auto plan_lds = [&](const Candidate &c) -> size_t {
+    const int nqp = (p->nq + c.xc - 1) / c.xc * c.xc;
+    size_t m = 0;
+    for (const HostBatch &hb : hbs) {
+      const bool l = has_lists(hb);
+      m = std::max(m, block_lds_bytes(nqp, l ? c.tr : c.ctr, l ? c.tc : c.ctc, p->mixed, l,
+                                      hb.layer == kLayerBoth));
+    }
+    return m;
+  };
+  auto fits = [&](const Candidate &c) {
+    return (!any_plain_coupling || c.ctr > 0) && plan_lds(c) <= ctx->lds_budget;
+  };
+  bool any_both = false;
+  for (const HostBatch &hb : hbs) any_both = any_both || hb.layer == kLayerBoth;
   std::vector<Candidate> cands;
   for (int xc : xcs) {
     const int nqp = (p->nq + xc - 1) / xc * xc;
@@ -385,9 +459,9 @@ int bem_plan_batched(bem_ctx *ctx, const bem_op *op, int32_t nbatch, const bem_b
     } else {
       int tr, tc;
       size_t lds;
-      if (block_tile_shape(nqp, p->mixed, ctx->lds_budget, &tr, &tc, &lds))
+      if (block_tile_shape(nqp, p->mixed, ctx->lds_budget, &tr, &tc, &lds, false, any_both))
         shapes.push_back({want.tile_rows ? want.tile_rows : tr, want.tile_cols ? want.tile_cols : tc});
-      if (want.autotune)
+      if (want.autotune && any_lists)
         for (auto sh : {std::make_pair(64, 32), std::make_pair(32, 32), std::make_pair(32, 64)}) {
           if (want.tile_rows) sh.first = want.tile_rows;
           if (want.tile_cols) sh.second = want.tile_cols;
@@ -402,11 +476,14 @@ int bem_plan_batched(bem_ctx *ctx, const bem_op *op, int32_t nbatch, const bem_b
       if (want.autotune) grids.insert(grids.end(), {ncu, 3 * ncu / 2});
     }
     for (auto sh : shapes) {
-      if (block_lds_bytes(nqp, sh.first, sh.second, p->mixed) > ctx->lds_budget) continue;
       for (int g : grids) {
-        if (want.granularity != 2) cands.push_back({g, sh.first, sh.second, xc, true});
-        if (want.granularity == 2 || (want.granularity == 0 && want.autotune))
-          cands.push_back({g, sh.first, sh.second, xc, false});
+        for (int whole = 1; whole >= 0; --whole) {
+          const bool take = whole ? want.granularity != 2
+                                  : want.granularity == 2 || (want.granularity == 0 && want.autotune);
+          if (!take) continue;
+          const Candidate c = make_cand(g, sh.first, sh.second, xc, whole == 1);
+          if (fits(c)) cands.push_back(c);
+        }
       }
     }
   }
@@ -414,14 +491,15 @@ int bem_plan_batched(bem_ctx *ctx, const bem_op *op, int32_t nbatch, const bem_b
     return bail(fail(ctx, BEM_EUNSUPPORTED, "no sub-tile shape fits the LDS budget"));
 
   // ---- per-candidate device state
-  std::map<std::tuple<int, int, bool>, std::vector<int4>> tile_sets;  // xc-independent
+  // queues depend on the sub-tile shapes and granularity, not on the chunk
+  std::map<std::tuple<int, int, bool, int, int>, std::vector<int4>> tile_sets;
   auto tiles_for = [&](const Candidate &c) -> const std::vector<int4> & {
-    auto key = std::make_tuple(c.tr, c.tc, c.whole);
+    auto key = std::make_tuple(c.tr, c.tc, c.whole, c.ctr, c.ctc);
     auto it = tile_sets.find(key);
     if (it == tile_sets.end()) {
       const int nqp = (p->nq + def_xc - 1) / def_xc * def_xc;
-      it = tile_sets.emplace(key, build_tiles(hbs, tris, p->meshes, c.tr, c.tc, nqp, op->q_singular,
-                                              c.whole)).first;
+      it = tile_sets.emplace(key, build_tiles(hbs, tris, p->meshes, shapes_of(c), p->kernel, nqp,
+                                              op->q_singular, c.whole)).first;
     }
     return it->second;
   };
@@ -442,6 +520,7 @@ int bem_plan_batched(bem_ctx *ctx, const bem_op *op, int32_t nbatch, const bem_b
             hipSuccess)
       return hip_fail(ctx, e, "hipMemcpy(tile queue)");
     std::vector<BlockArgs> ha((size_t)std::max(nbatch, 1));
+    const std::vector<std::pair<int, int>> sh = shapes_of(c);
     for (int32_t k = 0; k < nbatch; ++k) {
       const HostBatch &hb = hbs[k];
       const bem_mesh &m = p->meshes[hb.mesh];
@@ -463,12 +542,13 @@ int bem_plan_batched(bem_ctx *ctx, const bem_op *op, int32_t nbatch, const bem_b
       a.out_off = hb.blocks.out_off;
       a.mirror_off = hb.blocks.mirror_off;
       a.out = hb.out;
+      a.out2 = hb.out2;
       a.out_len = hb.out_len;
       a.rule = rules->tri;
       a.nq = rules->nq;
       a.nq_pad = (rules->nq + c.xc - 1) / c.xc * c.xc;
-      a.tr = c.tr;
-      a.tc = c.tc;
+      a.tr = sh[k].first;
+      a.tc = sh[k].second;
       for (int q = 0; q < 4; ++q) a.ss.eta[q] = rules->ss[q], a.ss.np[q] = rules->np[q];
       a.ss.xi = rules->xi;
       a.ss.q = rules->nxi;
@@ -481,28 +561,29 @@ int bem_plan_batched(bem_ctx *ctx, const bem_op *op, int32_t nbatch, const bem_b
             hipSuccess)
       return hip_fail(ctx, e, "hipMemcpy(batch arguments)");
     pa->batches = p->dbatch;
-    pa->coupling = p->dcoupling;
+    pa->mode = p->dmode;
     pa->tiles = p->dtiles;
     pa->ntiles = (int32_t)tl.size();
     pa->nbatch = nbatch;
     pa->counter = p->counter;
     pa->grid = (int32_t)std::min<int64_t>(c.grid, std::max<int64_t>((int64_t)tl.size(), 1));
     p->ntiles = (int64_t)tl.size();
-    p->lds = block_lds_bytes((p->nq + c.xc - 1) / c.xc * c.xc, c.tr, c.tc, p->mixed);
+    p->lds = plan_lds(c);
     return BEM_OK;
   };
   auto enqueue = [&](const PersistentArgs &pa, int xc, hipStream_t st) -> hipError_t {
     hipError_t e = launch_reset_counter(p->counter, st);
-    if (e == hipSuccess) e = launch_persistent(p->kernel, p->layer, p->mixed, xc, pa, p->lds, st);
+    if (e == hipSuccess) e = launch_persistent(p->kernel, p->mixed, xc, pa, p->lds, st);
     return e;
   };
 
   // ---- choose: cache, else time the candidates (or take the only one)
-  int64_t entries = 0, tri_total = 0, ncoup = 0;
+  int64_t entries = 0, tri_total = 0, ncoup = 0, nlayer[3] = {0, 0, 0};
   for (const HostBatch &hb : hbs) {
     for (int32_t b = 0; b < hb.blocks.n; ++b)
       entries += (int64_t)(hb.row_ptr[b + 1] - hb.row_ptr[b]) * (hb.col_ptr[b + 1] - hb.col_ptr[b]);
     ncoup += hb.coupling;
+    ++nlayer[hb.layer];
   }
   for (const bem_mesh &m : p->meshes) tri_total += m.nt;
   char arch[64] = "gfx";
@@ -512,7 +593,8 @@ int bem_plan_batched(bem_ctx *ctx, const bem_op *op, int32_t nbatch, const bem_b
       std::snprintf(arch, sizeof arch, "%s", prop.gcnArchName);
   }
   std::ostringstream ks;
-  ks << arch << "/cu" << ncu << "/k" << op->kernel << "l" << op->layer << "p" << op->precision
+  ks << arch << "/cu" << ncu << "/k" << op->kernel << "l" << nlayer[0] << "," << nlayer[1] << ","
+     << nlayer[2] << "p" << op->precision
      << "r" << op->regular_rule << "q" << op->q_regular << "s" << op->q_singular << "/b" << nbatch
      << "c" << ncoup << "t" << tri_total << "e" << entries << "/fix" << want.grid << ","
      << want.tile_rows << "," << want.tile_cols << "," << want.x_chunk << "," << want.granularity;
@@ -524,12 +606,15 @@ int bem_plan_batched(bem_ctx *ctx, const bem_op *op, int32_t nbatch, const bem_b
   if (hit) {
     const int nqp = valid_chunk(cached.x_chunk) ? (p->nq + cached.x_chunk - 1) / cached.x_chunk * cached.x_chunk : 0;
     hit = nqp > 0 && p->nq % cached.x_chunk == 0 && cached.grid > 0 && cached.tile_rows >= 1 &&
-          cached.tile_rows <= 64 && cached.tile_cols >= 1 && cached.tile_cols <= 64 &&
-          block_lds_bytes(nqp, cached.tile_rows, cached.tile_cols, p->mixed) <= ctx->lds_budget;
+          cached.tile_rows <= 64 && cached.tile_cols >= 1 && cached.tile_cols <= 64;
     hit = hit && (cached.granularity == 1 || cached.granularity == 2) &&
           (want.granularity == 0 || want.granularity == cached.granularity);
-    if (hit)
-      best = {cached.grid, cached.tile_rows, cached.tile_cols, cached.x_chunk, cached.granularity == 1};
+    if (hit) {
+      const Candidate c = make_cand(cached.grid, cached.tile_rows, cached.tile_cols,
+                                    cached.x_chunk, cached.granularity == 1);
+      hit = fits(c);
+      if (hit) best = c;
+    }
   }
   if (!hit && want.autotune && cands.size() > 1) {
     // successive halving: every candidate timed once (after one warm-up
@@ -605,7 +690,7 @@ int bem_plan_batched(bem_ctx *ctx, const bem_op *op, int32_t nbatch, const bem_b
   for (size_t q = 0; q < p->meshes.size() && le == hipSuccess; ++q)
     le = launch_geometry(p->meshes[q], p->geo + p->geo_off[q], p->geo_ld[q], ctx->flags, p->cap);
   if (le == hipSuccess)
-    le = launch_persistent(p->kernel, p->layer, p->mixed, best.xc, pa, p->lds, p->cap);
+    le = launch_persistent(p->kernel, p->mixed, best.xc, pa, p->lds, p->cap);
   e = hipStreamEndCapture(p->cap, &p->graph);
   if (le != hipSuccess) return bail(hip_fail(ctx, le, "kernel launch under capture"));
   if (e != hipSuccess) return bail(hip_fail(ctx, e, "hipStreamEndCapture"));

@@ -9,7 +9,11 @@
 * Against the oracle: sampled blocks at 1e-12 relative (plain FP64).
 * The autotuner: a valid configuration, results within rounding of the
   default plan's, and a second plan served from the cache file.
-* Host-visible errors (an out-of-range triangle id) are rejected at plan time.
+* One plan holding the whole matrix step of an H2 setup (near field of both
+  layers in one pass, single- and double-layer coupling, each list with its
+  own layer and sub-tile shape): every output equals the per-call bits.
+* Host-visible errors (an out-of-range triangle id, invalid layer choices)
+  are rejected at plan time.
 """
 import json
 
@@ -286,4 +290,76 @@ def test_batched_mirrored_lists_equal_per_call(pk, ctx):
     for r, o in zip(ref, outs):
         assert np.all(np.isfinite(r.cpu().numpy()))
         assert np.array_equal(_bits(o), _bits(r))
+    plan.close()
+
+
+@pytest.mark.parametrize("kernel,precision,kappa", [(0, 0, 0.0), (1, 0, 4.0), (0, 1, 0.0)])
+def test_batched_layers_in_one_plan_equal_per_call(pk, ctx, kernel, precision, kappa):
+    # one plan holding the whole matrix step of an H2 setup: the mirrored
+    # near field with both layers in one pass, the mirrored single-layer
+    # coupling and the double-layer coupling (each list its own layer and
+    # sub-tile shape in one queue); every output equals the per-call bits
+    import torch
+    from paper_1510_07244_amd.h2 import H2Setup
+    m = perturbed_sphere(23, n_min=16, n_max=16)
+    h = H2Setup(ctx, m.v, m.tri, kernel=kernel, kappa=kappa, q_regular=4, q_singular=4)
+    V, W = h.bases((0, 1))
+    near, n_near = h.near_blocks(mirror=True)
+    cs, n_cs = h.coupling_blocks(V, V, mirror=True)
+    cd, n_cd = h.coupling_blocks(V, W)
+    ops = [h.op(pk.SLP), h.op(pk.DLP)]
+    for op in ops:
+        op.precision = precision
+        op.near_singular_ratio = 0.5 if precision else 0.0
+    dt = dict(dtype=pk.out_dtype(ops[0]), device="cuda")
+    nan = float("nan")
+    ref = {k: torch.full((n,), nan, **dt) for k, n in
+           (("ns", n_near), ("nd", n_near), ("cs", n_cs), ("cd", n_cd))}
+    ctx.assemble_nearfield_both(h.mesh, ops[0], near, ref["ns"], ref["nd"])
+    ctx.assemble_coupling(h.mesh, ops[0], cs, ref["cs"])
+    ctx.assemble_coupling(h.mesh, ops[1], cd, ref["cd"])
+    ctx.check()
+    out = {k: torch.full_like(v, nan) for k, v in ref.items()}
+    # the operator's layer is the double layer: every entry names its own
+    plan = pk.Plan(ctx, ops[1], [(h.mesh, near, out["ns"], 0, pk.BATCH_BOTH, out["nd"]),
+                                 (h.mesh, cs, out["cs"], 1, pk.BATCH_SLP),
+                                 (h.mesh, cd, out["cd"], 1, pk.BATCH_OP_LAYER)])
+    for rep in range(2):
+        for o in out.values():
+            o.fill_(nan)
+        plan.run()
+        ctx.check()
+        for k in ref:
+            r = ref[k].cpu()
+            assert np.all(np.isfinite(torch.view_as_real(r).numpy() if r.is_complex() else r.numpy()))
+            assert np.array_equal(_bits(out[k]), _bits(ref[k])), (k, rep)
+    plan.close()
+
+
+def test_plan_layer_arguments_are_checked(pk, ctx):
+    import torch
+    m = perturbed_sphere(5, n_min=8, n_max=8)
+    mesh = pk.Mesh(torch.from_numpy(m.v), torch.from_numpy(m.tri))
+    idx = np.arange(12, dtype=np.int32)
+    blocks, total = pk.Blocks.from_lists([idx], [idx])
+    a = torch.zeros(total, dtype=torch.float64, device="cuda")
+    b = torch.zeros(total, dtype=torch.float64, device="cuda")
+    op = pk.make_op(pk.LAPLACE, pk.SLP)
+    bad = [[(mesh, blocks, a, 0, pk.BATCH_BOTH)],            # no second output
+           [(mesh, blocks, a, 0, pk.BATCH_BOTH, a)],         # the same buffer twice
+           [(mesh, blocks, a, 1, pk.BATCH_BOTH, b)],         # both layers of a coupling list
+           [(mesh, blocks, a, 0, pk.BATCH_DLP, b)],          # second output of one layer
+           [(mesh, blocks, a, 0, 4)]]                        # no such layer code
+    for entries in bad:
+        with pytest.raises(pk.BemError) as ei:
+            pk.Plan(ctx, op, entries)
+        assert ei.value.code == pk.BEM_EINVAL
+    plan = pk.Plan(ctx, op, [(mesh, blocks, a, 0, pk.BATCH_BOTH, b)])
+    plan.run()
+    ctx.check()
+    ra = torch.zeros_like(a)
+    rb = torch.zeros_like(b)
+    ctx.assemble_nearfield_both(mesh, op, blocks, ra, rb)
+    ctx.check()
+    assert np.array_equal(_bits(a), _bits(ra)) and np.array_equal(_bits(b), _bits(rb))
     plan.close()
