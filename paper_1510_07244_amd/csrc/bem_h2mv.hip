@@ -22,7 +22,6 @@ namespace {
 using namespace dev;
 
 constexpr int kMaxVec = 512;  // longest output and input of one group / block
-constexpr int kChunks = kMaxVec / kWave;
 
 // v of lane k, k uniform across the wave (two scalar reads of the halves)
 __device__ __forceinline__ double read_lane(double v, int k) {
@@ -93,20 +92,96 @@ struct Num<true> {
 // -- kPanel input columns of a block (TRANS false) or kPanel output columns
 // (TRANS true), 16 real or 8 complex -- dealt to the waves in turn, so that a
 // group of one small block still keeps every wave busy; a wave issues the
-// loads of a panel's 64 rows before it uses them (kPanel loads in flight),
-// since a product reads every matrix entry once and waits on memory.  TRANS
-// false: lane l takes output row l + 64 c of chunk c, the panel's inputs are
-// gathered one per lane and broadcast.  TRANS true: lane l takes input row
-// l + 64 c, runs along the panel's columns and the wave adds each column's
-// products up.  The waves' partial sums are added in wave order at the end:
-// every sum runs in a fixed order, so results are reproducible bit for bit.
+// loads of a panel before it uses them, since a product reads every matrix
+// entry once and waits on memory.  TRANS false: lane l takes output rows
+// l + 64 c of R consecutive chunks c in one pass (R = 2 when the group has
+// more than 64 outputs: a coupling block of rank 65 .. 128 is one pass of
+// 2 kPanel loads in flight per wave, not two passes of which the second
+// runs with a few lanes); the panel's inputs are gathered one per lane and
+// broadcast.  TRANS true: lane l takes input row l + 64 c, runs along the
+// panel's columns and the wave adds each column's products up.  The waves'
+// partial sums are added in wave order at the end: every sum runs in a
+// fixed order, so results are reproducible bit for bit.
 constexpr int kGemvThreads = 512;  // eight waves per group: more loads in flight
+
+// TRANS false: this wave's panels of the group's blocks for the output rows
+// of chunks c0 .. c0 + R - 1, into pw (the wave's row of partial sums).
+template <bool CPLX, int R>
+__device__ __forceinline__ void gemv_rows(const GemvArgs &a, int64_t m, int64_t b0, int64_t b1,
+                                          int c0, int wave, int lane, Num<CPLX> *pw) {
+  using T = Num<CPLX>;
+  constexpr int kPanel = CPLX ? 8 : 16;
+  constexpr int W = kGemvThreads / kWave;
+  const double *A = static_cast<const double *>(a.A);
+  const double *x = static_cast<const double *>(a.x);
+  T acc[R];
+#pragma unroll
+  for (int r = 0; r < R; ++r) acc[r] = T::zero();
+  int64_t task = 0;  // panels of the group's blocks so far
+  for (int64_t b = b0; b < b1; ++b) {
+    const int64_t i0 = a.in_ptr[b], i1 = a.in_ptr[b + 1], off = a.a_off[b];
+    const int64_t n = i1 - i0;
+    const int64_t np = (n + kPanel - 1) / kPanel;
+    int64_t p = ((wave - task) % W + W) % W;  // this wave's first panel of block b
+    task += np;
+    if (p >= np) continue;
+    if (!(i0 >= 0 && i0 <= i1 && i1 <= a.in_len && n <= kMaxVec && off >= 0 && off <= a.a_len &&
+          (m == 0 || n <= (a.a_len - off) / m))) {
+      if (lane == 0 && c0 == 0) atomicOr(a.flags, FLAG_EINVAL);
+      continue;  // uniform in the wave
+    }
+    // the panel's inputs, one per lane (gathered one panel ahead, so that
+    // the gather overlaps the current panel's matrix loads)
+    auto gather = [&](int64_t q) {
+      T v = T::zero();
+      const int64_t j = q * kPanel + lane;
+      if (lane < kPanel && j < n) {
+        const int id = a.in_idx[i0 + j];
+        if (id >= 0 && id < a.x_len) v = T::load(x, id);
+        else if (c0 == 0) atomicOr(a.flags, FLAG_EINVAL);
+      }
+      return v;
+    };
+    T xl = gather(p);
+    for (; p < np; p += W) {
+      const int64_t j0 = p * kPanel;
+      const int jn = (int)min((int64_t)kPanel, n - j0);
+      // the panel's first column at a uniform address, the rest by 32-bit
+      // offsets (m, n <= 512)
+      const double *P = A + (CPLX ? 2 : 1) * (off + m * j0);
+      const int mi = (int)m;
+      T av[R][kPanel];
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        const int i = lane + kWave * (c0 + r);
+        const bool in = i < mi;
+#pragma unroll
+        for (int u = 0; u < kPanel; ++u)
+          av[r][u] = in && u < jn ? T::load(P, i + mi * u) : T::zero();
+      }
+      const T xn = p + W < np ? gather(p + W) : T::zero();
+#pragma unroll
+      for (int u = 0; u < kPanel; ++u) {
+        const T xu = xl.lane(u);
+#pragma unroll
+        for (int r = 0; r < R; ++r) acc[r].fma(av[r][u], xu);
+      }
+      xl = xn;
+    }
+  }
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const int64_t i = lane + kWave * (int64_t)(c0 + r);
+    if (i < m) pw[i] = acc[r];
+  }
+}
 
 template <bool CPLX, bool TRANS>
 __global__ __launch_bounds__(kGemvThreads, 1) void k_gemv(const GemvArgs a) {
   using T = Num<CPLX>;
   constexpr int kPanel = CPLX ? 8 : 16;
   __shared__ T part[kGemvThreads / kWave][kMaxVec];
+  __shared__ T xw[TRANS ? kGemvThreads / kWave : 1][TRANS ? kMaxVec : 1];  // gathered inputs
   const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid / kWave;
   constexpr int W = kGemvThreads / kWave;
   const double *A = static_cast<const double *>(a.A);
@@ -122,82 +197,67 @@ __global__ __launch_bounds__(kGemvThreads, 1) void k_gemv(const GemvArgs a) {
       continue;  // uniform
     }
     for (int64_t i = lane; i < m; i += kWave) part[wave][i] = T::zero();
-    // TRANS false: one pass over the group per chunk of 64 output rows;
-    // TRANS true: one pass (the chunks are the inputs, summed per panel)
-    const int passes = TRANS ? 1 : (int)((m + kWave - 1) / kWave);
-    for (int c = 0; c < passes; ++c) {
-      T acc = T::zero();  // TRANS false: output row lane + 64 c
-      int64_t task = 0;   // panels of the group's blocks so far
+    if (!TRANS) {
+      // passes of two chunks of 64 output rows (one chunk if that is all)
+      const int nchunks = (int)((m + kWave - 1) / kWave);
+      if (nchunks <= 1) {
+        gemv_rows<CPLX, 1>(a, m, b0, b1, 0, wave, lane, part[wave]);
+      } else {
+        for (int c0 = 0; c0 < nchunks; c0 += 2)
+          gemv_rows<CPLX, 2>(a, m, b0, b1, c0, wave, lane, part[wave]);
+      }
+    } else {
+      int64_t task = 0;  // panels of the group's blocks so far
       for (int64_t b = b0; b < b1; ++b) {
         const int64_t i0 = a.in_ptr[b], i1 = a.in_ptr[b + 1], off = a.a_off[b];
         const int64_t n = i1 - i0;
-        const int64_t np = ((TRANS ? m : n) + kPanel - 1) / kPanel;
+        const int64_t np = (m + kPanel - 1) / kPanel;
         int64_t p = ((wave - task) % W + W) % W;  // this wave's first panel of block b
         task += np;
         if (p >= np) continue;
         if (!(i0 >= 0 && i0 <= i1 && i1 <= a.in_len && n <= kMaxVec && off >= 0 &&
               off <= a.a_len && (m == 0 || n <= (a.a_len - off) / m))) {
-          if (lane == 0 && c == 0) atomicOr(a.flags, FLAG_EINVAL);
+          if (lane == 0) atomicOr(a.flags, FLAG_EINVAL);
           continue;  // uniform in the wave
+        }
+        // the block's inputs, gathered once for all of this wave's panels
+        // into the wave's row of xw (each lane reads back only the rows it
+        // wrote: no barrier)
+        const int ni = (int)n;
+        for (int i = lane; i < ni; i += kWave) {
+          T v = T::zero();
+          const int id = a.in_idx[i0 + i];
+          if (id >= 0 && id < a.x_len) v = T::load(x, id);
+          else atomicOr(a.flags, FLAG_EINVAL);
+          xw[wave][i] = v;
         }
         for (; p < np; p += W) {
           const int64_t j0 = p * kPanel;
-          if (!TRANS) {
-            const int jn = (int)min((int64_t)kPanel, n - j0);
-            T xl = T::zero();
-            if (lane < jn) {
-              const int id = a.in_idx[i0 + j0 + lane];
-              if (id >= 0 && id < a.x_len) xl = T::load(x, id);
-              else if (c == 0) atomicOr(a.flags, FLAG_EINVAL);
-            }
-            // the panel's first column at a uniform address, the rest by
-            // 32-bit offsets (m, n <= 512)
-            const double *P = A + (CPLX ? 2 : 1) * (off + m * j0);
-            const int i = lane + kWave * c, mi = (int)m;
-            const bool in = i < mi;
+          const int jn = (int)min((int64_t)kPanel, m - j0);
+          T s[kPanel];
+#pragma unroll
+          for (int u = 0; u < kPanel; ++u) s[u] = T::zero();
+          const double *P = A + (CPLX ? 2 : 1) * (off + n * j0);
+#pragma unroll 1
+          for (int i = lane; i - lane < ni; i += kWave) {  // uniform trip count
+            const T xi = i < ni ? xw[wave][i] : T::zero();
             T av[kPanel];
 #pragma unroll
             for (int u = 0; u < kPanel; ++u)
-              av[u] = in && u < jn ? T::load(P, i + mi * u) : T::zero();
+              av[u] = i < ni && u < jn ? T::load(P, i + ni * u) : T::zero();
 #pragma unroll
-            for (int u = 0; u < kPanel; ++u) acc.fma(av[u], xl.lane(u));
-          } else {
-            const int jn = (int)min((int64_t)kPanel, m - j0);
-            T s[kPanel];
-#pragma unroll
-            for (int u = 0; u < kPanel; ++u) s[u] = T::zero();
-            const double *P = A + (CPLX ? 2 : 1) * (off + n * j0);
-            const int ni = (int)n;
-#pragma unroll 1
-            for (int i = lane; i - lane < ni; i += kWave) {  // uniform trip count
-              T xi = T::zero();
-              if (i < ni) {
-                const int id = a.in_idx[i0 + i];
-                if (id >= 0 && id < a.x_len) xi = T::load(x, id);
-                else atomicOr(a.flags, FLAG_EINVAL);
-              }
-              T av[kPanel];
-#pragma unroll
-              for (int u = 0; u < kPanel; ++u)
-                av[u] = i < ni && u < jn ? T::load(P, i + ni * u) : T::zero();
-#pragma unroll
-              for (int u = 0; u < kPanel; ++u) s[u].fma(av[u], xi);
-            }
-            // butterfly sums leave every column's total in every lane; lane
-            // u adds output j0 + u
-            T mine = T::zero();
-#pragma unroll
-            for (int u = 0; u < kPanel; ++u) {
-              const T t = s[u].shfl_down_sum();
-              if (lane == u) mine = t;
-            }
-            if (lane < jn) part[wave][j0 + lane].add(mine);
+            for (int u = 0; u < kPanel; ++u) s[u].fma(av[u], xi);
           }
+          // butterfly sums leave every column's total in every lane; lane
+          // u adds output j0 + u
+          T mine = T::zero();
+#pragma unroll
+          for (int u = 0; u < kPanel; ++u) {
+            const T t = s[u].shfl_down_sum();
+            if (lane == u) mine = t;
+          }
+          if (lane < jn) part[wave][j0 + lane].add(mine);
         }
-      }
-      if (!TRANS) {
-        const int64_t i = lane + kWave * (int64_t)c;
-        if (i < m) part[wave][i] = acc;
       }
     }
     __syncthreads();

@@ -149,20 +149,66 @@ class H2Matrix:
 
     def matvec(self, x, y, stream=None, accumulate=False):
         """y (+)= H x for device vectors of n entries, on `stream` (default:
-        torch's current stream)."""
+        torch's current stream).  The near field runs on a second stream
+        beside the chain forward transformation -> coupling -> backward
+        transformation, which needs y only at its leaf level: that level
+        waits for the near field, so y receives its terms in the same order
+        as on one stream (bit for bit the same result)."""
+        import torch
         with _on(stream):
-            if not accumulate:
-                y.zero_()
+            main = torch.cuda.current_stream()
+            if getattr(self, "_side", None) is None:
+                self._side = torch.cuda.Stream()
+            side = self._side
+            side.wait_stream(main)
+            bufs = {"x": x, "y": y, "xh": self.xh, "yh": self.yh}
+            with torch.cuda.stream(side):
+                if not accumulate:
+                    y.zero_()
+                for c in self.near_calls:
+                    self._run(c, bufs, None)
             self.xh.zero_()
             self.yh.zero_()
-            bufs = {"x": x, "y": y, "xh": self.xh, "yh": self.yh}
-            for c in self.near_calls:
-                self._run(c, bufs, None)
             for c in self.fwd:
                 self._run(c, bufs, None)
             self._run(self.coupling_call, bufs, None)
+            joined = False
             for c in self.bwd:
+                if c.dst == "y" and not joined:
+                    main.wait_stream(side)
+                    joined = True
                 self._run(c, bufs, None)
+            if not joined:
+                main.wait_stream(side)
+        return y
+
+
+class GraphedMatvec:
+    """H.matvec captured in a HIP graph, one graph per pair of vector
+    buffers: the first call with a pair runs the product once and captures
+    it, later calls replay the graph (one launch for the whole product
+    instead of one per kernel).  The graphs read and write the buffers they
+    were captured with, so callers that keep their vectors in place (like
+    cg and bicgstab) reuse them.  Usable wherever H.matvec is."""
+
+    def __init__(self, H, accumulate=False):
+        self.H, self.accumulate = H, accumulate
+        self.graphs = {}
+
+    def __call__(self, x, y, stream=None):
+        import torch
+        key = (x.data_ptr(), y.data_ptr(), x.numel(), y.numel(), x.dtype, y.dtype)
+        with _on(stream):
+            hit = self.graphs.get(key)
+            if hit is None:
+                self.H.matvec(x, y, accumulate=self.accumulate)  # eager, before capture
+                g = torch.cuda.CUDAGraph()
+                torch.cuda.current_stream().synchronize()
+                with torch.cuda.graph(g):
+                    self.H.matvec(x, y, accumulate=self.accumulate)
+                self.graphs[key] = (g, x, y)  # keeps the buffers alive
+                hit = self.graphs[key]
+            hit[0].replay()
         return y
 
 

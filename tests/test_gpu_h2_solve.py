@@ -5,7 +5,8 @@ problems of Sec. 4, solved on the GPU (GPU tests, through the C-ABI).
   oracle matrix times the same seeded vector within 1e-6 (the H^2
   approximation error), Laplace SLP and DLP and Helmholtz; against the
   host evaluation of the same near-field blocks, coupling matrices and
-  nested bases at 1e-12 (the kernels' arithmetic alone).
+  nested bases at 1e-12 (the kernels' arithmetic alone).  The product
+  captured in a HIP graph replays the eager product bit for bit.
 * Interior Dirichlet problem for the Laplace equation (Sec. 4): the Galerkin
   system V alpha = (1/2 M + K) beta for f1 = x1^2 - x3^2,
   f2 = g(x, (1.2, 1.2, 1.2)), f3 = g(x, (1, 0.25, 1)) on the octahedron
@@ -114,6 +115,44 @@ def test_h2_matvec(pk, ctx, kernel, kappa):
         H.matvec(xd, y, accumulate=True)
         ctx.check()
         assert np.allclose(y.cpu().numpy(), 2 * got, rtol=0, atol=1e-13 * np.abs(got).max())
+
+
+@pytest.mark.parametrize("kernel,kappa", [(0, 0.0), (1, 4.0)])
+def test_h2_matvec_graph_replays_match_eager(pk, ctx, kernel, kappa):
+    # the product captured in a HIP graph (near field on a second stream
+    # inside the capture): every replay, with eager work and
+    # synchronisations between replays, gives the eager product bit for bit
+    import torch
+    from paper_1510_07244_amd.h2mv import GraphedMatvec
+    m = octahedron_sphere(16)
+    h, Hv, Hk = _assembled(pk, ctx, m, kernel, kappa)
+    rng = np.random.Generator(np.random.PCG64(9))
+    x = rng.standard_normal(m.nt) + (1j * rng.standard_normal(m.nt) if kernel else 0)
+    dt = torch.complex128 if kernel else torch.float64
+    xd = torch.from_numpy(x).to(device="cuda", dtype=dt)
+    view = (lambda t: torch.view_as_real(t).cpu().numpy()) if kernel else (lambda t: t.cpu().numpy())
+    for H in (Hv, Hk):
+        ref = torch.empty_like(xd)
+        H.matvec(xd, ref)
+        ctx.check()
+        want = view(ref).view(np.uint64)
+        G = GraphedMatvec(H)
+        y = torch.empty_like(xd)
+        for rep in range(4):
+            y.fill_(float("nan"))  # eager work between replays
+            torch.cuda.synchronize()
+            G(xd, y)
+            ctx.check()
+            assert np.array_equal(view(y).view(np.uint64), want), rep
+        assert len(G.graphs) == 1
+        # another buffer pair gets its own graph; the first one still replays
+        y2 = torch.empty_like(xd)
+        G(xd, y2)
+        G(xd, y)
+        ctx.check()
+        assert len(G.graphs) == 2
+        assert np.array_equal(view(y2).view(np.uint64), want)
+        assert np.array_equal(view(y).view(np.uint64), want)
 
 
 def test_h2_matvec_sphere8192_deterministic(pk, ctx):
@@ -246,3 +285,59 @@ def test_helmholtz_brakhage_werner_exterior(pk, ctx):
     print("Brakhage-Werner exterior errors (512/2048/8192 triangles):", errs, flush=True)
     assert errs[1] < errs[0] and errs[2] < errs[1], errs
     assert errs[2] <= 1e-2, errs
+
+
+@pytest.mark.parametrize("cplx", [False, True])
+@pytest.mark.parametrize("trans", [False, True])
+def test_gemv_grouped_ragged_against_numpy(pk, ctx, cplx, trans):
+    # the grouped product on its own, with group output lengths and block
+    # input lengths from 1 to the maximum 512 (one and several chunks of 64
+    # rows, ragged tails, groups of one block and of many), gathered inputs
+    # and scattered outputs; against numpy in FP64 at 1e-12 (accumulation
+    # into y included)
+    import torch
+    rng = np.random.Generator(np.random.PCG64(17 + 2 * cplx + trans))
+    nx, ny = 3000, 6000
+    ms = [1, 7, 64, 65, 100, 128, 129, 200, 300, 512, 33, 64]
+    out_perm = rng.permutation(ny)
+    groups, o = [], 0
+    for g, m in enumerate(ms):
+        nb = 1 if g % 3 == 0 else int(rng.integers(2, 6))
+        blocks = []
+        for _ in range(nb):
+            n = int(rng.choice([1, 5, 16, 17, 63, 64, 80, 130, 257, 512]))
+            inp = rng.choice(nx, size=n, replace=False).astype(np.int32)
+            shape = (n, m) if trans else (m, n)
+            A = rng.standard_normal(shape) + (1j * rng.standard_normal(shape) if cplx else 0)
+            blocks.append((A, inp))
+        groups.append((out_perm[o:o + m].astype(np.int32), blocks))
+        o += m
+    x = rng.standard_normal(nx) + (1j * rng.standard_normal(nx) if cplx else 0)
+    y0 = rng.standard_normal(ny) + (1j * rng.standard_normal(ny) if cplx else 0)
+    ref = y0.copy()
+    grp_ptr, out_ptr, out_idx, in_ptr, in_idx, a_off, Aflat = [0], [0], [], [0], [], [], []
+    off = 0
+    for out, blocks in groups:
+        acc = np.zeros(out.size, dtype=ref.dtype)
+        for A, inp in blocks:
+            acc += (A.T if trans else A) @ x[inp]
+            a_off.append(off)
+            Aflat.append(A.ravel(order="F"))
+            off += A.size
+            in_idx.append(inp)
+            in_ptr.append(in_ptr[-1] + inp.size)
+        ref[out] += acc
+        out_idx.append(out)
+        out_ptr.append(out_ptr[-1] + out.size)
+        grp_ptr.append(len(a_off))
+    dt = torch.complex128 if cplx else torch.float64
+    i32 = lambda a: torch.from_numpy(np.asarray(a, dtype=np.int32)).cuda()
+    A = torch.from_numpy(np.concatenate(Aflat)).to(device="cuda", dtype=dt)
+    xd = torch.from_numpy(x).to(device="cuda", dtype=dt)
+    yd = torch.from_numpy(y0).to(device="cuda", dtype=dt)
+    ctx.gemv_grouped(trans, i32(grp_ptr), i32(out_ptr), i32(np.concatenate(out_idx)), i32(in_ptr),
+                     i32(np.concatenate(in_idx)), torch.tensor(a_off, dtype=torch.int64).cuda(),
+                     A, xd, yd)
+    ctx.check()
+    got = yd.cpu().numpy()
+    assert np.abs(got - ref).max() <= 1e-12 * np.abs(ref).max()
