@@ -657,9 +657,12 @@ __device__ __forceinline__ T uniform_copy(const T *p) {
 // its own copy, so that nothing but the queue state is live across the
 // choice of layer.
 template <int KERNEL, int LAYER, int XC, bool MIXED>
-__device__ __forceinline__ void persistent_item(const BlockArgs *batches, int4 d, int cp,
+__device__ __forceinline__ void persistent_item(const BlockArgs *__restrict__ batches, int4 d, int cp,
                                                 double *lds_raw, int *carved) {
-  const BlockArgs a = uniform_copy(batches + d.x);
+  // the entry's arguments are read where used (scalar loads from read-only
+  // memory, which the compiler may repeat instead of holding or spilling
+  // them across the sub-tile loops)
+  const BlockArgs &a = batches[d.x];
   if (d.y < 0 || d.y >= a.nblocks) {
     if (thread_id() == 0) atomicOr(a.flags, FLAG_EINVAL);
     return;
@@ -686,15 +689,15 @@ __device__ __forceinline__ void persistent_item(const BlockArgs *batches, int4 d
 }
 
 template <int KERNEL, int XC, bool MIXED>
-__global__ __launch_bounds__(kThreads, 2) void k_persistent(const BlockArgs *batches,
+__global__ __launch_bounds__(kThreads, 2) void k_persistent(const BlockArgs *__restrict__ batches,
                                                             const int32_t *mode,
                                                             const int4 *tiles, int32_t ntiles,
                                                             int32_t nbatch, int32_t *counter) {
   extern __shared__ __align__(16) double lds_raw[];  // 16-byte aligned: ds_read_b128 of points
   __shared__ int s_tile;
-  // the queue and the batch arguments are read-only here: wave-uniform
-  // (scalar) loads keep every argument, pointer and loop bound in scalar
-  // registers as in the per-block kernel
+  // the queue and the batch arguments are read-only here: their loads have
+  // wave-uniform addresses and are scalar, as the per-block kernel's
+  // argument loads
   typedef const int32_t __attribute__((address_space(4))) *cint_t;
   int carved = -1;  // sub-tile shape whose LDS layout holds the rule, -1: none yet
   for (;;) {
