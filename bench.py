@@ -914,7 +914,7 @@ def solve_leg(torch, pk, ctx, hb, stream, reps=20):
     Roofline of the product: bytes of the matrices read once per product
     (near-field entries, coupling entries, transfer matrices) over its time,
     against HBM."""
-    from paper_1510_07244_amd.h2mv import GraphedMatvec, H2Matrix, cg
+    from paper_1510_07244_amd.h2mv import GraphedMatvec, H2Matrix, cg, cg_device
     h, o, m = hb.h, hb.out, hb.m
     Hv = H2Matrix(h, hb.V, hb.V, o["ns"], o["cs"])
     Hk = H2Matrix(h, hb.V, hb.W, o["nd"], o["cd"])
@@ -951,10 +951,20 @@ def solve_leg(torch, pk, ctx, hb, stream, reps=20):
     rhs = torch.empty_like(beta)
     Hk.matvec(beta, rhs, stream)
     ctx.mass_apply(h.mesh, 0.5, beta, rhs, stream)
+    alpha_h = torch.zeros_like(beta)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    it_h, _ = cg(ctx, GraphedMatvec(Hv), rhs, alpha_h, tol=1e-8, maxit=1000, stream=stream)
+    torch.cuda.synchronize()
+    t_host = time.perf_counter() - t0
+    # every step on the device (the step captured in a HIP graph, the host
+    # reads the stopping flag every 8 steps; capture included in the timed
+    # call, after one warm-up call)
+    cg_device(ctx, Hv, rhs, torch.zeros_like(beta), tol=1e-8, maxit=1000, stream=stream)
     alpha = torch.zeros_like(beta)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    it, rel = cg(ctx, GraphedMatvec(Hv), rhs, alpha, tol=1e-8, maxit=1000, stream=stream)
+    it, rel = cg_device(ctx, Hv, rhs, alpha, tol=1e-8, maxit=1000, stream=stream)
     torch.cuda.synchronize()
     t_cg = time.perf_counter() - t0
     x = c / np.linalg.norm(c, axis=1)[:, None]
@@ -965,7 +975,13 @@ def solve_leg(torch, pk, ctx, hb, stream, reps=20):
     err = float(np.sqrt((area * (a - dn) ** 2).sum() / (area * dn ** 2).sum()))
     ctx.check(stream)
     res["laplace_dirichlet_f1"] = {"cg_iterations": it, "relative_residual": rel,
-                                   "solve_s": t_cg, "neumann_l2_rel_err": err}
+                                   "solve_s": t_cg, "neumann_l2_rel_err": err,
+                                   "solve_s_host_scalars": t_host,
+                                   "host_scalars_iterations": it_h,
+                                   "note": "solve_s: cg_device (steps captured in a HIP graph, "
+                                           "scalars on the device); host_scalars: cg with the "
+                                           "graph-captured product and the step scalars read "
+                                           "back every step"}
     return res
 
 

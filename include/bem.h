@@ -632,6 +632,27 @@ int bem_vec_dot(bem_ctx *ctx, int32_t is_complex, int32_t conj, int64_t n, const
 int bem_vec_axpby(bem_ctx *ctx, int32_t is_complex, int64_t n, double ar, double ai,
                   const void *x, double br, double bi, void *y, void *stream);
 
+/* One step of the conjugate-gradient method (Hestenes-Stiefel; Sec. 4
+ * solves the single-layer system by conjugate gradients) with its scalars
+ * in device memory, for real vectors of n entries:
+ *     alpha = r.r / p.q,  x += alpha p,  r -= alpha q,
+ *     r.r' = r.r (new),   p = r + (r.r' / r.r) p,   r.r = r.r',
+ * the caller having formed q = A p and p.q (bem_vec_dot into state + 2)
+ * before.  state: device double[10]:
+ *   [0] r.r   [1] 0 (imaginary part of the dot product)
+ *   [2] p.q   [3] 0
+ *   [4] new r.r (written here)   [5] 0
+ *   [6] stopping threshold on r.r (tol^2 b.b)
+ *   [7] 1 while iterating, 0 once r.r <= [6], the iteration limit is
+ *       reached or p.q = 0 (then the step leaves x, r and p unchanged)
+ *   [8] steps taken   [9] iteration limit
+ * Nothing comes back to the host: a caller may enqueue (or capture in a
+ * graph) several steps and read [7] and [8] now and then.  x, r, p, q:
+ * device double[n]; q is not written.  Uses the context's dot-product
+ * scratch (calls on one context must not overlap in time). */
+int bem_cg_step(bem_ctx *ctx, int64_t n, double *state, void *x, void *r, void *p,
+                const void *q, void *stream);
+
 /* y += c M x with c = cr + i ci and M the Galerkin mass matrix of the
  * piecewise constants, diagonal with M_ii = |tau_i| (the identity term
  * (1/2) I of Sec. 4 in Galerkin form); x, y device arrays of mesh->nt

@@ -375,6 +375,7 @@ def _setup_h2mv_api():
     _lib.bem_vec_dot.argtypes = [P, i32, i32, i64, P, P, P, P]
     _lib.bem_vec_axpby.argtypes = [P, i32, i64, f64, f64, P, f64, f64, P, P]
     _lib.bem_mass_apply.argtypes = [P, ctypes.POINTER(bem_mesh), i32, f64, f64, P, P, P]
+    _lib.bem_cg_step.argtypes = [P, i64, P, P, P, P, P, P]
 
 
 _setup_h2mv_api()
@@ -407,6 +408,13 @@ def _context_vec_axpby(self, alpha, x, beta, y, stream=None):
     a, b = complex(alpha), complex(beta)
     self._rc(_lib.bem_vec_axpby(self.h, int(x.is_complex()), _n(x), a.real, a.imag, _ptr(x),
                                 b.real, b.imag, _ptr(y), _stream(stream)))
+
+
+def _context_cg_step(self, state, x, r, p, q, stream=None):
+    """bem_cg_step: one conjugate-gradient step with its scalars in the
+    device double[10] `state` (layout in include/bem.h)."""
+    self._rc(_lib.bem_cg_step(self.h, _n(x), _ptr(state), _ptr(x), _ptr(r), _ptr(p), _ptr(q),
+                              _stream(stream)))
 
 
 def _context_mass_apply(self, mesh, c, x, y, stream=None):
@@ -447,6 +455,7 @@ Context.p1_gather = _context_p1_gather
 Context.gemv_grouped = _context_gemv_grouped
 Context.vec_dot = _context_vec_dot
 Context.vec_axpby = _context_vec_axpby
+Context.cg_step = _context_cg_step
 Context.mass_apply = _context_mass_apply
 def _context_pivot_inverse(self, is_complex, nrows, rank, max_rank, piv_rows, piv_cols, A, a_off,
                            acols, pinv, stream=None):

@@ -543,6 +543,19 @@ int bem_vec_axpby(bem_ctx *ctx, int32_t is_complex, int64_t n, double ar, double
   return BEM_OK;
 }
 
+int bem_cg_step(bem_ctx *ctx, int64_t n, double *state, void *x, void *r, void *p,
+                const void *q, void *stream) {
+  if (!ctx) return BEM_EINVAL;
+  if (n < 0 || !state || (n > 0 && (!x || !r || !p || !q)))
+    return fail(ctx, BEM_EINVAL, "bad size or NULL array");
+  DeviceGuard g(ctx->device);
+  hipError_t e = bem::launch_cg_step(n, state, static_cast<double *>(x), static_cast<double *>(r),
+                                     static_cast<double *>(p), static_cast<const double *>(q),
+                                     ctx->dot_part, static_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return hip_fail(ctx, e, "conjugate-gradient kernel launch");
+  return BEM_OK;
+}
+
 int bem_mass_apply(bem_ctx *ctx, const bem_mesh *mesh, int32_t is_complex, double cr, double ci,
                    const void *x, void *y, void *stream) {
   if (!ctx) return BEM_EINVAL;

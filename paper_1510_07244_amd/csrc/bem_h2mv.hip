@@ -364,7 +364,57 @@ __global__ __launch_bounds__(kThreads) void k_mass(int32_t nt, const double *geo
   }
 }
 
+// Conjugate-gradient updates with the step scalars in device memory (the
+// layout of the state array is documented at bem_cg_step): the host reads
+// them only to decide when to stop, not once per step.
+__global__ __launch_bounds__(kThreads) void k_cg_xr(int64_t n, const double *st, const double *p,
+                                                    const double *q, double *x, double *r) {
+  const bool go = st[7] != 0.0 && st[2] != 0.0;
+  const double alpha = go ? st[0] / st[2] : 0.0;
+  const double one = 1.0;
+  for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * kThreads) {
+    x[i] = alpha * p[i] + one * x[i];
+    r[i] = -alpha * q[i] + one * r[i];
+  }
+}
+
+__global__ __launch_bounds__(kThreads) void k_cg_p(int64_t n, const double *st, const double *r,
+                                                   double *p) {
+  if (!(st[7] != 0.0 && st[2] != 0.0)) return;  // uniform: stopped, p stays
+  const double beta = st[4] / st[0];
+  const double one = 1.0;
+  for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * kThreads)
+    p[i] = one * r[i] + beta * p[i];
+}
+
+__global__ void k_cg_close(double *st) {
+  if (st[7] == 0.0) return;
+  if (st[2] == 0.0) {  // p.q = 0: breakdown, stop with the current iterate
+    st[7] = 0.0;
+    return;
+  }
+  st[0] = st[4];
+  st[8] += 1.0;
+  st[7] = st[0] > st[6] && st[8] < st[9] ? 1.0 : 0.0;
+}
+
 }  // namespace
+
+hipError_t launch_cg_step(int64_t n, double *state, double *x, double *r, double *p,
+                          const double *q, double *dot_part, hipStream_t s) {
+  const dim3 grid((unsigned)std::min<int64_t>(std::max<int64_t>((n + kThreads - 1) / kThreads, 1), 4096)),
+      block(kThreads);
+  hipLaunchKernelGGL(k_cg_xr, grid, block, 0, s, n, state, p, q, x, r);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  e = launch_dot(false, false, n, r, r, dot_part, state + 4, s);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_cg_p, grid, block, 0, s, n, state, r, p);
+  hipLaunchKernelGGL(k_cg_close, dim3(1), dim3(1), 0, s, state);
+  return hipGetLastError();
+}
 
 hipError_t launch_gemv(bool cplx, bool trans, const GemvArgs &a, hipStream_t s) {
   if (a.ngroups == 0) return hipSuccess;

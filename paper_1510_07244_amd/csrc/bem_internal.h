@@ -200,6 +200,9 @@ hipError_t launch_dot(bool cplx, bool conj, int64_t n, const double *x, const do
                       double *part, double *out, hipStream_t s);
 hipError_t launch_axpby(bool cplx, int64_t n, double ar, double ai, const double *x, double br,
                         double bi, double *y, hipStream_t s);
+// one conjugate-gradient update with the scalars in state (bem_cg_step)
+hipError_t launch_cg_step(int64_t n, double *state, double *x, double *r, double *p,
+                          const double *q, double *dot_part, hipStream_t s);
 hipError_t launch_mass(bool cplx, int32_t nt, const double *geo, int64_t ldg, double cr, double ci,
                        const double *x, double *y, hipStream_t s);
 

@@ -261,6 +261,45 @@ def _cg(ctx, apply, b, x, tol, maxit):
     return it, float(np.sqrt(rr / bb))
 
 
+def cg_device(ctx, H, b, x, tol=1e-10, maxit=1000, check=8, stream=None):
+    """Conjugate gradients for an assembled symmetric positive definite H^2
+    matrix H (real) with every step on the device: one step -- the product
+    q = H p, p.q and bem_cg_step -- is captured in a HIP graph and replayed
+    `check` times between the host's reads of the stopping flag.  Steps
+    after the stopping test holds change nothing (bem_cg_step stops
+    updating), so the iterate and the count are those of `cg` with the same
+    tolerance.  Returns (iterations, relative residual)."""
+    import torch
+    with _on(stream):
+        r, q, p = torch.empty_like(b), torch.empty_like(b), torch.empty_like(b)
+        st = torch.zeros(10, dtype=torch.float64, device="cuda")
+        bb_buf = torch.zeros(2, dtype=torch.float64, device="cuda")
+        H.matvec(x, q)
+        r.copy_(b)
+        ctx.vec_axpby(-1.0, q, 1.0, r)  # r = b - A x
+        p.copy_(r)
+        ctx.vec_dot(r, r, st[0:2])
+        ctx.vec_dot(b, b, bb_buf)
+        rr, bb = st[0].item(), bb_buf[0].item()
+        thr = tol * tol * bb
+        if not (rr > thr and maxit > 0):
+            return 0, float(np.sqrt(rr / bb))
+        st[6:10] = torch.tensor([thr, 1.0, 0.0, float(maxit)], dtype=torch.float64)
+        g = torch.cuda.CUDAGraph()
+        torch.cuda.current_stream().synchronize()
+        with torch.cuda.graph(g):
+            H.matvec(p, q)
+            ctx.vec_dot(p, q, st[2:4])
+            ctx.cg_step(st, x, r, p, q)
+        while True:
+            for _ in range(check):
+                g.replay()
+            active, it, rr = st[7].item(), st[8].item(), st[0].item()
+            if active == 0.0:
+                break
+        return int(it), float(np.sqrt(rr / bb))
+
+
 def bicgstab(ctx, apply, b, x, tol=1e-10, maxit=1000, stream=None):
     """BiCGStab (van der Vorst) for a general (complex) operator
     `apply(p, q)`; stops when |r| <= tol |b|.  Returns (iterations, relative

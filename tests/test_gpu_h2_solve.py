@@ -13,7 +13,9 @@ problems of Sec. 4, solved on the GPU (GPU tests, through the C-ABI).
   spheres with 512, 2048 and 8192 triangles, solved by conjugate gradients:
   the Neumann data converge like O(h) to the exact ones (the error halves
   with h), and on the 512-triangle sphere the solution equals the dense
-  oracle system's (numpy solve) within the H^2 and solver tolerances.
+  oracle system's (numpy solve) within the H^2 and solver tolerances.  The
+  solver with every step on the device (bem_cg_step, graph replays) takes
+  the host-driven one's iterations to the same iterate.
 * Exterior Dirichlet problem for the Helmholtz equation by the
   Brakhage-Werner formulation (Sec. 4): kappa = 3, eta = kappa, data
   f = g(x, (0, 0, 0.2)); (1/2 M + K - i eta V) w = (int f psi_i) by
@@ -230,6 +232,37 @@ def test_laplace_dirichlet_neumann_converges(pk, ctx):
     ratios = errs[:-1] / errs[1:]
     assert np.all(ratios >= 1.6), ratios  # O(h): halving h halves the error
     assert np.all(errs[-1] <= 0.05), errs[-1]
+
+
+def test_cg_on_the_device_matches_host_cg(pk, ctx):
+    # the conjugate gradients with every step on the device (one step
+    # captured in a HIP graph, bem_cg_step keeping the scalars on the
+    # device) take the host-driven solver's iterations to the same iterate,
+    # also when the stopping test holds in the middle of a batch of replays
+    import torch
+    from paper_1510_07244_amd.h2mv import cg, cg_device
+    m = octahedron_sphere(16)
+    h, Hv, Hk = _assembled(pk, ctx, m)
+    beta, _ = _laplace_data(m)[0]
+    bd = torch.from_numpy(beta).cuda()
+    rhs = torch.empty_like(bd)
+    Hk.matvec(bd, rhs)
+    ctx.mass_apply(h.mesh, 0.5, bd, rhs)
+    for tol, check in ((1e-10, 8), (1e-6, 5), (1e-10, 1)):
+        a_host = torch.zeros_like(bd)
+        it_h, res_h = cg(ctx, Hv.matvec, rhs, a_host, tol=tol, maxit=500)
+        a_dev = torch.zeros_like(bd)
+        it_d, res_d = cg_device(ctx, Hv, rhs, a_dev, tol=tol, maxit=500, check=check)
+        ctx.check()
+        assert it_d == it_h, (tol, check, it_d, it_h)
+        assert res_d <= tol and abs(res_d - res_h) <= 1e-3 * res_h
+        x, y = a_dev.cpu().numpy(), a_host.cpu().numpy()
+        assert np.linalg.norm(x - y) <= 1e-12 * np.linalg.norm(y)
+    # the iteration limit stops it too
+    a_dev = torch.zeros_like(bd)
+    it_d, res_d = cg_device(ctx, Hv, rhs, a_dev, tol=1e-14, maxit=7, check=4)
+    ctx.check()
+    assert it_d == 7 and res_d > 1e-14
 
 
 def test_helmholtz_brakhage_werner_exterior(pk, ctx):
