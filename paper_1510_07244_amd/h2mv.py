@@ -39,8 +39,12 @@ class _Call:
 
     def __init__(self, groups, trans, A, src, dst):
         """groups: list of (out_idx, [(a_off, in_idx), ...]); src / dst name
-        the buffers read and written ('x', 'y', 'xh', 'yh')."""
+        the buffers read and written ('x', 'y', 'xh', 'yh').  The groups are
+        listed by decreasing size (matrix entries), so that a launch with
+        more groups than workgroup slots starts its largest ones first."""
         import torch
+        size = lambda g: len(g[0]) * sum(len(inp) for _, inp in g[1])
+        groups = sorted(groups, key=lambda g: -size(g))  # stable: ties keep their order
         grp_ptr, out_ptr, out_idx, in_ptr, in_idx, a_off = [0], [0], [], [0], [], []
         for out, blocks in groups:
             out_idx.append(np.asarray(out, dtype=np.int32))
