@@ -898,7 +898,8 @@ def batched_config2_leg(torch, pk, ctx, hb, stream, steps=10):
             for k in out}
     for p in plans:
         p.close()
-    return {"ms_per_step": ms, "plan_tuning_s": t_tune, "plan_cached_tuning_s": t_cached,
+    return {"value": hb.entries_evaluated() / (ms * 1e-3), "unit": "entries/s",
+            "ms_per_step": ms, "plan_tuning_s": t_tune, "plan_cached_tuning_s": t_cached,
             "h2_setup_s": float(hb.t_setup) + t_cached, "tune": tuned,
             "rel_diff_vs_plain_step": diff,
             "note": "one persistent graph replay (near field of both layers in one pass, "
@@ -1076,6 +1077,10 @@ def main():
     solve = solve_leg(torch, pk, ctx, hb, stream)
     batched_c2 = None if args.batched_meshes <= 0 else batched_config2_leg(torch, pk, ctx, hb,
                                                                            stream)
+    # mixed + batched: the same plan with the mixed operator (FP32 regular
+    # pairs, lists with pair lists everywhere), against the mixed step
+    batched_c2m = None if args.batched_meshes <= 0 else batched_config2_leg(torch, pk, ctx, hm,
+                                                                            stream)
     helmholtz = None if args.no_helmholtz else helmholtz_near_leg(torch, pk, ctx, stream, 5)
     helmholtz_h2 = None if args.no_helmholtz else helmholtz_h2_leg(torch, pk, ctx, stream)
     batched = None
@@ -1253,6 +1258,11 @@ def main():
         result["forms"]["batched"] = batched
     if batched_c2:
         result["forms"]["batched_config2"] = batched_c2
+    if batched_c2m:
+        batched_c2m["speedup_vs_plain"] = ms_step / batched_c2m["ms_per_step"]
+        batched_c2m["note"] = ("mixed operator: " + batched_c2m["note"] +
+                               "; rel_diff against the mixed step's outputs")
+        result["forms"]["mixed_batched_config2"] = batched_c2m
     if learned:
         result["forms"]["learned"] = learned
     # H2 setup time of the 8192-sphere matrix by form (tree, bases, first
@@ -1261,6 +1271,8 @@ def main():
     by_form = {"plain_fp64": float(st[best, 0]), "mixed": float(hm.t_setup)}
     if batched_c2:
         by_form["batched"] = float(st[best, 0]) + batched_c2["plan_cached_tuning_s"]
+    if batched_c2m:
+        by_form["mixed_batched"] = float(hm.t_setup) + batched_c2m["plan_cached_tuning_s"]
     if learned:
         by_form["learned_coupling"] = float(st[best, 0]) + learned["h2_step"]["select_s"]
     result["h2_setup_s_by_form"] = by_form
