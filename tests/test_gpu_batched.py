@@ -293,7 +293,7 @@ def test_batched_mirrored_lists_equal_per_call(pk, ctx):
     plan.close()
 
 
-@pytest.mark.parametrize("kernel,precision,kappa", [(0, 0, 0.0), (1, 0, 4.0), (0, 1, 0.0)])
+@pytest.mark.parametrize("kernel,precision,kappa", [(0, 0, 0.0), (1, 0, 4.0), (0, 1, 0.0), (1, 1, 4.0)])
 def test_batched_layers_in_one_plan_equal_per_call(pk, ctx, kernel, precision, kappa):
     # one plan holding the whole matrix step of an H2 setup: the mirrored
     # near field with both layers in one pass, the mirrored single-layer
