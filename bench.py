@@ -477,6 +477,7 @@ class LearnedBench:
         ct = pk.ClusterTree(m.v, m.tri, leaf=64)
         near, _ = pk.block_tree(ct, eta=2.0)
         self.nblocks = len(near)
+        self.near_idx = [(ct.idx(t), ct.idx(s)) for t, s in near]
         self.blocks, self.total = pk.Blocks.from_lists([ct.idx(t) for t, s in near],
                                                        [ct.idx(s) for t, s in near])
         # blocks for the error check (seeded sample), as offsets into the output
@@ -549,7 +550,7 @@ class LearnedBench:
                 "max_block_rel_err_vs_plain": max(errs), "near_field_rel_err_vs_plain": tot,
                 "entries": int(self.total)}
 
-    def result(self, torch, stream, steps, warmup):
+    def result(self, torch, stream, steps, warmup, cpu_seconds=0.0):
         pk = self.pk
         legs = {}
         for name, op in (("laplace_slp", pk.make_op(pk.LAPLACE, pk.SLP, q_regular=4, q_singular=4)),
@@ -559,6 +560,20 @@ class LearnedBench:
                          ("helmholtz8_dlp", pk.make_op(pk.HELMHOLTZ, pk.DLP, q_regular=5,
                                                        q_singular=5, kappa=8.0))):
             legs[name] = self.leg(torch, op, stream, steps, warmup)
+        if cpu_seconds > 0:
+            # the oracle on a seeded sample of the same near-field blocks
+            # (Laplace single layer, q = 4, all host threads)
+            import oracle
+            oracle.use_native_build()
+            rng = np.random.Generator(np.random.PCG64(2))
+            work = [(*self.near_idx[k], 0) for k in rng.permutation(self.nblocks)]
+            n, used, dt = oracle_block_run(self.m, work, cpu_seconds)
+            leg = legs["laplace_slp"]
+            leg["cpu_oracle"] = {"value": n / dt, "unit": "entries/s",
+                                 "cores": oracle.num_threads(), "kind": "oracle",
+                                 "sample": f"{used} of {self.nblocks} blocks (seeded order): "
+                                           f"{n} entries in {dt:.1f} s",
+                                 "gpu_plain_value": leg["entries"] / (leg["plain_ms"] * 1e-3)}
         return {
             "workload": f"near field of the octahedron sphere with {self.m.nt} triangles "
                         f"({self.nblocks} blocks, leaf 64, eta 2): plain fixed order (q=4 Laplace, "
@@ -807,13 +822,15 @@ def step_flops(hb):
     return {"nb": f_nb, "cs": f_cs, "cd": f_cd}
 
 
-def helmholtz_h2_leg(torch, pk, ctx, stream, steps=3, warmup=1, peak64=None):
+def helmholtz_h2_leg(torch, pk, ctx, stream, steps=3, warmup=1, peak64=None, cpu_seconds=0.0):
     """The Helmholtz workloads: SLP + DLP H^2 matrices of the 32768-triangle
     sphere and the 24576-triangle cube surface, kappa 2, 4 and 8, q = 5,
     plain complex128 and mixed complex64: setup time (trees, bases with the
     host pivot search, first assembly) and the step on one stream (bases
     replay, one-pass near field, both couplings) with per-phase HIP-event
-    times and the roofline of the longest launch."""
+    times and the roofline of the longest launch.  With cpu_seconds > 0
+    the plain kappa = 4 records carry the oracle's rate on a seeded sample
+    of the same step's blocks (all host threads, that many seconds)."""
     from bem_inputs import cube_surface, octahedron_sphere
     out = []
     for name, mesh in (("sphere32768", octahedron_sphere(64)), ("cube24576", cube_surface(32))):
@@ -838,6 +855,9 @@ def helmholtz_h2_leg(torch, pk, ctx, stream, steps=3, warmup=1, peak64=None):
                                  "bound": "alu", "achieved": ach, "peak": peak, "unit": "TFLOP/s",
                                  "frac": ach / peak, "flops_per_launch": fl[longest]},
                 })
+                if cpu_seconds > 0 and kappa == 4.0 and not mixed:
+                    out[-1]["cpu_oracle"] = oracle_sample(mesh, hb, cpu_seconds, pk.HELMHOLTZ,
+                                                          kappa, 5)
                 del hb
     return out
 
@@ -996,34 +1016,62 @@ def cpu_model():
     return "unknown"
 
 
+def oracle_block_run(m, work, limit, kernel=0, kappa=0.0, q=Q):
+    """The FP64 oracle over a list of (rows, cols, layer) blocks in order
+    until `limit` seconds have passed: (entries, blocks, seconds)."""
+    import oracle
+    n = used = 0
+    t0 = time.perf_counter()
+    for r, c, layer in work:
+        n += oracle.block(m.v, m.tri, r, c, kernel=kernel, kappa=kappa, layer=layer, q_reg=q,
+                          q_sing=q).size
+        used += 1
+        if time.perf_counter() - t0 > limit:
+            break
+    return n, used, time.perf_counter() - t0
+
+
+def h2_oracle_work(hb, seed=1):
+    """The blocks of an H2 step in a seeded order: near-field blocks and
+    coupling blocks (on the pivots), each with both layers."""
+    h = hb.h
+    rng = np.random.Generator(np.random.PCG64(seed))
+    items = [("near", k) for k in range(len(h.near))] + [("far", k) for k in range(len(h.far))]
+    work = []
+    for idx in rng.permutation(len(items)):
+        kind, k = items[idx]
+        if kind == "near":
+            t, s = h.near[k]
+            work += [(h.ct.idx(t), h.ct.idx(s), 0), (h.ct.idx(t), h.ct.idx(s), 1)]
+        else:
+            t, s = h.far[k]
+            work += [(hb.V.piv[t], hb.V.piv[s], 0), (hb.V.piv[t], hb.W.piv[s], 1)]
+    return work, len(items)
+
+
+def oracle_sample(m, hb, seconds, kernel, kappa, q):
+    """The oracle's rate (all host threads) on a seeded sample of an H2
+    step's blocks, near field and coupling, both layers."""
+    import oracle
+    oracle.use_native_build()
+    work, nitems = h2_oracle_work(hb)
+    n, used, dt = oracle_block_run(m, work, seconds, kernel, kappa, q)
+    return {"value": n / dt, "unit": "entries/s", "cores": oracle.num_threads(),
+            "kind": "oracle", "sample": f"{(used + 1) // 2} of {nitems} blocks (seeded order), "
+                                        f"both layers: {n} entries in {dt:.1f} s"}
+
+
 def cpu_baseline(m, hb, seconds):
     """The FP64 oracle (built here with -O3 -march=native) on a seeded
     sample of the step's blocks, near field and coupling, both layers: all
     host threads for `seconds`, then one thread for a third of that."""
     import oracle
     oracle.use_native_build()
-    h = hb.h
-    rng = np.random.Generator(np.random.PCG64(1))
-    work = [("near", k) for k in range(len(h.near))] + [("far", k) for k in range(len(h.far))]
-    order = rng.permutation(len(work))
+    work, nitems = h2_oracle_work(hb)
 
     def run(limit):
-        n = used = 0
-        t0 = time.perf_counter()
-        for idx in order:
-            kind, k = work[idx]
-            if kind == "near":
-                t, s = h.near[k]
-                pairs = [(h.ct.idx(t), h.ct.idx(s), 0), (h.ct.idx(t), h.ct.idx(s), 1)]
-            else:
-                t, s = h.far[k]
-                pairs = [(hb.V.piv[t], hb.V.piv[s], 0), (hb.V.piv[t], hb.W.piv[s], 1)]
-            for r, c, layer in pairs:
-                n += oracle.block(m.v, m.tri, r, c, layer=layer, q_reg=Q, q_sing=Q).size
-            used += 1
-            if time.perf_counter() - t0 > limit:
-                break
-        return n, used, time.perf_counter() - t0
+        n, used, dt = oracle_block_run(m, work, limit)
+        return n, (used + 1) // 2, dt
 
     threads = oracle.num_threads()
     n, used, dt = run(seconds)
@@ -1031,7 +1079,7 @@ def cpu_baseline(m, hb, seconds):
     n1, used1, dt1 = run(seconds / 3)
     oracle.set_threads(threads)
     return {"value": n / dt, "unit": "entries/s", "cores": threads, "kind": "oracle",
-            "sample": f"{used} of {len(work)} blocks (near field and coupling, seeded order), SLP "
+            "sample": f"{used} of {nitems} blocks (near field and coupling, seeded order), SLP "
                       f"and DLP each: {n} entries in {dt:.1f} s on {threads} threads",
             "one_thread": {"value": n1 / dt1, "sample": f"first {used1} blocks of the same "
                                                         f"order: {n1} entries in {dt1:.1f} s"},
@@ -1082,7 +1130,8 @@ def main():
     batched_c2m = None if args.batched_meshes <= 0 else batched_config2_leg(torch, pk, ctx, hm,
                                                                             stream)
     helmholtz = None if args.no_helmholtz else helmholtz_near_leg(torch, pk, ctx, stream, 5)
-    helmholtz_h2 = None if args.no_helmholtz else helmholtz_h2_leg(torch, pk, ctx, stream)
+    helmholtz_h2 = None if args.no_helmholtz else helmholtz_h2_leg(
+        torch, pk, ctx, stream, cpu_seconds=0.0 if args.no_cpu_baseline else args.cpu_seconds / 3)
     batched = None
     if args.batched_meshes > 0:
         bb = BatchedBench(pk, ctx, args.batched_meshes)
@@ -1092,7 +1141,8 @@ def main():
     if args.learned_n > 0:
         lb = LearnedBench(pk, ctx, args.learned_n)
         lb.GROUP = args.learned_group
-        learned = lb.result(torch, stream, min(args.steps, 10), 1)
+        learned = lb.result(torch, stream, min(args.steps, 10), 1,
+                            cpu_seconds=0.0 if args.no_cpu_baseline else args.cpu_seconds / 3)
         learned["h2_step"] = learned_h2_leg(torch, pk, ctx, hb, lb.sel, stream,
                                             min(args.steps, 10), 2)
         learned["h2_step"]["plain_ms_per_step_one_stream"] = ms_seq
