@@ -48,7 +48,7 @@ FLOPS_PER_POINT = {(0, 0): 11.0, (0, 1): 19.0, (1, 0): 18.0, (1, 1): 30.0}
 SS_EXTRA = 24.0
 SS_REGIONS = {3: 6, 2: 5, 1: 2}
 Q = 4
-FP32_VALU_PEAK = 157.3e12  # published, with packed FP32 (this build does not use packed FP32)
+FP32_VALU_PEAK = 157.3e12  # published, with packed FP32 (the library is compiled without it)
 MIXED_RATIO = 0.5  # mixed form: pairs with box gap < 0.5 max diameter stay FP64
 
 
