@@ -191,8 +191,11 @@ def cmd_traffic(a):
            "(output) | write / output | SQ_INSTS_VALU | SQ_INSTS_LDS | FP64 FLOP counted | "
            "FP32 FLOP counted | algorithmic FLOP | counted / algorithmic | ms (trace, last 5; "
            "else the FLOP pass) | "
-           "counted TFLOP/s |",
-           "|---|---|---|---|---|---|---|---|---|---|---|---|---|---|"]
+           "counted TFLOP/s | counted / measured FP64 peak |",
+           "|---|---|---|---|---|---|---|---|---|---|---|---|---|---|---|"]
+    peak = None  # TFLOP/s, bem_valu_peak in the bench run of the trace
+    if js and isinstance(js.get("roofline"), dict):
+        peak = js["roofline"].get("peak_measured")
     stored = None
     for label, name, wg, k, out_bytes, key in launches:
         f, w = value(name, wg, k, "FETCH_SIZE"), value(name, wg, k, "WRITE_SIZE")
@@ -225,7 +228,8 @@ def cmd_traffic(a):
                    f"{fmt(value(name, wg, k, 'SQ_INSTS_LDS'), '.4g')} | {fmt(f64, '.4g')} | "
                    f"{fmt(f32, '.4g')} | {fmt(model, '.4g')} | "
                    f"{fmt(None if model is None or f64 is None else (f64 + (f32 or 0)) / model, '.3f')} | "
-                   f"{fmt(ms, '.4f')} | {fmt(None if ms is None or f64 is None else f64 / ms / 1e9, '.2f')} |")
+                   f"{fmt(ms, '.4f')} | {fmt(None if ms is None or f64 is None else f64 / ms / 1e9, '.2f')} | "
+                   f"{fmt(None if ms is None or f64 is None or not peak else f64 / ms / 1e9 / peak, '.2f')} |")
         if key == "roofline":
             stored = (f, w, f64)
     out += ["", f"Algorithmic output: near field {a.near_entries:,} FP64 entries = "
@@ -234,7 +238,9 @@ def cmd_traffic(a):
             "Counted FLOP = 64 lanes x (2 FMA + ADD + MUL + TRANS) per wave instruction; the",
             "algorithmic FLOP are bench.py's model (the roofline numerator): counted over model",
             "is the instruction overhead of the reciprocal square root, its Newton step and the",
-            "quadrature bookkeeping.", ""]
+            "quadrature bookkeeping.  The measured FP64 peak is bem_valu_peak's in the bench run",
+            f"of the trace ({peak:.1f} TFLOP/s): the headline fraction of counted FLOP." if peak else
+            "No measured peak in the bench log.", ""]
     h = hashlib.sha256()
     for src in a.sources:
         h.update(open(os.path.join(a.root, src), "rb").read())
