@@ -4,6 +4,8 @@ Tolerance (FP64 path): per compared set, ||G_gpu - G_oracle||_F <= 1e-12
 ||G_oracle||_F and max |G_gpu - G_oracle| <= 1e-12 max |G_oracle|.  Block
 lists come from the oracle's own cluster / block tree; pivot lists are seeded
 random subsets of admissible cluster pairs (no input comes from the HIP path).
+The Helmholtz path at kappa = 0 reproduces the Laplace path (imaginary parts
+exactly zero).
 """
 import numpy as np
 import pytest
@@ -159,6 +161,34 @@ def test_coupling_on_pivot_lists(pk, ctx):
     got = _assemble(pk, ctx, m, op, rows, cols, coupling=True)
     for g, r, c in zip(got, rows, cols):
         _close(g, oracle.block(m.v, m.tri, r, c, **_op_kw(op)).real)
+
+
+@pytest.mark.parametrize("layer", [0, 1])
+@pytest.mark.parametrize("precision", [0, 1])
+def test_helmholtz_at_kappa_zero_is_laplace(pk, ctx, layer, precision):
+    # the Helmholtz kernels at kappa = 0 reduce to the Laplace ones: the
+    # Helmholtz path (its own sine and cosine, Sauter-Schwab xi sums by the
+    # rule instead of moments) gives the Laplace path's entries up to
+    # rounding, with imaginary parts exactly zero; near field (every pair
+    # class) and coupling lists, plain and mixed
+    m = octahedron_sphere(16)
+    cl, near, far = _near_lists(m)
+    lap = pk.make_op(pk.LAPLACE, layer, precision=precision, q_regular=4, q_singular=4,
+                     near_singular_ratio=0.5 if precision else 0.0)
+    hel = pk.make_op(pk.HELMHOLTZ, layer, precision=precision, q_regular=4, q_singular=4,
+                     kappa=0.0, near_singular_ratio=0.5 if precision else 0.0)
+    tol = 1e-5 if precision else 1e-13
+    nrows = [cl[t].idx for t, s in near[:24]]
+    ncols = [cl[s].idx for t, s in near[:24]]
+    pick = sample_subset(np.arange(len(far)), 12, seed=7)
+    crows = [sample_subset(cl[far[k][0]].idx, 20, seed=k) for k in pick]
+    ccols = [sample_subset(cl[far[k][1]].idx, 30, seed=k + 1) for k in pick]
+    for rows, cols, coupling in ((nrows, ncols, False), (crows, ccols, True)):
+        a = _assemble(pk, ctx, m, lap, rows, cols, coupling=coupling)
+        b = _assemble(pk, ctx, m, hel, rows, cols, coupling=coupling)
+        for x, y in zip(a, b):
+            assert np.all(y.imag == 0.0)
+            _close(y.real, x, tol)
 
 
 def test_coupling_rejects_adjacent_pairs(pk, ctx):
