@@ -58,6 +58,10 @@ extern "C" {
 #define BEM_EDEVICE (-3)       /* HIP runtime error (text in bem_last_error) */
 #define BEM_EUNSUPPORTED (-4)  /* valid but not supported combination */
 #define BEM_ENONFINITE (-5)    /* a computed entry is not finite */
+/* Fault injection: with the environment variable BEM_FAULT_INJECT=alloc
+ * (read at every call) the library's own device allocations fail as on an
+ * exhausted device, and the calls that need them return BEM_ENOMEM, so that
+ * callers can test their error handling. */
 
 /* bem_op.kernel */
 #define BEM_LAPLACE 0

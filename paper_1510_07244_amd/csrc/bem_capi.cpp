@@ -2,6 +2,8 @@
 // quadrature tables) and kernel launches.  See include/bem.h.
 #include <hip/hip_runtime.h>
 
+#include <cstdlib>
+
 #include <algorithm>
 #include <cmath>
 #include <cstring>
@@ -14,6 +16,18 @@ namespace bem {
 int fail(bem_ctx *ctx, int code, const std::string &msg) {
   if (ctx) ctx->err = msg;
   return code;
+}
+
+// Device allocation of the library's own buffers.  The environment variable
+// BEM_FAULT_INJECT=alloc makes it fail as an exhausted device would (read at
+// every call), so that callers can test their handling of BEM_ENOMEM.
+hipError_t dev_malloc(void **p, size_t bytes) {
+  const char *f = std::getenv("BEM_FAULT_INJECT");
+  if (f && std::strcmp(f, "alloc") == 0) {
+    *p = nullptr;
+    return hipErrorOutOfMemory;
+  }
+  return hipMalloc(p, bytes);
 }
 
 int hip_fail(bem_ctx *ctx, hipError_t e, const char *where) {
@@ -72,7 +86,7 @@ int ensure_geo(bem_ctx *ctx, int32_t nt, int64_t *ldg) {
     if (ctx->geo) (void)hipFree(ctx->geo);
     ctx->geo = nullptr;
     ctx->geo_cap = 0;
-    e = hipMalloc(&ctx->geo, need * sizeof(double));
+    e = dev_malloc((void **)&ctx->geo, need * sizeof(double));
     if (e != hipSuccess) return hip_fail(ctx, e, "hipMalloc(geometry)");
     ctx->geo_cap = need;
   }
@@ -90,6 +104,16 @@ int get_rules(bem_ctx *ctx, const bem_op *op, const bem::DevRules **out) {
     return BEM_OK;
   }
   bem::DevRules d;
+  // the tables of a failed build are released (nothing is kept half-built)
+  struct Release {
+    bem::DevRules *d;
+    ~Release() {
+      if (!d) return;
+      for (void *m : {(void *)d->tri, (void *)d->xi, (void *)d->ss[0], (void *)d->ss[1],
+                      (void *)d->ss[2], (void *)d->ss[3]})
+        if (m) (void)hipFree(m);
+    }
+  } release{&d};
   try {
     const bem::TriRule tr = bem::triangle_rule(op->regular_rule, op->q_regular);
     d.nq = (int)tr.s.size();
@@ -97,7 +121,7 @@ int get_rules(bem_ctx *ctx, const bem_op *op, const bem::DevRules **out) {
     h.insert(h.end(), tr.s.begin(), tr.s.end());
     h.insert(h.end(), tr.t.begin(), tr.t.end());
     h.insert(h.end(), tr.w.begin(), tr.w.end());
-    hipError_t e = hipMalloc(&d.tri, h.size() * sizeof(double));
+    hipError_t e = dev_malloc((void **)&d.tri, h.size() * sizeof(double));
     if (e != hipSuccess) return hip_fail(ctx, e, "hipMalloc(rule)");
     e = hipMemcpy(d.tri, h.data(), h.size() * sizeof(double), hipMemcpyHostToDevice);
     if (e != hipSuccess) return hip_fail(ctx, e, "hipMemcpy(rule)");
@@ -117,7 +141,7 @@ int get_rules(bem_ctx *ctx, const bem_op *op, const bem::DevRules **out) {
       hx[3 * q] = m1;
       hx[3 * q + 1] = m2;
       d.nxi = q;
-      e = hipMalloc(&d.xi, hx.size() * sizeof(double));
+      e = dev_malloc((void **)&d.xi, hx.size() * sizeof(double));
       if (e != hipSuccess) return hip_fail(ctx, e, "hipMalloc(xi rule)");
       e = hipMemcpy(d.xi, hx.data(), hx.size() * sizeof(double), hipMemcpyHostToDevice);
       if (e != hipSuccess) return hip_fail(ctx, e, "hipMemcpy(xi rule)");
@@ -128,7 +152,7 @@ int get_rules(bem_ctx *ctx, const bem_op *op, const bem::DevRules **out) {
       d.np[cls] = (int)r.w.size();
       std::vector<double> hs;
       for (const auto *vec : {&r.xs, &r.xt, &r.ys, &r.yt, &r.w}) hs.insert(hs.end(), vec->begin(), vec->end());
-      e = hipMalloc(&d.ss[cls], hs.size() * sizeof(double));
+      e = dev_malloc((void **)&d.ss[cls], hs.size() * sizeof(double));
       if (e != hipSuccess) return hip_fail(ctx, e, "hipMalloc(ss rule)");
       e = hipMemcpy(d.ss[cls], hs.data(), hs.size() * sizeof(double), hipMemcpyHostToDevice);
       if (e != hipSuccess) return hip_fail(ctx, e, "hipMemcpy(ss rule)");
@@ -139,6 +163,7 @@ int get_rules(bem_ctx *ctx, const bem_op *op, const bem::DevRules **out) {
     return fail(ctx, BEM_EINVAL, ex.what());
   }
   auto ins = ctx->rules.emplace(key, d);
+  release.d = nullptr;  // kept by the context
   *out = &ins.first->second;
   return BEM_OK;
 }

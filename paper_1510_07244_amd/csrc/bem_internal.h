@@ -359,6 +359,8 @@ struct DeviceGuard {  // make the context's device current, restore on exit
 // context's error text and return a BEM_ code
 int fail(bem_ctx *ctx, int code, const std::string &msg);
 int hip_fail(bem_ctx *ctx, hipError_t e, const char *where);
+// hipMalloc of the library's buffers; fails when BEM_FAULT_INJECT=alloc
+hipError_t dev_malloc(void **p, size_t bytes);
 int check_op(bem_ctx *ctx, const bem_op *op);
 int check_mesh(bem_ctx *ctx, const bem_mesh *m);
 int check_blocks(bem_ctx *ctx, const bem_blocks *b, const void *out, int64_t out_len);

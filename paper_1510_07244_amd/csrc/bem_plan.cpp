@@ -376,11 +376,11 @@ int bem_plan_batched(bem_ctx *ctx, const bem_op *op, int32_t nbatch, const bem_b
       p->geo_ld.push_back(ld);
       total += (int64_t)GEO_NF * ld;
     }
-    if (total > 0 && (e = hipMalloc(&p->geo, (size_t)total * sizeof(double))) != hipSuccess)
+    if (total > 0 && (e = dev_malloc((void **)&p->geo, (size_t)total * sizeof(double))) != hipSuccess)
       return bail(hip_fail(ctx, e, "hipMalloc(plan geometry)"));
-    if ((e = hipMalloc(&p->counter, 256)) != hipSuccess ||
-        (e = hipMalloc(&p->dmode, sizeof(int32_t) * std::max(nbatch, 1))) != hipSuccess ||
-        (e = hipMalloc(&p->dbatch, sizeof(BlockArgs) * std::max(nbatch, 1))) != hipSuccess)
+    if ((e = dev_malloc((void **)&p->counter, 256)) != hipSuccess ||
+        (e = dev_malloc((void **)&p->dmode, sizeof(int32_t) * std::max(nbatch, 1))) != hipSuccess ||
+        (e = dev_malloc((void **)&p->dbatch, sizeof(BlockArgs) * std::max(nbatch, 1))) != hipSuccess)
       return bail(hip_fail(ctx, e, "hipMalloc(plan)"));
     for (size_t q = 0; q < p->meshes.size(); ++q)
       if ((e = launch_geometry(p->meshes[q], p->geo + p->geo_off[q], p->geo_ld[q], ctx->flags, s)) !=
@@ -511,7 +511,7 @@ int bem_plan_batched(bem_ctx *ctx, const bem_op *op, int32_t nbatch, const bem_b
       if (p->dtiles) (void)hipFree(p->dtiles);
       p->dtiles = nullptr;
       tiles_cap = 0;
-      if ((e = hipMalloc(&p->dtiles, tl.size() * sizeof(int4))) != hipSuccess)
+      if ((e = dev_malloc((void **)&p->dtiles, tl.size() * sizeof(int4))) != hipSuccess)
         return hip_fail(ctx, e, "hipMalloc(tile queue)");
       tiles_cap = tl.size();
     }

@@ -13,7 +13,9 @@
   layers in one pass, single- and double-layer coupling, each list with its
   own layer and sub-tile shape): every output equals the per-call bits.
 * Host-visible errors (an out-of-range triangle id, invalid layer choices)
-  are rejected at plan time.
+  are rejected at plan time; a corrupt tuning cache is ignored; device
+  allocation failures forced from the host (BEM_FAULT_INJECT=alloc) are
+  reported as BEM_ENOMEM and leave the context usable.
 """
 import json
 
@@ -363,3 +365,56 @@ def test_plan_layer_arguments_are_checked(pk, ctx):
     ctx.check()
     assert np.array_equal(_bits(a), _bits(ra)) and np.array_equal(_bits(b), _bits(rb))
     plan.close()
+
+
+def test_corrupt_tuning_cache_is_ignored(pk, ctx, batch, tmp_path):
+    # a cache file with garbage, a line of this workload's key with missing
+    # fields and one with invalid values: the autotuner times the candidates
+    # as with no cache and appends a valid line
+    import torch
+    op = pk.make_op(pk.LAPLACE, pk.SLP, q_regular=4, q_singular=4)
+    first, _ = _plan(pk, ctx, op, batch, autotune=True, cache=str(tmp_path / "ok.jsonl"))
+    key = json.loads(open(tmp_path / "ok.jsonl").readline())["key"]
+    first.close()
+    cache = tmp_path / "bad.jsonl"
+    cache.write_text("not json at all\n"
+                     '{"key": "%s", "grid": 512}\n'
+                     '{"key": "%s", "grid": -3, "tile_rows": 900, "tile_cols": 0, "x_chunk": 6, '
+                     '"granularity": 7, "ms": 1.0}\n' % (key, key))
+    plan, outs = _plan(pk, ctx, op, batch, autotune=True, cache=str(cache))
+    assert plan.config["tuned_ms"] > 0  # timed: nothing usable was cached
+    lines = open(cache).read().splitlines()
+    assert len(lines) == 4 and json.loads(lines[-1])["key"] == key
+    plan.run()
+    ctx.check()
+    for e, o in zip(batch, outs):
+        ref = _per_call(pk, ctx, op, e).cpu().numpy()
+        assert np.abs(o.cpu().numpy() - ref).max() <= 1e-13 * np.abs(ref).max()
+    plan.close()
+    torch.cuda.synchronize()
+
+
+def test_allocation_failure_forced_from_the_host(pk, batch, monkeypatch):
+    # BEM_FAULT_INJECT=alloc makes the library's device allocations fail:
+    # a fresh context's first assembly and a plan report BEM_ENOMEM, write
+    # nothing and leave the context usable once the variable is gone
+    import torch
+    c = pk.Context(0)
+    op = pk.make_op(pk.LAPLACE, pk.SLP, q_regular=4, q_singular=4)
+    e = batch[0]
+    out = torch.full((e["total"],), float("nan"), dtype=torch.float64, device="cuda")
+    monkeypatch.setenv("BEM_FAULT_INJECT", "alloc")
+    with pytest.raises(pk.BemError) as ei:
+        c.assemble_nearfield(e["mesh"], op, e["blocks"], out)
+    assert ei.value.code == pk.BEM_ENOMEM
+    with pytest.raises(pk.BemError) as ei:
+        pk.Plan(c, op, [(e["mesh"], e["blocks"], out, 0)])
+    assert ei.value.code == pk.BEM_ENOMEM
+    torch.cuda.synchronize()
+    assert torch.isnan(out).all()
+    monkeypatch.delenv("BEM_FAULT_INJECT")
+    c.assemble_nearfield(e["mesh"], op, e["blocks"], out)
+    c.check()
+    ref = _per_call(pk, c, op, e)
+    assert np.array_equal(_bits(out), _bits(ref))
+    c.close()
