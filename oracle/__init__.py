@@ -32,6 +32,13 @@ def use_native_build():
     _lib, _lib_path = None, NATIVE_LIB
 
 
+def use_library(path):
+    """Load the oracle from another build of the same source (the tests run
+    an address- and undefined-behaviour-sanitized build through this)."""
+    global _lib, _lib_path
+    _lib, _lib_path = None, path
+
+
 def lib():
     global _lib
     if _lib is None:
