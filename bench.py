@@ -777,6 +777,21 @@ def run_concurrent(torch, hb, stream, steps, warmup):
     return (t1 - t0) * 1e3 / steps, a.elapsed_time(b) / steps
 
 
+def step_spread(torch, hb, stream, n):
+    """min / median / max of n steps timed one by one (HIP events on the
+    joining stream), after the bracketed timing."""
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+          for _ in range(n)]
+    for a, b in ev:
+        a.record(stream)
+        hb.step_concurrent(torch, stream)
+        b.record(stream)
+    torch.cuda.synchronize()
+    hb.check_concurrent()
+    ms = sorted(a.elapsed_time(b) for a, b in ev)
+    return {"min": ms[0], "median": float(np.median(ms)), "max": ms[-1], "steps": n}
+
+
 def per_layer_near(torch, hb, stream, reps):
     """HIP-event means of the per-layer near-field passes (mirrored single
     layer, full double layer) that the one-pass call replaces."""
@@ -1116,8 +1131,10 @@ def main():
     per_layer = per_layer_near(torch, hb, stream, max(5, min(args.steps, 20)))
     if args.one_stream:
         ms_step, ms_step_ev = ms_seq, ms_seq
+        spread = None
     else:
         ms_step, ms_step_ev = run_concurrent(torch, hb, stream, args.steps, args.warmup)
+        spread = step_spread(torch, hb, stream, max(5, min(args.steps, 10)))
     hm = H2Bench(pk, ctx, m, mixed=True)
     ms_seq_m, phase_m = run_leg(torch, ctx, hm, stream, args.steps, args.warmup)
     ms_step_m = ms_seq_m if args.one_stream else run_concurrent(torch, hm, stream, args.steps,
@@ -1221,6 +1238,7 @@ def main():
                          "DLP coupling) on four streams, joined per step; phase_ms from the same "
                          "step run on one stream"),
         "ms_per_step_events": ms_step_ev,
+        "step_ms_spread": spread,
         "sequential": {"ms_per_step": ms_seq, "value": hb.entries_evaluated() / (ms_seq * 1e-3)},
         "roofline": {
             "kernel": "k_blocks<Laplace, DLP> coupling (the step's longest launch; "
