@@ -340,10 +340,11 @@ class BatchedBench:
         self.pk, self.ctx = pk, ctx
         self.meshes = perturbed_sphere_batch(count)
         t0 = time.perf_counter()
-        self.items = []
+        self.items, self.bases = [], []
         for m in self.meshes:
             h = H2Setup(ctx, m.v, m.tri, kernel=pk.LAPLACE, q_regular=Q, q_singular=Q)
             V = h.basis(0)
+            self.bases.append(V)
             near, n_near = h.near_blocks(mirror=True)
             cs, n_cs = h.coupling_blocks(V, V, mirror=True)
             self.items.append((h, near, n_near, cs, n_cs))
@@ -403,11 +404,36 @@ class BatchedBench:
         self.ctx.check(stream)
         return dt
 
-    def result(self, torch, stream, steps, warmup):
+    def cpu_oracle(self, seconds):
+        """The oracle's rate (all host threads) on a seeded sample of the
+        meshes' near-field and coupling blocks (single layer)."""
+        import oracle
+        oracle.use_native_build()
+        work = []
+        for m, (h, *_), V in zip(self.meshes, self.items, self.bases):
+            work += [(m, h.ct.idx(t), h.ct.idx(s)) for t, s in h.near]
+            work += [(m, V.piv[t], V.piv[s]) for t, s in h.far]
+        order = np.random.Generator(np.random.PCG64(3)).permutation(len(work))
+        n = used = 0
+        t0 = time.perf_counter()
+        for k in order:
+            m, r, c = work[k]
+            n += oracle.block(m.v, m.tri, r, c, layer=0, q_reg=Q, q_sing=Q).size
+            used += 1
+            if time.perf_counter() - t0 > seconds:
+                break
+        dt = time.perf_counter() - t0
+        return {"value": n / dt, "unit": "entries/s", "cores": oracle.num_threads(),
+                "kind": "oracle", "sample": f"{used} of {len(work)} blocks of the "
+                                            f"{len(self.meshes)} meshes (seeded order): {n} "
+                                            f"entries in {dt:.1f} s"}
+
+    def result(self, torch, stream, steps, warmup, cpu_seconds=0.0):
         ms_b = self.time(torch, self.batched, stream, steps, warmup)
         ms_p = self.time(torch, self.per_call, stream, steps, warmup)
         sizes = [int(m.nt) for m in self.meshes]
-        return {
+        extra = {"cpu_oracle": self.cpu_oracle(cpu_seconds)} if cpu_seconds > 0 else {}
+        return {**extra,
             "value": self.n_entries / (ms_b * 1e-3), "unit": "entries/s", "ms_per_step": ms_b,
             "per_call_ms_per_step": ms_p, "per_call_value": self.n_entries / (ms_p * 1e-3),
             "speedup_vs_per_call": ms_p / ms_b, "entries_per_step": int(self.n_entries),
@@ -1152,7 +1178,8 @@ def main():
     batched = None
     if args.batched_meshes > 0:
         bb = BatchedBench(pk, ctx, args.batched_meshes)
-        batched = bb.result(torch, stream, args.steps, args.warmup)
+        batched = bb.result(torch, stream, args.steps, args.warmup,
+                            cpu_seconds=0.0 if args.no_cpu_baseline else args.cpu_seconds / 3)
         del bb
     learned = None
     if args.learned_n > 0:
