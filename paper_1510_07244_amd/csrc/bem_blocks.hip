@@ -315,8 +315,18 @@ __device__ __forceinline__ void singular_chunk_both(const BlockArgs &a, const Ld
   if (active)
     have = pair_geometry(a.v, a.tri, a.nv, a.geo, a.ldg, l.rid[rl], l.cid[cl], cls, a.flags, &g);
   if (!have) idle(&g);
-  const Acc<KERNEL> vs = ss_pair_lane<KERNEL, BEM_SLP>(g, a.ss, cls, a.kappa);
-  const Acc<KERNEL> vd = ss_pair_lane<KERNEL, BEM_DLP>(g, a.ss, cls, a.kappa);
+  // a Helmholtz pair with an edge or a vertex in common takes both layers
+  // from one pass over its eta points (uniform branch: the class is the
+  // wave's)
+  const bool fuse = KERNEL == BEM_HELMHOLTZ && cls != CLS_IDENTICAL;
+  Acc<KERNEL> vs, vd;
+  if constexpr (KERNEL == BEM_HELMHOLTZ) {
+    if (fuse) ss_pair_lane_both(g, a.ss, cls, a.kappa, &vs, &vd);
+  }
+  if (!fuse) {
+    vs = ss_pair_lane<KERNEL, BEM_SLP>(g, a.ss, cls, a.kappa);
+    vd = ss_pair_lane<KERNEL, BEM_DLP>(g, a.ss, cls, a.kappa);
+  }
   if (have) {
     store_as<KERNEL, MIXED>(a.out, dst, vs, a.flags);
     store_as<KERNEL, MIXED>(a.out2, dst, vd, a.flags);
@@ -328,9 +338,14 @@ __device__ __forceinline__ void singular_chunk_both(const BlockArgs &a, const Ld
   if (active)
     have = pair_geometry(a.v, a.tri, a.nv, a.geo, a.ldg, l.cid[cl], l.rid[rl], cls, a.flags, &g);
   if (!have) idle(&g);
-  const Acc<KERNEL> md = ss_pair_lane<KERNEL, BEM_DLP>(g, a.ss, cls, a.kappa);
-  Acc<KERNEL> ms = vs;
-  if (cls == CLS_EDGE) ms = ss_pair_lane<KERNEL, BEM_SLP>(g, a.ss, cls, a.kappa);
+  Acc<KERNEL> ms = vs, md;
+  if constexpr (KERNEL == BEM_HELMHOLTZ) {
+    if (cls == CLS_EDGE) ss_pair_lane_both(g, a.ss, cls, a.kappa, &ms, &md);
+  }
+  if (KERNEL != BEM_HELMHOLTZ || cls != CLS_EDGE) {
+    md = ss_pair_lane<KERNEL, BEM_DLP>(g, a.ss, cls, a.kappa);
+    if (cls == CLS_EDGE) ms = ss_pair_lane<KERNEL, BEM_SLP>(g, a.ss, cls, a.kappa);
+  }
   if (have) {
     store_as<KERNEL, MIXED>(a.out, mdst, ms, a.flags);
     store_as<KERNEL, MIXED>(a.out2, mdst, md, a.flags);

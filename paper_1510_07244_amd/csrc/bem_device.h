@@ -426,6 +426,59 @@ __device__ __forceinline__ Acc<KERNEL> ss_pair_lane(const PairGeo &g, const SSAr
   return ss_finish<KERNEL, LAYER>(g, ss, re, im);
 }
 
+// Both layers of one Helmholtz singular pair per lane in one pass over the
+// eta points (edge- and vertex-adjacent pairs, whose single and double
+// layer share the eta table): the difference vector, its length and the
+// sine and cosine of every xi point serve both sums.  Each sum takes the
+// same operands in the same order as ss_pair_lane's for its layer.
+__device__ __forceinline__ void ss_pair_lane_both(const PairGeo &g, const SSArgs &ss, int cls,
+                                                  double kappa, Acc<BEM_HELMHOLTZ> *vs,
+                                                  Acc<BEM_HELMHOLTZ> *vd) {
+  const uniform_ptr T = (uniform_ptr)(pick4(ss.eta, cls));
+  const uniform_ptr X = (uniform_ptr)(ss.xi);
+  const int n = pick4(ss.np, cls), q = ss.q;
+  constexpr int U = 2;
+  double sre[U], sim[U], dre[U], dim[U];
+#pragma unroll
+  for (int u = 0; u < U; ++u) sre[u] = sim[u] = dre[u] = dim[u] = 0.0;
+  auto point = [&](int p, int u) {
+    const double g1 = T[p], g2 = T[n + p], g3 = T[2 * n + p], g4 = T[3 * n + p];
+    const double w = T[4 * n + p];
+    double d[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+      d[c] = fma(g1, g.E1i[c], fma(g2, g.E2i[c], fma(-g3, g.E1j[c], -g4 * g.E2j[c])));
+    const double rho2 = fma(d[0], d[0], fma(d[1], d[1], d[2] * d[2]));
+    const double z = rsqrt_newton(rho2);  // 1 / |d|
+    const double rho = rho2 * z;
+    const double bs = w * z;
+    const double bd = w * fma(d[0], g.n[0], fma(d[1], g.n[1], d[2] * g.n[2])) * z * z * z;
+    for (int a = 0; a < q; ++a) {
+      const double xa = X[a];
+      const double kr = kappa * xa * rho;
+      double sn, cs;
+      sincos_cw(kr, &sn, &cs);
+      const double c1 = bs * X[q + a];  // w_a xi_a^2
+      sre[u] = fma(c1, cs, sre[u]);
+      sim[u] = fma(c1, sn, sim[u]);
+      const double c2 = bd * X[2 * q + a];  // w_a xi_a
+      dre[u] = fma(c2, fma(kr, sn, cs), dre[u]);
+      dim[u] = fma(c2, fma(-kr, cs, sn), dim[u]);
+    }
+  };
+  int p = 0;
+  for (; p + U <= n; p += U) {
+#pragma unroll
+    for (int u = 0; u < U; ++u) point(p + u, u);
+  }
+  for (; p < n; ++p) point(p, 0);
+  double a0 = sre[0], a1 = sim[0], b0 = dre[0], b1 = dim[0];
+#pragma unroll
+  for (int u = 1; u < U; ++u) a0 += sre[u], a1 += sim[u], b0 += dre[u], b1 += dim[u];
+  *vs = ss_finish<BEM_HELMHOLTZ, BEM_SLP>(g, ss, a0, a1);
+  *vd = ss_finish<BEM_HELMHOLTZ, BEM_DLP>(g, ss, b0, b1);
+}
+
 // One singular pair per wave: lanes stride over the eta points, then a
 // butterfly sum.  Every lane returns the entry.
 template <int KERNEL, int LAYER>
