@@ -10,6 +10,8 @@
   the 2048-triangle sphere's list are written; the 8192-triangle sphere is
   the benchmark's launch), and against the per-layer entry point on the
   whole list at 1e-13 of the largest entry (rounding order differs).
+* Entries of pairs with a common vertex (Laplace and Helmholtz) equal those
+  of the per-layer passes bit for bit.
 * The mixed form (FP32 regular pairs, FP64 singular and near-singular ones)
   of the one-pass call: every sampled block of both outputs within 1e-6
   relative Frobenius error of the oracle, and within 1e-6 of the per-layer
@@ -162,6 +164,40 @@ def test_both_unmirrored_equals_per_layer(pk, ctx):
         ctx.check()
         ref = ref.cpu().numpy()
         assert np.abs(got - ref).max() <= 1e-13 * np.abs(ref).max()
+
+
+def _shares_vertex(tr, tc):
+    # (len(tr), len(tc)) counts of common vertices
+    return (tr[:, None, :, None] == tc[None, :, None, :]).sum(axis=(2, 3))
+
+
+@pytest.mark.parametrize("kernel,kappa", [(0, 0.0), (1, 4.0)])
+def test_both_singular_entries_bitwise_per_layer(pk, ctx, kernel, kappa):
+    # pairs with a common vertex: the one-pass form sums each layer with the
+    # per-layer Sauter-Schwab loop's operands in its order (Helmholtz edge-
+    # and vertex-adjacent pairs share one eta pass), so the entries are
+    # equal bit for bit
+    import torch
+    m = octahedron_sphere(8)
+    mesh = pk.Mesh(torch.from_numpy(m.v), torch.from_numpy(m.tri))
+    idx = np.arange(m.nt, dtype=np.int32)
+    rows, cols = [idx[:300], idx[300:]], [idx[:300], idx[:211]]
+    blocks, total = pk.Blocks.from_lists(rows, cols)
+    op = pk.make_op(kernel, pk.SLP, q_regular=4, q_singular=4, kappa=kappa)
+    s, d = _both(pk, ctx, mesh, op, blocks, total)
+    # column-major blocks: entry (i, j) of a block at i + rows * j
+    common = np.concatenate([_shares_vertex(m.tri[r], m.tri[c]).T.ravel()
+                             for r, c in zip(rows, cols)])
+    assert all(np.count_nonzero(common == k) for k in (1, 2, 3))
+    mask = common > 0
+    for layer, got in ((pk.SLP, s), (pk.DLP, d)):
+        ref = torch.full((total,), float("nan"), dtype=pk.out_dtype(op), device="cuda")
+        ctx.assemble_nearfield(mesh, pk.make_op(kernel, layer, q_regular=4, q_singular=4,
+                                                kappa=kappa), blocks, ref)
+        ctx.check()
+        ref = ref.cpu().numpy()
+        assert np.all(np.isfinite(got[mask]))
+        assert np.array_equal(got[mask], ref[mask]), (layer, np.abs(got - ref)[mask].max())
 
 
 def test_both_error_paths(pk, ctx):
